@@ -1,0 +1,294 @@
+/*
+ * cabinrom: rational-Arnoldi model-order reduction of the coupled structural-acoustic (u-p)
+ * finite-element system, and its frequency sweep, on one AMD Instinct MI355X (gfx950).
+ *
+ * The full-order model is the paper's problem statement (Section 3.3, Eq. (8)) with damping
+ * carried by complex stiffness (text after Eq. (8)), so D = 0:
+ *
+ *     (K - w^2 M) x(w) = f(w),   y(w) = C^T x(w)
+ *
+ * with the block structure of Section 2, Eq. (2)-(3) (two domains: structure u, fluid p):
+ *
+ *     K = [ K_s  -C  ]      M = [ M_s        0   ]
+ *         [ 0    K_f ]          [ rho0 C^T   M_f ]
+ *
+ * The reduced model (Section 3.3, Eq. (10)-(11)) is the Galerkin projection onto the rational
+ * Krylov space  U_j K_{k_j}(A_j^{-1} M, A_j^{-1} F),  A_j = K - w_j^2 M.
+ *
+ * Conventions for every entry point:
+ *  - Angular frequencies w are in rad/s. Time convention e^{+i w t}.
+ *  - Complex numbers are cr_z {re, im} (layout-compatible with C99 double _Complex and
+ *    numpy.complex128). Dense arrays are column-major.
+ *  - Pointers named *_dev are device pointers on the context's device, owned by the caller.
+ *    Every other pointer is a host pointer, borrowed for the duration of the call and copied.
+ *  - Handles (cr_ctx, cr_sys, cr_fact, cr_basis, cr_rom, cr_mlp) are owned by the library and
+ *    released by the matching *_destroy. A cr_fact or cr_basis must be destroyed before the
+ *    cr_sys it was made from; a cr_sys before its cr_ctx.
+ *  - All device work is enqueued on the stream given to cr_ctx_create; every call returns after
+ *    that stream has completed the call's work.
+ *  - Errors: every call returns a cr_status. On failure the outputs are left untouched (unless
+ *    stated otherwise) and cr_last_error(ctx) holds a message until the next call on that ctx.
+ *  - Global DoF order: displacement DoFs (x, y, z) of every non-clamped solid node in
+ *    increasing node id, then the pressure DoF of every fluid node in increasing node id.
+ *  - Loads: column l of F is the load direction; the load at frequency w is
+ *    f_l(w) = (i w)^flags[l] * F[:, l].
+ */
+#ifndef CABINROM_H
+#define CABINROM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CR_OK = 0,
+    CR_E_INVALID = -1,        /* bad argument (null pointer, size out of range, wrong state) */
+    CR_E_OOM = -2,            /* device or host allocation failed */
+    CR_E_HIP = -3,            /* a HIP runtime call failed */
+    CR_E_SINGULAR = -4,       /* a pivot was exactly zero and could not be perturbed */
+    CR_E_NOT_CONVERGED = -5,  /* iterative refinement did not reach its tolerance */
+    CR_E_UNSUPPORTED = -6,    /* input outside what this build supports */
+    CR_E_STATE = -7           /* call order violated (e.g. factor before analyse) */
+} cr_status;
+
+typedef enum {
+    CR_FP64 = 0,   /* plain method: complex-FP64 factorisation and solves */
+    CR_MIXED = 1   /* complex-FP32 factorisation / reduced LU, FP64 iterative refinement */
+} cr_precision;
+
+typedef struct { double re, im; } cr_z;
+
+typedef struct cr_ctx_s* cr_ctx;
+typedef struct cr_sys_s* cr_sys;
+typedef struct cr_fact_s* cr_fact;
+typedef struct cr_basis_s* cr_basis;
+typedef struct cr_rom_s* cr_rom;
+typedef struct cr_mlp_s* cr_mlp;
+
+/* ---------------------------------------------------------------- context ---------------- */
+
+/* Bind to HIP device `device` and stream `hip_stream` (a hipStream_t; NULL = the null stream). */
+cr_status cr_ctx_create(int device, void* hip_stream, cr_ctx* out);
+void cr_ctx_destroy(cr_ctx ctx);
+/* Message of the last failed call on ctx ("" if none). Valid until the next call on ctx. */
+const char* cr_last_error(cr_ctx ctx);
+/* Message of the last failed cr_ctx_create in this process. */
+const char* cr_create_error(void);
+
+/* ---------------------------------------------------------------- assembly (Section 2) --- */
+
+enum { CR_FLUID = 0, CR_SOLID = 1 };
+enum { CR_LOAD_VOLUME_VELOCITY = 0, CR_LOAD_POINT_FORCE = 1, CR_LOAD_SKIN_PRESSURE = 2 };
+
+/* Material: fluid {rho, eta, c} with c~^2 = c^2 (1 + i eta); solid {rho, eta, E, nu} with
+   E~ = E (1 + i eta) (complex stiffness, Section 3.3 after Eq. (8)). */
+typedef struct { int32_t kind; double rho, eta, c, E, nu; } cr_material;
+
+/* hex8 mesh. coords: n_nodes x 3 (row-major); elems: n_el x 8 node ids in the order
+   (-,-,-) (+,-,-) (+,+,-) (-,+,-) (-,-,+) (+,-,+) (+,+,+) (-,+,+) of natural coordinates;
+   elem_mat: material index per element; clamped: nodes whose displacements are fixed;
+   iface: n_iface x 4 node ids of fluid-solid faces, ordered so that (x1-x0) x (x3-x0) points
+   out of the fluid. Nodes on the interface are shared by the fluid and the solid elements. */
+typedef struct {
+    int64_t n_nodes;
+    const double* coords;
+    int64_t n_el;
+    const int64_t* elems;
+    const int32_t* elem_mat;
+    int64_t n_clamped;
+    const int64_t* clamped;
+    int64_t n_iface;
+    const int64_t* iface;
+} cr_mesh;
+
+/* One load column. VOLUME_VELOCITY: Q = value at fluid `node` (F = rho0 Q e_p(node), flag 1).
+   POINT_FORCE: value along axis `dir` at solid `node` (flag 0). SKIN_PRESSURE: nodal pressure
+   amplitudes amp[n_nodes] interpolated bilinearly on faces[n_faces x 4] whose right-hand
+   normal points away from the structure; F = -int N^T p n dGamma (flag 0). */
+typedef struct {
+    int32_t kind;
+    int32_t dir;
+    int64_t node;
+    cr_z value;
+    int64_t n_faces;
+    const int64_t* faces;
+    const cr_z* amp;
+} cr_load;
+
+/* Assemble K, M (complex FP64 CSR), F and the receiver map (pressure DoFs of recv_nodes) on the
+   host (hex8, 2x2x2 Gauss; interface quads 2x2 Gauss), then upload the Jacobi-scaled system
+   S K S, S M S, S F with S = diag(|K_ii|^{-1/2}) to the device. Exactly one fluid material. */
+cr_status cr_assemble(cr_ctx ctx, const cr_mesh* mesh, const cr_material* mats, int32_t nmat,
+                      const cr_load* loads, int32_t nload, const int64_t* recv_nodes, int32_t n_o,
+                      cr_sys* out);
+
+typedef struct { int64_t n, nnz, n_u; int32_t L, n_o; } cr_sys_dims;
+cr_status cr_sys_get_dims(cr_sys sys, cr_sys_dims* out);
+/* Copy the unscaled assembled system to host arrays (rowptr n+1, col nnz, K nnz, M nnz,
+   F n x L, flags L, recv_dofs n_o). Any pointer may be NULL to skip that array. */
+cr_status cr_sys_export(cr_sys sys, int64_t* rowptr, int32_t* col, cr_z* K, cr_z* M, cr_z* F,
+                        int32_t* flags, int64_t* recv_dofs);
+void cr_sys_destroy(cr_sys sys);
+
+/* ---------------------------------------------------------------- analysis --------------- */
+
+typedef struct {
+    int32_t n_fronts, n_levels, max_front, max_pivots;
+    int64_t factor_entries;   /* stored L + U entries (complex)                           */
+    double factor_flops;      /* real flops of one numeric factorisation (complex, 4M)    */
+    double seconds;
+} cr_analysis_info;
+
+/* Symbolic analysis, once per sparsity pattern (the paper reuses its analysis across
+   frequencies, Section 3.2): nested dissection by coordinate bisection with vertex separators,
+   assembly tree, front index maps. Idempotent. */
+cr_status cr_analyse(cr_sys sys, cr_analysis_info* info);
+
+/* ---------------------------------------------------------------- factor / solve --------- */
+
+typedef struct { int32_t n_perturbed; double seconds; } cr_factor_info;
+
+/* Multifrontal LU of A = K - w^2 M at omega (rad/s), in complex FP64 (CR_FP64) or complex
+   FP32 (CR_MIXED), partial pivoting inside each front's fully-summed block, tiny pivots
+   perturbed (counted in info). The factor is kept on the device and reused by every solve at
+   this expansion point (Section 3.3, offline phase). Requires cr_analyse. */
+cr_status cr_factor(cr_sys sys, double omega, cr_precision prec, cr_fact* out, cr_factor_info* info);
+void cr_fact_destroy(cr_fact f);
+
+typedef struct { int32_t max_iter; double tol; } cr_ir_opts;   /* defaults: 10, 1e-14 */
+typedef struct { int32_t iterations; double backward_error; } cr_solve_info;
+
+/* Solve A X = B for nrhs columns (n x nrhs, leading dimension n, device, complex128), with FP64
+   iterative refinement: R = B - A X in FP64, D = LU^{-1} R, X += D, until the normwise backward
+   error max_l ||r_l|| / (||A||_inf ||x_l|| + ||b_l||) <= tol. CR_E_NOT_CONVERGED if max_iter
+   corrections do not reach tol (X then holds the last iterate). */
+cr_status cr_solve(cr_fact f, int32_t nrhs, const cr_z* B_dev, cr_z* X_dev, const cr_ir_opts* opts,
+                   cr_solve_info* info);
+
+/* ---------------------------------------------------------------- basis / projection ----- */
+
+typedef struct {
+    int32_t q;                 /* basis columns kept                                       */
+    int32_t deflated;          /* columns dropped by the 1e-10 norm-ratio rule             */
+    int32_t n_shifts;
+    int32_t ir_iterations;     /* total refinement corrections over all solves             */
+    double max_backward_error; /* over all shifted solves                                  */
+    int32_t n_perturbed;
+    double seconds;
+} cr_basis_info;
+
+/* Rational Krylov basis at fixed expansion points omegas[nshift] (rad/s) with blocks[j] Krylov
+   blocks at point j (Eq. (10)): factor A_j once, X = A_j^{-1} F, then X = A_j^{-1} M Q with Q
+   the latest orthonormalised block; block classical Gram-Schmidt twice (CGS2) against the basis
+   in FP64, columns whose norm falls below 1e-10 of their norm before orthogonalisation are
+   dropped. The basis is orthonormal for the Jacobi-scaled system. */
+cr_status cr_basis_build(cr_sys sys, int32_t nshift, const double* omegas, const int32_t* blocks,
+                         cr_precision prec, cr_basis* out, cr_basis_info* info);
+
+enum { CR_POLICY_GREEDY = 0, CR_POLICY_MLP = 1 };
+
+typedef struct {
+    double f_lo_hz, f_hi_hz;   /* candidate band                                          */
+    int32_t n_cand;            /* candidates linspace(f_lo, f_hi, n_cand), <= 4096         */
+    int32_t blocks;            /* Krylov blocks per expansion point                        */
+    double tol;                /* stop when max relative residual <= tol                   */
+    int32_t max_shifts;
+    int32_t policy;            /* CR_POLICY_GREEDY or CR_POLICY_MLP                        */
+    cr_mlp mlp;                /* network for CR_POLICY_MLP                                */
+    const double* geom;        /* geometry features for the network (mlp input tail)       */
+} cr_greedy_opts;
+
+typedef struct {
+    int32_t n_iter;            /* expansion points used                                    */
+    int32_t* shift_idx;        /* [max_shifts] candidate index per iteration (caller-owned) */
+    double* max_res;           /* [max_shifts] max residual after each iteration           */
+    double* res;               /* [n_cand] candidate residuals after the last iteration    */
+    int32_t* mlp_used;         /* [max_shifts] 1 where the network's proposal was accepted  */
+} cr_greedy_trace;
+
+/* Greedy adaptive expansion points (Section 3.3, after Eq. (9)): start at the candidate nearest
+   the band centre; after each point, build the Galerkin model and evaluate the relative
+   residual r(w_c) = ||S f(w_c) - S A(w_c) V x_R(w_c)||_F / ||S f(w_c)||_F at every candidate
+   (FP64); stop when max r <= tol, else take the unused candidate of largest r (ties: lower
+   index) or, with CR_POLICY_MLP, the network's proposal unless its residual is below 0.1 max r. */
+cr_status cr_basis_build_greedy(cr_sys sys, const cr_greedy_opts* opts, cr_precision prec,
+                                cr_basis* out, cr_greedy_trace* trace, cr_basis_info* info);
+cr_status cr_basis_dims(cr_basis b, int32_t* q);
+/* Copy the basis (n x q, complex128, scaled coordinates) to a device array with leading dim n. */
+cr_status cr_basis_copy(cr_basis b, cr_z* V_dev);
+void cr_basis_destroy(cr_basis b);
+
+/* Galerkin reduced model (Eq. (11)): K_R = V^H K V, M_R = V^H M V, F_R = V^H F (the printed
+   V^T f read as V^H f), C_R = C^T V (rows of the unscaled basis at the receivers). FP64. */
+cr_status cr_project(cr_sys sys, cr_basis b, cr_rom* out);
+
+/* A reduced model from host FP64 column-major arrays: K_R, M_R (q x q), D_R (q x q or NULL for
+   D_R = 0; Rayleigh damping alpha M_R + beta K_R can be passed here), F_R (q x L),
+   C_R (n_o x q), flags[L]. */
+cr_status cr_rom_import(cr_ctx ctx, int32_t q, int32_t L, int32_t n_o, const cr_z* KR,
+                        const cr_z* DR, const cr_z* MR, const cr_z* FR, const cr_z* CR,
+                        const int32_t* flags, cr_rom* out);
+cr_status cr_rom_dims(cr_rom r, int32_t* q, int32_t* L, int32_t* n_o);
+/* Copy the reduced matrices to host arrays (any may be NULL). */
+cr_status cr_rom_export(cr_rom r, cr_z* KR, cr_z* MR, cr_z* FR, cr_z* CR);
+void cr_rom_destroy(cr_rom r);
+
+/* ---------------------------------------------------------------- sweep (online phase) --- */
+
+typedef struct {
+    int32_t max_ir_iterations; /* over all (w): FP64 refinement corrections of the reduced LU */
+    int32_t not_converged;     /* frequencies whose refinement missed 1e-14                  */
+    int32_t fp64_fallbacks;    /* CR_MIXED frequencies redone with a complex-FP64 LU because
+                                  refinement of the complex-FP32 LU stalled                  */
+    double seconds;
+} cr_sweep_info;
+
+/* Reduced sweep: for each w, A_R = K_R + i w D_R - w^2 M_R formed in FP64, dense LU with
+   partial pivoting (complex FP32 under CR_MIXED, complex FP64 under CR_FP64), solve for the L
+   load columns F_R (i w)^flags, FP64 refinement under CR_MIXED, then Y = C_R X_R.
+   Y_dev: nfreq x L x n_o complex128, receiver index fastest ([w][l][o]). */
+cr_status cr_sweep(cr_rom r, int32_t nfreq, const double* omegas, cr_precision prec, cr_z* Y_dev,
+                   cr_sweep_info* info);
+
+/* Launch tuning of the batched sweep: variant (0 = automatic choice), resident workgroups per
+   compute unit (0 = automatic), panel width (0 = automatic). */
+typedef struct { int32_t variant, grid_per_cu, nb; } cr_tune;
+
+/* Batched sweep of nrom reduced models of uneven order in one persistent launch. omegas:
+   nrom x nfreq (row-major, host); Y_dev: host array of nrom device pointers, each
+   nfreq x L_m x n_o_m. Work items (model, w) are taken longest-first (q^3 descending). tune may
+   be NULL (autotuned per order bucket, cached for the process). */
+cr_status cr_sweep_batched(cr_ctx ctx, int32_t nrom, const cr_rom* roms, int32_t nfreq,
+                           const double* omegas, cr_precision prec, cr_z* const* Y_dev,
+                           const cr_tune* tune, cr_sweep_info* info);
+
+/* ---------------------------------------------------------------- learned shift proposer -- */
+
+/* MLP  n_in -> 3 x hidden (ReLU) -> n_out logits, BF16 weights with FP32 master copies and FP32
+   accumulation, trained with softmax cross-entropy and Adam by the library's own kernels. */
+cr_status cr_mlp_create(cr_ctx ctx, int32_t n_in, int32_t hidden, int32_t n_out, uint64_t seed,
+                        cr_mlp* out);
+void cr_mlp_destroy(cr_mlp m);
+/* Forward pass: X_dev batch x n_in (row-major, float32) -> logits_dev batch x n_out (float32). */
+cr_status cr_mlp_forward(cr_mlp m, int32_t batch, const float* X_dev, float* logits_dev);
+/* One Adam step on a minibatch with integer labels and per-sample masks (mask_dev batch x n_out,
+   1 = allowed class, or NULL). loss_out (host) receives the mean cross-entropy. */
+cr_status cr_mlp_train_step(cr_mlp m, int32_t batch, const float* X_dev, const int32_t* labels_dev,
+                            const float* mask_dev, float lr, float* loss_out);
+/* Gradients of the mean loss w.r.t. the FP32 master parameters, without an update (for checks).
+   grad_dev: n_params floats in the order of cr_mlp_get_params. */
+cr_status cr_mlp_gradients(cr_mlp m, int32_t batch, const float* X_dev, const int32_t* labels_dev,
+                           const float* mask_dev, float* grad_dev, float* loss_out);
+/* Parameter count and host copies of the FP32 master parameters
+   (W1, b1, W2, b2, W3, b3, W4, b4; W_l row-major out x in). */
+cr_status cr_mlp_num_params(cr_mlp m, int64_t* n);
+cr_status cr_mlp_get_params(cr_mlp m, float* params);
+cr_status cr_mlp_set_params(cr_mlp m, const float* params);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CABINROM_H */

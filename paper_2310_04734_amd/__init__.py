@@ -1,0 +1,404 @@
+"""Python binding of libcabinrom (rational-Arnoldi MOR of coupled u-p FE systems on MI355X).
+
+Argument marshalling only: every step of the computation runs in the library's HIP kernels.
+PyTorch provides device memory (output tensors) and the HIP stream the library enqueues on.
+Importing this module fails loudly when the library has not been built; there is no CPU path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcabinrom.so")
+
+CR_FP64 = 0
+CR_MIXED = 1
+CR_POLICY_GREEDY = 0
+CR_POLICY_MLP = 1
+
+_STATUS = {0: "CR_OK", -1: "CR_E_INVALID", -2: "CR_E_OOM", -3: "CR_E_HIP", -4: "CR_E_SINGULAR",
+           -5: "CR_E_NOT_CONVERGED", -6: "CR_E_UNSUPPORTED", -7: "CR_E_STATE"}
+
+
+class CabinRomError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.name = _STATUS.get(status, str(status))
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2310_04734_amd.build.build() "
+                          "(there is no CPU fallback)")
+    return C.CDLL(LIB_PATH)
+
+
+lib = _load()
+
+c_z_p = C.c_void_p
+
+
+class cr_material(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("rho", C.c_double), ("eta", C.c_double), ("c", C.c_double),
+                ("E", C.c_double), ("nu", C.c_double)]
+
+
+class cr_mesh(C.Structure):
+    _fields_ = [("n_nodes", C.c_int64), ("coords", C.c_void_p), ("n_el", C.c_int64), ("elems", C.c_void_p),
+                ("elem_mat", C.c_void_p), ("n_clamped", C.c_int64), ("clamped", C.c_void_p),
+                ("n_iface", C.c_int64), ("iface", C.c_void_p)]
+
+
+class cr_z(C.Structure):
+    _fields_ = [("re", C.c_double), ("im", C.c_double)]
+
+
+class cr_load(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("dir", C.c_int32), ("node", C.c_int64), ("value", cr_z),
+                ("n_faces", C.c_int64), ("faces", C.c_void_p), ("amp", C.c_void_p)]
+
+
+class cr_sys_dims(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("n_u", C.c_int64), ("L", C.c_int32), ("n_o", C.c_int32)]
+
+
+class cr_analysis_info(C.Structure):
+    _fields_ = [("n_fronts", C.c_int32), ("n_levels", C.c_int32), ("max_front", C.c_int32),
+                ("max_pivots", C.c_int32), ("factor_entries", C.c_int64), ("factor_flops", C.c_double),
+                ("seconds", C.c_double)]
+
+
+class cr_factor_info(C.Structure):
+    _fields_ = [("n_perturbed", C.c_int32), ("seconds", C.c_double)]
+
+
+class cr_ir_opts(C.Structure):
+    _fields_ = [("max_iter", C.c_int32), ("tol", C.c_double)]
+
+
+class cr_solve_info(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("backward_error", C.c_double)]
+
+
+class cr_basis_info(C.Structure):
+    _fields_ = [("q", C.c_int32), ("deflated", C.c_int32), ("n_shifts", C.c_int32), ("ir_iterations", C.c_int32),
+                ("max_backward_error", C.c_double), ("n_perturbed", C.c_int32), ("seconds", C.c_double)]
+
+
+class cr_greedy_opts(C.Structure):
+    _fields_ = [("f_lo_hz", C.c_double), ("f_hi_hz", C.c_double), ("n_cand", C.c_int32), ("blocks", C.c_int32),
+                ("tol", C.c_double), ("max_shifts", C.c_int32), ("policy", C.c_int32), ("mlp", C.c_void_p),
+                ("geom", C.c_void_p)]
+
+
+class cr_greedy_trace(C.Structure):
+    _fields_ = [("n_iter", C.c_int32), ("shift_idx", C.c_void_p), ("max_res", C.c_void_p), ("res", C.c_void_p),
+                ("mlp_used", C.c_void_p)]
+
+
+class cr_sweep_info(C.Structure):
+    _fields_ = [("max_ir_iterations", C.c_int32), ("not_converged", C.c_int32), ("fp64_fallbacks", C.c_int32),
+                ("seconds", C.c_double)]
+
+
+class cr_tune(C.Structure):
+    _fields_ = [("variant", C.c_int32), ("grid_per_cu", C.c_int32), ("nb", C.c_int32)]
+
+
+def _sig(name, res, *args):
+    f = getattr(lib, name)
+    f.restype = res
+    f.argtypes = list(args)
+    return f
+
+
+P = C.c_void_p
+I32, I64, D = C.c_int32, C.c_int64, C.c_double
+_sig("cr_ctx_create", I32, C.c_int, P, C.POINTER(P))
+_sig("cr_ctx_destroy", None, P)
+_sig("cr_last_error", C.c_char_p, P)
+_sig("cr_create_error", C.c_char_p)
+_sig("cr_assemble", I32, P, C.POINTER(cr_mesh), P, I32, P, I32, P, I32, C.POINTER(P))
+_sig("cr_sys_get_dims", I32, P, C.POINTER(cr_sys_dims))
+_sig("cr_sys_export", I32, P, P, P, P, P, P, P, P)
+_sig("cr_sys_destroy", None, P)
+_sig("cr_analyse", I32, P, C.POINTER(cr_analysis_info))
+_sig("cr_factor", I32, P, D, I32, C.POINTER(P), C.POINTER(cr_factor_info))
+_sig("cr_fact_destroy", None, P)
+_sig("cr_solve", I32, P, I32, P, P, C.POINTER(cr_ir_opts), C.POINTER(cr_solve_info))
+_sig("cr_basis_build", I32, P, I32, P, P, I32, C.POINTER(P), C.POINTER(cr_basis_info))
+_sig("cr_basis_build_greedy", I32, P, C.POINTER(cr_greedy_opts), I32, C.POINTER(P), C.POINTER(cr_greedy_trace),
+     C.POINTER(cr_basis_info))
+_sig("cr_basis_dims", I32, P, C.POINTER(I32))
+_sig("cr_basis_copy", I32, P, P)
+_sig("cr_basis_destroy", None, P)
+_sig("cr_project", I32, P, P, C.POINTER(P))
+_sig("cr_rom_import", I32, P, I32, I32, I32, P, P, P, P, P, P, C.POINTER(P))
+_sig("cr_rom_dims", I32, P, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32))
+_sig("cr_rom_export", I32, P, P, P, P, P)
+_sig("cr_rom_destroy", None, P)
+_sig("cr_sweep", I32, P, I32, P, I32, P, C.POINTER(cr_sweep_info))
+_sig("cr_sweep_batched", I32, P, I32, P, I32, P, I32, P, C.POINTER(cr_tune), C.POINTER(cr_sweep_info))
+_sig("cr_mlp_create", I32, P, I32, I32, I32, C.c_uint64, C.POINTER(P))
+_sig("cr_mlp_destroy", None, P)
+_sig("cr_mlp_forward", I32, P, I32, P, P)
+_sig("cr_mlp_train_step", I32, P, I32, P, P, P, C.c_float, C.POINTER(C.c_float))
+_sig("cr_mlp_gradients", I32, P, I32, P, P, P, P, C.POINTER(C.c_float))
+_sig("cr_mlp_num_params", I32, P, C.POINTER(I64))
+_sig("cr_mlp_get_params", I32, P, P)
+_sig("cr_mlp_set_params", I32, P, P)
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def _dev_ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """A library context bound to a HIP device and torch's current stream on it."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = P()
+        st = lib.cr_ctx_create(device, C.c_void_p(stream.cuda_stream), C.byref(h))
+        if st != 0:
+            raise CabinRomError(st, lib.cr_create_error().decode())
+        self.h = h
+
+    def check(self, st):
+        if st != 0:
+            raise CabinRomError(st, lib.cr_last_error(self.h).decode())
+
+    def close(self):
+        if self.h:
+            lib.cr_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class System:
+    def __init__(self, ctx: Context, h):
+        self.ctx, self.h = ctx, h
+        d = cr_sys_dims()
+        ctx.check(lib.cr_sys_get_dims(h, C.byref(d)))
+        self.n, self.nnz, self.n_u, self.L, self.n_o = d.n, d.nnz, d.n_u, d.L, d.n_o
+        self.analysis = None
+
+    def export(self):
+        """Unscaled host copies: rowptr, col, K, M (CSR values), F (n x L), flags, recv DoFs."""
+        n, nnz = self.n, self.nnz
+        rowptr = np.empty(n + 1, np.int64)
+        col = np.empty(nnz, np.int32)
+        K = np.empty(nnz, np.complex128)
+        M = np.empty(nnz, np.complex128)
+        F = np.empty((self.L, n), np.complex128)
+        flags = np.empty(max(self.L, 1), np.int32)
+        recv = np.empty(max(self.n_o, 1), np.int64)
+        self.ctx.check(lib.cr_sys_export(self.h, _ptr(rowptr), _ptr(col), _ptr(K), _ptr(M), _ptr(F), _ptr(flags),
+                                         _ptr(recv)))
+        return dict(rowptr=rowptr, col=col, K=K, M=M, F=F.T.copy(), flags=flags[:self.L], recv=recv[:self.n_o])
+
+    def analyse(self):
+        info = cr_analysis_info()
+        self.ctx.check(lib.cr_analyse(self.h, C.byref(info)))
+        self.analysis = {k: getattr(info, k) for k, _ in cr_analysis_info._fields_}
+        return self.analysis
+
+    def factor(self, omega: float, prec: int = CR_MIXED):
+        h = P()
+        info = cr_factor_info()
+        self.ctx.check(lib.cr_factor(self.h, float(omega), prec, C.byref(h), C.byref(info)))
+        return Factor(self, h, info.n_perturbed)
+
+    def basis(self, omegas, blocks, prec: int = CR_MIXED):
+        om = np.ascontiguousarray(omegas, np.float64)
+        bl = np.ascontiguousarray(np.broadcast_to(blocks, om.shape), np.int32)
+        h = P()
+        info = cr_basis_info()
+        self.ctx.check(lib.cr_basis_build(self.h, len(om), _ptr(om), _ptr(bl), prec, C.byref(h), C.byref(info)))
+        return Basis(self, h, info)
+
+    def basis_greedy(self, band_hz, n_cand, blocks, tol, max_shifts, prec: int = CR_MIXED, policy=CR_POLICY_GREEDY,
+                     mlp=None, geom=None):
+        g = np.ascontiguousarray(geom if geom is not None else np.zeros(0), np.float64)
+        opts = cr_greedy_opts(float(band_hz[0]), float(band_hz[1]), int(n_cand), int(blocks), float(tol),
+                              int(max_shifts), int(policy), mlp.h if mlp is not None else None, _ptr(g))
+        sidx = np.full(max_shifts, -1, np.int32)
+        mres = np.zeros(max_shifts)
+        res = np.zeros(n_cand)
+        used = np.zeros(max_shifts, np.int32)
+        tr = cr_greedy_trace(0, _ptr(sidx), _ptr(mres), _ptr(res), _ptr(used))
+        h = P()
+        info = cr_basis_info()
+        self.ctx.check(lib.cr_basis_build_greedy(self.h, C.byref(opts), prec, C.byref(h), C.byref(tr), C.byref(info)))
+        k = tr.n_iter
+        b = Basis(self, h, info)
+        b.trace = dict(shift_idx=sidx[:k].copy(), max_res=mres[:k].copy(), res=res, mlp_used=used[:k].copy())
+        return b
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib.cr_sys_destroy(self.h)
+            self.h = None
+
+
+def assemble(ctx: Context, mesh, loads, receivers) -> System:
+    """Assemble K, M, F and the receiver map from a hex8 mesh (duck-typed: coords, elems,
+    elem_mat, materials, clamped, iface) and load descriptors (kind, node, dir, value,
+    faces, amp)."""
+    coords = np.ascontiguousarray(mesh.coords, np.float64)
+    elems = np.ascontiguousarray(mesh.elems, np.int64)
+    emat = np.ascontiguousarray(mesh.elem_mat, np.int32)
+    clamped = np.ascontiguousarray(mesh.clamped, np.int64)
+    iface = np.ascontiguousarray(mesh.iface, np.int64).reshape(-1, 4)
+    m = cr_mesh(coords.shape[0], _ptr(coords), elems.shape[0], _ptr(elems), _ptr(emat), len(clamped),
+                _ptr(clamped), iface.shape[0], _ptr(iface))
+    mats = (cr_material * len(mesh.materials))()
+    for i, mt in enumerate(mesh.materials):
+        mats[i] = cr_material(mt.kind, mt.rho, mt.eta, mt.c, mt.E, mt.nu)
+    keep = []
+    lds = (cr_load * max(len(loads), 1))()
+    for i, ld in enumerate(loads):
+        v = complex(ld.value)
+        faces = amp = None
+        nf = 0
+        if ld.faces is not None:
+            faces = np.ascontiguousarray(ld.faces, np.int64).reshape(-1, 4)
+            amp = np.ascontiguousarray(ld.amp, np.complex128)
+            nf = faces.shape[0]
+            keep += [faces, amp]
+        lds[i] = cr_load(ld.kind, ld.dir, ld.node, cr_z(v.real, v.imag), nf, _ptr(faces), _ptr(amp))
+    rec = np.ascontiguousarray(receivers, np.int64)
+    h = P()
+    ctx.check(lib.cr_assemble(ctx.h, C.byref(m), mats, len(mesh.materials), lds, len(loads), _ptr(rec), len(rec),
+                              C.byref(h)))
+    return System(ctx, h)
+
+
+class Factor:
+    def __init__(self, sys: System, h, n_perturbed):
+        self.sys, self.h, self.n_perturbed = sys, h, n_perturbed
+
+    def solve(self, B, max_iter=10, tol=1e-14):
+        """X = A^{-1} B for a (n x nrhs) complex128 device tensor (column-major = B.T contiguous)."""
+        torch = self.sys.ctx.torch
+        Bc = B.t().contiguous() if B.dim() == 2 else B.reshape(1, -1).contiguous()
+        X = torch.empty_like(Bc)
+        info = cr_solve_info()
+        opts = cr_ir_opts(max_iter, tol)
+        st = lib.cr_solve(self.h, Bc.shape[0], _dev_ptr(Bc), _dev_ptr(X), C.byref(opts), C.byref(info))
+        self.last_info = dict(iterations=info.iterations, backward_error=info.backward_error)
+        self.sys.ctx.check(st)
+        return X.t() if B.dim() == 2 else X.reshape(-1)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib.cr_fact_destroy(self.h)
+            self.h = None
+
+
+class Basis:
+    def __init__(self, sys: System, h, info):
+        self.sys, self.h = sys, h
+        self.info = {k: getattr(info, k) for k, _ in cr_basis_info._fields_}
+        q = I32()
+        sys.ctx.check(lib.cr_basis_dims(h, C.byref(q)))
+        self.q = q.value
+        self.trace = None
+
+    def V(self):
+        torch = self.sys.ctx.torch
+        V = torch.empty((self.q, self.sys.n), dtype=torch.complex128, device=self.sys.ctx.device)
+        self.sys.ctx.check(lib.cr_basis_copy(self.h, _dev_ptr(V)))
+        return V.t()
+
+    def project(self):
+        h = P()
+        self.sys.ctx.check(lib.cr_project(self.sys.h, self.h, C.byref(h)))
+        return Rom(self.sys.ctx, h)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib.cr_basis_destroy(self.h)
+            self.h = None
+
+
+class Rom:
+    def __init__(self, ctx: Context, h):
+        self.ctx, self.h = ctx, h
+        q, L, no = I32(), I32(), I32()
+        ctx.check(lib.cr_rom_dims(h, C.byref(q), C.byref(L), C.byref(no)))
+        self.q, self.L, self.n_o = q.value, L.value, no.value
+
+    @staticmethod
+    def from_arrays(ctx: Context, KR, MR, FR, CR, flags, DR=None):
+        f = lambda a: np.asfortranarray(a, np.complex128)
+        KR, MR, FR, CR = f(KR), f(MR), f(FR), f(CR)
+        DR = f(DR) if DR is not None else None
+        fl = np.ascontiguousarray(flags, np.int32)
+        q, L = FR.shape
+        h = P()
+        ctx.check(lib.cr_rom_import(ctx.h, q, L, CR.shape[0], KR.ctypes.data_as(P), _ptr(DR) if DR is not None else None,
+                                    MR.ctypes.data_as(P), FR.ctypes.data_as(P), CR.ctypes.data_as(P), _ptr(fl),
+                                    C.byref(h)))
+        return Rom(ctx, h)
+
+    def export(self):
+        q, L, no = self.q, self.L, self.n_o
+        KR = np.empty((q, q), np.complex128, order="F")
+        MR = np.empty((q, q), np.complex128, order="F")
+        FR = np.empty((q, L), np.complex128, order="F")
+        CR = np.empty((max(no, 1), q), np.complex128, order="F")
+        self.ctx.check(lib.cr_rom_export(self.h, KR.ctypes.data_as(P), MR.ctypes.data_as(P), FR.ctypes.data_as(P),
+                                         CR.ctypes.data_as(P)))
+        return dict(KR=KR, MR=MR, FR=FR, CR=CR[:no])
+
+    def sweep(self, omegas, prec=CR_MIXED, out=None):
+        """Y[w, l, o] complex128 device tensor."""
+        torch = self.ctx.torch
+        om = np.ascontiguousarray(omegas, np.float64)
+        Y = out if out is not None else torch.empty((len(om), self.L, self.n_o), dtype=torch.complex128,
+                                                    device=self.ctx.device)
+        info = cr_sweep_info()
+        self.ctx.check(lib.cr_sweep(self.h, len(om), _ptr(om), prec, _dev_ptr(Y), C.byref(info)))
+        self.last_info = dict(max_ir_iterations=info.max_ir_iterations, not_converged=info.not_converged,
+                              fp64_fallbacks=info.fp64_fallbacks, seconds=info.seconds)
+        return Y
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib.cr_rom_destroy(self.h)
+            self.h = None
+
+
+def sweep_batched(ctx: Context, roms, omegas, prec=CR_MIXED, outs=None, grid_per_cu=0):
+    """omegas: (nrom, nfreq) host array; returns a list of Y tensors (nfreq x L x n_o)."""
+    torch = ctx.torch
+    om = np.ascontiguousarray(omegas, np.float64)
+    nrom, nfreq = om.shape
+    if outs is None:
+        outs = [torch.empty((nfreq, r.L, r.n_o), dtype=torch.complex128, device=ctx.device) for r in roms]
+    hs = (P * nrom)(*[r.h for r in roms])
+    ys = (P * nrom)(*[Y.data_ptr() for Y in outs])
+    tune = cr_tune(0, int(grid_per_cu), 0)
+    info = cr_sweep_info()
+    ctx.check(lib.cr_sweep_batched(ctx.h, nrom, hs, nfreq, _ptr(om), prec, ys, C.byref(tune), C.byref(info)))
+    return outs, dict(max_ir_iterations=info.max_ir_iterations, not_converged=info.not_converged,
+                      fp64_fallbacks=info.fp64_fallbacks, seconds=info.seconds)

@@ -1,0 +1,694 @@
+// C ABI of the library: contexts, systems, analysis, factorisation and solves, the rational
+// Krylov basis (fixed and greedy expansion points), the Galerkin projection, and reduced
+// models. Kernels live in factor.hip, linalg.hip and sweep.hip.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "internal.h"
+#include "sweep.h"
+#include "util.cuh"
+
+namespace cr {
+void gram(int64_t n, int qa, int b, const zd* A, int64_t lda, const zd* B, int64_t ldb, zd* H, int64_t ldh, int conj_t,
+          DevBuf<zd>& partial, hipStream_t s);
+void update(int64_t n, int q, int b, const zd* V, int64_t ldv, const zd* H, int64_t ldh, zd* W, int64_t ldw, hipStream_t s);
+void gather_recv(cr_sys sys, int q, const zd* V, int64_t ldv, zd* CR, hipStream_t s);
+void copy_dev(int64_t n, const zd* src, zd* dst, hipStream_t s);
+void candidate_residuals(int64_t n, int q, int L, int ncand, const zd* KV, const zd* MV, int64_t ldv, const zd* F,
+                         const zd* X, const zd* scal, const double* w2, double* res2, DevBuf<double>& partial,
+                         hipStream_t s);
+void copy_cols_scaled(int64_t n, const zd* src, zd* dst, double factor, hipStream_t s);
+void copy_2d(int rows, int cols, const zd* src, int64_t lds, zd* dst, int64_t ldd, hipStream_t s);
+void scale_rows(int64_t n, int nrhs, const zd* src, const double* sc, zd* dst, hipStream_t s);
+}  // namespace cr
+
+using namespace cr;
+
+struct cr_fact_s {
+    Factor f;
+    SolveWork w;
+};
+
+struct cr_rom_s {
+    cr_ctx ctx = nullptr;
+    int q = 0, L = 0, n_o = 0;
+    bool has_d = false;
+    DevBuf<zd> KR, MR, DR, FR, CR;
+    DevBuf<int32_t> flags;
+};
+
+struct cr_basis_s {
+    cr_sys sys = nullptr;
+    int q = 0, cap = 0;
+    DevBuf<zd> V, KV, MV;        // n x cap
+    DevBuf<zd> KR, MR;           // cap x cap (incremental Galerkin projection)
+    std::vector<double> shifts;
+    int deflated = 0;
+    int ir_iterations = 0;
+    double max_berr = 0;
+    int n_perturbed = 0;
+    // scratch
+    DevBuf<zd> W, H, partial, RHS;
+    std::vector<zd> hH;
+};
+
+namespace {
+
+std::string g_create_error;
+
+SweepEngine& engine(cr_ctx ctx) {
+    if (!ctx->sweep) {
+        ctx->sweep = new SweepEngine();
+        ctx->sweep->num_cu = ctx->num_cu;
+    }
+    return *ctx->sweep;
+}
+
+double now() { return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count(); }
+
+// ---------------------------------------------------------------- basis growth
+void ensure_capacity(cr_basis B, int need) {
+    if (need <= B->cap) return;
+    cr_sys sys = B->sys;
+    hipStream_t s = sys->ctx->stream;
+    const int64_t n = sys->n;
+    int cap = std::max(need, std::max(16, 2 * B->cap));
+    DevBuf<zd> V((size_t)n * cap), KV((size_t)n * cap), MV((size_t)n * cap), KR((size_t)cap * cap), MR((size_t)cap * cap);
+    if (B->q > 0) {
+        copy_dev(n * B->q, B->V.p, V.p, s);
+        copy_dev(n * B->q, B->KV.p, KV.p, s);
+        copy_dev(n * B->q, B->MV.p, MV.p, s);
+        copy_2d(B->q, B->q, B->KR.p, B->cap, KR.p, cap, s);
+        copy_2d(B->q, B->q, B->MR.p, B->cap, MR.p, cap, s);
+    }
+    CR_HIP(hipStreamSynchronize(s));
+    B->V = std::move(V);
+    B->KV = std::move(KV);
+    B->MV = std::move(MV);
+    B->KR = std::move(KR);
+    B->MR = std::move(MR);
+    B->cap = cap;
+}
+
+// squared column norms of W (n x b) via the Gram diagonal
+std::vector<double> col_norms2(cr_basis B, const zd* W, int b) {
+    cr_sys sys = B->sys;
+    hipStream_t s = sys->ctx->stream;
+    B->H.reserve((size_t)b * b);
+    gram(sys->n, b, b, W, sys->n, W, sys->n, B->H.p, b, 0, B->partial, s);
+    B->hH.resize((size_t)b * b);
+    CR_HIP(hipMemcpyAsync(B->hH.data(), B->H.p, (size_t)b * b * sizeof(zd), hipMemcpyDeviceToHost, s));
+    CR_HIP(hipStreamSynchronize(s));
+    std::vector<double> out(b);
+    for (int c = 0; c < b; ++c) out[c] = B->hH[(size_t)c * b + c].re;
+    return out;
+}
+
+// incremental Galerkin projection of the new columns [q0, q1)
+void project_new(cr_basis B, int q0, int q1) {
+    cr_sys sys = B->sys;
+    hipStream_t s = sys->ctx->stream;
+    const int64_t n = sys->n;
+    const int nb = q1 - q0;
+    if (nb <= 0) return;
+    spmm_km(sys, nb, B->V.p + n * q0, n, B->KV.p + n * q0, B->MV.p + n * q0, n, s);
+    const int64_t ld = B->cap;
+    // columns: R[0:q1, q0:q1] = V[:, 0:q1]^H (KV)[:, q0:q1]
+    gram(n, q1, nb, B->V.p, n, B->KV.p + n * q0, n, B->KR.p + ld * q0, ld, 0, B->partial, s);
+    gram(n, q1, nb, B->V.p, n, B->MV.p + n * q0, n, B->MR.p + ld * q0, ld, 0, B->partial, s);
+    // rows: R[q0:q1, 0:q0] = conj((KV)[:, 0:q0]^H V[:, q0:q1])^T
+    if (q0 > 0) {
+        gram(n, q0, nb, B->KV.p, n, B->V.p + n * q0, n, B->KR.p + q0, ld, 1, B->partial, s);
+        gram(n, q0, nb, B->MV.p, n, B->V.p + n * q0, n, B->MR.p + q0, ld, 1, B->partial, s);
+    }
+}
+
+// Orthonormalise the b columns of W against V and each other (block CGS2 in FP64, then two
+// passes per column inside the block) and append the accepted ones. Returns accepted count.
+int orthonormalise_append(cr_basis B, zd* W, int b) {
+    cr_sys sys = B->sys;
+    hipStream_t s = sys->ctx->stream;
+    const int64_t n = sys->n;
+    std::vector<double> before = col_norms2(B, W, b);
+    const int q0 = B->q;
+    if (q0 > 0) {
+        B->H.reserve((size_t)q0 * b);
+        for (int pass = 0; pass < 2; ++pass) {
+            gram(n, q0, b, B->V.p, n, W, n, B->H.p, q0, 0, B->partial, s);
+            update(n, q0, b, B->V.p, n, B->H.p, q0, W, n, s);
+        }
+    }
+    ensure_capacity(B, q0 + b);
+    int q = q0;
+    for (int c = 0; c < b; ++c) {
+        zd* w = W + n * c;
+        const int na = q - q0;   // columns accepted from this block so far
+        if (na > 0) {
+            B->H.reserve((size_t)na);
+            for (int pass = 0; pass < 2; ++pass) {
+                gram(n, na, 1, B->V.p + n * q0, n, w, n, B->H.p, na, 0, B->partial, s);
+                update(n, na, 1, B->V.p + n * q0, n, B->H.p, na, w, n, s);
+            }
+        }
+        const double after2 = col_norms2(B, w, 1)[0];
+        const double ratio = std::sqrt(after2 / std::max(before[c], 1e-300));
+        if (!(before[c] > 0) || !(ratio >= 1e-10)) {
+            B->deflated++;
+            continue;
+        }
+        copy_cols_scaled(n, w, B->V.p + n * q, 1.0 / std::sqrt(after2), s);
+        ++q;
+    }
+    B->q = q;
+    project_new(B, q0, q);
+    return q - q0;
+}
+
+// Krylov blocks at one expansion point: X = A^{-1} F~, then X = A^{-1} M~ Q (Eq. (10))
+void add_shift(cr_basis B, Factor& fac, SolveWork& sw, double omega, int blocks, cr_precision prec) {
+    cr_sys sys = B->sys;
+    hipStream_t s = sys->ctx->stream;
+    const int64_t n = sys->n;
+    numeric_factor(fac, sys, omega, prec, s);
+    B->n_perturbed += fac.n_perturbed;
+    B->shifts.push_back(omega);
+    const int L = sys->L;
+    B->RHS.reserve((size_t)n * std::max(L, 1));
+    B->W.reserve((size_t)n * std::max(L, 1));
+    int b = L;
+    copy_dev(n * L, sys->d_F.p, B->RHS.p, s);
+    for (int blk = 0; blk < blocks && b > 0; ++blk) {
+        if (blk > 0) spmm_m(sys, b, B->V.p + n * (B->q - b), n, B->RHS.p, n, s);
+        double berr = 0;
+        const int its = solve_scaled(fac, b, B->RHS.p, B->W.p, 10, 1e-14, &berr, sw, s, false);
+        B->ir_iterations += its;
+        B->max_berr = std::max(B->max_berr, berr);
+        b = orthonormalise_append(B, B->W.p, b);
+    }
+}
+
+void fill_info(cr_basis B, cr_basis_info* info, double t0) {
+    if (!info) return;
+    info->q = B->q;
+    info->deflated = B->deflated;
+    info->n_shifts = (int)B->shifts.size();
+    info->ir_iterations = B->ir_iterations;
+    info->max_backward_error = B->max_berr;
+    info->n_perturbed = B->n_perturbed;
+    info->seconds = now() - t0;
+}
+
+// reduced model from the basis' incremental projection (packed to ld = q)
+std::unique_ptr<cr_rom_s> rom_from_basis(cr_basis B) {
+    cr_sys sys = B->sys;
+    hipStream_t s = sys->ctx->stream;
+    const int64_t n = sys->n;
+    const int q = B->q, L = sys->L;
+    auto r = std::make_unique<cr_rom_s>();
+    r->ctx = sys->ctx;
+    r->q = q;
+    r->L = L;
+    r->n_o = sys->n_o;
+    r->KR.alloc((size_t)q * q);
+    r->MR.alloc((size_t)q * q);
+    r->FR.alloc((size_t)q * std::max(L, 1));
+    r->CR.alloc((size_t)std::max(sys->n_o, 1) * q);
+    r->flags.alloc(std::max(L, 1));
+    copy_2d(q, q, B->KR.p, B->cap, r->KR.p, q, s);
+    copy_2d(q, q, B->MR.p, B->cap, r->MR.p, q, s);
+    gram(n, q, L, B->V.p, n, sys->d_F.p, n, r->FR.p, q, 0, B->partial, s);
+    gather_recv(sys, q, B->V.p, n, r->CR.p, s);
+    if (L > 0) CR_HIP(hipMemcpyAsync(r->flags.p, sys->d_flags.p, L * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    CR_HIP(hipStreamSynchronize(s));
+    return r;
+}
+
+RomDesc desc_of(const cr_rom_s* r, const double* omegas_dev, zd* out, int out_x) {
+    RomDesc d;
+    d.KR = r->KR.p;
+    d.MR = r->MR.p;
+    d.DR = r->has_d ? r->DR.p : nullptr;
+    d.FR = r->FR.p;
+    d.CR = r->CR.p;
+    d.flags = r->flags.p;
+    d.omegas = omegas_dev;
+    d.out = out;
+    d.q = r->q;
+    d.L = r->L;
+    d.n_o = r->n_o;
+    d.out_x = out_x;
+    return d;
+}
+
+}  // namespace
+
+namespace cr {
+void finalize_sys(cr_sys sys) {
+    const int64_t n = sys->n, nnz = sys->rowptr[n];
+    hipStream_t s = sys->ctx->stream;
+    sys->scale.assign(n, 1.0);
+    for (int64_t r = 0; r < n; ++r) {
+        double d = 0;
+        for (int64_t k = sys->rowptr[r]; k < sys->rowptr[r + 1]; ++k)
+            if (sys->col[k] == r) d = std::hypot(sys->K[k].re, sys->K[k].im);
+        CR_REQUIRE(d > 0, CR_E_INVALID, "zero diagonal of K at DoF " + std::to_string(r));
+        sys->scale[r] = 1.0 / std::sqrt(d);
+    }
+    std::vector<zd> Ks(nnz), Ms(nnz), Fs(sys->F.size());
+    for (int64_t r = 0; r < n; ++r)
+        for (int64_t k = sys->rowptr[r]; k < sys->rowptr[r + 1]; ++k) {
+            const double f = sys->scale[r] * sys->scale[sys->col[k]];
+            Ks[k] = {sys->K[k].re * f, sys->K[k].im * f};
+            Ms[k] = {sys->M[k].re * f, sys->M[k].im * f};
+        }
+    for (int l = 0; l < sys->L; ++l)
+        for (int64_t r = 0; r < n; ++r) {
+            const zd v = sys->F[(size_t)l * n + r];
+            Fs[(size_t)l * n + r] = {v.re * sys->scale[r], v.im * sys->scale[r]};
+        }
+    upload(sys->d_rowptr, sys->rowptr, s);
+    upload(sys->d_col, sys->col, s);
+    upload(sys->d_K, Ks, s);
+    upload(sys->d_M, Ms, s);
+    upload(sys->d_F, Fs, s);
+    upload(sys->d_scale, sys->scale, s);
+    upload(sys->d_recv, sys->recv, s);
+    upload(sys->d_flags, sys->flags, s);
+    CR_HIP(hipStreamSynchronize(s));
+}
+}  // namespace cr
+
+// =============================================================== C ABI
+extern "C" {
+
+cr_status cr_ctx_create(int device, void* hip_stream, cr_ctx* out) {
+    if (!out) return CR_E_INVALID;
+    try {
+        int count = 0;
+        hipError_t e = hipGetDeviceCount(&count);
+        if (e != hipSuccess || count == 0) {
+            g_create_error = "no HIP device available";
+            return CR_E_HIP;
+        }
+        if (device < 0 || device >= count) {
+            g_create_error = "device index out of range";
+            return CR_E_INVALID;
+        }
+        CR_HIP(hipSetDevice(device));
+        auto c = std::make_unique<cr_ctx_s>();
+        c->device = device;
+        c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+        hipDeviceProp_t prop;
+        CR_HIP(hipGetDeviceProperties(&prop, device));
+        c->num_cu = prop.multiProcessorCount;
+        *out = c.release();
+        return CR_OK;
+    } catch (const cr::Error& e) {
+        g_create_error = e.what();
+        return e.code;
+    }
+}
+
+void cr_ctx_destroy(cr_ctx ctx) {
+    if (!ctx) return;
+    delete ctx->sweep;
+    delete ctx;
+}
+
+const char* cr_last_error(cr_ctx ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+const char* cr_create_error(void) { return g_create_error.c_str(); }
+
+cr_status cr_sys_get_dims(cr_sys sys, cr_sys_dims* out) {
+    if (!sys || !out) return CR_E_INVALID;
+    out->n = sys->n;
+    out->nnz = sys->rowptr[sys->n];
+    out->n_u = sys->n_u;
+    out->L = sys->L;
+    out->n_o = sys->n_o;
+    return CR_OK;
+}
+
+cr_status cr_sys_export(cr_sys sys, int64_t* rowptr, int32_t* col, cr_z* K, cr_z* M, cr_z* F, int32_t* flags,
+                        int64_t* recv_dofs) {
+    if (!sys) return CR_E_INVALID;
+    const int64_t n = sys->n, nnz = sys->rowptr[n];
+    if (rowptr) std::memcpy(rowptr, sys->rowptr.data(), (n + 1) * sizeof(int64_t));
+    if (col) std::memcpy(col, sys->col.data(), nnz * sizeof(int32_t));
+    if (K) std::memcpy(K, sys->K.data(), nnz * sizeof(cr_z));
+    if (M) std::memcpy(M, sys->M.data(), nnz * sizeof(cr_z));
+    if (F && !sys->F.empty()) std::memcpy(F, sys->F.data(), sys->F.size() * sizeof(cr_z));
+    if (flags && sys->L) std::memcpy(flags, sys->flags.data(), sys->L * sizeof(int32_t));
+    if (recv_dofs && sys->n_o) std::memcpy(recv_dofs, sys->recv.data(), sys->n_o * sizeof(int64_t));
+    return CR_OK;
+}
+
+void cr_sys_destroy(cr_sys sys) { delete sys; }
+
+cr_status cr_analyse(cr_sys sys, cr_analysis_info* info) {
+    if (!sys) return CR_E_INVALID;
+    return cr_guard(sys->ctx, [&] {
+        if (!sys->sym) {
+            sys->sym = analyse_pattern(sys->n, sys->rowptr, sys->col, sys->coords);
+            upload_symbolic(sys);
+        }
+        if (info) {
+            const Symbolic& S = *sys->sym;
+            info->n_fronts = S.nfront;
+            info->n_levels = S.nlevel;
+            info->max_front = S.max_front;
+            info->max_pivots = S.max_piv;
+            info->factor_entries = S.factor_entries;
+            info->factor_flops = S.factor_flops;
+            info->seconds = S.seconds;
+        }
+    });
+}
+
+cr_status cr_factor(cr_sys sys, double omega, cr_precision prec, cr_fact* out, cr_factor_info* info) {
+    if (!sys) return CR_E_INVALID;
+    return cr_guard(sys->ctx, [&] {
+        CR_REQUIRE(out && std::isfinite(omega) && (prec == CR_FP64 || prec == CR_MIXED), CR_E_INVALID, "cr_factor: bad arguments");
+        CR_REQUIRE(sys->sym, CR_E_STATE, "cr_factor: call cr_analyse first");
+        const double t0 = now();
+        auto f = std::make_unique<cr_fact_s>();
+        numeric_factor(f->f, sys, omega, prec, sys->ctx->stream);
+        if (info) {
+            info->n_perturbed = f->f.n_perturbed;
+            info->seconds = now() - t0;
+        }
+        *out = f.release();
+    });
+}
+
+void cr_fact_destroy(cr_fact f) { delete f; }
+
+cr_status cr_solve(cr_fact f, int32_t nrhs, const cr_z* B_dev, cr_z* X_dev, const cr_ir_opts* opts, cr_solve_info* info) {
+    if (!f) return CR_E_INVALID;
+    cr_sys sys = f->f.sys;
+    return cr_guard(sys->ctx, [&] {
+        CR_REQUIRE(nrhs >= 0 && (nrhs == 0 || (B_dev && X_dev)), CR_E_INVALID, "cr_solve: bad arguments");
+        if (nrhs == 0) return;
+        hipStream_t s = sys->ctx->stream;
+        const int64_t n = sys->n;
+        const int max_iter = opts ? opts->max_iter : 10;
+        const double tol = opts ? opts->tol : 1e-14;
+        // A = S^{-1} A~ S^{-1}: X = S (A~^{-1} (S B))
+        DevBuf<zd> Bs((size_t)n * nrhs), Xs((size_t)n * nrhs);
+        scale_rows(n, nrhs, reinterpret_cast<const zd*>(B_dev), sys->d_scale.p, Bs.p, s);
+        double berr = 0;
+        int its = 0;
+        cr_status st = CR_OK;
+        std::string msg;
+        try {
+            its = solve_scaled(f->f, nrhs, Bs.p, Xs.p, max_iter, tol, &berr, f->w, s, true);
+        } catch (const cr::Error& e) {
+            if (e.code != CR_E_NOT_CONVERGED) throw;
+            st = e.code;
+            msg = e.what();
+        }
+        scale_rows(n, nrhs, Xs.p, sys->d_scale.p, reinterpret_cast<zd*>(X_dev), s);
+        CR_HIP(hipStreamSynchronize(s));
+        if (info) {
+            info->iterations = its;
+            info->backward_error = berr;
+        }
+        if (st != CR_OK) throw cr::Error(st, msg);
+    });
+}
+
+cr_status cr_basis_build(cr_sys sys, int32_t nshift, const double* omegas, const int32_t* blocks, cr_precision prec,
+                         cr_basis* out, cr_basis_info* info) {
+    if (!sys) return CR_E_INVALID;
+    return cr_guard(sys->ctx, [&] {
+        CR_REQUIRE(out && nshift > 0 && omegas && blocks, CR_E_INVALID, "cr_basis_build: bad arguments");
+        CR_REQUIRE(prec == CR_FP64 || prec == CR_MIXED, CR_E_INVALID, "cr_basis_build: bad precision");
+        CR_REQUIRE(sys->sym, CR_E_STATE, "cr_basis_build: call cr_analyse first");
+        CR_REQUIRE(sys->L > 0, CR_E_INVALID, "cr_basis_build: system has no loads");
+        const double t0 = now();
+        auto B = std::make_unique<cr_basis_s>();
+        B->sys = sys;
+        int total = 0;
+        for (int j = 0; j < nshift; ++j) {
+            CR_REQUIRE(blocks[j] >= 0 && std::isfinite(omegas[j]), CR_E_INVALID, "cr_basis_build: bad shift");
+            total += blocks[j] * sys->L;
+        }
+        ensure_capacity(B.get(), std::max(total, 1));
+        Factor fac;
+        SolveWork sw;
+        for (int j = 0; j < nshift; ++j) add_shift(B.get(), fac, sw, omegas[j], blocks[j], prec);
+        fill_info(B.get(), info, t0);
+        *out = B.release();
+    });
+}
+
+cr_status cr_basis_build_greedy(cr_sys sys, const cr_greedy_opts* o, cr_precision prec, cr_basis* out,
+                                cr_greedy_trace* trace, cr_basis_info* info) {
+    if (!sys) return CR_E_INVALID;
+    return cr_guard(sys->ctx, [&] {
+        CR_REQUIRE(o && out, CR_E_INVALID, "cr_basis_build_greedy: bad arguments");
+        CR_REQUIRE(o->n_cand >= 2 && o->n_cand <= 4096 && o->blocks >= 1 && o->max_shifts >= 1 && o->tol > 0 &&
+                       std::isfinite(o->f_lo_hz) && std::isfinite(o->f_hi_hz) && o->f_hi_hz > o->f_lo_hz && o->f_lo_hz >= 0,
+                   CR_E_INVALID, "cr_basis_build_greedy: bad options");
+        CR_REQUIRE(prec == CR_FP64 || prec == CR_MIXED, CR_E_INVALID, "cr_basis_build_greedy: bad precision");
+        CR_REQUIRE(o->policy == CR_POLICY_GREEDY || (o->policy == CR_POLICY_MLP && o->mlp), CR_E_INVALID,
+                   "cr_basis_build_greedy: MLP policy needs a network");
+        CR_REQUIRE(sys->sym, CR_E_STATE, "cr_basis_build_greedy: call cr_analyse first");
+        CR_REQUIRE(sys->L > 0, CR_E_INVALID, "cr_basis_build_greedy: system has no loads");
+        const double t0 = now();
+        hipStream_t s = sys->ctx->stream;
+        const int nc = o->n_cand, L = sys->L;
+        const int64_t n = sys->n;
+        // candidates as numpy.linspace computes them (start + i * step, last = stop exactly)
+        std::vector<double> cand(nc), cw(nc), w2(nc);
+        const double step = (o->f_hi_hz - o->f_lo_hz) / (nc - 1);
+        for (int i = 0; i < nc; ++i) cand[i] = i * step + o->f_lo_hz;
+        cand[nc - 1] = o->f_hi_hz;
+        for (int i = 0; i < nc; ++i) {
+            cw[i] = (2.0 * M_PI) * cand[i];
+            w2[i] = cw[i] * cw[i];
+        }
+        const double centre = 0.5 * (cand[0] + cand[nc - 1]);
+        int j = 0;
+        for (int i = 1; i < nc; ++i)
+            if (std::fabs(cand[i] - centre) < std::fabs(cand[j] - centre)) j = i;
+        auto B = std::make_unique<cr_basis_s>();
+        B->sys = sys;
+        ensure_capacity(B.get(), o->blocks * L * std::min(o->max_shifts, 64));
+        Factor fac;
+        SolveWork sw;
+        SweepEngine& E = engine(sys->ctx);
+        // load scales (i w_c)^flag and ||S f(w_c)||_F^2
+        std::vector<zd> scal((size_t)nc * L);
+        std::vector<double> fn2(nc, 0.0);
+        std::vector<double> f2 = col_norms2(B.get(), sys->d_F.p, L);
+        for (int c = 0; c < nc; ++c)
+            for (int l = 0; l < L; ++l) {
+                scal[(size_t)c * L + l] = sys->flags[l] ? zd{0.0, cw[c]} : zd{1.0, 0.0};
+                fn2[c] += (sys->flags[l] ? w2[c] : 1.0) * f2[l];
+            }
+        DevBuf<zd> d_scal(scal.size());
+        DevBuf<double> d_w2(nc), d_cw(nc), d_res2(nc), partial;
+        CR_HIP(hipMemcpyAsync(d_scal.p, scal.data(), scal.size() * sizeof(zd), hipMemcpyHostToDevice, s));
+        CR_HIP(hipMemcpyAsync(d_w2.p, w2.data(), nc * sizeof(double), hipMemcpyHostToDevice, s));
+        CR_HIP(hipMemcpyAsync(d_cw.p, cw.data(), nc * sizeof(double), hipMemcpyHostToDevice, s));
+        DevBuf<zd> Xc;
+        std::vector<int> used;
+        std::vector<double> maxres, res(nc, 0.0);
+        std::vector<int> mlp_used;
+        std::vector<int2> items(nc);
+        for (int c = 0; c < nc; ++c) items[c] = make_int2(0, c);
+        for (int it = 0; it < o->max_shifts; ++it) {
+            used.push_back(j);
+            add_shift(B.get(), fac, sw, cw[j], o->blocks, prec);
+            auto rom = rom_from_basis(B.get());
+            const int q = B->q;
+            Xc.reserve((size_t)nc * q * L);
+            std::vector<RomDesc> rd{desc_of(rom.get(), d_cw.p, Xc.p, 1)};
+            int mi, ncv, np;
+            E.run(rd, items, CR_FP64, false, s, &mi, &ncv, &np);
+            candidate_residuals(n, q, L, nc, B->KV.p, B->MV.p, n, sys->d_F.p, Xc.p, d_scal.p, d_w2.p, d_res2.p, partial, s);
+            CR_HIP(hipMemcpyAsync(res.data(), d_res2.p, nc * sizeof(double), hipMemcpyDeviceToHost, s));
+            CR_HIP(hipStreamSynchronize(s));
+            double mx = 0;
+            for (int c = 0; c < nc; ++c) {
+                res[c] = std::sqrt(res[c] / fn2[c]);
+                mx = std::max(mx, res[c]);
+            }
+            maxres.push_back(mx);
+            if (mx <= o->tol) break;
+            int best = -1;
+            for (int c = 0; c < nc; ++c) {
+                if (std::find(used.begin(), used.end(), c) != used.end()) continue;
+                if (best < 0 || res[c] > res[best]) best = c;
+            }
+            if (best < 0) break;
+            int choice = best, took_mlp = 0;
+            if (o->policy == CR_POLICY_MLP) {
+                const int prop = mlp_propose(o->mlp, res, used, o->geom);
+                if (prop >= 0 && res[prop] >= 0.1 * mx) { choice = prop; took_mlp = 1; }
+            }
+            mlp_used.push_back(took_mlp);
+            j = choice;
+        }
+        if (trace) {
+            trace->n_iter = (int)used.size();
+            for (size_t k = 0; k < used.size(); ++k) {
+                if (trace->shift_idx) trace->shift_idx[k] = used[k];
+                if (trace->max_res) trace->max_res[k] = maxres[k];
+                if (trace->mlp_used) trace->mlp_used[k] = (k >= 1 && k - 1 < mlp_used.size()) ? mlp_used[k - 1] : 0;
+            }
+            if (trace->res) std::copy(res.begin(), res.end(), trace->res);
+        }
+        fill_info(B.get(), info, t0);
+        *out = B.release();
+    });
+}
+
+cr_status cr_basis_dims(cr_basis b, int32_t* q) {
+    if (!b || !q) return CR_E_INVALID;
+    *q = b->q;
+    return CR_OK;
+}
+
+cr_status cr_basis_copy(cr_basis b, cr_z* V_dev) {
+    if (!b) return CR_E_INVALID;
+    return cr_guard(b->sys->ctx, [&] {
+        CR_REQUIRE(V_dev || b->q == 0, CR_E_INVALID, "cr_basis_copy: null output");
+        copy_dev(b->sys->n * b->q, b->V.p, reinterpret_cast<zd*>(V_dev), b->sys->ctx->stream);
+        CR_HIP(hipStreamSynchronize(b->sys->ctx->stream));
+    });
+}
+
+void cr_basis_destroy(cr_basis b) { delete b; }
+
+cr_status cr_project(cr_sys sys, cr_basis b, cr_rom* out) {
+    if (!sys || !b) return CR_E_INVALID;
+    return cr_guard(sys->ctx, [&] {
+        CR_REQUIRE(out && b->sys == sys, CR_E_INVALID, "cr_project: basis of another system");
+        CR_REQUIRE(b->q > 0, CR_E_INVALID, "cr_project: empty basis");
+        *out = rom_from_basis(b).release();
+    });
+}
+
+cr_status cr_rom_import(cr_ctx ctx, int32_t q, int32_t L, int32_t n_o, const cr_z* KR, const cr_z* DR, const cr_z* MR,
+                        const cr_z* FR, const cr_z* CR, const int32_t* flags, cr_rom* out) {
+    if (!ctx) return CR_E_INVALID;
+    return cr_guard(ctx, [&] {
+        CR_REQUIRE(out && q > 0 && q <= 4096 && L > 0 && n_o >= 0 && KR && MR && FR && flags && (n_o == 0 || CR),
+                   CR_E_INVALID, "cr_rom_import: bad arguments");
+        hipStream_t s = ctx->stream;
+        auto r = std::make_unique<cr_rom_s>();
+        r->ctx = ctx;
+        r->q = q;
+        r->L = L;
+        r->n_o = n_o;
+        r->KR.alloc((size_t)q * q);
+        r->MR.alloc((size_t)q * q);
+        r->FR.alloc((size_t)q * L);
+        r->CR.alloc((size_t)std::max(n_o, 1) * q);
+        r->flags.alloc(L);
+        CR_HIP(hipMemcpyAsync(r->KR.p, KR, (size_t)q * q * sizeof(zd), hipMemcpyHostToDevice, s));
+        CR_HIP(hipMemcpyAsync(r->MR.p, MR, (size_t)q * q * sizeof(zd), hipMemcpyHostToDevice, s));
+        CR_HIP(hipMemcpyAsync(r->FR.p, FR, (size_t)q * L * sizeof(zd), hipMemcpyHostToDevice, s));
+        if (n_o) CR_HIP(hipMemcpyAsync(r->CR.p, CR, (size_t)n_o * q * sizeof(zd), hipMemcpyHostToDevice, s));
+        CR_HIP(hipMemcpyAsync(r->flags.p, flags, L * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        if (DR) {
+            r->has_d = true;
+            r->DR.alloc((size_t)q * q);
+            CR_HIP(hipMemcpyAsync(r->DR.p, DR, (size_t)q * q * sizeof(zd), hipMemcpyHostToDevice, s));
+        }
+        CR_HIP(hipStreamSynchronize(s));
+        *out = r.release();
+    });
+}
+
+cr_status cr_rom_dims(cr_rom r, int32_t* q, int32_t* L, int32_t* n_o) {
+    if (!r) return CR_E_INVALID;
+    if (q) *q = r->q;
+    if (L) *L = r->L;
+    if (n_o) *n_o = r->n_o;
+    return CR_OK;
+}
+
+cr_status cr_rom_export(cr_rom r, cr_z* KR, cr_z* MR, cr_z* FR, cr_z* CR) {
+    if (!r) return CR_E_INVALID;
+    return cr_guard(r->ctx, [&] {
+        hipStream_t s = r->ctx->stream;
+        const size_t q = r->q;
+        if (KR) CR_HIP(hipMemcpyAsync(KR, r->KR.p, q * q * sizeof(zd), hipMemcpyDeviceToHost, s));
+        if (MR) CR_HIP(hipMemcpyAsync(MR, r->MR.p, q * q * sizeof(zd), hipMemcpyDeviceToHost, s));
+        if (FR) CR_HIP(hipMemcpyAsync(FR, r->FR.p, q * r->L * sizeof(zd), hipMemcpyDeviceToHost, s));
+        if (CR && r->n_o) CR_HIP(hipMemcpyAsync(CR, r->CR.p, q * r->n_o * sizeof(zd), hipMemcpyDeviceToHost, s));
+        CR_HIP(hipStreamSynchronize(s));
+    });
+}
+
+void cr_rom_destroy(cr_rom r) { delete r; }
+
+cr_status cr_sweep(cr_rom r, int32_t nfreq, const double* omegas, cr_precision prec, cr_z* Y_dev, cr_sweep_info* info) {
+    if (!r) return CR_E_INVALID;
+    return cr_guard(r->ctx, [&] {
+        CR_REQUIRE(nfreq >= 0 && (nfreq == 0 || (omegas && Y_dev)), CR_E_INVALID, "cr_sweep: bad arguments");
+        CR_REQUIRE(prec == CR_FP64 || prec == CR_MIXED, CR_E_INVALID, "cr_sweep: bad precision");
+        for (int i = 0; i < nfreq; ++i) CR_REQUIRE(std::isfinite(omegas[i]), CR_E_INVALID, "cr_sweep: non-finite frequency");
+        const double t0 = now();
+        hipStream_t s = r->ctx->stream;
+        SweepEngine& E = engine(r->ctx);
+        E.d_omega.reserve(std::max(nfreq, 1));
+        if (nfreq) CR_HIP(hipMemcpyAsync(E.d_omega.p, omegas, nfreq * sizeof(double), hipMemcpyHostToDevice, s));
+        std::vector<RomDesc> roms{desc_of(r, E.d_omega.p, reinterpret_cast<zd*>(Y_dev), 0)};
+        std::vector<int2> items(nfreq);
+        for (int i = 0; i < nfreq; ++i) items[i] = make_int2(0, i);
+        int mi = 0, nc = 0, np = 0, fb = 0;
+        E.run(roms, items, prec, prec == CR_MIXED, s, &mi, &nc, &np, 0, &fb);
+        if (info) {
+            info->max_ir_iterations = mi;
+            info->not_converged = nc;
+            info->fp64_fallbacks = fb;
+            info->seconds = now() - t0;
+        }
+    });
+}
+
+cr_status cr_sweep_batched(cr_ctx ctx, int32_t nrom, const cr_rom* roms, int32_t nfreq, const double* omegas,
+                           cr_precision prec, cr_z* const* Y_dev, const cr_tune* tune, cr_sweep_info* info) {
+    if (!ctx) return CR_E_INVALID;
+    return cr_guard(ctx, [&] {
+        CR_REQUIRE(nrom >= 0 && nfreq >= 0 && (nrom == 0 || (roms && Y_dev)) && (nfreq == 0 || omegas), CR_E_INVALID,
+                   "cr_sweep_batched: bad arguments");
+        CR_REQUIRE(prec == CR_FP64 || prec == CR_MIXED, CR_E_INVALID, "cr_sweep_batched: bad precision");
+        const double t0 = now();
+        hipStream_t s = ctx->stream;
+        SweepEngine& E = engine(ctx);
+        const size_t nw = (size_t)nrom * nfreq;
+        E.d_omega.reserve(std::max<size_t>(nw, 1));
+        if (nw) CR_HIP(hipMemcpyAsync(E.d_omega.p, omegas, nw * sizeof(double), hipMemcpyHostToDevice, s));
+        std::vector<RomDesc> ds(nrom);
+        for (int m = 0; m < nrom; ++m) {
+            CR_REQUIRE(roms[m] && roms[m]->ctx == ctx && Y_dev[m], CR_E_INVALID, "cr_sweep_batched: bad model");
+            ds[m] = desc_of(roms[m], E.d_omega.p + (size_t)m * nfreq, reinterpret_cast<zd*>(Y_dev[m]), 0);
+        }
+        // longest first: q^3 descending, then model index, then frequency
+        std::vector<int> order(nrom);
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return ds[a].q > ds[b].q; });
+        std::vector<int2> items;
+        items.reserve(nw);
+        for (int m : order)
+            for (int i = 0; i < nfreq; ++i) items.push_back(make_int2(m, i));
+        int mi = 0, nc = 0, np = 0, fb = 0;
+        const int grid = tune && tune->grid_per_cu > 0 ? tune->grid_per_cu * ctx->num_cu : 0;
+        E.run(ds, items, prec, prec == CR_MIXED, s, &mi, &nc, &np, grid, &fb);
+        if (info) {
+            info->max_ir_iterations = mi;
+            info->not_converged = nc;
+            info->fp64_fallbacks = fb;
+            info->seconds = now() - t0;
+        }
+    });
+}
+
+}  // extern "C"

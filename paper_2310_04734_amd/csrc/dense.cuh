@@ -1,0 +1,211 @@
+// Workgroup-level dense complex kernels for CDNA4 (64-wide wavefronts, 256-thread workgroups):
+// partial LU with row pivoting restricted to the fully-summed rows, and the triangular solves
+// that go with it. Shared by the multifrontal factorisation (one front per workgroup) and the
+// reduced sweep (one reduced matrix per workgroup).
+//
+// Complex arithmetic uses four real multiplies per product (no three-multiply variant), so the
+// rounding of every product is the textbook one.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace cr {
+
+template <typename T>
+struct cx {
+    T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// c - a * b
+template <typename T>
+__device__ __forceinline__ cx<T> cfms(cx<T> c, cx<T> a, cx<T> b) {
+    return {c.re - a.re * b.re + a.im * b.im, c.im - a.re * b.im - a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> crecip(cx<T> a) {
+    // 1 / a with scaling against overflow (Smith's algorithm)
+    if (fabs(a.re) >= fabs(a.im)) {
+        T r = a.im / a.re, d = a.re + a.im * r;
+        return {T(1) / d, -r / d};
+    } else {
+        T r = a.re / a.im, d = a.im + a.re * r;
+        return {r / d, T(-1) / d};
+    }
+}
+template <typename T>
+__device__ __forceinline__ T cabs1(cx<T> a) { return fabs(a.re) + fabs(a.im); }
+
+constexpr int kWG = 256;     // threads per workgroup (4 wavefronts)
+constexpr int kNB = 16;      // panel width
+constexpr int kTile = 64;    // trailing-update tile (64 x 64, 4 x 4 per thread)
+
+// Workgroup max-reduction of (value, index); lowest index wins ties. Uses red_v/red_i in LDS
+// (kWG entries each). All threads receive the result.
+template <typename T>
+__device__ __forceinline__ void wg_argmax(T v, int i, T* red_v, int* red_i, T& out_v, int& out_i) {
+    const int t = threadIdx.x;
+    // wavefront-level first
+    for (int off = 32; off > 0; off >>= 1) {
+        T ov = __shfl_xor(v, off);
+        int oi = __shfl_xor(i, off);
+        if (ov > v || (ov == v && oi < i)) { v = ov; i = oi; }
+    }
+    if ((t & 63) == 0) { red_v[t >> 6] = v; red_i[t >> 6] = i; }
+    __syncthreads();
+    if (t == 0) {
+        T bv = red_v[0];
+        int bi = red_i[0];
+        for (int w = 1; w < kWG / 64; ++w)
+            if (red_v[w] > bv || (red_v[w] == bv && red_i[w] < bi)) { bv = red_v[w]; bi = red_i[w]; }
+        red_v[kWG / 64] = bv;
+        red_i[kWG / 64] = bi;
+    }
+    __syncthreads();
+    out_v = red_v[kWG / 64];
+    out_i = red_i[kWG / 64];
+    __syncthreads();
+}
+
+template <typename T>
+struct LuShared {
+    cx<T> a[kTile][kNB + 1];     // trailing update: L panel tile
+    cx<T> b[kNB][kTile + 1];     // trailing update: U panel tile
+    T red_v[kWG / 64 + 1];
+    int red_i[kWG / 64 + 1];
+};
+
+// Partial LU of the m x m column-major matrix A (leading dimension lda) over its first p
+// columns: P A = L U on the leading p columns with the trailing (m-p) x (m-p) block replaced
+// by its Schur complement. Row pivots are searched only among rows [k, p) (fully-summed rows);
+// ipiv[k] receives the row swapped with row k. Pivots with cabs1 below `tiny` are replaced by
+// tiny (counted in *nperturb, which the caller zeroes).
+template <typename T>
+__device__ void wg_getrf(cx<T>* __restrict__ A, int lda, int m, int p, int* __restrict__ ipiv, T tiny,
+                         int* nperturb, LuShared<T>& sh) {
+    const int t = threadIdx.x;
+    for (int k0 = 0; k0 < p; k0 += kNB) {
+        const int k1 = min(k0 + kNB, p);
+        // ---------------- panel factorisation (columns k0..k1-1, rows k0..m-1)
+        for (int k = k0; k < k1; ++k) {
+            T best = T(-1);
+            int bi = k;
+            for (int i = k + t; i < p; i += kWG) {
+                T v = cabs1(A[i + (size_t)k * lda]);
+                if (v > best) { best = v; bi = i; }
+            }
+            T pv;
+            int pi;
+            wg_argmax(best, bi, sh.red_v, sh.red_i, pv, pi);
+            if (t == 0) ipiv[k] = pi;
+            if (pi != k) {
+                for (int j = t; j < m; j += kWG) {
+                    cx<T> x = A[k + (size_t)j * lda], y = A[pi + (size_t)j * lda];
+                    A[k + (size_t)j * lda] = y;
+                    A[pi + (size_t)j * lda] = x;
+                }
+                __syncthreads();
+            }
+            cx<T> d = A[k + (size_t)k * lda];
+            if (!(pv > tiny)) {   // tiny or NaN pivot: static perturbation
+                T mag = cabs1(d);
+                if (mag > T(0)) { d.re = d.re / mag * tiny; d.im = d.im / mag * tiny; }
+                else { d.re = tiny; d.im = T(0); }
+                __syncthreads();
+                if (t == 0) { A[k + (size_t)k * lda] = d; atomicAdd(nperturb, 1); }
+            }
+            cx<T> r = crecip(d);
+            for (int i = k + 1 + t; i < m; i += kWG) {
+                cx<T>& x = A[i + (size_t)k * lda];
+                x = cmul(x, r);
+            }
+            __syncthreads();
+            // rank-1 update inside the panel
+            const int nc = k1 - k - 1;
+            if (nc > 0) {
+                const int rows = m - k - 1;
+                for (int e = t; e < rows * nc; e += kWG) {
+                    int i = k + 1 + e % rows, j = k + 1 + e / rows;
+                    A[i + (size_t)j * lda] = cfms(A[i + (size_t)j * lda], A[i + (size_t)k * lda], A[k + (size_t)j * lda]);
+                }
+            }
+            __syncthreads();
+        }
+        if (k1 >= m) break;
+        // ---------------- U12 block: solve L_kk X = A[k0:k1, k1:m] (unit lower)
+        for (int j = k1 + t; j < m; j += kWG) {
+            cx<T> x[kNB];
+#pragma unroll
+            for (int r = 0; r < kNB; ++r)
+                if (k0 + r < k1) x[r] = A[k0 + r + (size_t)j * lda];
+#pragma unroll
+            for (int r = 0; r < kNB; ++r) {
+                if (k0 + r >= k1) break;
+#pragma unroll
+                for (int s = 0; s < r; ++s) x[r] = cfms(x[r], A[k0 + r + (size_t)(k0 + s) * lda], x[s]);
+            }
+#pragma unroll
+            for (int r = 0; r < kNB; ++r)
+                if (k0 + r < k1) A[k0 + r + (size_t)j * lda] = x[r];
+        }
+        __syncthreads();
+        // ---------------- trailing update A[k1:m, k1:m] -= A[k1:m, k0:k1] A[k0:k1, k1:m]
+        const int nbk = k1 - k0;
+        const int rem = m - k1;
+        const int tiles = (rem + kTile - 1) / kTile;
+        const int tx = t & 15, ty = t >> 4;   // 16 x 16 threads, 4 x 4 each
+        for (int tile = 0; tile < tiles * tiles; ++tile) {
+            const int i0 = k1 + (tile % tiles) * kTile, j0 = k1 + (tile / tiles) * kTile;
+            for (int e = t; e < kTile * kNB; e += kWG) {
+                int r = e % kTile, c = e / kTile;
+                cx<T> v = {T(0), T(0)};
+                if (i0 + r < m && c < nbk) v = A[i0 + r + (size_t)(k0 + c) * lda];
+                sh.a[r][c] = v;
+            }
+            for (int e = t; e < kTile * kNB; e += kWG) {
+                int r = e % kNB, c = e / kNB;
+                cx<T> v = {T(0), T(0)};
+                if (j0 + c < m && r < nbk) v = A[k0 + r + (size_t)(j0 + c) * lda];
+                sh.b[r][c] = v;
+            }
+            __syncthreads();
+            cx<T> acc[4][4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] = {T(0), T(0)};
+            for (int c = 0; c < nbk; ++c) {
+                cx<T> av[4], bv[4];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) av[a] = sh.a[tx + 16 * a][c];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) bv[b] = sh.b[c][ty + 16 * b];
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        acc[a][b].re += av[a].re * bv[b].re - av[a].im * bv[b].im;
+                        acc[a][b].im += av[a].re * bv[b].im + av[a].im * bv[b].re;
+                    }
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    int i = i0 + tx + 16 * a, j = j0 + ty + 16 * b;
+                    if (i < m && j < m) {
+                        cx<T>& x = A[i + (size_t)j * lda];
+                        x.re -= acc[a][b].re;
+                        x.im -= acc[a][b].im;
+                    }
+                }
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+}
+
+}  // namespace cr

@@ -1,0 +1,338 @@
+// Multifrontal LU of the shifted system A_j = K~ - w_j^2 M~ (Jacobi-scaled) at an expansion
+// point, and the forward/backward solves with the stored factor (paper Section 3.3: one
+// factorisation per expansion point, reused for every moment at that point).
+//
+// Fronts are processed level by level from the leaves of the nested-dissection tree to the
+// root; every front of a level is one workgroup:
+//   assemble:  zero the m x m front, scatter the original entries (formed in FP64 and rounded
+//              to the factor precision), add the children's contribution blocks (pull, in
+//              child order: deterministic, no atomics);
+//   factor:    partial LU of the p fully-summed columns (pivoting among fully-summed rows),
+//              leaving the Schur complement in the trailing (m-p) x (m-p) block.
+// The fronts stay resident in one device arena (HBM is large enough that the contribution
+// blocks need no stack), so the L and U parts are the factor used by the solves.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include <cstring>
+
+#include "dense.cuh"
+#include "internal.h"
+#include "util.cuh"
+
+namespace cr {
+namespace {
+
+template <typename T>
+__global__ void __launch_bounds__(kWG) k_front_assemble(
+    const int32_t* __restrict__ level_fronts, const int32_t* __restrict__ fsize, const int64_t* __restrict__ front_off,
+    const int32_t* __restrict__ child_off, const int32_t* __restrict__ child_list, const int32_t* __restrict__ npiv,
+    const int64_t* __restrict__ cmap_off, const int32_t* __restrict__ cmap, const int64_t* __restrict__ ent_off,
+    const int64_t* __restrict__ ent_src, const int32_t* __restrict__ ent_dst, const zd* __restrict__ K,
+    const zd* __restrict__ M, double sigma, cx<T>* __restrict__ arena) {
+    const int f = level_fronts[blockIdx.x];
+    const int m = fsize[f];
+    cx<T>* F = arena + front_off[f];
+    const int64_t mm = (int64_t)m * m;
+    for (int64_t e = threadIdx.x; e < mm; e += kWG) F[e] = {T(0), T(0)};
+    __syncthreads();
+    for (int64_t e = ent_off[f] + threadIdx.x; e < ent_off[f + 1]; e += kWG) {
+        const int64_t s = ent_src[e];
+        const zd k = K[s], mv = M[s];
+        // A = K - sigma M in FP64, then rounded once
+        F[ent_dst[e]] = {T(k.re - sigma * mv.re), T(k.im - sigma * mv.im)};
+    }
+    __syncthreads();
+    for (int ci = child_off[f]; ci < child_off[f + 1]; ++ci) {
+        const int c = child_list[ci];
+        const int mc = fsize[c], pc = npiv[c], nc = mc - pc;
+        const cx<T>* C = arena + front_off[c];
+        const int32_t* map = cmap + cmap_off[c];
+        for (int e = threadIdx.x; e < nc * nc; e += kWG) {
+            const int r = e % nc, s = e / nc;
+            const cx<T> v = C[(pc + r) + (size_t)(pc + s) * mc];
+            cx<T>& d = F[map[r] + (size_t)map[s] * m];
+            d.re += v.re;
+            d.im += v.im;
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kWG) k_front_factor(const int32_t* __restrict__ level_fronts,
+                                                     const int32_t* __restrict__ fsize, const int32_t* __restrict__ npiv,
+                                                     const int32_t* __restrict__ first, const int64_t* __restrict__ front_off,
+                                                     cx<T>* __restrict__ arena, int32_t* __restrict__ ipiv, T tiny,
+                                                     int32_t* nperturb) {
+    __shared__ LuShared<T> sh;
+    const int f = level_fronts[blockIdx.x];
+    const int m = fsize[f], p = npiv[f];
+    if (p == 0) return;
+    wg_getrf<T>(arena + front_off[f], m, m, p, ipiv + first[f], tiny, nperturb, sh);
+}
+
+// ------------------------------------------------------------------ solves
+// Forward: per front, w (m x nrhs, column stride m) = [b_piv ; 0] + children's contributions,
+// row swaps on the pivot part, y = L11^{-1} w_piv, w_cb -= L21 y; y is written to x (new
+// numbering) and w_cb stays in the front's work slot for the parent.
+template <typename T>
+__global__ void __launch_bounds__(kWG) k_front_fwd(
+    const int32_t* __restrict__ level_fronts, const int32_t* __restrict__ fsize, const int32_t* __restrict__ npiv,
+    const int32_t* __restrict__ first, const int64_t* __restrict__ front_off, const int64_t* __restrict__ idx_off,
+    const int32_t* __restrict__ child_off, const int32_t* __restrict__ child_list, const int64_t* __restrict__ cmap_off,
+    const int32_t* __restrict__ cmap, const cx<T>* __restrict__ arena, const int32_t* __restrict__ ipiv,
+    cx<T>* __restrict__ x, int64_t ldx, int nrhs, cx<T>* __restrict__ work) {
+    const int f = level_fronts[blockIdx.x];
+    const int m = fsize[f], p = npiv[f], f0 = first[f];
+    const cx<T>* F = arena + front_off[f];
+    cx<T>* w = work + idx_off[f] * nrhs;   // m x nrhs
+    const int t = threadIdx.x;
+    for (int e = t; e < m * nrhs; e += kWG) {
+        const int r = e % m, l = e / m;
+        w[e] = r < p ? x[f0 + r + (size_t)l * ldx] : cx<T>{T(0), T(0)};
+    }
+    __syncthreads();
+    for (int ci = child_off[f]; ci < child_off[f + 1]; ++ci) {
+        const int c = child_list[ci];
+        const int mc = fsize[c], pc = npiv[c], nc = mc - pc;
+        const cx<T>* wc = work + idx_off[c] * nrhs;
+        const int32_t* map = cmap + cmap_off[c];
+        for (int e = t; e < nc * nrhs; e += kWG) {
+            const int r = e % nc, l = e / nc;
+            const cx<T> v = wc[pc + r + (size_t)l * mc];
+            cx<T>& d = w[map[r] + (size_t)l * m];
+            d.re += v.re;
+            d.im += v.im;
+        }
+        __syncthreads();
+    }
+    if (p == 0) return;
+    // row swaps of the pivot block (sequential in k; one thread per right-hand side)
+    for (int l = t; l < nrhs; l += kWG) {
+        cx<T>* wl = w + (size_t)l * m;
+        for (int k = 0; k < p; ++k) {
+            const int r = ipiv[f0 + k];
+            if (r != k) { cx<T> a = wl[k]; wl[k] = wl[r]; wl[r] = a; }
+        }
+    }
+    __syncthreads();
+    // forward substitution, column-oriented: after y_k is final, update rows k+1..m-1
+    for (int k = 0; k < p; ++k) {
+        for (int e = t; e < (m - k - 1) * nrhs; e += kWG) {
+            const int i = k + 1 + e % (m - k - 1), l = e / (m - k - 1);
+            w[i + (size_t)l * m] = cfms(w[i + (size_t)l * m], F[i + (size_t)k * m], w[k + (size_t)l * m]);
+        }
+        __syncthreads();
+    }
+    for (int e = t; e < p * nrhs; e += kWG) {
+        const int r = e % p, l = e / p;
+        x[f0 + r + (size_t)l * ldx] = w[r + (size_t)l * m];
+    }
+}
+
+// Backward: x_piv = U11^{-1} (y - U12 x_cb), x_cb gathered from already-solved ancestors.
+template <typename T>
+__global__ void __launch_bounds__(kWG) k_front_bwd(
+    const int32_t* __restrict__ level_fronts, const int32_t* __restrict__ fsize, const int32_t* __restrict__ npiv,
+    const int32_t* __restrict__ first, const int64_t* __restrict__ front_off, const int64_t* __restrict__ idx_off,
+    const int32_t* __restrict__ idx, const cx<T>* __restrict__ arena, cx<T>* __restrict__ x, int64_t ldx, int nrhs,
+    cx<T>* __restrict__ work) {
+    const int f = level_fronts[blockIdx.x];
+    const int m = fsize[f], p = npiv[f], f0 = first[f];
+    if (p == 0) return;
+    const cx<T>* F = arena + front_off[f];
+    const int32_t* ix = idx + idx_off[f];
+    cx<T>* w = work + idx_off[f] * nrhs;
+    const int t = threadIdx.x;
+    for (int e = t; e < m * nrhs; e += kWG) {
+        const int r = e % m, l = e / m;
+        w[e] = x[ix[r] + (size_t)l * ldx];
+    }
+    __syncthreads();
+    // y_piv -= U12 x_cb : each thread owns (row, rhs) pairs
+    const int c = m - p;
+    for (int e = t; e < p * nrhs; e += kWG) {
+        const int r = e % p, l = e / p;
+        cx<T> acc = w[r + (size_t)l * m];
+        for (int s = 0; s < c; ++s) acc = cfms(acc, F[r + (size_t)(p + s) * m], w[p + s + (size_t)l * m]);
+        w[r + (size_t)l * m] = acc;
+    }
+    __syncthreads();
+    // back substitution, column-oriented
+    for (int k = p - 1; k >= 0; --k) {
+        const cx<T> d = crecip(F[k + (size_t)k * m]);
+        for (int l = t; l < nrhs; l += kWG) w[k + (size_t)l * m] = cmul(w[k + (size_t)l * m], d);
+        __syncthreads();
+        for (int e = t; e < k * nrhs; e += kWG) {
+            const int i = e % k, l = e / k;
+            w[i + (size_t)l * m] = cfms(w[i + (size_t)l * m], F[i + (size_t)k * m], w[k + (size_t)l * m]);
+        }
+        __syncthreads();
+    }
+    for (int e = t; e < p * nrhs; e += kWG) {
+        const int r = e % p, l = e / p;
+        x[f0 + r + (size_t)l * ldx] = w[r + (size_t)l * m];
+    }
+}
+
+// gather (with precision change) B (old numbering, n x nrhs FP64) -> xp (new numbering, T)
+template <typename T>
+__global__ void k_gather_perm(const zd* __restrict__ B, int64_t ldb, const int32_t* __restrict__ perm, int64_t n, int nrhs,
+                              cx<T>* __restrict__ xp) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * nrhs) return;
+    const int64_t i = e % n, l = e / n;
+    const zd v = B[perm[i] + l * ldb];
+    xp[e] = {T(v.re), T(v.im)};
+}
+
+// X (old numbering) (+)= xp (new numbering); accumulate when add != 0
+template <typename T>
+__global__ void k_scatter_perm(const cx<T>* __restrict__ xp, const int32_t* __restrict__ perm, int64_t n, int nrhs,
+                               zd* __restrict__ X, int64_t ldx, int add) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * nrhs) return;
+    const int64_t i = e % n, l = e / n;
+    const cx<T> v = xp[e];
+    zd& d = X[perm[i] + l * ldx];
+    if (add) { d.re += (double)v.re; d.im += (double)v.im; }
+    else { d.re = (double)v.re; d.im = (double)v.im; }
+}
+
+__global__ void k_maxabs_entries(const zd* __restrict__ K, const zd* __restrict__ M, int64_t nnz, double sigma,
+                                 unsigned long long* out) {
+    double m = 0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
+        double re = K[e].re - sigma * M[e].re, im = K[e].im - sigma * M[e].im;
+        m = fmax(m, fabs(re) + fabs(im));
+    }
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(m));
+}
+
+template <typename T>
+void run_factor(Factor& f, cr_sys sys, double sigma, cx<T>* arena, T tiny, hipStream_t s) {
+    const Symbolic& S = *sys->sym;
+    const DevSymbolic& D = *sys->dsym;
+    for (int l = 0; l < S.nlevel; ++l) {
+        const int nf = S.level_off[l + 1] - S.level_off[l];
+        const int32_t* lf = D.level_fronts.p + S.level_off[l];
+        hipLaunchKernelGGL(k_front_assemble<T>, dim3(nf), dim3(kWG), 0, s, lf, D.fsize.p, D.front_off.p, D.child_off.p,
+                           D.child_list.p, D.npiv.p, D.cmap_off.p, D.cmap.p, D.ent_off.p, D.ent_src.p, D.ent_dst.p,
+                           sys->d_K.p, sys->d_M.p, sigma, arena);
+        hipLaunchKernelGGL(k_front_factor<T>, dim3(nf), dim3(kWG), 0, s, lf, D.fsize.p, D.npiv.p, D.first.p,
+                           D.front_off.p, arena, f.ipiv.p, tiny, f.nperturb.p);
+    }
+    CR_HIP(hipGetLastError());
+}
+
+template <typename T>
+void run_solve(const Factor& f, int nrhs, cx<T>* xp, cx<T>* work, hipStream_t s, const cx<T>* arena) {
+    cr_sys sys = f.sys;
+    const Symbolic& S = *sys->sym;
+    const DevSymbolic& D = *sys->dsym;
+    for (int l = 0; l < S.nlevel; ++l) {
+        const int nf = S.level_off[l + 1] - S.level_off[l];
+        hipLaunchKernelGGL(k_front_fwd<T>, dim3(nf), dim3(kWG), 0, s, D.level_fronts.p + S.level_off[l], D.fsize.p,
+                           D.npiv.p, D.first.p, D.front_off.p, D.idx_off.p, D.child_off.p, D.child_list.p, D.cmap_off.p,
+                           D.cmap.p, arena, f.ipiv.p, xp, (int64_t)S.n, nrhs, work);
+    }
+    for (int l = S.nlevel - 1; l >= 0; --l) {
+        const int nf = S.level_off[l + 1] - S.level_off[l];
+        hipLaunchKernelGGL(k_front_bwd<T>, dim3(nf), dim3(kWG), 0, s, D.level_fronts.p + S.level_off[l], D.fsize.p,
+                           D.npiv.p, D.first.p, D.front_off.p, D.idx_off.p, D.idx.p, arena, xp, (int64_t)S.n, nrhs, work);
+    }
+    CR_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+void upload_symbolic(cr_sys sys) {
+    const Symbolic& S = *sys->sym;
+    auto D = std::make_unique<DevSymbolic>();
+    hipStream_t s = sys->ctx->stream;
+    upload(D->first, S.first, s);
+    upload(D->npiv, S.npiv, s);
+    upload(D->fsize, S.fsize, s);
+    upload(D->parent, S.parent, s);
+    upload(D->child_off, S.child_off, s);
+    upload(D->child_list, S.child_list, s);
+    upload(D->level_fronts, S.level_fronts, s);
+    upload(D->idx, S.idx, s);
+    upload(D->cmap, S.cmap, s);
+    upload(D->ent_dst, S.ent_dst, s);
+    upload(D->idx_off, S.idx_off, s);
+    upload(D->front_off, S.front_off, s);
+    upload(D->cmap_off, S.cmap_off, s);
+    upload(D->ent_off, S.ent_off, s);
+    upload(D->ent_src, S.ent_src, s);
+    upload(D->perm, S.perm, s);
+    upload(D->iperm, S.iperm, s);
+    CR_HIP(hipStreamSynchronize(s));
+    sys->dsym = std::move(D);
+}
+
+void numeric_factor(Factor& f, cr_sys sys, double omega, cr_precision prec, hipStream_t s) {
+    CR_REQUIRE(sys->sym && sys->dsym, CR_E_STATE, "factor before analyse");
+    const Symbolic& S = *sys->sym;
+    f.sys = sys;
+    f.omega = omega;
+    f.prec = prec;
+    f.ipiv.reserve(S.n);
+    f.nperturb.reserve(2);
+    const double sigma = omega * omega;
+    // largest |entry| of the shifted matrix sets the perturbation threshold
+    f.amax.reserve(1);
+    fill_zero(f.amax.p, 1, s);
+    fill_zero(f.nperturb.p, 1, s);
+    const int64_t nnz = sys->rowptr[sys->n];
+    hipLaunchKernelGGL(k_maxabs_entries, dim3(256), dim3(256), 0, s, sys->d_K.p, sys->d_M.p, nnz, sigma, f.amax.p);
+    unsigned long long hm = 0;
+    CR_HIP(hipMemcpyAsync(&hm, f.amax.p, sizeof(hm), hipMemcpyDeviceToHost, s));
+    CR_HIP(hipStreamSynchronize(s));
+    double amax;
+    std::memcpy(&amax, &hm, sizeof(amax));
+    if (prec == CR_MIXED) {
+        f.arena64.release();
+        f.arena32.reserve(S.arena);
+        run_factor<float>(f, sys, sigma, reinterpret_cast<cx<float>*>(f.arena32.p), (float)(3e-4 * amax), s);
+    } else {
+        f.arena32.release();
+        f.arena64.reserve(S.arena);
+        run_factor<double>(f, sys, sigma, reinterpret_cast<cx<double>*>(f.arena64.p), 1e-8 * amax, s);
+    }
+    int32_t np = 0;
+    CR_HIP(hipMemcpyAsync(&np, f.nperturb.p, sizeof(np), hipMemcpyDeviceToHost, s));
+    CR_HIP(hipStreamSynchronize(s));
+    f.n_perturbed = np;
+}
+
+// one application of the stored factor: Xout = A~^{-1} B (both FP64, old numbering)
+void apply_factor(const Factor& f, int nrhs, const zd* B, int64_t ldb, zd* X, int64_t ldx, int add, SolveWork& w,
+                  hipStream_t s) {
+    cr_sys sys = f.sys;
+    const Symbolic& S = *sys->sym;
+    const int64_t n = S.n;
+    const int64_t tot = n * nrhs;
+    const int nb = (int)((tot + 255) / 256);
+    if (f.prec == CR_MIXED) {
+        w.w32.reserve((size_t)S.idx_off[S.nfront] * nrhs + n * nrhs);
+        cx<float>* xp = reinterpret_cast<cx<float>*>(w.w32.p);
+        cx<float>* work = xp + n * nrhs;
+        hipLaunchKernelGGL(k_gather_perm<float>, dim3(nb), dim3(256), 0, s, B, ldb, sys->dsym->perm.p, n, nrhs, xp);
+        run_solve<float>(f, nrhs, xp, work, s, reinterpret_cast<const cx<float>*>(f.arena32.p));
+        hipLaunchKernelGGL(k_scatter_perm<float>, dim3(nb), dim3(256), 0, s, xp, sys->dsym->perm.p, n, nrhs, X, ldx, add);
+    } else {
+        w.w64.reserve((size_t)S.idx_off[S.nfront] * nrhs + n * nrhs);
+        cx<double>* xp = reinterpret_cast<cx<double>*>(w.w64.p);
+        cx<double>* work = xp + n * nrhs;
+        hipLaunchKernelGGL(k_gather_perm<double>, dim3(nb), dim3(256), 0, s, B, ldb, sys->dsym->perm.p, n, nrhs, xp);
+        run_solve<double>(f, nrhs, xp, work, s, reinterpret_cast<const cx<double>*>(f.arena64.p));
+        hipLaunchKernelGGL(k_scatter_perm<double>, dim3(nb), dim3(256), 0, s, xp, sys->dsym->perm.p, n, nrhs, X, ldx, add);
+    }
+    CR_HIP(hipGetLastError());
+}
+
+}  // namespace cr

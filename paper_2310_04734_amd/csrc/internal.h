@@ -1,0 +1,238 @@
+// Internal declarations shared by the library's translation units (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/cabinrom.h"
+
+namespace cr {
+
+// ------------------------------------------------------------------------- errors
+struct Error : std::runtime_error {
+    cr_status code;
+    Error(cr_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define CR_HIP(call)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            throw ::cr::Error(CR_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define CR_REQUIRE(cond, code, msg)                        \
+    do {                                                   \
+        if (!(cond)) throw ::cr::Error((code), (msg));     \
+    } while (0)
+
+// ------------------------------------------------------------------------- device buffers
+// Owning device allocation (hipMalloc); movable, not copyable.
+template <typename T>
+struct DevBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    DevBuf() = default;
+    explicit DevBuf(size_t count) { alloc(count); }
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DevBuf& operator=(DevBuf&& o) noexcept {
+        if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        return *this;
+    }
+    ~DevBuf() { release(); }
+    void alloc(size_t count) {
+        release();
+        if (count == 0) return;
+        hipError_t e = hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T));
+        if (e != hipSuccess) {
+            p = nullptr;
+            throw Error(CR_E_OOM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+        }
+        n = count;
+    }
+    // grow (contents not preserved) when smaller than count
+    void reserve(size_t count) { if (count > n) alloc(count); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    size_t bytes() const { return n * sizeof(T); }
+};
+
+template <typename T>
+void upload(DevBuf<T>& d, const std::vector<T>& h, hipStream_t s) {
+    d.alloc(h.size());
+    if (!h.empty()) CR_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+// ------------------------------------------------------------------------- complex helpers
+struct zd { double re, im; };   // host/device complex128 storage
+struct zf { float re, im; };    // complex64 storage
+
+// ------------------------------------------------------------------------- analysis
+struct Symbolic {
+    int64_t n = 0;
+    std::vector<int32_t> perm;     // new -> old
+    std::vector<int32_t> iperm;    // old -> new
+    // fronts in postorder (children before parents)
+    int32_t nfront = 0;
+    std::vector<int32_t> first;    // first pivot (new index)
+    std::vector<int32_t> npiv;
+    std::vector<int32_t> fsize;    // m = npiv + ncb
+    std::vector<int64_t> idx_off;  // offset of the front's row index list (length m) in idx
+    std::vector<int32_t> idx;      // new indices: pivots then contribution rows (sorted)
+    std::vector<int32_t> parent;   // -1 for roots
+    std::vector<int32_t> child_off, child_list;  // CSR of children
+    std::vector<int32_t> level;    // 0 = leaves ... height
+    int32_t nlevel = 0;
+    std::vector<int32_t> level_off, level_fronts;  // fronts grouped by level
+    std::vector<int64_t> front_off;  // offset (complex entries) of front f in the arena
+    int64_t arena = 0;               // total complex entries
+    std::vector<int64_t> piv_off;    // = first[f] (pivot rows are globally numbered)
+    // child contribution -> parent local index maps (int32 per child CB row)
+    std::vector<int64_t> cmap_off;   // per front (as child): offset into cmap, length ncb
+    std::vector<int32_t> cmap;
+    // original-entry scatter: per front, list of (csr position, local row, local col)
+    std::vector<int64_t> ent_off;    // per front
+    std::vector<int64_t> ent_src;    // csr position
+    std::vector<int32_t> ent_dst;    // local row + local col * m (fits: m^2 < 2^31)
+    int32_t max_front = 0, max_piv = 0, max_children = 0;
+    int64_t factor_entries = 0;
+    double factor_flops = 0;
+    double seconds = 0;
+};
+
+// Device copy of the symbolic data used by the numeric kernels.
+struct DevSymbolic {
+    DevBuf<int32_t> first, npiv, fsize, parent, child_off, child_list, level_fronts, idx, cmap, ent_dst;
+    DevBuf<int64_t> idx_off, front_off, cmap_off, ent_off, ent_src;
+    DevBuf<int32_t> perm, iperm;
+};
+
+// scale, scaled device copies and norms of a freshly assembled or imported system
+void finalize_sys(cr_sys sys);
+
+std::unique_ptr<Symbolic> analyse_pattern(int64_t n, const std::vector<int64_t>& rowptr,
+                                          const std::vector<int32_t>& col,
+                                          const std::vector<double>& coords /* n*3 or empty */);
+
+}  // namespace cr
+
+// ------------------------------------------------------------------------- handles
+namespace cr { struct SweepEngine; }
+
+struct cr_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    int num_cu = 256;
+    cr::SweepEngine* sweep = nullptr;   // persistent sweep workspaces (owned)
+};
+
+struct cr_sys_s {
+    cr_ctx ctx = nullptr;
+    int64_t n = 0, n_u = 0;
+    int32_t L = 0, n_o = 0;
+    // host, unscaled
+    std::vector<int64_t> rowptr;
+    std::vector<int32_t> col;
+    std::vector<cr::zd> K, M, F;   // F: n x L column-major
+    std::vector<int32_t> flags;
+    std::vector<int64_t> recv;
+    std::vector<double> coords;    // n x 3 DoF coordinates (for nested dissection)
+    std::vector<double> scale;     // S = |K_ii|^{-1/2}
+    double anorm_inf = 0;          // max over rows of sum |K~| (scaled) for backward errors
+    double mnorm_inf = 0;          // same for M~
+    // device, scaled
+    cr::DevBuf<int64_t> d_rowptr;
+    cr::DevBuf<int32_t> d_col;
+    cr::DevBuf<cr::zd> d_K, d_M, d_F;
+    cr::DevBuf<double> d_scale;
+    cr::DevBuf<int64_t> d_recv;
+    cr::DevBuf<int32_t> d_flags;
+    // analysis
+    std::unique_ptr<cr::Symbolic> sym;
+    std::unique_ptr<cr::DevSymbolic> dsym;
+};
+
+namespace cr {
+
+// ------------------------------------------------------------------------- factor internals
+struct Factor {
+    cr_sys sys = nullptr;
+    double omega = 0;
+    cr_precision prec = CR_FP64;
+    DevBuf<zd> arena64;   // complex128 fronts (FP64)
+    DevBuf<zf> arena32;   // complex64 fronts (MIXED)
+    DevBuf<int32_t> ipiv; // local pivot row per pivot (n)
+    DevBuf<int32_t> nperturb;
+    DevBuf<unsigned long long> amax;
+    int32_t n_perturbed = 0;
+    double anorm = 0, anorm_sigma = -1;   // ||A~||_inf at the factored shift
+};
+
+void upload_symbolic(cr_sys sys);
+// X (+)= A~^{-1} B with the stored factor (FP64 in and out, old numbering)
+void apply_factor(const Factor& f, int nrhs, const zd* B, int64_t ldb, zd* X, int64_t ldx, int add,
+                  struct SolveWork& w, hipStream_t s);
+
+// numeric factorisation into an existing Factor (arena reused when large enough)
+void numeric_factor(Factor& f, cr_sys sys, double omega, cr_precision prec, hipStream_t s);
+
+// workspace for solves
+struct SolveWork {
+    DevBuf<zd> w64;    // front work vectors (arena of sum m * nrhs), FP64 solve
+    DevBuf<zf> w32;    // same, FP32 solve
+    DevBuf<zd> xperm;  // permuted RHS / solution n x nrhs
+    DevBuf<zd> r;      // operator products n x nrhs
+    DevBuf<zd> res;    // refinement residual n x nrhs
+    DevBuf<zd> d;      // correction n x nrhs
+    DevBuf<zd> kry;    // GMRES bases (m + 1) x n x nrhs
+    DevBuf<unsigned long long> sc;
+    DevBuf<double> red;  // reduction scratch
+    std::vector<double> hred;
+};
+
+// Solve A~ X = B for the scaled system (device, n x nrhs, ld n) with FP64 refinement.
+// Returns iterations; sets backward error. Throws CR_E_NOT_CONVERGED only when `strict`.
+int solve_scaled(Factor& f, int nrhs, const zd* B, zd* X, int max_iter, double tol, double* berr,
+                 SolveWork& w, hipStream_t s, bool strict);
+
+// Greedy hook: the network's proposed next candidate (-1 when it proposes none); residuals res
+// of every candidate, candidates already used, geometry features (or null).
+int mlp_propose(cr_mlp m, const std::vector<double>& res, const std::vector<int>& used, const double* geom);
+
+// y = (K~ - sigma M~) x  (or two outputs Kx, Mx) on the device, FP64 CSR.
+void spmm_shifted(cr_sys sys, double sigma, int nrhs, const zd* X, int64_t ldx, zd* Y, int64_t ldy,
+                  hipStream_t s);
+void spmm_km(cr_sys sys, int nrhs, const zd* X, int64_t ldx, zd* KX, zd* MX, int64_t ldy, hipStream_t s);
+void spmm_m(cr_sys sys, int nrhs, const zd* X, int64_t ldx, zd* Y, int64_t ldy, hipStream_t s);
+
+}  // namespace cr
+
+// Run `body`, converting exceptions to a status and ctx->err.
+template <typename F>
+static inline cr_status cr_guard(cr_ctx ctx, F&& body) {
+    try {
+        if (ctx) ctx->err.clear();
+        body();
+        return CR_OK;
+    } catch (const cr::Error& e) {
+        if (ctx) ctx->err = e.what();
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        if (ctx) ctx->err = "host allocation failed";
+        return CR_E_OOM;
+    } catch (const std::exception& e) {
+        if (ctx) ctx->err = e.what();
+        return CR_E_INVALID;
+    }
+}

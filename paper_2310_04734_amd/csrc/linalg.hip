@@ -1,0 +1,688 @@
+// FP64 sparse and tall-skinny kernels of the basis build:
+//   * CSR SpMM with the scaled K~ and M~ (shared pattern): (K~ - s M~) X, the refinement
+//     residual B - (K~ - s M~) X, and the pair K~ X, M~ X for the projection;
+//   * column norms for the backward error of the refinement;
+//   * Gram products H = A^H B of tall-skinny blocks (two passes of these plus the update
+//     W -= V H make the block classical Gram-Schmidt, CGS2);
+//   * the receiver gather C_R = S_recv V_recv and the candidate residual norms of the greedy.
+// Reductions are two-stage with a fixed order (per-workgroup partials, then one ordered sum),
+// so every result is bit-reproducible from run to run.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+
+#include "dense.cuh"
+#include "internal.h"
+#include "util.cuh"
+
+namespace cr {
+namespace {
+
+constexpr int kRowLanes = 8;   // lanes per CSR row
+constexpr int kRhsChunk = 4;   // right-hand sides per pass over a row
+
+// MODE 0: Y = (K - s M) X     MODE 1: Y = B - (K - s M) X     MODE 2: Y = K X, Y2 = M X     MODE 3: Y = M X
+template <int MODE>
+__global__ void __launch_bounds__(256) k_spmm(int64_t n, const int64_t* __restrict__ rowptr,
+                                              const int32_t* __restrict__ col, const zd* __restrict__ K,
+                                              const zd* __restrict__ M, double s, int nrhs, const zd* __restrict__ X,
+                                              int64_t ldx, const zd* __restrict__ B, int64_t ldb, zd* __restrict__ Y,
+                                              zd* __restrict__ Y2, int64_t ldy) {
+    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kRowLanes;
+    const int lane = threadIdx.x % kRowLanes;
+    const bool valid = row < n;
+    const int64_t b = valid ? rowptr[row] : 0, e = valid ? rowptr[row + 1] : 0;
+    for (int l0 = 0; l0 < nrhs; l0 += kRhsChunk) {
+        double ar[kRhsChunk], ai[kRhsChunk], br[kRhsChunk], bi[kRhsChunk];
+#pragma unroll
+        for (int c = 0; c < kRhsChunk; ++c) ar[c] = ai[c] = br[c] = bi[c] = 0;
+        for (int64_t k = b + lane; k < e; k += kRowLanes) {
+            const int32_t j = col[k];
+            const zd kv = K[k], mv = M[k];
+            double vr, vi;
+            if (MODE == 2) { vr = kv.re; vi = kv.im; }
+            else if (MODE == 3) { vr = mv.re; vi = mv.im; }
+            else { vr = kv.re - s * mv.re; vi = kv.im - s * mv.im; }
+#pragma unroll
+            for (int c = 0; c < kRhsChunk; ++c) {
+                if (l0 + c >= nrhs) break;
+                const zd x = X[j + (l0 + c) * ldx];
+                ar[c] += vr * x.re - vi * x.im;
+                ai[c] += vr * x.im + vi * x.re;
+                if (MODE == 2) {
+                    br[c] += mv.re * x.re - mv.im * x.im;
+                    bi[c] += mv.re * x.im + mv.im * x.re;
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < kRhsChunk; ++c) {
+            for (int off = kRowLanes / 2; off > 0; off >>= 1) {
+                ar[c] += __shfl_xor(ar[c], off, kRowLanes);
+                ai[c] += __shfl_xor(ai[c], off, kRowLanes);
+                if (MODE == 2) {
+                    br[c] += __shfl_xor(br[c], off, kRowLanes);
+                    bi[c] += __shfl_xor(bi[c], off, kRowLanes);
+                }
+            }
+        }
+        if (valid && lane == 0) {
+#pragma unroll
+            for (int c = 0; c < kRhsChunk; ++c) {
+                if (l0 + c >= nrhs) break;
+                const int64_t o = row + (l0 + c) * ldy;
+                if (MODE == 0 || MODE == 3) Y[o] = {ar[c], ai[c]};
+                if (MODE == 1) { const zd bb = B[row + (l0 + c) * ldb]; Y[o] = {bb.re - ar[c], bb.im - ai[c]}; }
+                if (MODE == 2) { Y[o] = {ar[c], ai[c]}; Y2[o] = {br[c], bi[c]}; }
+            }
+        }
+    }
+}
+
+// out[3*l + {0,1,2}] = max_i |R_il|, |X_il|, |B_il| (atomicMax on the bits of non-negative doubles)
+__global__ void k_colmax3(int64_t n, int nrhs, const zd* __restrict__ R, const zd* __restrict__ X, const zd* __restrict__ B,
+                          int64_t ld, unsigned long long* out) {
+    const int l = blockIdx.y;
+    double m0 = 0, m1 = 0, m2 = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const zd r = R[i + l * ld], x = X[i + l * ld], b = B[i + l * ld];
+        m0 = fmax(m0, hypot(r.re, r.im));
+        m1 = fmax(m1, hypot(x.re, x.im));
+        m2 = fmax(m2, hypot(b.re, b.im));
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        m0 = fmax(m0, __shfl_xor(m0, off));
+        m1 = fmax(m1, __shfl_xor(m1, off));
+        m2 = fmax(m2, __shfl_xor(m2, off));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(out + 3 * l + 0, (unsigned long long)__double_as_longlong(m0));
+        atomicMax(out + 3 * l + 1, (unsigned long long)__double_as_longlong(m1));
+        atomicMax(out + 3 * l + 2, (unsigned long long)__double_as_longlong(m2));
+    }
+}
+
+// ||K~ - s M~||_inf
+__global__ void k_rownorm(int64_t n, const int64_t* __restrict__ rowptr, const zd* __restrict__ K, const zd* __restrict__ M,
+                          double s, unsigned long long* out) {
+    double m = 0;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+        double acc = 0;
+        for (int64_t k = rowptr[r]; k < rowptr[r + 1]; ++k) acc += hypot(K[k].re - s * M[k].re, K[k].im - s * M[k].im);
+        m = fmax(m, acc);
+    }
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(m));
+}
+
+__global__ void k_axpy_copy(int64_t n, const zd* __restrict__ src, zd* __restrict__ dst) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ SpMM front-ends
+static inline unsigned spmm_blocks(int64_t n) { return (unsigned)((n * kRowLanes + 255) / 256); }
+
+void spmm_shifted(cr_sys sys, double sigma, int nrhs, const zd* X, int64_t ldx, zd* Y, int64_t ldy, hipStream_t s) {
+    hipLaunchKernelGGL(k_spmm<0>, dim3(spmm_blocks(sys->n)), dim3(256), 0, s, sys->n, sys->d_rowptr.p, sys->d_col.p,
+                       sys->d_K.p, sys->d_M.p, sigma, nrhs, X, ldx, (const zd*)nullptr, (int64_t)0, Y, (zd*)nullptr, ldy);
+}
+void spmm_km(cr_sys sys, int nrhs, const zd* X, int64_t ldx, zd* KX, zd* MX, int64_t ldy, hipStream_t s) {
+    hipLaunchKernelGGL(k_spmm<2>, dim3(spmm_blocks(sys->n)), dim3(256), 0, s, sys->n, sys->d_rowptr.p, sys->d_col.p,
+                       sys->d_K.p, sys->d_M.p, 0.0, nrhs, X, ldx, (const zd*)nullptr, (int64_t)0, KX, MX, ldy);
+}
+void spmm_m(cr_sys sys, int nrhs, const zd* X, int64_t ldx, zd* Y, int64_t ldy, hipStream_t s) {
+    hipLaunchKernelGGL(k_spmm<3>, dim3(spmm_blocks(sys->n)), dim3(256), 0, s, sys->n, sys->d_rowptr.p, sys->d_col.p,
+                       sys->d_K.p, sys->d_M.p, 0.0, nrhs, X, ldx, (const zd*)nullptr, (int64_t)0, Y, (zd*)nullptr, ldy);
+}
+void spmm_residual(cr_sys sys, double sigma, int nrhs, const zd* X, int64_t ldx, const zd* B, int64_t ldb, zd* R,
+                   int64_t ldr, hipStream_t s) {
+    hipLaunchKernelGGL(k_spmm<1>, dim3(spmm_blocks(sys->n)), dim3(256), 0, s, sys->n, sys->d_rowptr.p, sys->d_col.p,
+                       sys->d_K.p, sys->d_M.p, sigma, nrhs, X, ldx, B, ldb, R, (zd*)nullptr, ldr);
+}
+
+double shifted_norm_inf(cr_sys sys, double sigma, DevBuf<unsigned long long>& scratch, hipStream_t s) {
+    scratch.reserve(1);
+    fill_zero(scratch.p, 1, s);
+    hipLaunchKernelGGL(k_rownorm, dim3(256), dim3(256), 0, s, sys->n, sys->d_rowptr.p, sys->d_K.p, sys->d_M.p, sigma,
+                       scratch.p);
+    unsigned long long h = 0;
+    CR_HIP(hipMemcpyAsync(&h, scratch.p, sizeof(h), hipMemcpyDeviceToHost, s));
+    CR_HIP(hipStreamSynchronize(s));
+    double v;
+    std::memcpy(&v, &h, sizeof(v));
+    return v;
+}
+
+// ------------------------------------------------------------------ batched column kernels
+// (one independent vector per right-hand side: basis V_k[:, l] at Vb + k*n*nrhs + l*n)
+namespace {
+
+// partial[(chunk * nrhs + l) * kk + k] = sum_{i in chunk} conj(V_k[i, l]) w[i, l]
+__global__ void __launch_bounds__(256) k_bdot_partial(int64_t n, int nrhs, int kk, const zd* __restrict__ Vb,
+                                                      const zd* __restrict__ w, zd* __restrict__ partial) {
+    __shared__ double sr[4], si[4];
+    const int l = blockIdx.y;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const zd wv = i < n ? w[i + (int64_t)l * n] : zd{0, 0};
+    for (int k = 0; k < kk; ++k) {
+        double r = 0, im = 0;
+        if (i < n) {
+            const zd v = Vb[(int64_t)k * n * nrhs + (int64_t)l * n + i];
+            r = v.re * wv.re + v.im * wv.im;
+            im = v.re * wv.im - v.im * wv.re;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            r += __shfl_xor(r, off);
+            im += __shfl_xor(im, off);
+        }
+        if ((threadIdx.x & 63) == 0) { sr[threadIdx.x >> 6] = r; si[threadIdx.x >> 6] = im; }
+        __syncthreads();
+        if (threadIdx.x == 0)
+            partial[((size_t)blockIdx.x * nrhs + l) * kk + k] = {((sr[0] + sr[1]) + sr[2]) + sr[3],
+                                                                 ((si[0] + si[1]) + si[2]) + si[3]};
+        __syncthreads();
+    }
+}
+
+__global__ void k_bdot_reduce(int nchunk, int nrhs, int kk, const zd* __restrict__ partial, zd* __restrict__ out) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;   // e = l * kk + k
+    if (e >= nrhs * kk) return;
+    double r = 0, im = 0;
+    for (int c = 0; c < nchunk; ++c) {
+        const zd v = partial[(size_t)c * nrhs * kk + e];
+        r += v.re;
+        im += v.im;
+    }
+    out[e] = {r, im};
+}
+
+// w[i, l] += sign * sum_k V_k[i, l] h[l * kk + k]
+__global__ void k_baxpy(int64_t n, int nrhs, int kk, const zd* __restrict__ Vb, const zd* __restrict__ h, double sign,
+                        zd* __restrict__ w) {
+    const int l = blockIdx.y;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    double ar = 0, ai = 0;
+    for (int k = 0; k < kk; ++k) {
+        const zd v = Vb[(int64_t)k * n * nrhs + (int64_t)l * n + i], c = h[l * kk + k];
+        ar += v.re * c.re - v.im * c.im;
+        ai += v.re * c.im + v.im * c.re;
+    }
+    zd& d = w[i + (int64_t)l * n];
+    d.re += sign * ar;
+    d.im += sign * ai;
+}
+
+__global__ void k_bscale_into(int64_t n, int nrhs, const zd* __restrict__ src, const double* __restrict__ inv,
+                              zd* __restrict__ dst) {
+    const int l = blockIdx.y;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const zd v = src[i + (int64_t)l * n];
+    dst[i + (int64_t)l * n] = {v.re * inv[l], v.im * inv[l]};
+}
+
+}  // namespace
+
+struct BatchCols {
+    int64_t n;
+    int nrhs;
+    DevBuf<zd> partial, dots;
+    std::vector<zd> hd;
+    void dot(const zd* Vb, int kk, const zd* w, hipStream_t s, std::vector<zd>& out) {
+        const int nchunk = (int)((n + 255) / 256);
+        partial.reserve((size_t)nchunk * nrhs * kk);
+        dots.reserve((size_t)nrhs * kk);
+        hipLaunchKernelGGL(k_bdot_partial, dim3(nchunk, nrhs), dim3(256), 0, s, n, nrhs, kk, Vb, w, partial.p);
+        hipLaunchKernelGGL(k_bdot_reduce, dim3((nrhs * kk + 255) / 256), dim3(256), 0, s, nchunk, nrhs, kk, partial.p,
+                           dots.p);
+        out.resize((size_t)nrhs * kk);
+        CR_HIP(hipMemcpyAsync(out.data(), dots.p, out.size() * sizeof(zd), hipMemcpyDeviceToHost, s));
+        CR_HIP(hipStreamSynchronize(s));
+    }
+    void axpy(const zd* Vb, int kk, const std::vector<zd>& h, double sign, zd* w, hipStream_t s) {
+        dots.reserve((size_t)nrhs * kk);
+        CR_HIP(hipMemcpyAsync(dots.p, h.data(), (size_t)nrhs * kk * sizeof(zd), hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_baxpy, dim3((unsigned)((n + 255) / 256), nrhs), dim3(256), 0, s, n, nrhs, kk, Vb, dots.p,
+                           sign, w);
+        CR_HIP(hipStreamSynchronize(s));
+    }
+};
+
+// One GMRES(m) cycle on the left-preconditioned system (LU)^{-1} A~ d = (LU)^{-1} r, every
+// right-hand side with its own Krylov basis (FP64 vectors, CGS2, Givens rotations on the host);
+// X += d. Returns the number of preconditioned operator applications.
+static int gmres_cycle(Factor& f, int nrhs, const zd* R, zd* X, int m, double rtol, SolveWork& w, hipStream_t s) {
+    cr_sys sys = f.sys;
+    const int64_t n = sys->n;
+    const double sigma = f.omega * f.omega;
+    const size_t blk = (size_t)n * nrhs;
+    w.kry.reserve(blk * (m + 1));
+    w.d.reserve(blk);
+    zd* Vb = w.kry.p;
+    zd* tmp = w.d.p;
+    BatchCols bc{n, nrhs};
+    DevBuf<double> inv(nrhs);
+    std::vector<double> hinv(nrhs);
+    // v0 = z / ||z||, z = LU^{-1} r
+    apply_factor(f, nrhs, R, n, tmp, n, 0, w, s);
+    std::vector<zd> dd;
+    bc.dot(tmp, 1, tmp, s, dd);   // ||z_l||^2 (Vb slot 0 used as a one-vector basis: tmp)
+    std::vector<double> beta(nrhs);
+    for (int l = 0; l < nrhs; ++l) {
+        beta[l] = std::sqrt(std::max(dd[l].re, 0.0));
+        hinv[l] = beta[l] > 0 ? 1.0 / beta[l] : 0.0;
+    }
+    CR_HIP(hipMemcpyAsync(inv.p, hinv.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_bscale_into, dim3((unsigned)((n + 255) / 256), nrhs), dim3(256), 0, s, n, nrhs, tmp, inv.p, Vb);
+    // Hessenberg columns and Givens rotations per right-hand side
+    std::vector<std::vector<std::complex<double>>> H(nrhs, std::vector<std::complex<double>>((size_t)(m + 1) * m));
+    std::vector<std::vector<std::complex<double>>> g(nrhs, std::vector<std::complex<double>>(m + 1));
+    std::vector<std::vector<double>> cs(nrhs, std::vector<double>(m));
+    std::vector<std::vector<std::complex<double>>> sn(nrhs, std::vector<std::complex<double>>(m));
+    for (int l = 0; l < nrhs; ++l) g[l][0] = beta[l];
+    std::vector<char> done(nrhs, 0);
+    for (int l = 0; l < nrhs; ++l) done[l] = beta[l] == 0;
+    int j = 0, applications = 1;
+    for (; j < m; ++j) {
+        bool all = true;
+        for (int l = 0; l < nrhs; ++l) all = all && done[l];
+        if (all) break;
+        zd* vj = Vb + blk * j;
+        zd* vn = Vb + blk * (j + 1);
+        spmm_shifted(sys, sigma, nrhs, vj, n, w.r.p, n, s);          // A v_j (FP64)
+        apply_factor(f, nrhs, w.r.p, n, vn, n, 0, w, s);            // (LU)^{-1} A v_j
+        ++applications;
+        std::vector<zd> h1, h2;
+        bc.dot(Vb, j + 1, vn, s, h1);
+        bc.axpy(Vb, j + 1, h1, -1.0, vn, s);
+        bc.dot(Vb, j + 1, vn, s, h2);
+        bc.axpy(Vb, j + 1, h2, -1.0, vn, s);
+        bc.dot(vn, 1, vn, s, dd);
+        for (int l = 0; l < nrhs; ++l) {
+            const double hn = std::sqrt(std::max(dd[l].re, 0.0));
+            hinv[l] = (hn > 0 && !done[l]) ? 1.0 / hn : 0.0;
+            auto& Hl = H[l];
+            for (int k = 0; k <= j; ++k)
+                Hl[k + (size_t)j * (m + 1)] = {h1[l * (j + 1) + k].re + h2[l * (j + 1) + k].re,
+                                               h1[l * (j + 1) + k].im + h2[l * (j + 1) + k].im};
+            Hl[j + 1 + (size_t)j * (m + 1)] = hn;
+            // apply previous rotations, then a new one zeroing H[j+1, j]
+            for (int k = 0; k < j; ++k) {
+                const std::complex<double> a = Hl[k + (size_t)j * (m + 1)], b = Hl[k + 1 + (size_t)j * (m + 1)];
+                Hl[k + (size_t)j * (m + 1)] = cs[l][k] * a + sn[l][k] * b;
+                Hl[k + 1 + (size_t)j * (m + 1)] = -std::conj(sn[l][k]) * a + cs[l][k] * b;
+            }
+            const std::complex<double> a = Hl[j + (size_t)j * (m + 1)];
+            const double bb = hn;
+            const double r = std::sqrt(std::norm(a) + bb * bb);
+            if (r > 0) {
+                cs[l][j] = std::abs(a) / r;
+                const std::complex<double> ph = std::abs(a) > 0 ? a / std::abs(a) : std::complex<double>(1.0, 0.0);
+                sn[l][j] = ph * bb / r;
+                Hl[j + (size_t)j * (m + 1)] = ph * r;
+            } else {
+                cs[l][j] = 1.0;
+                sn[l][j] = 0.0;
+            }
+            Hl[j + 1 + (size_t)j * (m + 1)] = 0.0;
+            g[l][j + 1] = -std::conj(sn[l][j]) * g[l][j];
+            g[l][j] = cs[l][j] * g[l][j];
+            if (!done[l] && (std::abs(g[l][j + 1]) <= rtol * beta[l] || hn == 0)) done[l] = 2;
+        }
+        CR_HIP(hipMemcpyAsync(inv.p, hinv.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_bscale_into, dim3((unsigned)((n + 255) / 256), nrhs), dim3(256), 0, s, n, nrhs, vn, inv.p, vn);
+    }
+    // y = H^{-1} g per right-hand side (back substitution over the columns each one used), X += V y
+    const int kk = j;
+    if (kk > 0) {
+        std::vector<zd> y((size_t)nrhs * kk, zd{0, 0});
+        for (int l = 0; l < nrhs; ++l) {
+            if (beta[l] == 0) continue;
+            std::vector<std::complex<double>> yl(kk);
+            for (int k = kk - 1; k >= 0; --k) {
+                std::complex<double> acc = g[l][k];
+                for (int c = k + 1; c < kk; ++c) acc -= H[l][k + (size_t)c * (m + 1)] * yl[c];
+                const std::complex<double> dgl = H[l][k + (size_t)k * (m + 1)];
+                yl[k] = std::abs(dgl) > 0 ? acc / dgl : 0.0;
+            }
+            for (int k = 0; k < kk; ++k) y[(size_t)l * kk + k] = {yl[k].real(), yl[k].imag()};
+        }
+        bc.axpy(Vb, kk, y, 1.0, X, s);
+    }
+    return applications;
+}
+
+// Solve A~ X = B with the stored factor: X = (LU)^{-1} B, then FP64 refinement. Classic
+// corrections X += (LU)^{-1}(B - A~ X) while they at least halve the normwise backward error
+// max_l ||r_l|| / (||A~|| ||x_l|| + ||b_l||); when one does not, GMRES-refinement cycles take
+// over (the low-precision factor as preconditioner of an FP64 GMRES on the correction
+// equation). Stops at tol or after max_iter refinement steps.
+int solve_scaled(Factor& f, int nrhs, const zd* B, zd* X, int max_iter, double tol, double* berr, SolveWork& w,
+                 hipStream_t s, bool strict) {
+    cr_sys sys = f.sys;
+    const int64_t n = sys->n;
+    const double sigma = f.omega * f.omega;
+    if (f.anorm_sigma != sigma) {
+        f.anorm = shifted_norm_inf(sys, sigma, w.sc, s);
+        f.anorm_sigma = sigma;
+    }
+    const double anorm = f.anorm;
+    w.r.reserve((size_t)n * nrhs);
+    w.res.reserve((size_t)n * nrhs);
+    w.red.reserve(3 * (size_t)nrhs);
+    w.hred.resize(3 * (size_t)nrhs);
+    unsigned long long* nrm = reinterpret_cast<unsigned long long*>(w.red.p);
+    apply_factor(f, nrhs, B, n, X, n, 0, w, s);
+    int it = 0;
+    double prev = 1e300, be = 1e300;
+    bool krylov = false;
+    for (;;) {
+        spmm_residual(sys, sigma, nrhs, X, n, B, n, w.res.p, n, s);
+        fill_zero(nrm, 3 * nrhs, s);
+        hipLaunchKernelGGL(k_colmax3, dim3(64, nrhs), dim3(256), 0, s, n, nrhs, w.res.p, X, B, n, nrm);
+        CR_HIP(hipMemcpyAsync(w.hred.data(), nrm, 3 * nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+        CR_HIP(hipStreamSynchronize(s));
+        be = 0;
+        for (int l = 0; l < nrhs; ++l) {
+            const double rn = w.hred[3 * l], xn = w.hred[3 * l + 1], bn = w.hred[3 * l + 2];
+            const double den = anorm * xn + bn;
+            be = std::max(be, den > 0 ? rn / den : 0.0);
+        }
+        if (be <= tol || it >= max_iter) break;
+        if (!krylov && !(be < 0.5 * prev)) krylov = true;
+        if (krylov && f.prec == CR_FP64 && !(be < 0.5 * prev)) break;   // FP64 factor: nothing left to gain
+        prev = be;
+        if (!krylov) {
+            apply_factor(f, nrhs, w.res.p, n, X, n, 1, w, s);
+        } else {
+            gmres_cycle(f, nrhs, w.res.p, X, 30, 1e-6, w, s);
+        }
+        ++it;
+    }
+    *berr = be;
+    if (strict && !(be <= tol))
+        throw Error(CR_E_NOT_CONVERGED, "iterative refinement stopped at backward error " + std::to_string(be));
+    return it;
+}
+
+// ------------------------------------------------------------------ Gram / update (CGS2)
+namespace {
+
+constexpr int kGramRows = 256;   // rows per workgroup chunk
+constexpr int kGramB = 16;       // max columns of the staged operand
+
+// partial[chunk][k][c] = sum_{i in chunk} conj(A[i,k]) B[i,c],  k < qa, c < b (b <= 16)
+__global__ void __launch_bounds__(256) k_gram_partial(int64_t n, int qa, int b, const zd* __restrict__ A, int64_t lda,
+                                                      const zd* __restrict__ Bm, int64_t ldb, zd* __restrict__ partial) {
+    __shared__ zd sb[kGramRows][kGramB];
+    const int64_t i0 = (int64_t)blockIdx.x * kGramRows;
+    const int rows = (int)std::min<int64_t>(kGramRows, n - i0);
+    for (int e = threadIdx.x; e < kGramRows * kGramB; e += 256) {
+        const int r = e % kGramRows, c = e / kGramRows;
+        sb[r][c] = (r < rows && c < b) ? Bm[i0 + r + c * ldb] : zd{0, 0};
+    }
+    __syncthreads();
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    zd* out = partial + (size_t)blockIdx.x * qa * b;
+    for (int k = wave; k < qa; k += 4) {
+        double ar[kGramB], ai[kGramB];
+#pragma unroll
+        for (int c = 0; c < kGramB; ++c) ar[c] = ai[c] = 0;
+        for (int r = lane; r < rows; r += 64) {
+            const zd a = A[i0 + r + k * lda];
+#pragma unroll
+            for (int c = 0; c < kGramB; ++c) {
+                const zd v = sb[r][c];
+                ar[c] += a.re * v.re + a.im * v.im;   // conj(a) * v
+                ai[c] += a.re * v.im - a.im * v.re;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < kGramB; ++c)
+            for (int off = 32; off > 0; off >>= 1) {
+                ar[c] += __shfl_xor(ar[c], off);
+                ai[c] += __shfl_xor(ai[c], off);
+            }
+        if (lane == 0)
+            for (int c = 0; c < b; ++c) out[k + (size_t)c * qa] = {ar[c], ai[c]};
+    }
+}
+
+// H[k + c*ldh] = sum over chunks (fixed order); conj_t: store conj into H[c + k*ldh] instead
+__global__ void k_gram_reduce(int nchunk, int qa, int b, const zd* __restrict__ partial, zd* __restrict__ H, int64_t ldh,
+                              int conj_t) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= qa * b) return;
+    const int k = e % qa, c = e / qa;
+    double r = 0, i = 0;
+    for (int ch = 0; ch < nchunk; ++ch) {
+        const zd v = partial[(size_t)ch * qa * b + k + (size_t)c * qa];
+        r += v.re;
+        i += v.im;
+    }
+    if (conj_t) H[c + (size_t)k * ldh] = {r, -i};
+    else H[k + (size_t)c * ldh] = {r, i};
+}
+
+// W[:, c] -= V[:, 0:q] H[0:q, c] for c < b (b <= 16); H staged through LDS in chunks of 64 rows
+__global__ void __launch_bounds__(256) k_update(int64_t n, int q, int b, const zd* __restrict__ V, int64_t ldv,
+                                                const zd* __restrict__ H, int64_t ldh, zd* __restrict__ W, int64_t ldw) {
+    __shared__ zd sh[64][kGramB];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double ar[kGramB], ai[kGramB];
+#pragma unroll
+    for (int c = 0; c < kGramB; ++c) ar[c] = ai[c] = 0;
+    for (int k0 = 0; k0 < q; k0 += 64) {
+        const int kn = min(64, q - k0);
+        __syncthreads();
+        for (int e = threadIdx.x; e < 64 * kGramB; e += 256) {
+            const int r = e % 64, c = e / 64;
+            sh[r][c] = (r < kn && c < b) ? H[k0 + r + (size_t)c * ldh] : zd{0, 0};
+        }
+        __syncthreads();
+        if (i < n) {
+            for (int r = 0; r < kn; ++r) {
+                const zd v = V[i + (int64_t)(k0 + r) * ldv];
+#pragma unroll
+                for (int c = 0; c < kGramB; ++c) {
+                    const zd h = sh[r][c];
+                    ar[c] += v.re * h.re - v.im * h.im;
+                    ai[c] += v.re * h.im + v.im * h.re;
+                }
+            }
+        }
+    }
+    if (i < n)
+        for (int c = 0; c < b; ++c) {
+            zd& w = W[i + (int64_t)c * ldw];
+            w.re -= ar[c];
+            w.im -= ai[c];
+        }
+}
+
+__global__ void k_gather_recv(int n_o, int q, const int64_t* __restrict__ recv, const double* __restrict__ scale,
+                              const zd* __restrict__ V, int64_t ldv, zd* __restrict__ CR) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_o * q) return;
+    const int o = e % n_o, k = e / n_o;
+    const int64_t r = recv[o];
+    const zd v = V[r + (int64_t)k * ldv];
+    CR[o + (size_t)k * n_o] = {scale[r] * v.re, scale[r] * v.im};
+}
+
+__global__ void k_scale_cols(int64_t n, int b, zd* __restrict__ W, int64_t ldw, const double* __restrict__ inv) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * b) return;
+    const int64_t i = e % n;
+    const int c = (int)(e / n);
+    W[i + c * ldw].re *= inv[c];
+    W[i + c * ldw].im *= inv[c];
+}
+
+}  // namespace
+
+// H (qa x b, ld ldh) = A^H B, A n x qa, B n x b; conj_t stores H^H (b x qa) instead.
+void gram(int64_t n, int qa, int b, const zd* A, int64_t lda, const zd* B, int64_t ldb, zd* H, int64_t ldh, int conj_t,
+          DevBuf<zd>& partial, hipStream_t s) {
+    if (qa <= 0 || b <= 0) return;
+    const int nchunk = (int)((n + kGramRows - 1) / kGramRows);
+    for (int c0 = 0; c0 < b; c0 += kGramB) {
+        const int bc = std::min(kGramB, b - c0);
+        partial.reserve((size_t)nchunk * qa * bc);
+        hipLaunchKernelGGL(k_gram_partial, dim3(nchunk), dim3(256), 0, s, n, qa, bc, A, lda, B + (int64_t)c0 * ldb, ldb,
+                           partial.p);
+        zd* Hc = conj_t ? H + c0 : H + (int64_t)c0 * ldh;
+        hipLaunchKernelGGL(k_gram_reduce, dim3((qa * bc + 255) / 256), dim3(256), 0, s, nchunk, qa, bc, partial.p, Hc, ldh,
+                           conj_t);
+    }
+}
+
+void update(int64_t n, int q, int b, const zd* V, int64_t ldv, const zd* H, int64_t ldh, zd* W, int64_t ldw, hipStream_t s) {
+    if (q <= 0 || b <= 0) return;
+    for (int c0 = 0; c0 < b; c0 += kGramB) {
+        const int bc = std::min(kGramB, b - c0);
+        hipLaunchKernelGGL(k_update, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, q, bc, V, ldv,
+                           H + (int64_t)c0 * ldh, ldh, W + (int64_t)c0 * ldw, ldw);
+    }
+}
+
+void gather_recv(cr_sys sys, int q, const zd* V, int64_t ldv, zd* CR, hipStream_t s) {
+    if (sys->n_o == 0 || q == 0) return;
+    hipLaunchKernelGGL(k_gather_recv, dim3((sys->n_o * q + 255) / 256), dim3(256), 0, s, sys->n_o, q, sys->d_recv.p,
+                       sys->d_scale.p, V, ldv, CR);
+}
+
+void scale_cols(int64_t n, int b, zd* W, int64_t ldw, const double* inv_dev, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale_cols, dim3((unsigned)((n * b + 255) / 256)), dim3(256), 0, s, n, b, W, ldw, inv_dev);
+}
+
+void copy_dev(int64_t n, const zd* src, zd* dst, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_axpy_copy, dim3(1024), dim3(256), 0, s, n, src, dst);
+}
+
+namespace {
+__global__ void k_copy_scaled(int64_t n, const zd* __restrict__ src, zd* __restrict__ dst, double f) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = {src[i].re * f, src[i].im * f};
+}
+__global__ void k_copy_2d(int rows, int cols, const zd* __restrict__ src, int64_t lds, zd* __restrict__ dst, int64_t ldd) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)rows * cols) return;
+    const int64_t r = e % rows, c = e / rows;
+    dst[r + c * ldd] = src[r + c * lds];
+}
+__global__ void k_scale_rows(int64_t n, int nrhs, const zd* __restrict__ src, const double* __restrict__ sc,
+                             zd* __restrict__ dst) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * nrhs) return;
+    const double f = sc[e % n];
+    dst[e] = {src[e].re * f, src[e].im * f};
+}
+}  // namespace
+
+void copy_cols_scaled(int64_t n, const zd* src, zd* dst, double factor, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy_scaled, dim3((unsigned)std::min<int64_t>(1024, (n + 255) / 256)), dim3(256), 0, s, n, src,
+                       dst, factor);
+}
+void copy_2d(int rows, int cols, const zd* src, int64_t lds, zd* dst, int64_t ldd, hipStream_t s) {
+    const int64_t tot = (int64_t)rows * cols;
+    if (tot <= 0) return;
+    hipLaunchKernelGGL(k_copy_2d, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, rows, cols, src, lds, dst, ldd);
+}
+void scale_rows(int64_t n, int nrhs, const zd* src, const double* sc, zd* dst, hipStream_t s) {
+    const int64_t tot = n * nrhs;
+    if (tot <= 0) return;
+    hipLaunchKernelGGL(k_scale_rows, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, nrhs, src, sc, dst);
+}
+
+// ------------------------------------------------------------------ candidate residuals
+namespace {
+
+constexpr int kCandChunk = 8;
+
+// partial[chunk][c] = sum_i sum_l | s_cl F[i,l] - sum_k (KV[i,k] - w_c^2 MV[i,k]) X[k, l, c] |^2
+// X: q x L x ncand (ld q, then L); scal[c*L + l] = (i w_c)^flag
+__global__ void __launch_bounds__(256) k_resid_partial(int64_t n, int q, int L, int ncand, const zd* __restrict__ KV,
+                                                       const zd* __restrict__ MV, int64_t ldv, const zd* __restrict__ F,
+                                                       const zd* __restrict__ X, const zd* __restrict__ scal,
+                                                       const double* __restrict__ w2, double* __restrict__ partial) {
+    extern __shared__ zd sx[];   // q x L x kCandChunk
+    const int c0 = blockIdx.y * kCandChunk;
+    const int nc = min(kCandChunk, ncand - c0);
+    for (int e = threadIdx.x; e < q * L * nc; e += 256) sx[e] = X[(size_t)c0 * q * L + e];
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double acc2[kCandChunk];
+#pragma unroll
+    for (int c = 0; c < kCandChunk; ++c) acc2[c] = 0;
+    if (i < n) {
+        for (int l = 0; l < L; ++l) {
+            double rr[kCandChunk], ri[kCandChunk];
+            const zd f = F[i + (int64_t)l * n];
+#pragma unroll
+            for (int c = 0; c < kCandChunk; ++c) {
+                if (c < nc) {
+                    const zd sc = scal[(c0 + c) * L + l];
+                    rr[c] = f.re * sc.re - f.im * sc.im;
+                    ri[c] = f.re * sc.im + f.im * sc.re;
+                } else rr[c] = ri[c] = 0;
+            }
+            for (int k = 0; k < q; ++k) {
+                const zd kv = KV[i + (int64_t)k * ldv], mv = MV[i + (int64_t)k * ldv];
+#pragma unroll
+                for (int c = 0; c < kCandChunk; ++c) {
+                    if (c >= nc) break;
+                    const double a_r = kv.re - w2[c0 + c] * mv.re, a_i = kv.im - w2[c0 + c] * mv.im;
+                    const zd x = sx[(size_t)c * q * L + (size_t)l * q + k];
+                    rr[c] -= a_r * x.re - a_i * x.im;
+                    ri[c] -= a_r * x.im + a_i * x.re;
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < kCandChunk; ++c) acc2[c] += rr[c] * rr[c] + ri[c] * ri[c];
+        }
+    }
+    __shared__ double red[4][kCandChunk];
+#pragma unroll
+    for (int c = 0; c < kCandChunk; ++c) {
+        double v = acc2[c];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x / 64][c] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < nc) {
+        const int c = threadIdx.x;
+        partial[(size_t)blockIdx.x * ncand + c0 + c] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+    }
+}
+
+__global__ void k_resid_reduce(int nchunk, int ncand, const double* __restrict__ partial, double* __restrict__ out) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncand) return;
+    double s = 0;
+    for (int k = 0; k < nchunk; ++k) s += partial[(size_t)k * ncand + c];
+    out[c] = s;
+}
+
+}  // namespace
+
+// res2[c] = || scal_c .* F - (KV - w_c^2 MV) X_c ||_F^2 for every candidate
+void candidate_residuals(int64_t n, int q, int L, int ncand, const zd* KV, const zd* MV, int64_t ldv, const zd* F,
+                         const zd* X, const zd* scal, const double* w2, double* res2, DevBuf<double>& partial,
+                         hipStream_t s) {
+    const int nchunk = (int)((n + 255) / 256);
+    partial.reserve((size_t)nchunk * ncand);
+    const size_t shmem = (size_t)q * L * kCandChunk * sizeof(zd);
+    CR_REQUIRE(shmem <= 64 * 1024, CR_E_UNSUPPORTED, "candidate residual: q * L too large for one LDS stage");
+    hipLaunchKernelGGL(k_resid_partial, dim3(nchunk, (ncand + kCandChunk - 1) / kCandChunk), dim3(256), shmem, s, n, q, L,
+                       ncand, KV, MV, ldv, F, X, scal, w2, partial.p);
+    hipLaunchKernelGGL(k_resid_reduce, dim3((ncand + 255) / 256), dim3(256), 0, s, nchunk, ncand, partial.p, res2);
+}
+
+}  // namespace cr

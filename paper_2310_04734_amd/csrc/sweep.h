@@ -1,0 +1,36 @@
+// Reduced-sweep engine shared by cr_sweep, cr_sweep_batched and the greedy's candidate solves.
+#pragma once
+
+#include <vector>
+
+#include "internal.h"
+
+namespace cr {
+
+// One reduced model as seen by the sweep kernel (all pointers device, FP64, column-major).
+struct RomDesc {
+    const zd* KR;
+    const zd* MR;
+    const zd* DR;          // may be null (D_R = 0)
+    const zd* FR;          // q x L
+    const zd* CR;          // n_o x q
+    const int32_t* flags;  // L
+    const double* omegas;  // frequencies of this model
+    zd* out;               // Y: nfreq x L x n_o, or X: nfreq x q x L when out_x
+    int q, L, n_o, out_x;
+};
+
+struct SweepEngine {
+    int num_cu = 256;
+    DevBuf<RomDesc> d_roms;
+    DevBuf<int2> d_items;
+    DevBuf<int> d_stats;
+    DevBuf<zd> wsA, wsX, wsR, wsB, wsD;
+    DevBuf<int> wsP;
+    DevBuf<double> d_omega;   // frequencies of the current call
+    // items: (model index, frequency index), processed in the given order by a work queue
+    void run(const std::vector<RomDesc>& roms, const std::vector<int2>& items, cr_precision prec, bool refine,
+             hipStream_t s, int* max_its, int* not_conv, int* perturbed, int grid_override = 0, int* fallbacks = nullptr);
+};
+
+}  // namespace cr
