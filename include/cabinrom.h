@@ -78,6 +78,14 @@ const char* cr_last_error(cr_ctx ctx);
 /* Message of the last failed cr_ctx_create in this process. */
 const char* cr_create_error(void);
 
+/* Kernel timing: when enabled, every launch of the library's hot kernels on ctx is bracketed
+   by HIP events on the context stream. cr_profile_enable clears the records. cr_profile_read
+   synchronises the stream and aggregates by kernel name: up to max entries, names as
+   NUL-terminated strings of at most 31 characters in names[32 * i]; counts[i] launches;
+   total_ms[i] summed event durations; *n receives the number of distinct names. */
+cr_status cr_profile_enable(cr_ctx ctx, int32_t on);
+cr_status cr_profile_read(cr_ctx ctx, int32_t max, char* names, int32_t* counts, double* total_ms, int32_t* n);
+
 /* ---------------------------------------------------------------- assembly (Section 2) --- */
 
 enum { CR_FLUID = 0, CR_SOLID = 1 };
@@ -177,6 +185,8 @@ typedef struct {
     int32_t ir_iterations;     /* total refinement corrections over all solves             */
     double max_backward_error; /* over all shifted solves                                  */
     int32_t n_perturbed;
+    int32_t fp64_refactorizations; /* CR_MIXED expansion points refactored in complex FP64
+                                      because FP64 refinement of the FP32 factor stalled   */
     double seconds;
 } cr_basis_info;
 

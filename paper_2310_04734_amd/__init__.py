@@ -86,7 +86,8 @@ class cr_solve_info(C.Structure):
 
 class cr_basis_info(C.Structure):
     _fields_ = [("q", C.c_int32), ("deflated", C.c_int32), ("n_shifts", C.c_int32), ("ir_iterations", C.c_int32),
-                ("max_backward_error", C.c_double), ("n_perturbed", C.c_int32), ("seconds", C.c_double)]
+                ("max_backward_error", C.c_double), ("n_perturbed", C.c_int32),
+                ("fp64_refactorizations", C.c_int32), ("seconds", C.c_double)]
 
 
 class cr_greedy_opts(C.Structure):
@@ -151,6 +152,8 @@ _sig("cr_mlp_gradients", I32, P, I32, P, P, P, P, C.POINTER(C.c_float))
 _sig("cr_mlp_num_params", I32, P, C.POINTER(I64))
 _sig("cr_mlp_get_params", I32, P, P)
 _sig("cr_mlp_set_params", I32, P, P)
+_sig("cr_profile_enable", I32, P, I32)
+_sig("cr_profile_read", I32, P, I32, P, P, P, C.POINTER(I32))
 
 
 def _ptr(a):
@@ -180,6 +183,25 @@ class Context:
     def check(self, st):
         if st != 0:
             raise CabinRomError(st, lib.cr_last_error(self.h).decode())
+
+    def profile(self, on: bool):
+        """Start (clearing earlier records) or stop event timing of the library's kernels."""
+        self.check(lib.cr_profile_enable(self.h, int(on)))
+
+    def profile_read(self):
+        """{kernel name: (launches, total ms)} over the launches since profile(True)."""
+        mx = 64
+        names = C.create_string_buffer(32 * mx)
+        counts = np.zeros(mx, np.int32)
+        tot = np.zeros(mx, np.float64)
+        n = I32()
+        self.check(lib.cr_profile_read(self.h, mx, names, _ptr(counts), _ptr(tot), C.byref(n)))
+        raw = names.raw
+        out = {}
+        for i in range(min(n.value, mx)):
+            nm = raw[32 * i:32 * i + 32].split(b"\0", 1)[0].decode()
+            out[nm] = (int(counts[i]), float(tot[i]))
+        return out
 
     def close(self):
         if self.h:

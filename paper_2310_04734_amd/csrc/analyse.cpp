@@ -268,6 +268,41 @@ std::unique_ptr<Symbolic> analyse_pattern(int64_t n, const std::vector<int64_t>&
             S.ent_dst[k] = local(f, i) + local(f, j) * S.fsize[f];
         }
     S.piv_off.assign(S.first.begin(), S.first.end());
+    // large fronts: panel steps of kPanel columns, update tiles of kUpd x kUpd
+    constexpr int kBigFront = 192, kPanel = 16, kUpd = 64;
+    S.big.assign(nf, 0);
+    S.big_off.assign(S.nlevel + 1, 0);
+    S.nsteps.assign(S.nlevel, 0);
+    S.step_off.assign(S.nlevel + 1, 0);
+    S.tile_off.clear();
+    S.tiles.clear();
+    for (int l = 0; l < S.nlevel; ++l) {
+        int steps = 0;
+        for (int q = S.level_off[l]; q < S.level_off[l + 1]; ++q) {
+            const int f = S.level_fronts[q];
+            if (S.fsize[f] >= kBigFront && S.npiv[f] > 0) {
+                S.big[f] = 1;
+                S.big_list.push_back(f);
+                steps = std::max(steps, (S.npiv[f] + kPanel - 1) / kPanel);
+            }
+        }
+        S.big_off[l + 1] = (int32_t)S.big_list.size();
+        S.nsteps[l] = steps;
+        S.step_off[l] = (int64_t)S.tile_off.size();
+        for (int j = 0; j < steps; ++j) {
+            S.tile_off.push_back((int64_t)S.tiles.size());
+            for (int q = S.big_off[l]; q < S.big_off[l + 1]; ++q) {
+                const int f = S.big_list[q];
+                const int m = S.fsize[f], p = S.npiv[f], k0 = j * kPanel;
+                if (k0 >= p) continue;
+                const int k1 = std::min(k0 + kPanel, p);
+                for (int j0 = k1; j0 < m; j0 += kUpd)
+                    for (int i0 = k1; i0 < m; i0 += kUpd) S.tiles.push_back(make_int4(f, i0, j0, k0));
+            }
+        }
+        S.tile_off.push_back((int64_t)S.tiles.size());
+    }
+    S.step_off[S.nlevel] = (int64_t)S.tile_off.size();
     S.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return sym;
 }

@@ -50,6 +50,7 @@ struct cr_basis_s {
     int ir_iterations = 0;
     double max_berr = 0;
     int n_perturbed = 0;
+    int fp64_refactorizations = 0;
     // scratch
     DevBuf<zd> W, H, partial, RHS;
     std::vector<zd> hH;
@@ -63,6 +64,7 @@ SweepEngine& engine(cr_ctx ctx) {
     if (!ctx->sweep) {
         ctx->sweep = new SweepEngine();
         ctx->sweep->num_cu = ctx->num_cu;
+        ctx->sweep->ctx = ctx;
     }
     return *ctx->sweep;
 }
@@ -183,7 +185,16 @@ void add_shift(cr_basis B, Factor& fac, SolveWork& sw, double omega, int blocks,
     for (int blk = 0; blk < blocks && b > 0; ++blk) {
         if (blk > 0) spmm_m(sys, b, B->V.p + n * (B->q - b), n, B->RHS.p, n, s);
         double berr = 0;
-        const int its = solve_scaled(fac, b, B->RHS.p, B->W.p, 10, 1e-14, &berr, sw, s, false);
+        int its = solve_scaled(fac, b, B->RHS.p, B->W.p, 10, 1e-14, &berr, sw, s, false, fac.prec == CR_FP64);
+        if (!(berr <= 1e-14) && fac.prec == CR_MIXED) {
+            // classic refinement of the complex-FP32 factor stalled (kappa(A_j) u_32 >~ 1): this
+            // expansion point is refactored in complex FP64 once, which is cheaper than a Krylov
+            // refinement of every one of its solves
+            numeric_factor(fac, sys, omega, CR_FP64, s);
+            B->n_perturbed += fac.n_perturbed;
+            B->fp64_refactorizations++;
+            its += solve_scaled(fac, b, B->RHS.p, B->W.p, 10, 1e-14, &berr, sw, s, false);
+        }
         B->ir_iterations += its;
         B->max_berr = std::max(B->max_berr, berr);
         b = orthonormalise_append(B, B->W.p, b);
@@ -198,6 +209,7 @@ void fill_info(cr_basis B, cr_basis_info* info, double t0) {
     info->ir_iterations = B->ir_iterations;
     info->max_backward_error = B->max_berr;
     info->n_perturbed = B->n_perturbed;
+    info->fp64_refactorizations = B->fp64_refactorizations;
     info->seconds = now() - t0;
 }
 
@@ -692,3 +704,42 @@ cr_status cr_sweep_batched(cr_ctx ctx, int32_t nrom, const cr_rom* roms, int32_t
 }
 
 }  // extern "C"
+
+extern "C" cr_status cr_profile_enable(cr_ctx ctx, int32_t on) {
+    if (!ctx) return CR_E_INVALID;
+    return cr_guard(ctx, [&] {
+        CR_HIP(hipStreamSynchronize(ctx->stream));
+        ctx->prof.clear();
+        ctx->prof.on = on != 0;
+    });
+}
+
+extern "C" cr_status cr_profile_read(cr_ctx ctx, int32_t max, char* names, int32_t* counts, double* total_ms, int32_t* n) {
+    if (!ctx) return CR_E_INVALID;
+    return cr_guard(ctx, [&] {
+        CR_REQUIRE(max >= 0 && n && (max == 0 || (names && counts && total_ms)), CR_E_INVALID, "cr_profile_read: bad arguments");
+        CR_HIP(hipStreamSynchronize(ctx->stream));
+        std::vector<std::string> keys;
+        std::vector<int> cnt;
+        std::vector<double> tot;
+        for (const auto& r : ctx->prof.recs) {
+            float ms = 0;
+            CR_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+            size_t k = std::find(keys.begin(), keys.end(), std::string(r.name)) - keys.begin();
+            if (k == keys.size()) {
+                keys.push_back(r.name);
+                cnt.push_back(0);
+                tot.push_back(0.0);
+            }
+            cnt[k]++;
+            tot[k] += ms;
+        }
+        *n = (int32_t)keys.size();
+        for (int i = 0; i < (int)keys.size() && i < max; ++i) {
+            std::strncpy(names + 32 * i, keys[i].c_str(), 31);
+            names[32 * i + 31] = 0;
+            counts[i] = cnt[i];
+            total_ms[i] = tot[i];
+        }
+    });
+}

@@ -1,7 +1,8 @@
 // Workgroup-level dense complex kernels for CDNA4 (64-wide wavefronts, 256-thread workgroups):
-// partial LU with row pivoting restricted to the fully-summed rows, and the triangular solves
-// that go with it. Shared by the multifrontal factorisation (one front per workgroup) and the
-// reduced sweep (one reduced matrix per workgroup).
+// partial LU with row pivoting restricted to the fully-summed rows, split into its panel step
+// (one workgroup) and its trailing-update tiles (any number of workgroups), so that a large
+// front can spread its Schur-complement update over the whole chip while small fronts run the
+// whole factorisation inside one workgroup.
 //
 // Complex arithmetic uses four real multiplies per product (no three-multiply variant), so the
 // rounding of every product is the textbook one.
@@ -44,11 +45,10 @@ constexpr int kNB = 16;      // panel width
 constexpr int kTile = 64;    // trailing-update tile (64 x 64, 4 x 4 per thread)
 
 // Workgroup max-reduction of (value, index); lowest index wins ties. Uses red_v/red_i in LDS
-// (kWG entries each). All threads receive the result.
+// (kWG / 64 + 1 entries each). All threads receive the result.
 template <typename T>
 __device__ __forceinline__ void wg_argmax(T v, int i, T* red_v, int* red_i, T& out_v, int& out_i) {
     const int t = threadIdx.x;
-    // wavefront-level first
     for (int off = 32; off > 0; off >>= 1) {
         T ov = __shfl_xor(v, off);
         int oi = __shfl_xor(i, off);
@@ -78,132 +78,143 @@ struct LuShared {
     int red_i[kWG / 64 + 1];
 };
 
-// Partial LU of the m x m column-major matrix A (leading dimension lda) over its first p
-// columns: P A = L U on the leading p columns with the trailing (m-p) x (m-p) block replaced
-// by its Schur complement. Row pivots are searched only among rows [k, p) (fully-summed rows);
-// ipiv[k] receives the row swapped with row k. Pivots with cabs1 below `tiny` are replaced by
-// tiny (counted in *nperturb, which the caller zeroes).
+// Panel step of the partial LU of the m x m column-major A (leading dimension lda): factor
+// columns [k0, k1) over rows [k0, m) with pivots searched among the fully-summed rows [k, p)
+// (ipiv[k] = row swapped with k; the swap is applied to whole rows), then U12 rows
+// [k0, k1) x columns [k1, m) = L_kk^{-1} A (unit lower). Pivots with cabs1 <= tiny (or NaN)
+// are replaced by tiny in their own direction and counted in *nperturb.
 template <typename T>
-__device__ void wg_getrf(cx<T>* __restrict__ A, int lda, int m, int p, int* __restrict__ ipiv, T tiny,
+__device__ void wg_panel(cx<T>* __restrict__ A, int lda, int m, int p, int k0, int k1, int* __restrict__ ipiv, T tiny,
                          int* nperturb, LuShared<T>& sh) {
     const int t = threadIdx.x;
-    for (int k0 = 0; k0 < p; k0 += kNB) {
-        const int k1 = min(k0 + kNB, p);
-        // ---------------- panel factorisation (columns k0..k1-1, rows k0..m-1)
-        for (int k = k0; k < k1; ++k) {
-            T best = T(-1);
-            int bi = k;
-            for (int i = k + t; i < p; i += kWG) {
-                T v = cabs1(A[i + (size_t)k * lda]);
-                if (v > best) { best = v; bi = i; }
-            }
-            T pv;
-            int pi;
-            wg_argmax(best, bi, sh.red_v, sh.red_i, pv, pi);
-            if (t == 0) ipiv[k] = pi;
-            if (pi != k) {
-                for (int j = t; j < m; j += kWG) {
-                    cx<T> x = A[k + (size_t)j * lda], y = A[pi + (size_t)j * lda];
-                    A[k + (size_t)j * lda] = y;
-                    A[pi + (size_t)j * lda] = x;
-                }
-                __syncthreads();
-            }
-            cx<T> d = A[k + (size_t)k * lda];
-            if (!(pv > tiny)) {   // tiny or NaN pivot: static perturbation
-                T mag = cabs1(d);
-                if (mag > T(0)) { d.re = d.re / mag * tiny; d.im = d.im / mag * tiny; }
-                else { d.re = tiny; d.im = T(0); }
-                __syncthreads();
-                if (t == 0) { A[k + (size_t)k * lda] = d; atomicAdd(nperturb, 1); }
-            }
-            cx<T> r = crecip(d);
-            for (int i = k + 1 + t; i < m; i += kWG) {
-                cx<T>& x = A[i + (size_t)k * lda];
-                x = cmul(x, r);
-            }
-            __syncthreads();
-            // rank-1 update inside the panel
-            const int nc = k1 - k - 1;
-            if (nc > 0) {
-                const int rows = m - k - 1;
-                for (int e = t; e < rows * nc; e += kWG) {
-                    int i = k + 1 + e % rows, j = k + 1 + e / rows;
-                    A[i + (size_t)j * lda] = cfms(A[i + (size_t)j * lda], A[i + (size_t)k * lda], A[k + (size_t)j * lda]);
-                }
+    for (int k = k0; k < k1; ++k) {
+        T best = T(-1);
+        int bi = k;
+        for (int i = k + t; i < p; i += kWG) {
+            T v = cabs1(A[i + (size_t)k * lda]);
+            if (v > best) { best = v; bi = i; }
+        }
+        T pv;
+        int pi;
+        wg_argmax(best, bi, sh.red_v, sh.red_i, pv, pi);
+        if (t == 0) ipiv[k] = pi;
+        if (pi != k) {
+            for (int j = t; j < m; j += kWG) {
+                cx<T> x = A[k + (size_t)j * lda], y = A[pi + (size_t)j * lda];
+                A[k + (size_t)j * lda] = y;
+                A[pi + (size_t)j * lda] = x;
             }
             __syncthreads();
         }
-        if (k1 >= m) break;
-        // ---------------- U12 block: solve L_kk X = A[k0:k1, k1:m] (unit lower)
-        for (int j = k1 + t; j < m; j += kWG) {
-            cx<T> x[kNB];
-#pragma unroll
-            for (int r = 0; r < kNB; ++r)
-                if (k0 + r < k1) x[r] = A[k0 + r + (size_t)j * lda];
-#pragma unroll
-            for (int r = 0; r < kNB; ++r) {
-                if (k0 + r >= k1) break;
-#pragma unroll
-                for (int s = 0; s < r; ++s) x[r] = cfms(x[r], A[k0 + r + (size_t)(k0 + s) * lda], x[s]);
-            }
-#pragma unroll
-            for (int r = 0; r < kNB; ++r)
-                if (k0 + r < k1) A[k0 + r + (size_t)j * lda] = x[r];
+        cx<T> d = A[k + (size_t)k * lda];
+        if (!(pv > tiny)) {   // tiny or NaN pivot: static perturbation
+            T mag = cabs1(d);
+            if (mag > T(0)) { d.re = d.re / mag * tiny; d.im = d.im / mag * tiny; }
+            else { d.re = tiny; d.im = T(0); }
+            __syncthreads();
+            if (t == 0) { A[k + (size_t)k * lda] = d; atomicAdd(nperturb, 1); }
+        }
+        const cx<T> r = crecip(d);
+        for (int i = k + 1 + t; i < m; i += kWG) {
+            cx<T>& x = A[i + (size_t)k * lda];
+            x = cmul(x, r);
         }
         __syncthreads();
-        // ---------------- trailing update A[k1:m, k1:m] -= A[k1:m, k0:k1] A[k0:k1, k1:m]
-        const int nbk = k1 - k0;
-        const int rem = m - k1;
-        const int tiles = (rem + kTile - 1) / kTile;
-        const int tx = t & 15, ty = t >> 4;   // 16 x 16 threads, 4 x 4 each
-        for (int tile = 0; tile < tiles * tiles; ++tile) {
-            const int i0 = k1 + (tile % tiles) * kTile, j0 = k1 + (tile / tiles) * kTile;
-            for (int e = t; e < kTile * kNB; e += kWG) {
-                int r = e % kTile, c = e / kTile;
-                cx<T> v = {T(0), T(0)};
-                if (i0 + r < m && c < nbk) v = A[i0 + r + (size_t)(k0 + c) * lda];
-                sh.a[r][c] = v;
+        const int nc = k1 - k - 1;
+        if (nc > 0) {
+            const int rows = m - k - 1;
+            for (int e = t; e < rows * nc; e += kWG) {
+                int i = k + 1 + e % rows, j = k + 1 + e / rows;
+                A[i + (size_t)j * lda] = cfms(A[i + (size_t)j * lda], A[i + (size_t)k * lda], A[k + (size_t)j * lda]);
             }
-            for (int e = t; e < kTile * kNB; e += kWG) {
-                int r = e % kNB, c = e / kNB;
-                cx<T> v = {T(0), T(0)};
-                if (j0 + c < m && r < nbk) v = A[k0 + r + (size_t)(j0 + c) * lda];
-                sh.b[r][c] = v;
-            }
-            __syncthreads();
-            cx<T> acc[4][4];
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) acc[a][b] = {T(0), T(0)};
-            for (int c = 0; c < nbk; ++c) {
-                cx<T> av[4], bv[4];
-#pragma unroll
-                for (int a = 0; a < 4; ++a) av[a] = sh.a[tx + 16 * a][c];
-#pragma unroll
-                for (int b = 0; b < 4; ++b) bv[b] = sh.b[c][ty + 16 * b];
-#pragma unroll
-                for (int a = 0; a < 4; ++a)
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) {
-                        acc[a][b].re += av[a].re * bv[b].re - av[a].im * bv[b].im;
-                        acc[a][b].im += av[a].re * bv[b].im + av[a].im * bv[b].re;
-                    }
-            }
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    int i = i0 + tx + 16 * a, j = j0 + ty + 16 * b;
-                    if (i < m && j < m) {
-                        cx<T>& x = A[i + (size_t)j * lda];
-                        x.re -= acc[a][b].re;
-                        x.im -= acc[a][b].im;
-                    }
-                }
-            __syncthreads();
         }
+        __syncthreads();
+    }
+    if (k1 >= m) return;
+    // U12 block: solve L_kk X = A[k0:k1, k1:m] (unit lower)
+    for (int j = k1 + t; j < m; j += kWG) {
+        cx<T> x[kNB];
+#pragma unroll
+        for (int r = 0; r < kNB; ++r)
+            if (k0 + r < k1) x[r] = A[k0 + r + (size_t)j * lda];
+#pragma unroll
+        for (int r = 0; r < kNB; ++r) {
+            if (k0 + r >= k1) break;
+#pragma unroll
+            for (int s = 0; s < r; ++s) x[r] = cfms(x[r], A[k0 + r + (size_t)(k0 + s) * lda], x[s]);
+        }
+#pragma unroll
+        for (int r = 0; r < kNB; ++r)
+            if (k0 + r < k1) A[k0 + r + (size_t)j * lda] = x[r];
+    }
+    __syncthreads();
+}
+
+// One 64 x 64 tile (rows i0.., columns j0..) of the trailing update
+// A[k1:m, k1:m] -= A[k1:m, k0:k1] A[k0:k1, k1:m], with k1 - k0 <= kNB.
+template <typename T>
+__device__ void wg_tile_update(cx<T>* __restrict__ A, int lda, int m, int k0, int k1, int i0, int j0, LuShared<T>& sh) {
+    const int t = threadIdx.x;
+    const int nbk = k1 - k0;
+    const int tx = t & 15, ty = t >> 4;   // 16 x 16 threads, 4 x 4 each
+    for (int e = t; e < kTile * kNB; e += kWG) {
+        int r = e % kTile, c = e / kTile;
+        cx<T> v = {T(0), T(0)};
+        if (i0 + r < m && c < nbk) v = A[i0 + r + (size_t)(k0 + c) * lda];
+        sh.a[r][c] = v;
+    }
+    for (int e = t; e < kTile * kNB; e += kWG) {
+        int r = e % kNB, c = e / kNB;
+        cx<T> v = {T(0), T(0)};
+        if (j0 + c < m && r < nbk) v = A[k0 + r + (size_t)(j0 + c) * lda];
+        sh.b[r][c] = v;
+    }
+    __syncthreads();
+    cx<T> acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = {T(0), T(0)};
+    for (int c = 0; c < nbk; ++c) {
+        cx<T> av[4], bv[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) av[a] = sh.a[tx + 16 * a][c];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) bv[b] = sh.b[c][ty + 16 * b];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                acc[a][b].re += av[a].re * bv[b].re - av[a].im * bv[b].im;
+                acc[a][b].im += av[a].re * bv[b].im + av[a].im * bv[b].re;
+            }
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            int i = i0 + tx + 16 * a, j = j0 + ty + 16 * b;
+            if (i < m && j < m) {
+                cx<T>& x = A[i + (size_t)j * lda];
+                x.re -= acc[a][b].re;
+                x.im -= acc[a][b].im;
+            }
+        }
+    __syncthreads();
+}
+
+// Whole partial LU inside one workgroup: P A = L U on the leading p columns with the trailing
+// (m-p) x (m-p) block replaced by its Schur complement.
+template <typename T>
+__device__ void wg_getrf(cx<T>* __restrict__ A, int lda, int m, int p, int* __restrict__ ipiv, T tiny, int* nperturb,
+                         LuShared<T>& sh) {
+    for (int k0 = 0; k0 < p; k0 += kNB) {
+        const int k1 = min(k0 + kNB, p);
+        wg_panel<T>(A, lda, m, p, k0, k1, ipiv, tiny, nperturb, sh);
+        if (k1 >= m) break;
+        const int tiles = (m - k1 + kTile - 1) / kTile;
+        for (int tile = 0; tile < tiles * tiles; ++tile)
+            wg_tile_update<T>(A, lda, m, k0, k1, k1 + (tile % tiles) * kTile, k1 + (tile / tiles) * kTile, sh);
     }
     __syncthreads();
 }

@@ -65,30 +65,88 @@ __global__ void __launch_bounds__(kWG) k_front_factor(const int32_t* __restrict_
                                                      const int32_t* __restrict__ fsize, const int32_t* __restrict__ npiv,
                                                      const int32_t* __restrict__ first, const int64_t* __restrict__ front_off,
                                                      cx<T>* __restrict__ arena, int32_t* __restrict__ ipiv, T tiny,
-                                                     int32_t* nperturb) {
+                                                     int32_t* nperturb, const int32_t* __restrict__ big) {
     __shared__ LuShared<T> sh;
     const int f = level_fronts[blockIdx.x];
     const int m = fsize[f], p = npiv[f];
-    if (p == 0) return;
+    if (p == 0 || big[f]) return;
     wg_getrf<T>(arena + front_off[f], m, m, p, ipiv + first[f], tiny, nperturb, sh);
 }
 
+// large fronts, panel step j: one workgroup per front factors columns [16j, 16j + 16)
+template <typename T>
+__global__ void __launch_bounds__(kWG) k_front_panel(const int32_t* __restrict__ big_list, int step,
+                                                    const int32_t* __restrict__ fsize, const int32_t* __restrict__ npiv,
+                                                    const int32_t* __restrict__ first, const int64_t* __restrict__ front_off,
+                                                    cx<T>* __restrict__ arena, int32_t* __restrict__ ipiv, T tiny,
+                                                    int32_t* nperturb) {
+    __shared__ LuShared<T> sh;
+    const int f = big_list[blockIdx.x];
+    const int m = fsize[f], p = npiv[f], k0 = step * kNB;
+    if (k0 >= p) return;
+    wg_panel<T>(arena + front_off[f], m, m, p, k0, min(k0 + kNB, p), ipiv + first[f], tiny, nperturb, sh);
+}
+
+// large fronts, trailing update after a panel step: one 64 x 64 tile per workgroup
+template <typename T>
+__global__ void __launch_bounds__(kWG) k_front_tiles(const int4* __restrict__ tiles, const int32_t* __restrict__ fsize,
+                                                    const int32_t* __restrict__ npiv, const int64_t* __restrict__ front_off,
+                                                    cx<T>* __restrict__ arena) {
+    __shared__ LuShared<T> sh;
+    const int4 tl = tiles[blockIdx.x];
+    const int f = tl.x, m = fsize[f], p = npiv[f];
+    wg_tile_update<T>(arena + front_off[f], m, m, tl.w, min(tl.w + kNB, p), tl.y, tl.z, sh);
+}
+
 // ------------------------------------------------------------------ solves
+// Both solves are blocked by 64 pivots (one wavefront): the 64 x 64 diagonal block is staged in
+// LDS and solved by one wave per right-hand side with one row per lane (values exchanged by
+// cross-lane shuffles, no barriers); the solved values are staged in LDS and the rest of the
+// front vector is updated by the whole workgroup with the block's column panel, whose loads
+// are independent of each other (unrolled). Two barriers per 64 pivots.
+
+constexpr int kSB = 64;     // solve block (= wavefront size)
+constexpr int kSR = 16;     // right-hand sides per pass
+
+template <typename T>
+__device__ __forceinline__ cx<T> shfl_cx(cx<T> v, int src) {
+    return {__shfl(v.re, src), __shfl(v.im, src)};
+}
+
+template <typename T>
+struct SolveShared {
+    cx<T> d[kSB][kSB + 1];   // diagonal block
+    cx<T> y[kSB][kSR];       // solved block values
+};
+
 // Forward: per front, w (m x nrhs, column stride m) = [b_piv ; 0] + children's contributions,
 // row swaps on the pivot part, y = L11^{-1} w_piv, w_cb -= L21 y; y is written to x (new
 // numbering) and w_cb stays in the front's work slot for the parent.
 template <typename T>
-__global__ void __launch_bounds__(kWG) k_front_fwd(
-    const int32_t* __restrict__ level_fronts, const int32_t* __restrict__ fsize, const int32_t* __restrict__ npiv,
-    const int32_t* __restrict__ first, const int64_t* __restrict__ front_off, const int64_t* __restrict__ idx_off,
-    const int32_t* __restrict__ child_off, const int32_t* __restrict__ child_list, const int64_t* __restrict__ cmap_off,
-    const int32_t* __restrict__ cmap, const cx<T>* __restrict__ arena, const int32_t* __restrict__ ipiv,
-    cx<T>* __restrict__ x, int64_t ldx, int nrhs, cx<T>* __restrict__ work) {
-    const int f = level_fronts[blockIdx.x];
+struct SolveArgs {
+    const int32_t *fsize, *npiv, *first, *child_off, *child_list, *cmap, *idx, *parent, *ipiv;
+    const int64_t *front_off, *idx_off, *cmap_off;
+    const cx<T>* arena;
+    cx<T>* x;
+    int64_t ldx;
+    int nrhs;
+    cx<T>* work;
+};
+
+template <typename T>
+__device__ void front_fwd(int f, const SolveArgs<T>& a, SolveShared<T>& sh) {
+    const int32_t *fsize = a.fsize, *npiv = a.npiv, *first = a.first, *child_off = a.child_off,
+                  *child_list = a.child_list, *cmap = a.cmap, *ipiv = a.ipiv;
+    const int64_t *front_off = a.front_off, *idx_off = a.idx_off, *cmap_off = a.cmap_off;
+    const cx<T>* arena = a.arena;
+    cx<T>* x = a.x;
+    cx<T>* work = a.work;
+    const int64_t ldx = a.ldx;
+    const int nrhs = a.nrhs;
     const int m = fsize[f], p = npiv[f], f0 = first[f];
     const cx<T>* F = arena + front_off[f];
     cx<T>* w = work + idx_off[f] * nrhs;   // m x nrhs
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     for (int e = t; e < m * nrhs; e += kWG) {
         const int r = e % m, l = e / m;
         w[e] = r < p ? x[f0 + r + (size_t)l * ldx] : cx<T>{T(0), T(0)};
@@ -109,7 +167,6 @@ __global__ void __launch_bounds__(kWG) k_front_fwd(
         __syncthreads();
     }
     if (p == 0) return;
-    // row swaps of the pivot block (sequential in k; one thread per right-hand side)
     for (int l = t; l < nrhs; l += kWG) {
         cx<T>* wl = w + (size_t)l * m;
         for (int k = 0; k < p; ++k) {
@@ -118,11 +175,37 @@ __global__ void __launch_bounds__(kWG) k_front_fwd(
         }
     }
     __syncthreads();
-    // forward substitution, column-oriented: after y_k is final, update rows k+1..m-1
-    for (int k = 0; k < p; ++k) {
-        for (int e = t; e < (m - k - 1) * nrhs; e += kWG) {
-            const int i = k + 1 + e % (m - k - 1), l = e / (m - k - 1);
-            w[i + (size_t)l * m] = cfms(w[i + (size_t)l * m], F[i + (size_t)k * m], w[k + (size_t)l * m]);
+    for (int kb = 0; kb < p; kb += kSB) {
+        const int nb = min(kSB, p - kb);
+        for (int e = t; e < kSB * kSB; e += kWG) {
+            const int i = e % kSB, k = e / kSB;
+            sh.d[i][k] = (i < nb && k < nb) ? F[kb + i + (size_t)(kb + k) * m] : cx<T>{T(0), T(0)};
+        }
+        for (int l0 = 0; l0 < nrhs; l0 += kSR) {
+            const int nr = min(kSR, nrhs - l0);
+            __syncthreads();
+            // diagonal block: unit lower triangular, one wave per right-hand side
+            for (int lr = wave; lr < nr; lr += kWG / 64) {
+                cx<T>* wl = w + (size_t)(l0 + lr) * m;
+                cx<T> wi = lane < nb ? wl[kb + lane] : cx<T>{T(0), T(0)};
+                for (int k = 0; k < nb - 1; ++k) {
+                    const cx<T> wk = shfl_cx(wi, k);
+                    if (lane > k) wi = cfms(wi, sh.d[lane][k], wk);
+                }
+                if (lane < nb) wl[kb + lane] = wi;
+                sh.y[lane][lr] = wi;
+            }
+            __syncthreads();
+            // rows below the block: w[r] -= F[r, kb:kb+nb] y
+            const int r0 = kb + nb, rows = m - r0;
+            for (int e = t; e < rows * nr; e += kWG) {
+                const int r = r0 + e % rows, lr = e / rows;
+                cx<T> acc = w[r + (size_t)(l0 + lr) * m];
+                const cx<T>* Fr = F + r + (size_t)kb * m;
+#pragma unroll 16
+                for (int k = 0; k < nb; ++k) acc = cfms(acc, Fr[(size_t)k * m], sh.y[k][lr]);
+                w[r + (size_t)(l0 + lr) * m] = acc;
+            }
         }
         __syncthreads();
     }
@@ -134,40 +217,92 @@ __global__ void __launch_bounds__(kWG) k_front_fwd(
 
 // Backward: x_piv = U11^{-1} (y - U12 x_cb), x_cb gathered from already-solved ancestors.
 template <typename T>
-__global__ void __launch_bounds__(kWG) k_front_bwd(
-    const int32_t* __restrict__ level_fronts, const int32_t* __restrict__ fsize, const int32_t* __restrict__ npiv,
-    const int32_t* __restrict__ first, const int64_t* __restrict__ front_off, const int64_t* __restrict__ idx_off,
-    const int32_t* __restrict__ idx, const cx<T>* __restrict__ arena, cx<T>* __restrict__ x, int64_t ldx, int nrhs,
-    cx<T>* __restrict__ work) {
-    const int f = level_fronts[blockIdx.x];
+__device__ void front_bwd(int f, const SolveArgs<T>& a, SolveShared<T>& sh) {
+    const int32_t *fsize = a.fsize, *npiv = a.npiv, *first = a.first, *idx = a.idx;
+    const int64_t *front_off = a.front_off, *idx_off = a.idx_off;
+    const cx<T>* arena = a.arena;
+    cx<T>* x = a.x;
+    cx<T>* work = a.work;
+    const int64_t ldx = a.ldx;
+    const int nrhs = a.nrhs;
     const int m = fsize[f], p = npiv[f], f0 = first[f];
     if (p == 0) return;
     const cx<T>* F = arena + front_off[f];
     const int32_t* ix = idx + idx_off[f];
     cx<T>* w = work + idx_off[f] * nrhs;
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     for (int e = t; e < m * nrhs; e += kWG) {
         const int r = e % m, l = e / m;
         w[e] = x[ix[r] + (size_t)l * ldx];
     }
     __syncthreads();
-    // y_piv -= U12 x_cb : each thread owns (row, rhs) pairs
+    // y_piv -= U12 x_cb, the contribution columns taken kSB at a time through LDS
     const int c = m - p;
-    for (int e = t; e < p * nrhs; e += kWG) {
-        const int r = e % p, l = e / p;
-        cx<T> acc = w[r + (size_t)l * m];
-        for (int s = 0; s < c; ++s) acc = cfms(acc, F[r + (size_t)(p + s) * m], w[p + s + (size_t)l * m]);
-        w[r + (size_t)l * m] = acc;
+    for (int l0 = 0; l0 < nrhs; l0 += kSR) {
+        const int nr = min(kSR, nrhs - l0);
+        for (int base = 0; base < p * nr; base += 4 * kWG) {
+            cx<T> acc[4];
+            for (int g = 0; g < 4; ++g) {
+                const int e = base + g * kWG + t;
+                acc[g] = e < p * nr ? w[e % p + (size_t)(l0 + e / p) * m] : cx<T>{T(0), T(0)};
+            }
+            for (int s0 = 0; s0 < c; s0 += kSB) {
+                const int ns = min(kSB, c - s0);
+                __syncthreads();
+                for (int e = t; e < kSB * kSR; e += kWG) {
+                    const int sidx = e % kSB, lr = e / kSB;
+                    sh.y[sidx][lr] = (sidx < ns && lr < nr) ? w[p + s0 + sidx + (size_t)(l0 + lr) * m] : cx<T>{T(0), T(0)};
+                }
+                __syncthreads();
+                for (int g = 0; g < 4; ++g) {
+                    const int e = base + g * kWG + t;
+                    if (e >= p * nr) break;
+                    const int r = e % p, lr = e / p;
+                    const cx<T>* Fr = F + r + (size_t)(p + s0) * m;
+                    cx<T> a = acc[g];
+#pragma unroll 16
+                    for (int k = 0; k < ns; ++k) a = cfms(a, Fr[(size_t)k * m], sh.y[k][lr]);
+                    acc[g] = a;
+                }
+            }
+            __syncthreads();
+            for (int g = 0; g < 4; ++g) {
+                const int e = base + g * kWG + t;
+                if (e < p * nr) w[e % p + (size_t)(l0 + e / p) * m] = acc[g];
+            }
+        }
     }
     __syncthreads();
-    // back substitution, column-oriented
-    for (int k = p - 1; k >= 0; --k) {
-        const cx<T> d = crecip(F[k + (size_t)k * m]);
-        for (int l = t; l < nrhs; l += kWG) w[k + (size_t)l * m] = cmul(w[k + (size_t)l * m], d);
-        __syncthreads();
-        for (int e = t; e < k * nrhs; e += kWG) {
-            const int i = e % k, l = e / k;
-            w[i + (size_t)l * m] = cfms(w[i + (size_t)l * m], F[i + (size_t)k * m], w[k + (size_t)l * m]);
+    for (int kb = ((p - 1) / kSB) * kSB; kb >= 0; kb -= kSB) {
+        const int nb = min(kSB, p - kb);
+        for (int e = t; e < kSB * kSB; e += kWG) {
+            const int i = e % kSB, k = e / kSB;
+            sh.d[i][k] = (i < nb && k < nb) ? F[kb + i + (size_t)(kb + k) * m] : cx<T>{T(1), T(0)};
+        }
+        for (int l0 = 0; l0 < nrhs; l0 += kSR) {
+            const int nr = min(kSR, nrhs - l0);
+            __syncthreads();
+            for (int lr = wave; lr < nr; lr += kWG / 64) {
+                cx<T>* wl = w + (size_t)(l0 + lr) * m;
+                cx<T> wi = lane < nb ? wl[kb + lane] : cx<T>{T(0), T(0)};
+                for (int k = nb - 1; k >= 0; --k) {
+                    if (lane == k) wi = cmul(wi, crecip(sh.d[k][k]));
+                    const cx<T> xk = shfl_cx(wi, k);
+                    if (lane < k) wi = cfms(wi, sh.d[lane][k], xk);
+                }
+                if (lane < nb) wl[kb + lane] = wi;
+                sh.y[lane][lr] = wi;
+            }
+            __syncthreads();
+            // rows above the block: w[r] -= F[r, kb:kb+nb] x_blk
+            for (int e = t; e < kb * nr; e += kWG) {
+                const int r = e % kb, lr = e / kb;
+                cx<T> acc = w[r + (size_t)(l0 + lr) * m];
+                const cx<T>* Fr = F + r + (size_t)kb * m;
+#pragma unroll 16
+                for (int k = 0; k < nb; ++k) acc = cfms(acc, Fr[(size_t)k * m], sh.y[k][lr]);
+                w[r + (size_t)(l0 + lr) * m] = acc;
+            }
         }
         __syncthreads();
     }
@@ -175,6 +310,18 @@ __global__ void __launch_bounds__(kWG) k_front_bwd(
         const int r = e % p, l = e / p;
         x[f0 + r + (size_t)l * ldx] = w[r + (size_t)l * m];
     }
+}
+
+// One launch per tree level and direction; every front of the level is one workgroup.
+template <typename T>
+__global__ void __launch_bounds__(kWG) k_front_fwd(const int32_t* __restrict__ level_fronts, SolveArgs<T> a) {
+    __shared__ SolveShared<T> sh;
+    front_fwd<T>(level_fronts[blockIdx.x], a, sh);
+}
+template <typename T>
+__global__ void __launch_bounds__(kWG) k_front_bwd(const int32_t* __restrict__ level_fronts, SolveArgs<T> a) {
+    __shared__ SolveShared<T> sh;
+    front_bwd<T>(level_fronts[blockIdx.x], a, sh);
 }
 
 // gather (with precision change) B (old numbering, n x nrhs FP64) -> xp (new numbering, T)
@@ -219,11 +366,31 @@ void run_factor(Factor& f, cr_sys sys, double sigma, cx<T>* arena, T tiny, hipSt
     for (int l = 0; l < S.nlevel; ++l) {
         const int nf = S.level_off[l + 1] - S.level_off[l];
         const int32_t* lf = D.level_fronts.p + S.level_off[l];
-        hipLaunchKernelGGL(k_front_assemble<T>, dim3(nf), dim3(kWG), 0, s, lf, D.fsize.p, D.front_off.p, D.child_off.p,
-                           D.child_list.p, D.npiv.p, D.cmap_off.p, D.cmap.p, D.ent_off.p, D.ent_src.p, D.ent_dst.p,
-                           sys->d_K.p, sys->d_M.p, sigma, arena);
-        hipLaunchKernelGGL(k_front_factor<T>, dim3(nf), dim3(kWG), 0, s, lf, D.fsize.p, D.npiv.p, D.first.p,
-                           D.front_off.p, arena, f.ipiv.p, tiny, f.nperturb.p);
+        {
+            ProfScope ps(sys->ctx, "front_assemble", s);
+            hipLaunchKernelGGL(k_front_assemble<T>, dim3(nf), dim3(kWG), 0, s, lf, D.fsize.p, D.front_off.p, D.child_off.p,
+                               D.child_list.p, D.npiv.p, D.cmap_off.p, D.cmap.p, D.ent_off.p, D.ent_src.p, D.ent_dst.p,
+                               sys->d_K.p, sys->d_M.p, sigma, arena);
+        }
+        {
+            ProfScope ps(sys->ctx, "front_factor", s);
+            hipLaunchKernelGGL(k_front_factor<T>, dim3(nf), dim3(kWG), 0, s, lf, D.fsize.p, D.npiv.p, D.first.p,
+                               D.front_off.p, arena, f.ipiv.p, tiny, f.nperturb.p, D.big.p);
+        }
+        const int nbig = S.big_off[l + 1] - S.big_off[l];
+        for (int j = 0; j < S.nsteps[l]; ++j) {
+            {
+                ProfScope ps(sys->ctx, "front_panel", s);
+                hipLaunchKernelGGL(k_front_panel<T>, dim3(nbig), dim3(kWG), 0, s, D.big_list.p + S.big_off[l], j,
+                                   D.fsize.p, D.npiv.p, D.first.p, D.front_off.p, arena, f.ipiv.p, tiny, f.nperturb.p);
+            }
+            const int64_t t0 = S.tile_off[S.step_off[l] + j], t1 = S.tile_off[S.step_off[l] + j + 1];
+            if (t1 > t0) {
+                ProfScope ps(sys->ctx, "front_tiles", s);
+                hipLaunchKernelGGL(k_front_tiles<T>, dim3((unsigned)(t1 - t0)), dim3(kWG), 0, s, D.tiles.p + t0,
+                                   D.fsize.p, D.npiv.p, D.front_off.p, arena);
+            }
+        }
     }
     CR_HIP(hipGetLastError());
 }
@@ -233,16 +400,35 @@ void run_solve(const Factor& f, int nrhs, cx<T>* xp, cx<T>* work, hipStream_t s,
     cr_sys sys = f.sys;
     const Symbolic& S = *sys->sym;
     const DevSymbolic& D = *sys->dsym;
-    for (int l = 0; l < S.nlevel; ++l) {
-        const int nf = S.level_off[l + 1] - S.level_off[l];
-        hipLaunchKernelGGL(k_front_fwd<T>, dim3(nf), dim3(kWG), 0, s, D.level_fronts.p + S.level_off[l], D.fsize.p,
-                           D.npiv.p, D.first.p, D.front_off.p, D.idx_off.p, D.child_off.p, D.child_list.p, D.cmap_off.p,
-                           D.cmap.p, arena, f.ipiv.p, xp, (int64_t)S.n, nrhs, work);
-    }
-    for (int l = S.nlevel - 1; l >= 0; --l) {
-        const int nf = S.level_off[l + 1] - S.level_off[l];
-        hipLaunchKernelGGL(k_front_bwd<T>, dim3(nf), dim3(kWG), 0, s, D.level_fronts.p + S.level_off[l], D.fsize.p,
-                           D.npiv.p, D.first.p, D.front_off.p, D.idx_off.p, D.idx.p, arena, xp, (int64_t)S.n, nrhs, work);
+    SolveArgs<T> a;
+    a.fsize = D.fsize.p;
+    a.npiv = D.npiv.p;
+    a.first = D.first.p;
+    a.child_off = D.child_off.p;
+    a.child_list = D.child_list.p;
+    a.cmap = D.cmap.p;
+    a.idx = D.idx.p;
+    a.parent = D.parent.p;
+    a.ipiv = f.ipiv.p;
+    a.front_off = D.front_off.p;
+    a.idx_off = D.idx_off.p;
+    a.cmap_off = D.cmap_off.p;
+    a.arena = arena;
+    a.x = xp;
+    a.ldx = (int64_t)S.n;
+    a.nrhs = nrhs;
+    a.work = const_cast<cx<T>*>(work);
+    {
+        for (int l = 0; l < S.nlevel; ++l) {
+            const int nf = S.level_off[l + 1] - S.level_off[l];
+            ProfScope ps(sys->ctx, "front_fwd", s);
+            hipLaunchKernelGGL(k_front_fwd<T>, dim3(nf), dim3(kWG), 0, s, D.level_fronts.p + S.level_off[l], a);
+        }
+        for (int l = S.nlevel - 1; l >= 0; --l) {
+            const int nf = S.level_off[l + 1] - S.level_off[l];
+            ProfScope ps(sys->ctx, "front_bwd", s);
+            hipLaunchKernelGGL(k_front_bwd<T>, dim3(nf), dim3(kWG), 0, s, D.level_fronts.p + S.level_off[l], a);
+        }
     }
     CR_HIP(hipGetLastError());
 }
@@ -270,6 +456,9 @@ void upload_symbolic(cr_sys sys) {
     upload(D->ent_src, S.ent_src, s);
     upload(D->perm, S.perm, s);
     upload(D->iperm, S.iperm, s);
+    upload(D->big, S.big, s);
+    upload(D->big_list, S.big_list, s);
+    upload(D->tiles, S.tiles, s);
     CR_HIP(hipStreamSynchronize(s));
     sys->dsym = std::move(D);
 }
@@ -336,3 +525,4 @@ void apply_factor(const Factor& f, int nrhs, const zd* B, int64_t ldb, zd* X, in
 }
 
 }  // namespace cr
+

@@ -105,6 +105,15 @@ struct Symbolic {
     std::vector<int64_t> ent_src;    // csr position
     std::vector<int32_t> ent_dst;    // local row + local col * m (fits: m^2 < 2^31)
     int32_t max_front = 0, max_piv = 0, max_children = 0;
+    // large fronts are factored panel by panel with the trailing update spread over many
+    // workgroups: per level the list of large fronts, the panel steps, and per (level, step)
+    // the update tiles (front, row, column, first panel column)
+    std::vector<int32_t> big;                  // per front: 1 = large
+    std::vector<int32_t> big_off, big_list;    // per level
+    std::vector<int32_t> nsteps;               // per level
+    std::vector<int64_t> step_off;             // per level: offset into tile_off
+    std::vector<int64_t> tile_off;             // per (level, step): offset into tiles
+    std::vector<int4> tiles;
     int64_t factor_entries = 0;
     double factor_flops = 0;
     double seconds = 0;
@@ -115,6 +124,8 @@ struct DevSymbolic {
     DevBuf<int32_t> first, npiv, fsize, parent, child_off, child_list, level_fronts, idx, cmap, ent_dst;
     DevBuf<int64_t> idx_off, front_off, cmap_off, ent_off, ent_src;
     DevBuf<int32_t> perm, iperm;
+    DevBuf<int32_t> big, big_list;
+    DevBuf<int4> tiles;
 };
 
 // scale, scaled device copies and norms of a freshly assembled or imported system
@@ -127,7 +138,38 @@ std::unique_ptr<Symbolic> analyse_pattern(int64_t n, const std::vector<int64_t>&
 }  // namespace cr
 
 // ------------------------------------------------------------------------- handles
-namespace cr { struct SweepEngine; }
+namespace cr {
+struct SweepEngine;
+
+// Event-bracketed kernel timing (off unless enabled through cr_profile_enable).
+struct Profiler {
+    bool on = false;
+    struct Rec {
+        const char* name;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t take() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    void clear() {
+        for (auto& r : recs) { pool.push_back(r.a); pool.push_back(r.b); }
+        recs.clear();
+    }
+    ~Profiler() {
+        clear();
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    }
+};
+}  // namespace cr
 
 struct cr_ctx_s {
     int device = 0;
@@ -135,7 +177,33 @@ struct cr_ctx_s {
     std::string err;
     int num_cu = 256;
     cr::SweepEngine* sweep = nullptr;   // persistent sweep workspaces (owned)
+    cr::Profiler prof;
 };
+
+namespace cr {
+// RAII bracket of one kernel launch (no-op while profiling is off)
+struct ProfScope {
+    cr_ctx_s* ctx;
+    hipStream_t s;
+    const char* name;
+    hipEvent_t a = nullptr;
+    ProfScope(cr_ctx_s* c, const char* n, hipStream_t st) : ctx(c), s(st), name(n) {
+        if (ctx && ctx->prof.on) {
+            a = ctx->prof.take();
+            if (a) (void)hipEventRecord(a, s);
+        }
+    }
+    ~ProfScope() {
+        if (a) {
+            hipEvent_t b = ctx->prof.take();
+            if (b) {
+                (void)hipEventRecord(b, s);
+                ctx->prof.recs.push_back({name, a, b});
+            }
+        }
+    }
+};
+}  // namespace cr
 
 struct cr_sys_s {
     cr_ctx ctx = nullptr;
@@ -204,7 +272,8 @@ struct SolveWork {
 // Solve A~ X = B for the scaled system (device, n x nrhs, ld n) with FP64 refinement.
 // Returns iterations; sets backward error. Throws CR_E_NOT_CONVERGED only when `strict`.
 int solve_scaled(Factor& f, int nrhs, const zd* B, zd* X, int max_iter, double tol, double* berr,
-                 SolveWork& w, hipStream_t s, bool strict);
+                 SolveWork& w, hipStream_t s, bool strict, bool allow_krylov = true);
+
 
 // Greedy hook: the network's proposed next candidate (-1 when it proposes none); residuals res
 // of every candidate, candidates already used, geometry features (or null).

@@ -127,19 +127,23 @@ __global__ void k_axpy_copy(int64_t n, const zd* __restrict__ src, zd* __restric
 static inline unsigned spmm_blocks(int64_t n) { return (unsigned)((n * kRowLanes + 255) / 256); }
 
 void spmm_shifted(cr_sys sys, double sigma, int nrhs, const zd* X, int64_t ldx, zd* Y, int64_t ldy, hipStream_t s) {
+    ProfScope ps(sys->ctx, "spmm", s);
     hipLaunchKernelGGL(k_spmm<0>, dim3(spmm_blocks(sys->n)), dim3(256), 0, s, sys->n, sys->d_rowptr.p, sys->d_col.p,
                        sys->d_K.p, sys->d_M.p, sigma, nrhs, X, ldx, (const zd*)nullptr, (int64_t)0, Y, (zd*)nullptr, ldy);
 }
 void spmm_km(cr_sys sys, int nrhs, const zd* X, int64_t ldx, zd* KX, zd* MX, int64_t ldy, hipStream_t s) {
+    ProfScope ps(sys->ctx, "spmm", s);
     hipLaunchKernelGGL(k_spmm<2>, dim3(spmm_blocks(sys->n)), dim3(256), 0, s, sys->n, sys->d_rowptr.p, sys->d_col.p,
                        sys->d_K.p, sys->d_M.p, 0.0, nrhs, X, ldx, (const zd*)nullptr, (int64_t)0, KX, MX, ldy);
 }
 void spmm_m(cr_sys sys, int nrhs, const zd* X, int64_t ldx, zd* Y, int64_t ldy, hipStream_t s) {
+    ProfScope ps(sys->ctx, "spmm", s);
     hipLaunchKernelGGL(k_spmm<3>, dim3(spmm_blocks(sys->n)), dim3(256), 0, s, sys->n, sys->d_rowptr.p, sys->d_col.p,
                        sys->d_K.p, sys->d_M.p, 0.0, nrhs, X, ldx, (const zd*)nullptr, (int64_t)0, Y, (zd*)nullptr, ldy);
 }
 void spmm_residual(cr_sys sys, double sigma, int nrhs, const zd* X, int64_t ldx, const zd* B, int64_t ldb, zd* R,
                    int64_t ldr, hipStream_t s) {
+    ProfScope ps(sys->ctx, "spmm", s);
     hipLaunchKernelGGL(k_spmm<1>, dim3(spmm_blocks(sys->n)), dim3(256), 0, s, sys->n, sys->d_rowptr.p, sys->d_col.p,
                        sys->d_K.p, sys->d_M.p, sigma, nrhs, X, ldx, B, ldb, R, (zd*)nullptr, ldr);
 }
@@ -363,7 +367,8 @@ static int gmres_cycle(Factor& f, int nrhs, const zd* R, zd* X, int m, double rt
 // over (the low-precision factor as preconditioner of an FP64 GMRES on the correction
 // equation). Stops at tol or after max_iter refinement steps.
 int solve_scaled(Factor& f, int nrhs, const zd* B, zd* X, int max_iter, double tol, double* berr, SolveWork& w,
-                 hipStream_t s, bool strict) {
+                 hipStream_t s, bool strict, bool allow_krylov) {
+
     cr_sys sys = f.sys;
     const int64_t n = sys->n;
     const double sigma = f.omega * f.omega;
@@ -394,7 +399,10 @@ int solve_scaled(Factor& f, int nrhs, const zd* B, zd* X, int max_iter, double t
             be = std::max(be, den > 0 ? rn / den : 0.0);
         }
         if (be <= tol || it >= max_iter) break;
-        if (!krylov && !(be < 0.5 * prev)) krylov = true;
+        if (!krylov && !(be < 0.5 * prev)) {
+            if (!allow_krylov) break;   // caller decides (e.g. refactor in FP64)
+            krylov = true;
+        }
         if (krylov && f.prec == CR_FP64 && !(be < 0.5 * prev)) break;   // FP64 factor: nothing left to gain
         prev = be;
         if (!krylov) {

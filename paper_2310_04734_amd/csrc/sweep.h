@@ -22,6 +22,7 @@ struct RomDesc {
 
 struct SweepEngine {
     int num_cu = 256;
+    cr_ctx_s* ctx = nullptr;
     DevBuf<RomDesc> d_roms;
     DevBuf<int2> d_items;
     DevBuf<int> d_stats;

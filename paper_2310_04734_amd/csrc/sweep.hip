@@ -253,6 +253,7 @@ void SweepEngine::run(const std::vector<RomDesc>& roms, const std::vector<int2>&
     wsR.reserve((size_t)grid * slot_v);
     wsB.reserve((size_t)grid * slot_v);
     wsD.reserve((size_t)grid * slot_v);
+    ProfScope ps(ctx, "sweep", s);
     if (prec == CR_MIXED) {
         hipLaunchKernelGGL(k_sweep<float>, dim3(grid), dim3(kWG), 0, s, d_roms.p, d_items.p, (int)items.size(), slot_a,
                            slot_v, wsA.p, wsP.p, wsX.p, wsR.p, wsB.p, wsD.p, 1, 10, 1e-14, d_stats.p);
