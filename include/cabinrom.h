@@ -209,6 +209,10 @@ typedef struct {
     int32_t policy;            /* CR_POLICY_GREEDY or CR_POLICY_MLP                        */
     cr_mlp mlp;                /* network for CR_POLICY_MLP                                */
     const double* geom;        /* geometry features for the network (mlp input tail)       */
+    int32_t lookahead;         /* 0, or K > 0: after each unconverged iteration try the K
+                                  largest residual peaks (at least 3 candidates apart, not
+                                  next to a used point) on a copy of the basis and record
+                                  the max residual each would leave (training labels)      */
 } cr_greedy_opts;
 
 typedef struct {
@@ -217,6 +221,9 @@ typedef struct {
     double* max_res;           /* [max_shifts] max residual after each iteration           */
     double* res;               /* [n_cand] candidate residuals after the last iteration    */
     int32_t* mlp_used;         /* [max_shifts] 1 where the network's proposal was accepted  */
+    double* res_hist;          /* [max_shifts x n_cand] residuals after each iteration, or NULL */
+    int32_t* la_cand;          /* [max_shifts x lookahead] tried candidates (-1 = none), or NULL */
+    double* la_res;            /* [max_shifts x lookahead] max residual after each trial, or NULL */
 } cr_greedy_trace;
 
 /* Greedy adaptive expansion points (Section 3.3, after Eq. (9)): start at the candidate nearest
@@ -263,9 +270,11 @@ typedef struct {
 cr_status cr_sweep(cr_rom r, int32_t nfreq, const double* omegas, cr_precision prec, cr_z* Y_dev,
                    cr_sweep_info* info);
 
-/* Launch tuning of the batched sweep: variant (0 = automatic choice), resident workgroups per
-   compute unit (0 = automatic), panel width (0 = automatic). */
-typedef struct { int32_t variant, grid_per_cu, nb; } cr_tune;
+/* Launch tuning of the batched sweep: variant (0 = automatic choice, 1 = LDS-resident reduced
+   matrix for orders that fit nb KiB of LDS, 2 = global-memory workspace only), resident
+   workgroups per compute unit (0 = automatic), nb, and refine (1 = also refine CR_FP64 sweeps
+   with FP64 residuals, e.g. to serve as a reference). */
+typedef struct { int32_t variant, grid_per_cu, nb, refine; } cr_tune;
 
 /* Batched sweep of nrom reduced models of uneven order in one persistent launch. omegas:
    nrom x nfreq (row-major, host); Y_dev: host array of nrom device pointers, each
@@ -274,6 +283,22 @@ typedef struct { int32_t variant, grid_per_cu, nb; } cr_tune;
 cr_status cr_sweep_batched(cr_ctx ctx, int32_t nrom, const cr_rom* roms, int32_t nfreq,
                            const double* omegas, cr_precision prec, cr_z* const* Y_dev,
                            const cr_tune* tune, cr_sweep_info* info);
+
+/* A batched sweep prepared for repeated execution (the online phase run again and again, e.g.
+   for parameter studies): descriptors and work queue uploaded once; the launch shape
+   (workgroups per CU, LDS budget of the LDS-resident variant for small orders) chosen by
+   timing candidate shapes on a stratified sample of the work items when tune is NULL or
+   tune->variant == 0 (otherwise taken from tune: grid_per_cu, nb = LDS budget in KiB); one
+   eager execution, then the launch captured in a HIP graph that execute replays. Arguments as
+   cr_sweep_batched; the roms, omegas and Y_dev buffers must stay valid while the plan exists. */
+typedef struct cr_sweep_plan_s* cr_sweep_plan;
+cr_status cr_sweep_plan_create(cr_ctx ctx, int32_t nrom, const cr_rom* roms, int32_t nfreq, const double* omegas,
+                               cr_precision prec, cr_z* const* Y_dev, const cr_tune* tune, cr_sweep_plan* out);
+cr_status cr_sweep_plan_execute(cr_sweep_plan plan, cr_sweep_info* info);
+/* The chosen shape (variant = 1 when the LDS-resident variant is enabled) and, when autotuned,
+   the sample times in ms of every candidate (up to max entries; *n receives the count). */
+cr_status cr_sweep_plan_tuning(cr_sweep_plan plan, cr_tune* chosen, double* ms, int32_t max, int32_t* n);
+void cr_sweep_plan_destroy(cr_sweep_plan plan);
 
 /* ---------------------------------------------------------------- learned shift proposer -- */
 
@@ -294,6 +319,13 @@ cr_status cr_mlp_gradients(cr_mlp m, int32_t batch, const float* X_dev, const in
                            const float* mask_dev, float* grad_dev, float* loss_out);
 /* Parameter count and host copies of the FP32 master parameters
    (W1, b1, W2, b2, W3, b3, W4, b4; W_l row-major out x in). */
+/* Network input for one greedy state (host arrays, no device work): x[c] = log10 r_c - max_c log10 r_c
+   for the n_cand candidate residuals res (values below 1e-300 are clamped), then the n_geom geometry
+   features; mask (n_cand floats, or NULL) is 0 at every used candidate index and its two
+   neighbours, 1 elsewhere. The greedy's CR_POLICY_MLP builds its input with the same function, so
+   training data and inference agree. x must hold n_cand + n_geom floats. */
+cr_status cr_mlp_features(int32_t n_cand, const double* res, int32_t n_used, const int32_t* used, int32_t n_geom,
+                          const double* geom, float* x, float* mask);
 cr_status cr_mlp_num_params(cr_mlp m, int64_t* n);
 cr_status cr_mlp_get_params(cr_mlp m, float* params);
 cr_status cr_mlp_set_params(cr_mlp m, const float* params);

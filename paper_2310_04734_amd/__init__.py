@@ -93,12 +93,12 @@ class cr_basis_info(C.Structure):
 class cr_greedy_opts(C.Structure):
     _fields_ = [("f_lo_hz", C.c_double), ("f_hi_hz", C.c_double), ("n_cand", C.c_int32), ("blocks", C.c_int32),
                 ("tol", C.c_double), ("max_shifts", C.c_int32), ("policy", C.c_int32), ("mlp", C.c_void_p),
-                ("geom", C.c_void_p)]
+                ("geom", C.c_void_p), ("lookahead", C.c_int32)]
 
 
 class cr_greedy_trace(C.Structure):
     _fields_ = [("n_iter", C.c_int32), ("shift_idx", C.c_void_p), ("max_res", C.c_void_p), ("res", C.c_void_p),
-                ("mlp_used", C.c_void_p)]
+                ("mlp_used", C.c_void_p), ("res_hist", C.c_void_p), ("la_cand", C.c_void_p), ("la_res", C.c_void_p)]
 
 
 class cr_sweep_info(C.Structure):
@@ -107,7 +107,7 @@ class cr_sweep_info(C.Structure):
 
 
 class cr_tune(C.Structure):
-    _fields_ = [("variant", C.c_int32), ("grid_per_cu", C.c_int32), ("nb", C.c_int32)]
+    _fields_ = [("variant", C.c_int32), ("grid_per_cu", C.c_int32), ("nb", C.c_int32), ("refine", C.c_int32)]
 
 
 def _sig(name, res, *args):
@@ -149,9 +149,14 @@ _sig("cr_mlp_destroy", None, P)
 _sig("cr_mlp_forward", I32, P, I32, P, P)
 _sig("cr_mlp_train_step", I32, P, I32, P, P, P, C.c_float, C.POINTER(C.c_float))
 _sig("cr_mlp_gradients", I32, P, I32, P, P, P, P, C.POINTER(C.c_float))
+_sig("cr_mlp_features", I32, I32, P, I32, P, I32, P, P, P)
 _sig("cr_mlp_num_params", I32, P, C.POINTER(I64))
 _sig("cr_mlp_get_params", I32, P, P)
 _sig("cr_mlp_set_params", I32, P, P)
+_sig("cr_sweep_plan_create", I32, P, I32, P, I32, P, I32, P, P, C.POINTER(P))
+_sig("cr_sweep_plan_execute", I32, P, C.POINTER(cr_sweep_info))
+_sig("cr_sweep_plan_tuning", I32, P, C.POINTER(cr_tune), P, I32, C.POINTER(I32))
+_sig("cr_sweep_plan_destroy", None, P)
 _sig("cr_profile_enable", I32, P, I32)
 _sig("cr_profile_read", I32, P, I32, P, P, P, C.POINTER(I32))
 
@@ -258,21 +263,26 @@ class System:
         return Basis(self, h, info)
 
     def basis_greedy(self, band_hz, n_cand, blocks, tol, max_shifts, prec: int = CR_MIXED, policy=CR_POLICY_GREEDY,
-                     mlp=None, geom=None):
+                     mlp=None, geom=None, lookahead=0):
         g = np.ascontiguousarray(geom if geom is not None else np.zeros(0), np.float64)
         opts = cr_greedy_opts(float(band_hz[0]), float(band_hz[1]), int(n_cand), int(blocks), float(tol),
-                              int(max_shifts), int(policy), mlp.h if mlp is not None else None, _ptr(g))
+                              int(max_shifts), int(policy), mlp.h if mlp is not None else None, _ptr(g), int(lookahead))
         sidx = np.full(max_shifts, -1, np.int32)
         mres = np.zeros(max_shifts)
         res = np.zeros(n_cand)
         used = np.zeros(max_shifts, np.int32)
-        tr = cr_greedy_trace(0, _ptr(sidx), _ptr(mres), _ptr(res), _ptr(used))
+        hist = np.zeros((max_shifts, n_cand))
+        K = max(int(lookahead), 1)
+        la_c = np.full((max_shifts, K), -1, np.int32)
+        la_r = np.full((max_shifts, K), -1.0)
+        tr = cr_greedy_trace(0, _ptr(sidx), _ptr(mres), _ptr(res), _ptr(used), _ptr(hist), _ptr(la_c), _ptr(la_r))
         h = P()
         info = cr_basis_info()
         self.ctx.check(lib.cr_basis_build_greedy(self.h, C.byref(opts), prec, C.byref(h), C.byref(tr), C.byref(info)))
         k = tr.n_iter
         b = Basis(self, h, info)
-        b.trace = dict(shift_idx=sidx[:k].copy(), max_res=mres[:k].copy(), res=res, mlp_used=used[:k].copy())
+        b.trace = dict(shift_idx=sidx[:k].copy(), max_res=mres[:k].copy(), res=res, mlp_used=used[:k].copy(),
+                       res_hist=hist[:k].copy(), la_cand=la_c[:k].copy(), la_res=la_r[:k].copy())
         return b
 
     def __del__(self):
@@ -410,6 +420,115 @@ class Rom:
             self.h = None
 
 
+class Mlp:
+    """The learned expansion-point proposer (n_in -> 3 x hidden ReLU -> n_out), trained on the GPU."""
+
+    def __init__(self, ctx: Context, n_in=259, hidden=256, n_out=256, seed=2310047347007):
+        self.ctx, self.n_in, self.hidden, self.n_out = ctx, n_in, hidden, n_out
+        h = P()
+        ctx.check(lib.cr_mlp_create(ctx.h, n_in, hidden, n_out, C.c_uint64(seed), C.byref(h)))
+        self.h = h
+        n = I64()
+        ctx.check(lib.cr_mlp_num_params(h, C.byref(n)))
+        self.n_params = n.value
+
+    def get_params(self):
+        p = np.empty(self.n_params, np.float32)
+        self.ctx.check(lib.cr_mlp_get_params(self.h, _ptr(p)))
+        return p
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, np.float32)
+        assert p.size == self.n_params
+        self.ctx.check(lib.cr_mlp_set_params(self.h, _ptr(p)))
+
+    def forward(self, X):
+        torch = self.ctx.torch
+        X = X.contiguous().to(torch.float32)
+        out = torch.empty((X.shape[0], self.n_out), dtype=torch.float32, device=self.ctx.device)
+        self.ctx.check(lib.cr_mlp_forward(self.h, X.shape[0], _dev_ptr(X), _dev_ptr(out)))
+        return out
+
+    def gradients(self, X, labels, mask=None):
+        torch = self.ctx.torch
+        X = X.contiguous().to(torch.float32)
+        lab = labels.contiguous().to(torch.int32)
+        m = mask.contiguous().to(torch.float32) if mask is not None else None
+        g = torch.empty(self.n_params, dtype=torch.float32, device=self.ctx.device)
+        loss = C.c_float()
+        self.ctx.check(lib.cr_mlp_gradients(self.h, X.shape[0], _dev_ptr(X), _dev_ptr(lab),
+                                            _dev_ptr(m) if m is not None else None, _dev_ptr(g), C.byref(loss)))
+        return loss.value, g
+
+    def train_step(self, X, labels, mask=None, lr=1e-3):
+        torch = self.ctx.torch
+        X = X.contiguous().to(torch.float32)
+        lab = labels.contiguous().to(torch.int32)
+        m = mask.contiguous().to(torch.float32) if mask is not None else None
+        loss = C.c_float()
+        self.ctx.check(lib.cr_mlp_train_step(self.h, X.shape[0], _dev_ptr(X), _dev_ptr(lab),
+                                             _dev_ptr(m) if m is not None else None, float(lr), C.byref(loss)))
+        return loss.value
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib.cr_mlp_destroy(self.h)
+            self.h = None
+
+
+def mlp_features(res, used, geom=None):
+    """Network input (float32 n_cand + n_geom) and class mask (float32 n_cand) for one greedy state."""
+    res = np.ascontiguousarray(res, np.float64)
+    used = np.ascontiguousarray(used, np.int32)
+    g = np.ascontiguousarray(geom if geom is not None else np.zeros(0), np.float64)
+    x = np.empty(res.size + g.size, np.float32)
+    m = np.empty(res.size, np.float32)
+    st = lib.cr_mlp_features(res.size, _ptr(res), used.size, _ptr(used), g.size, _ptr(g), _ptr(x), _ptr(m))
+    if st != 0:
+        raise CabinRomError(st, "cr_mlp_features: bad arguments")
+    return x, m
+
+
+class SweepPlan:
+    """A batched sweep prepared once (autotuned launch shape, HIP graph) and replayed."""
+
+    def __init__(self, ctx: Context, roms, omegas, prec=CR_MIXED, outs=None, tune=None):
+        torch = ctx.torch
+        self.ctx, self.roms = ctx, list(roms)
+        self.om = np.ascontiguousarray(omegas, np.float64)
+        nrom, nfreq = self.om.shape
+        self.outs = outs if outs is not None else [
+            torch.empty((nfreq, r.L, r.n_o), dtype=torch.complex128, device=ctx.device) for r in roms]
+        hs = (P * nrom)(*[r.h for r in roms])
+        ys = (P * nrom)(*[Y.data_ptr() for Y in self.outs])
+        t = None
+        if tune is not None:
+            t = cr_tune(int(tune.get("variant", 0)), int(tune.get("grid_per_cu", 0)), int(tune.get("nb", 0)),
+                        int(tune.get("refine", 0)))
+        h = P()
+        ctx.check(lib.cr_sweep_plan_create(ctx.h, nrom, hs, nfreq, _ptr(self.om), prec, ys,
+                                           C.byref(t) if t is not None else None, C.byref(h)))
+        self.h = h
+
+    def execute(self):
+        info = cr_sweep_info()
+        self.ctx.check(lib.cr_sweep_plan_execute(self.h, C.byref(info)))
+        return dict(max_ir_iterations=info.max_ir_iterations, not_converged=info.not_converged,
+                    fp64_fallbacks=info.fp64_fallbacks, seconds=info.seconds)
+
+    def tuning(self):
+        ch = cr_tune()
+        ms = np.zeros(64)
+        n = I32()
+        self.ctx.check(lib.cr_sweep_plan_tuning(self.h, C.byref(ch), _ptr(ms), 64, C.byref(n)))
+        return dict(variant=ch.variant, grid_per_cu=ch.grid_per_cu, lds_kib=ch.nb, sample_ms=ms[:n.value].tolist())
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib.cr_sweep_plan_destroy(self.h)
+            self.h = None
+
+
 def sweep_batched(ctx: Context, roms, omegas, prec=CR_MIXED, outs=None, grid_per_cu=0):
     """omegas: (nrom, nfreq) host array; returns a list of Y tensors (nfreq x L x n_o)."""
     torch = ctx.torch
@@ -419,7 +538,7 @@ def sweep_batched(ctx: Context, roms, omegas, prec=CR_MIXED, outs=None, grid_per
         outs = [torch.empty((nfreq, r.L, r.n_o), dtype=torch.complex128, device=ctx.device) for r in roms]
     hs = (P * nrom)(*[r.h for r in roms])
     ys = (P * nrom)(*[Y.data_ptr() for Y in outs])
-    tune = cr_tune(0, int(grid_per_cu), 0)
+    tune = cr_tune(0, int(grid_per_cu), 0, 0)
     info = cr_sweep_info()
     ctx.check(lib.cr_sweep_batched(ctx.h, nrom, hs, nfreq, _ptr(om), prec, ys, C.byref(tune), C.byref(info)))
     return outs, dict(max_ir_iterations=info.max_ir_iterations, not_converged=info.not_converged,

@@ -201,6 +201,25 @@ void add_shift(cr_basis B, Factor& fac, SolveWork& sw, double omega, int blocks,
     }
 }
 
+// independent copy of a basis and its incremental projection (for look-ahead trials)
+std::unique_ptr<cr_basis_s> clone_basis(cr_basis B) {
+    cr_sys sys = B->sys;
+    hipStream_t s = sys->ctx->stream;
+    const int64_t n = sys->n;
+    auto C = std::make_unique<cr_basis_s>();
+    C->sys = sys;
+    ensure_capacity(C.get(), B->cap);
+    copy_dev(n * B->q, B->V.p, C->V.p, s);
+    copy_dev(n * B->q, B->KV.p, C->KV.p, s);
+    copy_dev(n * B->q, B->MV.p, C->MV.p, s);
+    copy_2d(B->q, B->q, B->KR.p, B->cap, C->KR.p, C->cap, s);
+    copy_2d(B->q, B->q, B->MR.p, B->cap, C->MR.p, C->cap, s);
+    CR_HIP(hipStreamSynchronize(s));
+    C->q = B->q;
+    C->shifts = B->shifts;
+    return C;
+}
+
 void fill_info(cr_basis B, cr_basis_info* info, double t0) {
     if (!info) return;
     info->q = B->q;
@@ -529,8 +548,47 @@ cr_status cr_basis_build_greedy(cr_sys sys, const cr_greedy_opts* o, cr_precisio
                 res[c] = std::sqrt(res[c] / fn2[c]);
                 mx = std::max(mx, res[c]);
             }
+            if (trace && trace->res_hist) std::copy(res.begin(), res.end(), trace->res_hist + (size_t)it * nc);
             maxres.push_back(mx);
             if (mx <= o->tol) break;
+            if (o->lookahead > 0) {
+                // one-step look-ahead over the K largest residual peaks, each tried on a copy
+                const int K = o->lookahead;
+                std::vector<int> idx(nc);
+                std::iota(idx.begin(), idx.end(), 0);
+                std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return res[a] > res[b]; });
+                std::vector<int> picks;
+                for (int c : idx) {
+                    if ((int)picks.size() >= K) break;
+                    bool bad = false;
+                    for (int u : used) bad = bad || std::abs(u - c) <= 1;
+                    for (int pk : picks) bad = bad || std::abs(pk - c) < 3;
+                    if (!bad) picks.push_back(c);
+                }
+                std::vector<double> rtmp(nc);
+                for (int k = 0; k < K; ++k) {
+                    double best_after = -1.0;
+                    const int c = k < (int)picks.size() ? picks[k] : -1;
+                    if (c >= 0) {
+                        auto Bc = clone_basis(B.get());
+                        add_shift(Bc.get(), fac, sw, cw[c], o->blocks, prec);
+                        auto romc = rom_from_basis(Bc.get());
+                        const int qc = Bc->q;
+                        Xc.reserve((size_t)nc * qc * L);
+                        std::vector<RomDesc> rdc{desc_of(romc.get(), d_cw.p, Xc.p, 1)};
+                        int mi2, ncv2, np2;
+                        E.run(rdc, items, CR_FP64, false, s, &mi2, &ncv2, &np2);
+                        candidate_residuals(n, qc, L, nc, Bc->KV.p, Bc->MV.p, n, sys->d_F.p, Xc.p, d_scal.p, d_w2.p,
+                                            d_res2.p, partial, s);
+                        CR_HIP(hipMemcpyAsync(rtmp.data(), d_res2.p, nc * sizeof(double), hipMemcpyDeviceToHost, s));
+                        CR_HIP(hipStreamSynchronize(s));
+                        best_after = 0;
+                        for (int cc = 0; cc < nc; ++cc) best_after = std::max(best_after, std::sqrt(rtmp[cc] / fn2[cc]));
+                    }
+                    if (trace && trace->la_cand) trace->la_cand[(size_t)it * K + k] = c;
+                    if (trace && trace->la_res) trace->la_res[(size_t)it * K + k] = best_after;
+                }
+            }
             int best = -1;
             for (int c = 0; c < nc; ++c) {
                 if (std::find(used.begin(), used.end(), c) != used.end()) continue;
@@ -743,3 +801,114 @@ extern "C" cr_status cr_profile_read(cr_ctx ctx, int32_t max, char* names, int32
         }
     });
 }
+
+// ---------------------------------------------------------------- sweep plans (graph replay)
+struct cr_sweep_plan_s {
+    cr_ctx ctx = nullptr;
+    cr_precision prec = CR_MIXED;
+    std::unique_ptr<SweepEngine> eng;
+    DevBuf<double> omegas;
+    int gpc = 2, lds = 0;
+    std::vector<double> tune_ms;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~cr_sweep_plan_s() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+};
+
+extern "C" cr_status cr_sweep_plan_create(cr_ctx ctx, int32_t nrom, const cr_rom* roms, int32_t nfreq,
+                                          const double* omegas, cr_precision prec, cr_z* const* Y_dev,
+                                          const cr_tune* tune, cr_sweep_plan* out) {
+    if (!ctx) return CR_E_INVALID;
+    return cr_guard(ctx, [&] {
+        CR_REQUIRE(out && nrom > 0 && nfreq > 0 && roms && omegas && Y_dev, CR_E_INVALID, "cr_sweep_plan_create: bad arguments");
+        CR_REQUIRE(prec == CR_FP64 || prec == CR_MIXED, CR_E_INVALID, "cr_sweep_plan_create: bad precision");
+        hipStream_t s = ctx->stream;
+        auto P = std::make_unique<cr_sweep_plan_s>();
+        P->ctx = ctx;
+        P->prec = prec;
+        P->eng = std::make_unique<SweepEngine>();
+        P->eng->num_cu = ctx->num_cu;
+        P->eng->ctx = ctx;
+        const size_t nw = (size_t)nrom * nfreq;
+        P->omegas.alloc(nw);
+        CR_HIP(hipMemcpyAsync(P->omegas.p, omegas, nw * sizeof(double), hipMemcpyHostToDevice, s));
+        std::vector<RomDesc> ds(nrom);
+        for (int m = 0; m < nrom; ++m) {
+            CR_REQUIRE(roms[m] && roms[m]->ctx == ctx && Y_dev[m], CR_E_INVALID, "cr_sweep_plan_create: bad model");
+            ds[m] = desc_of(roms[m], P->omegas.p + (size_t)m * nfreq, reinterpret_cast<zd*>(Y_dev[m]), 0);
+        }
+        std::vector<int> order(nrom);
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return ds[a].q > ds[b].q; });
+        std::vector<int2> items;
+        items.reserve(nw);
+        for (int m : order)
+            for (int i = 0; i < nfreq; ++i) items.push_back(make_int2(m, i));
+        const bool refine = prec == CR_MIXED || (tune && tune->refine);
+        if (!tune || tune->variant == 0) {
+            P->eng->autotune(ds, items, prec, refine, s, &P->gpc, &P->lds, &P->tune_ms);
+        } else {
+            P->gpc = tune->grid_per_cu > 0 ? tune->grid_per_cu : 2;
+            P->lds = tune->variant == 1 ? std::max(0, tune->nb) * 1024 : 0;
+        }
+        P->eng->prepare(ds, items, s);
+        P->eng->launch(prec, refine, P->gpc, P->lds, s);   // eager run: allocates the workspaces
+        CR_HIP(hipStreamSynchronize(s));
+        CR_HIP(hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking));
+        const bool prof = ctx->prof.on;
+        ctx->prof.on = false;
+        CR_HIP(hipStreamBeginCapture(P->cap, hipStreamCaptureModeThreadLocal));
+        try {
+            P->eng->launch(prec, refine, P->gpc, P->lds, P->cap);
+        } catch (...) {
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(P->cap, &g);
+            if (g) (void)hipGraphDestroy(g);
+            ctx->prof.on = prof;
+            throw;
+        }
+        CR_HIP(hipStreamEndCapture(P->cap, &P->graph));
+        ctx->prof.on = prof;
+        CR_HIP(hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0));
+        *out = P.release();
+    });
+}
+
+extern "C" cr_status cr_sweep_plan_execute(cr_sweep_plan plan, cr_sweep_info* info) {
+    if (!plan) return CR_E_INVALID;
+    return cr_guard(plan->ctx, [&] {
+        const double t0 = now();
+        hipStream_t s = plan->ctx->stream;
+        {
+            ProfScope ps(plan->ctx, "sweep_graph", s);
+            CR_HIP(hipGraphLaunch(plan->exec, s));
+        }
+        int mi = 0, nc = 0, np = 0, fb = 0;
+        plan->eng->read_stats(s, &mi, &nc, &np, &fb);
+        if (info) {
+            info->max_ir_iterations = mi;
+            info->not_converged = nc;
+            info->fp64_fallbacks = fb;
+            info->seconds = now() - t0;
+        }
+    });
+}
+
+extern "C" cr_status cr_sweep_plan_tuning(cr_sweep_plan plan, cr_tune* chosen, double* ms, int32_t max, int32_t* n) {
+    if (!plan) return CR_E_INVALID;
+    if (chosen) {
+        chosen->variant = plan->lds > 0 ? 1 : 0;
+        chosen->grid_per_cu = plan->gpc;
+        chosen->nb = plan->lds / 1024;
+    }
+    if (n) *n = (int32_t)plan->tune_ms.size();
+    for (int i = 0; ms && i < max && i < (int)plan->tune_ms.size(); ++i) ms[i] = plan->tune_ms[i];
+    return CR_OK;
+}
+
+extern "C" void cr_sweep_plan_destroy(cr_sweep_plan plan) { delete plan; }

@@ -670,6 +670,63 @@ __global__ void __launch_bounds__(256) k_resid_partial(int64_t n, int q, int L, 
     }
 }
 
+// Large q x L: one candidate per workgroup column of the grid, one row per thread, X_c staged
+// through LDS 32 rows at a time, up to 16 load columns per pass.
+__global__ void __launch_bounds__(256) k_resid_partial_big(int64_t n, int q, int L, int ncand, const zd* __restrict__ KV,
+                                                           const zd* __restrict__ MV, int64_t ldv, const zd* __restrict__ F,
+                                                           const zd* __restrict__ X, const zd* __restrict__ scal,
+                                                           const double* __restrict__ w2, double* __restrict__ partial) {
+    constexpr int kKc = 32, kLc = 16;
+    __shared__ zd xs[kKc][kLc];
+    __shared__ double red[4];
+    const int c = blockIdx.y;
+    const zd* Xc = X + (size_t)c * q * L;
+    const double w2c = w2[c];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool act = i < n;
+    double acc2 = 0;
+    for (int l0 = 0; l0 < L; l0 += kLc) {
+        const int nl = min(kLc, L - l0);
+        double rr[kLc], ri[kLc];
+#pragma unroll
+        for (int l = 0; l < kLc; ++l) {
+            rr[l] = ri[l] = 0;
+            if (act && l < nl) {
+                const zd f = F[i + (int64_t)(l0 + l) * n], sc = scal[c * L + l0 + l];
+                rr[l] = f.re * sc.re - f.im * sc.im;
+                ri[l] = f.re * sc.im + f.im * sc.re;
+            }
+        }
+        for (int k0 = 0; k0 < q; k0 += kKc) {
+            const int nk = min(kKc, q - k0);
+            __syncthreads();
+            for (int e = threadIdx.x; e < kKc * kLc; e += 256) {
+                const int kk = e % kKc, l = e / kKc;
+                xs[kk][l] = (kk < nk && l < nl) ? Xc[k0 + kk + (size_t)(l0 + l) * q] : zd{0, 0};
+            }
+            __syncthreads();
+            if (act) {
+                for (int kk = 0; kk < nk; ++kk) {
+                    const zd kv = KV[i + (int64_t)(k0 + kk) * ldv], mv = MV[i + (int64_t)(k0 + kk) * ldv];
+                    const double ar = kv.re - w2c * mv.re, ai = kv.im - w2c * mv.im;
+#pragma unroll
+                    for (int l = 0; l < kLc; ++l) {
+                        const zd x = xs[kk][l];
+                        rr[l] -= ar * x.re - ai * x.im;
+                        ri[l] -= ar * x.im + ai * x.re;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int l = 0; l < kLc; ++l) acc2 += rr[l] * rr[l] + ri[l] * ri[l];
+    }
+    for (int off = 32; off > 0; off >>= 1) acc2 += __shfl_xor(acc2, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x / 64] = acc2;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[(size_t)blockIdx.x * ncand + c] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
 __global__ void k_resid_reduce(int nchunk, int ncand, const double* __restrict__ partial, double* __restrict__ out) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncand) return;
@@ -687,9 +744,13 @@ void candidate_residuals(int64_t n, int q, int L, int ncand, const zd* KV, const
     const int nchunk = (int)((n + 255) / 256);
     partial.reserve((size_t)nchunk * ncand);
     const size_t shmem = (size_t)q * L * kCandChunk * sizeof(zd);
-    CR_REQUIRE(shmem <= 64 * 1024, CR_E_UNSUPPORTED, "candidate residual: q * L too large for one LDS stage");
-    hipLaunchKernelGGL(k_resid_partial, dim3(nchunk, (ncand + kCandChunk - 1) / kCandChunk), dim3(256), shmem, s, n, q, L,
-                       ncand, KV, MV, ldv, F, X, scal, w2, partial.p);
+    if (shmem <= 64 * 1024) {
+        hipLaunchKernelGGL(k_resid_partial, dim3(nchunk, (ncand + kCandChunk - 1) / kCandChunk), dim3(256), shmem, s, n,
+                           q, L, ncand, KV, MV, ldv, F, X, scal, w2, partial.p);
+    } else {
+        hipLaunchKernelGGL(k_resid_partial_big, dim3(nchunk, ncand), dim3(256), 0, s, n, q, L, ncand, KV, MV, ldv, F, X,
+                           scal, w2, partial.p);
+    }
     hipLaunchKernelGGL(k_resid_reduce, dim3((ncand + 255) / 256), dim3(256), 0, s, nchunk, ncand, partial.p, res2);
 }
 

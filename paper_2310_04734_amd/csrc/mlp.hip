@@ -244,15 +244,28 @@ float backward(cr_mlp m, int batch, const float* X, const int32_t* labels, const
 }  // namespace
 
 namespace cr {
-int mlp_propose(cr_mlp m, const std::vector<double>& res, const std::vector<int>& used, const double* geom) {
-    const int nc = (int)res.size();
-    const int ng = m->n_in - m->n_out;
-    if (nc != m->n_out || ng < 0) throw Error(CR_E_INVALID, "network does not match the candidate count");
-    std::vector<float> x(m->n_in, 0.f);
+// network input: log10 residuals shifted so that the largest is 0, then the geometry features;
+// mask: 0 at used candidates and their neighbours, 1 elsewhere
+void mlp_features(int nc, const double* res, int n_used, const int* used, int ng, const double* geom, float* x,
+                  float* mask) {
     double mx = -1e300;
     for (int c = 0; c < nc; ++c) mx = std::max(mx, std::log10(std::max(res[c], 1e-300)));
     for (int c = 0; c < nc; ++c) x[c] = (float)(std::log10(std::max(res[c], 1e-300)) - mx);
     for (int k = 0; k < ng; ++k) x[nc + k] = geom ? (float)geom[k] : 0.f;
+    if (mask) {
+        for (int c = 0; c < nc; ++c) mask[c] = 1.f;
+        for (int k = 0; k < n_used; ++k)
+            for (int d = -1; d <= 1; ++d)
+                if (used[k] + d >= 0 && used[k] + d < nc) mask[used[k] + d] = 0.f;
+    }
+}
+
+int mlp_propose(cr_mlp m, const std::vector<double>& res, const std::vector<int>& used, const double* geom) {
+    const int nc = (int)res.size();
+    const int ng = m->n_in - m->n_out;
+    if (nc != m->n_out || ng < 0) throw Error(CR_E_INVALID, "network does not match the candidate count");
+    std::vector<float> x(m->n_in, 0.f), mask(nc);
+    mlp_features(nc, res.data(), (int)used.size(), used.data(), ng, geom, x.data(), mask.data());
     hipStream_t s = m->ctx->stream;
     m->xin.reserve(m->n_in);
     CR_HIP(hipMemcpyAsync(m->xin.p, x.data(), m->n_in * sizeof(float), hipMemcpyHostToDevice, s));
@@ -262,10 +275,7 @@ int mlp_propose(cr_mlp m, const std::vector<double>& res, const std::vector<int>
     CR_HIP(hipStreamSynchronize(s));
     int best = -1;
     for (int c = 0; c < nc; ++c) {
-        bool banned = false;
-        for (int u : used)
-            if (std::abs(u - c) <= 1) banned = true;
-        if (banned) continue;
+        if (mask[c] == 0.f) continue;
         if (best < 0 || lg[c] > lg[best]) best = c;
     }
     return best;
@@ -273,6 +283,14 @@ int mlp_propose(cr_mlp m, const std::vector<double>& res, const std::vector<int>
 }  // namespace cr
 
 extern "C" {
+
+cr_status cr_mlp_features(int32_t n_cand, const double* res, int32_t n_used, const int32_t* used, int32_t n_geom,
+                          const double* geom, float* x, float* mask) {
+    if (n_cand < 1 || !res || !x || n_used < 0 || (n_used > 0 && !used) || n_geom < 0 || (n_geom > 0 && !geom))
+        return CR_E_INVALID;
+    cr::mlp_features(n_cand, res, n_used, used, n_geom, geom, x, mask);
+    return CR_OK;
+}
 
 cr_status cr_mlp_create(cr_ctx ctx, int32_t n_in, int32_t hidden, int32_t n_out, uint64_t seed, cr_mlp* out) {
     if (!ctx) return CR_E_INVALID;

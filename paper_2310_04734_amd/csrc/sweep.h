@@ -29,9 +29,15 @@ struct SweepEngine {
     DevBuf<zd> wsA, wsX, wsR, wsB, wsD;
     DevBuf<int> wsP;
     DevBuf<double> d_omega;   // frequencies of the current call
+    int qmax = 0, Lmax = 0, nitems = 0;
     // items: (model index, frequency index), processed in the given order by a work queue
+    void prepare(const std::vector<RomDesc>& roms, const std::vector<int2>& items, hipStream_t s);
+    void launch(cr_precision prec, bool refine, int grid_per_cu, int lds_bytes, hipStream_t s);
+    void read_stats(hipStream_t s, int* max_its, int* not_conv, int* perturbed, int* fallbacks);
     void run(const std::vector<RomDesc>& roms, const std::vector<int2>& items, cr_precision prec, bool refine,
              hipStream_t s, int* max_its, int* not_conv, int* perturbed, int grid_override = 0, int* fallbacks = nullptr);
+    void autotune(const std::vector<RomDesc>& roms, const std::vector<int2>& items, cr_precision prec, bool refine,
+                  hipStream_t s, int* best_gpc, int* best_lds, std::vector<double>* ms);
 };
 
 }  // namespace cr

@@ -38,6 +38,7 @@ __device__ void wg_lu_solve(const cx<T>* __restrict__ A, int lda, int q, const i
         }
     }
     __syncthreads();
+    // column-oriented substitutions over independent (row, right-hand side) entries
     for (int k = 0; k < q - 1; ++k) {
         const int rows = q - k - 1;
         for (int e = t; e < rows * L; e += kWG) {
@@ -114,25 +115,60 @@ __device__ bool solve_item(const RomDesc& rd, double w, cx<T>* __restrict__ A, i
         __syncthreads();
         if (!refine) { conv = true; break; }
         // R = B - A_R X in FP64; backward error max ||r||_inf / (||A||_inf ||x||_inf + ||b||_inf),
-        // pooled over the load columns
+        // pooled over the load columns. One thread per row reads K_R, M_R (and D_R) once per
+        // refinement step for up to kLc load columns; X comes through LDS kJc rows at a time.
+        constexpr int kLc = 16, kJc = 32;
+        __shared__ zd xs[kJc][kLc];
         double anorm_part = 0, rmax = 0, xmax = 0, bmax = 0;
-        for (int e = t; e < q * L; e += kWG) {
-            const int i = e % q, l = e / q;
-            double rr = Bv[e].re, ri = Bv[e].im, rowsum = 0;
-            for (int j = 0; j < q; ++j) {
-                const zd k = rd.KR[i + (size_t)j * q], m = rd.MR[i + (size_t)j * q];
-                double ar = k.re - w2 * m.re, ai = k.im - w2 * m.im;
-                if (rd.DR) { const zd d = rd.DR[i + (size_t)j * q]; ar -= w * d.im; ai += w * d.re; }
-                const zd x = X[j + (size_t)l * q];
-                rr -= ar * x.re - ai * x.im;
-                ri -= ar * x.im + ai * x.re;
-                if (l == 0) rowsum += hypot(ar, ai);
+        for (int l0 = 0; l0 < L; l0 += kLc) {
+            const int nl = min(kLc, L - l0);
+            for (int i0 = 0; i0 < q; i0 += kWG) {
+                const int i = i0 + t;
+                const bool act = i < q;
+                double rr[kLc], ri[kLc], rowsum = 0;
+#pragma unroll
+                for (int c = 0; c < kLc; ++c) {
+                    rr[c] = (act && c < nl) ? Bv[i + (size_t)(l0 + c) * q].re : 0.0;
+                    ri[c] = (act && c < nl) ? Bv[i + (size_t)(l0 + c) * q].im : 0.0;
+                }
+                for (int j0 = 0; j0 < q; j0 += kJc) {
+                    const int nj = min(kJc, q - j0);
+                    __syncthreads();
+                    for (int e = t; e < kJc * kLc; e += kWG) {
+                        const int jj = e % kJc, c = e / kJc;
+                        xs[jj][c] = (jj < nj && c < nl) ? X[j0 + jj + (size_t)(l0 + c) * q] : zd{0.0, 0.0};
+                    }
+                    __syncthreads();
+                    if (act) {
+                        for (int jj = 0; jj < nj; ++jj) {
+                            const size_t o = i + (size_t)(j0 + jj) * q;
+                            const zd k = rd.KR[o], m = rd.MR[o];
+                            double ar = k.re - w2 * m.re, ai = k.im - w2 * m.im;
+                            if (rd.DR) { const zd d = rd.DR[o]; ar -= w * d.im; ai += w * d.re; }
+                            if (l0 == 0) rowsum += hypot(ar, ai);
+#pragma unroll
+                            for (int c = 0; c < kLc; ++c) {
+                                const zd x = xs[jj][c];
+                                rr[c] -= ar * x.re - ai * x.im;
+                                ri[c] -= ar * x.im + ai * x.re;
+                            }
+                        }
+                    }
+                }
+                if (act) {
+                    anorm_part = fmax(anorm_part, rowsum);
+#pragma unroll
+                    for (int c = 0; c < kLc; ++c) {
+                        if (c < nl) {
+                            const size_t e = i + (size_t)(l0 + c) * q;
+                            R[e] = {rr[c], ri[c]};
+                            rmax = fmax(rmax, hypot(rr[c], ri[c]));
+                            xmax = fmax(xmax, hypot(X[e].re, X[e].im));
+                            bmax = fmax(bmax, hypot(Bv[e].re, Bv[e].im));
+                        }
+                    }
+                }
             }
-            R[e] = {rr, ri};
-            anorm_part = fmax(anorm_part, rowsum);
-            rmax = fmax(rmax, hypot(rr, ri));
-            xmax = fmax(xmax, hypot(X[e].re, X[e].im));
-            bmax = fmax(bmax, hypot(Bv[e].re, Bv[e].im));
         }
         const double an = wg_max(anorm_part, red);
         const double rn = wg_max(rmax, red);
@@ -155,8 +191,9 @@ __global__ void __launch_bounds__(kWG) k_sweep(const RomDesc* __restrict__ roms,
                                                int64_t slot_a, int64_t slot_v, zd* __restrict__ wsA, int* __restrict__ wsP,
                                                zd* __restrict__ wsX, zd* __restrict__ wsR, zd* __restrict__ wsB,
                                                zd* __restrict__ wsD, int refine, int max_iter, double tol,
-                                               int* __restrict__ stats) {
+                                               int* __restrict__ stats, int q_lds) {
     __shared__ LuShared<double> sh;   // large enough for the FP32 variant as well
+    extern __shared__ double dyn_lds[];   // reduced matrix of orders q <= q_lds (LDS-resident variant)
     __shared__ double red[8];
     __shared__ int s_item;
     __shared__ int s_perturb;
@@ -185,7 +222,8 @@ __global__ void __launch_bounds__(kWG) k_sweep(const RomDesc* __restrict__ roms,
         }
         __syncthreads();
         int its = 0, fell_back = 0;
-        bool conv = solve_item<T>(rd, w, reinterpret_cast<cx<T>*>(Aslot), ipiv, X, R, Bv, reinterpret_cast<cx<T>*>(Dslot),
+        cx<T>* Awork = q <= q_lds ? reinterpret_cast<cx<T>*>(dyn_lds) : reinterpret_cast<cx<T>*>(Aslot);
+        bool conv = solve_item<T>(rd, w, Awork, ipiv, X, R, Bv, reinterpret_cast<cx<T>*>(Dslot),
                                   refine != 0, max_iter, tol, reinterpret_cast<LuShared<T>&>(sh), red, &s_perturb, &its);
         if (!conv && sizeof(T) == 4) {
             // complex-FP32 LU too inaccurate for refinement to converge (kappa(A_R) u_32 >~ 1):
@@ -200,17 +238,26 @@ __global__ void __launch_bounds__(kWG) k_sweep(const RomDesc* __restrict__ roms,
             zd* o = rd.out + (size_t)it.y * q * L;
             for (int e = t; e < q * L; e += kWG) o[e] = X[e];
         } else {
+            // Y = C_R X: one thread per (receiver, group of 4 loads); C_R read once per group
             const int no = rd.n_o;
             zd* o = rd.out + (size_t)it.y * L * no;
-            for (int e = t; e < no * L; e += kWG) {
-                const int oo = e % no, l = e / no;
-                double yr = 0, yi = 0;
+            const int ng = (L + 3) / 4;
+            for (int e = t; e < no * ng; e += kWG) {
+                const int oo = e % no, l0 = 4 * (e / no);
+                const int nl = min(4, L - l0);
+                double yr[4] = {0, 0, 0, 0}, yi[4] = {0, 0, 0, 0};
                 for (int k = 0; k < q; ++k) {
-                    const zd c = rd.CR[oo + (size_t)k * no], x = X[k + (size_t)l * q];
-                    yr += c.re * x.re - c.im * x.im;
-                    yi += c.re * x.im + c.im * x.re;
+                    const zd c = rd.CR[oo + (size_t)k * no];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        if (j < nl) {
+                            const zd x = X[k + (size_t)(l0 + j) * q];
+                            yr[j] += c.re * x.re - c.im * x.im;
+                            yi[j] += c.re * x.im + c.im * x.re;
+                        }
+                    }
                 }
-                o[oo + (size_t)l * no] = {yr, yi};
+                for (int j = 0; j < nl; ++j) o[oo + (size_t)(l0 + j) * no] = {yr[j], yi[j]};
             }
         }
         if (t == 0) {
@@ -225,50 +272,121 @@ __global__ void __launch_bounds__(kWG) k_sweep(const RomDesc* __restrict__ roms,
 
 }  // namespace
 
-void SweepEngine::run(const std::vector<RomDesc>& roms, const std::vector<int2>& items, cr_precision prec, bool refine,
-                      hipStream_t s, int* max_its, int* not_conv, int* perturbed, int grid_override, int* fallbacks) {
-    if (fallbacks) *fallbacks = 0;
-    if (items.empty()) {
-        *max_its = *not_conv = *perturbed = 0;
-        return;
-    }
-    int qmax = 0, Lmax = 0;
+// LDS-resident variant: the reduced matrix stays in LDS when q^2 entries fit the budget
+static int q_lds_for(cr_precision prec, int lds_bytes) {
+    const int elt = prec == CR_MIXED ? (int)sizeof(cx<float>) : (int)sizeof(cx<double>);
+    int q = 0;
+    while ((q + 1) * (q + 1) * elt <= lds_bytes) ++q;
+    return q;
+}
+
+void SweepEngine::prepare(const std::vector<RomDesc>& roms, const std::vector<int2>& items, hipStream_t s) {
+    qmax = 0;
+    Lmax = 0;
     for (const RomDesc& r : roms) {
         qmax = std::max(qmax, r.q);
         Lmax = std::max(Lmax, r.L);
     }
     CR_REQUIRE(qmax <= 4096, CR_E_UNSUPPORTED, "reduced order above 4096");
-    const int64_t slot_a = (int64_t)qmax * qmax, slot_v = (int64_t)qmax * std::max(Lmax, 1);
-    const int grid = grid_override > 0 ? std::min<int>((int)items.size(), grid_override)
-                                       : std::min<int>((int)items.size(), 2 * num_cu);
+    nitems = (int)items.size();
     d_roms.reserve(roms.size());
     d_items.reserve(items.size());
     d_stats.reserve(8);
-    CR_HIP(hipMemcpyAsync(d_roms.p, roms.data(), roms.size() * sizeof(RomDesc), hipMemcpyHostToDevice, s));
-    CR_HIP(hipMemcpyAsync(d_items.p, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice, s));
-    fill_zero(d_stats.p, 8, s);
+    if (!roms.empty())
+        CR_HIP(hipMemcpyAsync(d_roms.p, roms.data(), roms.size() * sizeof(RomDesc), hipMemcpyHostToDevice, s));
+    if (!items.empty())
+        CR_HIP(hipMemcpyAsync(d_items.p, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+    CR_HIP(hipStreamSynchronize(s));
+}
+
+// Launch the prepared items with grid = min(items, grid_per_cu * CUs) resident workgroups and an
+// LDS budget for the LDS-resident variant. Only kernels are enqueued (no memset / memcpy), so
+// the launch can be captured in a graph.
+void SweepEngine::launch(cr_precision prec, bool refine, int grid_per_cu, int lds_bytes, hipStream_t s) {
+    if (nitems == 0) return;
+    const int64_t slot_a = (int64_t)qmax * qmax, slot_v = (int64_t)qmax * std::max(Lmax, 1);
+    const int grid = std::min<int>(nitems, std::max(1, grid_per_cu) * num_cu);
     wsA.reserve((size_t)grid * slot_a);
     wsP.reserve((size_t)grid * 4096);
     wsX.reserve((size_t)grid * slot_v);
     wsR.reserve((size_t)grid * slot_v);
     wsB.reserve((size_t)grid * slot_v);
     wsD.reserve((size_t)grid * slot_v);
+    fill_zero(d_stats.p, 8, s);
+    const int q_lds = q_lds_for(prec, lds_bytes);
+    const size_t dyn = q_lds > 0 ? (size_t)lds_bytes : 0;
     ProfScope ps(ctx, "sweep", s);
     if (prec == CR_MIXED) {
-        hipLaunchKernelGGL(k_sweep<float>, dim3(grid), dim3(kWG), 0, s, d_roms.p, d_items.p, (int)items.size(), slot_a,
-                           slot_v, wsA.p, wsP.p, wsX.p, wsR.p, wsB.p, wsD.p, 1, 10, 1e-14, d_stats.p);
+        if (dyn > 65536) CR_HIP(hipFuncSetAttribute((const void*)k_sweep<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
+        hipLaunchKernelGGL(k_sweep<float>, dim3(grid), dim3(kWG), dyn, s, d_roms.p, d_items.p, nitems, slot_a, slot_v,
+                           wsA.p, wsP.p, wsX.p, wsR.p, wsB.p, wsD.p, 1, 10, 1e-14, d_stats.p, q_lds);
     } else {
-        hipLaunchKernelGGL(k_sweep<double>, dim3(grid), dim3(kWG), 0, s, d_roms.p, d_items.p, (int)items.size(), slot_a,
-                           slot_v, wsA.p, wsP.p, wsX.p, wsR.p, wsB.p, wsD.p, refine ? 1 : 0, 10, 1e-14, d_stats.p);
+        if (dyn > 65536) CR_HIP(hipFuncSetAttribute((const void*)k_sweep<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
+        hipLaunchKernelGGL(k_sweep<double>, dim3(grid), dim3(kWG), dyn, s, d_roms.p, d_items.p, nitems, slot_a, slot_v,
+                           wsA.p, wsP.p, wsX.p, wsR.p, wsB.p, wsD.p, refine ? 1 : 0, 10, 1e-14, d_stats.p, q_lds);
     }
     CR_HIP(hipGetLastError());
-    int st[8];
-    CR_HIP(hipMemcpyAsync(st, d_stats.p, sizeof(st), hipMemcpyDeviceToHost, s));
+}
+
+void SweepEngine::read_stats(hipStream_t s, int* max_its, int* not_conv, int* perturbed, int* fallbacks) {
+    int st[8] = {0};
+    if (nitems > 0) CR_HIP(hipMemcpyAsync(st, d_stats.p, sizeof(st), hipMemcpyDeviceToHost, s));
     CR_HIP(hipStreamSynchronize(s));
     *max_its = st[0];
     *not_conv = st[1];
     *perturbed = st[2];
     if (fallbacks) *fallbacks = st[3];
+}
+
+void SweepEngine::run(const std::vector<RomDesc>& roms, const std::vector<int2>& items, cr_precision prec, bool refine,
+                      hipStream_t s, int* max_its, int* not_conv, int* perturbed, int grid_override, int* fallbacks) {
+    prepare(roms, items, s);
+    const int gpc = grid_override > 0 ? std::max(1, grid_override / num_cu) : 2;
+    launch(prec, refine, gpc, 0, s);
+    read_stats(s, max_its, not_conv, perturbed, fallbacks);
+}
+
+// Autotune the launch shape on a stratified sample of the prepared items (every k-th item, so
+// the sample keeps the order mix): workgroups per CU in {1, 2, 4} x LDS budget in
+// {0, 32 KB, 64 KB, 120 KB}. Returns the best (grid_per_cu, lds_bytes) and fills the timings.
+void SweepEngine::autotune(const std::vector<RomDesc>& roms, const std::vector<int2>& items, cr_precision prec,
+                           bool refine, hipStream_t s, int* best_gpc, int* best_lds, std::vector<double>* ms) {
+    const int target = 32 * num_cu;   // enough items that every shape runs several per workgroup
+    std::vector<int2> sample;
+    const size_t stride = std::max<size_t>(1, items.size() / (size_t)target);
+    for (size_t i = 0; i < items.size(); i += stride) sample.push_back(items[i]);
+    prepare(roms, sample, s);
+    const int gpcs[3] = {1, 2, 4};
+    const int ldss[4] = {0, 32768, 65536, 98304};   // static LDS of the kernel is ~50 KB of 160 KB
+    hipEvent_t e0, e1;
+    CR_HIP(hipEventCreate(&e0));
+    CR_HIP(hipEventCreate(&e1));
+    double best = 1e300;
+    *best_gpc = 2;
+    *best_lds = 0;
+    if (ms) ms->clear();
+    for (int g : gpcs)
+        for (int l : ldss) {
+            float t = 0;
+            try {
+                launch(prec, refine, g, l, s);   // warm (allocation, code load)
+                CR_HIP(hipEventRecord(e0, s));
+                launch(prec, refine, g, l, s);
+                CR_HIP(hipEventRecord(e1, s));
+                CR_HIP(hipEventSynchronize(e1));
+                CR_HIP(hipEventElapsedTime(&t, e0, e1));
+            } catch (const Error&) {
+                (void)hipGetLastError();   // a shape the device refuses (e.g. LDS budget): skip it
+                CR_HIP(hipStreamSynchronize(s));
+                if (ms) ms->push_back(-1.0);
+                continue;
+            }
+            if (ms) ms->push_back(t);
+            if (t < best) { best = t; *best_gpc = g; *best_lds = l; }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    prepare(roms, items, s);
 }
 
 }  // namespace cr
