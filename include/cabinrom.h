@@ -155,6 +155,14 @@ typedef struct {
    assembly tree, front index maps. Idempotent. */
 cr_status cr_analyse(cr_sys sys, cr_analysis_info* info);
 
+/* Front classes used by the numeric kernels, set before cr_analyse (CR_E_STATE after): fronts of
+   order m >= big_m (default 192, >= 32) are factored by 16-column panels with their updates spread
+   over many workgroups and the trailing update as a complex GEMM on the matrix cores; fronts with
+   m >= huge_m (default 1024, >= 64) are solved 64 pivots at a time with their rows spread over
+   many workgroups. Smaller fronts are factored and solved by one workgroup each. The classes
+   change the schedule, not the arithmetic's definition (same pivots up to rounding). */
+cr_status cr_set_front_classes(cr_sys sys, int32_t big_m, int32_t huge_m);
+
 /* ---------------------------------------------------------------- factor / solve --------- */
 
 typedef struct { int32_t n_perturbed; double seconds; } cr_factor_info;

@@ -34,6 +34,9 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_2310_04734_amd.build.build() "
                           "(there is no CPU fallback)")
+    # torch first: the library then binds the HIP runtime torch already loaded (same soname), so
+    # device memory and streams from torch and the library's kernels live in one runtime
+    import torch  # noqa: F401
     return C.CDLL(LIB_PATH)
 
 
@@ -128,6 +131,7 @@ _sig("cr_sys_get_dims", I32, P, C.POINTER(cr_sys_dims))
 _sig("cr_sys_export", I32, P, P, P, P, P, P, P, P)
 _sig("cr_sys_destroy", None, P)
 _sig("cr_analyse", I32, P, C.POINTER(cr_analysis_info))
+_sig("cr_set_front_classes", I32, P, I32, I32)
 _sig("cr_factor", I32, P, D, I32, C.POINTER(P), C.POINTER(cr_factor_info))
 _sig("cr_fact_destroy", None, P)
 _sig("cr_solve", I32, P, I32, P, P, C.POINTER(cr_ir_opts), C.POINTER(cr_solve_info))
@@ -242,6 +246,9 @@ class System:
                                          _ptr(recv)))
         return dict(rowptr=rowptr, col=col, K=K, M=M, F=F.T.copy(), flags=flags[:self.L], recv=recv[:self.n_o])
 
+    def set_front_classes(self, big_m=192, huge_m=1024):
+        self.ctx.check(lib.cr_set_front_classes(self.h, int(big_m), int(huge_m)))
+
     def analyse(self):
         info = cr_analysis_info()
         self.ctx.check(lib.cr_analyse(self.h, C.byref(info)))
@@ -286,7 +293,7 @@ class System:
         return b
 
     def __del__(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and lib is not None:
             lib.cr_sys_destroy(self.h)
             self.h = None
 
@@ -341,7 +348,7 @@ class Factor:
         return X.t() if B.dim() == 2 else X.reshape(-1)
 
     def __del__(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and lib is not None:
             lib.cr_fact_destroy(self.h)
             self.h = None
 
@@ -367,7 +374,7 @@ class Basis:
         return Rom(self.sys.ctx, h)
 
     def __del__(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and lib is not None:
             lib.cr_basis_destroy(self.h)
             self.h = None
 
@@ -415,7 +422,7 @@ class Rom:
         return Y
 
     def __del__(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and lib is not None:
             lib.cr_rom_destroy(self.h)
             self.h = None
 
@@ -471,7 +478,7 @@ class Mlp:
         return loss.value
 
     def __del__(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and lib is not None:
             lib.cr_mlp_destroy(self.h)
             self.h = None
 
@@ -524,7 +531,7 @@ class SweepPlan:
         return dict(variant=ch.variant, grid_per_cu=ch.grid_per_cu, lds_kib=ch.nb, sample_ms=ms[:n.value].tolist())
 
     def __del__(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and lib is not None:
             lib.cr_sweep_plan_destroy(self.h)
             self.h = None
 

@@ -134,7 +134,8 @@ struct Builder {
 }  // namespace
 
 std::unique_ptr<Symbolic> analyse_pattern(int64_t n, const std::vector<int64_t>& rowptr,
-                                          const std::vector<int32_t>& col, const std::vector<double>& coords) {
+                                          const std::vector<int32_t>& col, const std::vector<double>& coords,
+                                          const FrontClasses& fc) {
     auto t0 = std::chrono::steady_clock::now();
     CR_REQUIRE(n > 0 && (int64_t)rowptr.size() == n + 1, CR_E_INVALID, "analyse: bad pattern");
     Builder b(n, rowptr, col, coords);
@@ -268,41 +269,34 @@ std::unique_ptr<Symbolic> analyse_pattern(int64_t n, const std::vector<int64_t>&
             S.ent_dst[k] = local(f, i) + local(f, j) * S.fsize[f];
         }
     S.piv_off.assign(S.first.begin(), S.first.end());
-    // large fronts: panel steps of kPanel columns, update tiles of kUpd x kUpd
-    constexpr int kBigFront = 192, kPanel = 16, kUpd = 64;
+    // large fronts: factored by 16-column panels with deferred 64-column trailing GEMMs spread
+    // over many workgroups; per level the list of large fronts and the number of panel steps
+    constexpr int kPanel = 16;
     S.big.assign(nf, 0);
     S.big_off.assign(S.nlevel + 1, 0);
     S.nsteps.assign(S.nlevel, 0);
-    S.step_off.assign(S.nlevel + 1, 0);
-    S.tile_off.clear();
-    S.tiles.clear();
+    S.huge.assign(nf, 0);
+    S.huge_off.assign(S.nlevel + 1, 0);
+    S.huge_piv.assign(S.nlevel, 0);
     for (int l = 0; l < S.nlevel; ++l) {
         int steps = 0;
         for (int q = S.level_off[l]; q < S.level_off[l + 1]; ++q) {
             const int f = S.level_fronts[q];
-            if (S.fsize[f] >= kBigFront && S.npiv[f] > 0) {
+            if (S.fsize[f] >= fc.big_m && S.npiv[f] > 0) {
                 S.big[f] = 1;
                 S.big_list.push_back(f);
                 steps = std::max(steps, (S.npiv[f] + kPanel - 1) / kPanel);
             }
-        }
-        S.big_off[l + 1] = (int32_t)S.big_list.size();
-        S.nsteps[l] = steps;
-        S.step_off[l] = (int64_t)S.tile_off.size();
-        for (int j = 0; j < steps; ++j) {
-            S.tile_off.push_back((int64_t)S.tiles.size());
-            for (int q = S.big_off[l]; q < S.big_off[l + 1]; ++q) {
-                const int f = S.big_list[q];
-                const int m = S.fsize[f], p = S.npiv[f], k0 = j * kPanel;
-                if (k0 >= p) continue;
-                const int k1 = std::min(k0 + kPanel, p);
-                for (int j0 = k1; j0 < m; j0 += kUpd)
-                    for (int i0 = k1; i0 < m; i0 += kUpd) S.tiles.push_back(make_int4(f, i0, j0, k0));
+            if (S.fsize[f] >= fc.huge_m && S.npiv[f] > 0) {
+                S.huge[f] = 1;
+                S.huge_list.push_back(f);
+                S.huge_piv[l] = std::max(S.huge_piv[l], S.npiv[f]);
             }
         }
-        S.tile_off.push_back((int64_t)S.tiles.size());
+        S.big_off[l + 1] = (int32_t)S.big_list.size();
+        S.huge_off[l + 1] = (int32_t)S.huge_list.size();
+        S.nsteps[l] = steps;
     }
-    S.step_off[S.nlevel] = (int64_t)S.tile_off.size();
     S.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return sym;
 }

@@ -378,11 +378,21 @@ cr_status cr_sys_export(cr_sys sys, int64_t* rowptr, int32_t* col, cr_z* K, cr_z
 
 void cr_sys_destroy(cr_sys sys) { delete sys; }
 
+cr_status cr_set_front_classes(cr_sys sys, int32_t big_m, int32_t huge_m) {
+    if (!sys) return CR_E_INVALID;
+    return cr_guard(sys->ctx, [&] {
+        CR_REQUIRE(!sys->sym, CR_E_STATE, "cr_set_front_classes: call before cr_analyse");
+        CR_REQUIRE(big_m >= 32 && huge_m >= 64, CR_E_INVALID, "cr_set_front_classes: thresholds too small");
+        sys->fclass.big_m = big_m;
+        sys->fclass.huge_m = huge_m;
+    });
+}
+
 cr_status cr_analyse(cr_sys sys, cr_analysis_info* info) {
     if (!sys) return CR_E_INVALID;
     return cr_guard(sys->ctx, [&] {
         if (!sys->sym) {
-            sys->sym = analyse_pattern(sys->n, sys->rowptr, sys->col, sys->coords);
+            sys->sym = analyse_pattern(sys->n, sys->rowptr, sys->col, sys->coords, sys->fclass);
             upload_symbolic(sys);
         }
         if (info) {

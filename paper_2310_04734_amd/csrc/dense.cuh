@@ -80,12 +80,13 @@ struct LuShared {
 
 // Panel step of the partial LU of the m x m column-major A (leading dimension lda): factor
 // columns [k0, k1) over rows [k0, m) with pivots searched among the fully-summed rows [k, p)
-// (ipiv[k] = row swapped with k; the swap is applied to whole rows), then U12 rows
-// [k0, k1) x columns [k1, m) = L_kk^{-1} A (unit lower). Pivots with cabs1 <= tiny (or NaN)
-// are replaced by tiny in their own direction and counted in *nperturb.
+// (ipiv[k] = row swapped with k; the swap is applied to columns [sw0, sw1) of the two rows),
+// then, when trsm is set, U12 rows [k0, k1) x columns [k1, m) = L_kk^{-1} A (unit lower).
+// Pivots with cabs1 <= tiny (or NaN) are replaced by tiny in their own direction and counted
+// in *nperturb.
 template <typename T>
 __device__ void wg_panel(cx<T>* __restrict__ A, int lda, int m, int p, int k0, int k1, int* __restrict__ ipiv, T tiny,
-                         int* nperturb, LuShared<T>& sh) {
+                         int* nperturb, LuShared<T>& sh, int sw0, int sw1, bool trsm) {
     const int t = threadIdx.x;
     for (int k = k0; k < k1; ++k) {
         T best = T(-1);
@@ -99,7 +100,7 @@ __device__ void wg_panel(cx<T>* __restrict__ A, int lda, int m, int p, int k0, i
         wg_argmax(best, bi, sh.red_v, sh.red_i, pv, pi);
         if (t == 0) ipiv[k] = pi;
         if (pi != k) {
-            for (int j = t; j < m; j += kWG) {
+            for (int j = sw0 + t; j < sw1; j += kWG) {
                 cx<T> x = A[k + (size_t)j * lda], y = A[pi + (size_t)j * lda];
                 A[k + (size_t)j * lda] = y;
                 A[pi + (size_t)j * lda] = x;
@@ -130,7 +131,7 @@ __device__ void wg_panel(cx<T>* __restrict__ A, int lda, int m, int p, int k0, i
         }
         __syncthreads();
     }
-    if (k1 >= m) return;
+    if (!trsm || k1 >= m) return;
     // U12 block: solve L_kk X = A[k0:k1, k1:m] (unit lower)
     for (int j = k1 + t; j < m; j += kWG) {
         cx<T> x[kNB];
@@ -210,7 +211,7 @@ __device__ void wg_getrf(cx<T>* __restrict__ A, int lda, int m, int p, int* __re
                          LuShared<T>& sh) {
     for (int k0 = 0; k0 < p; k0 += kNB) {
         const int k1 = min(k0 + kNB, p);
-        wg_panel<T>(A, lda, m, p, k0, k1, ipiv, tiny, nperturb, sh);
+        wg_panel<T>(A, lda, m, p, k0, k1, ipiv, tiny, nperturb, sh, 0, m, true);
         if (k1 >= m) break;
         const int tiles = (m - k1 + kTile - 1) / kTile;
         for (int tile = 0; tile < tiles * tiles; ++tile)

@@ -18,6 +18,7 @@
 #include <cstring>
 
 #include "dense.cuh"
+#include "gemm.cuh"
 #include "internal.h"
 #include "util.cuh"
 
@@ -73,7 +74,17 @@ __global__ void __launch_bounds__(kWG) k_front_factor(const int32_t* __restrict_
     wg_getrf<T>(arena + front_off[f], m, m, p, ipiv + first[f], tiny, nperturb, sh);
 }
 
-// large fronts, panel step j: one workgroup per front factors columns [16j, 16j + 16)
+// Large fronts are factored by 64-column blocks of four 16-column panels. Panel step j:
+//   k_front_colstrip  (not the block's first panel) the panel's columns, rows [k0, m), receive
+//                     the block's earlier panels (rows tiled over workgroups);
+//   k_front_panel     one workgroup per front: pivots, scaling and the in-panel updates, row
+//                     swaps applied inside the block's columns [K0, k1) only;
+//   k_front_rowstrip  columns tiled over workgroups: the panel's row swaps on columns [k1, m)
+//                     and [0, K0), then rows [k0, k1) of columns [k1, m) receive the block's
+//                     earlier panels and are solved with the panel's unit-lower diagonal block;
+//   k_front_gemm      after the block's last panel: trailing GEMM with K = 64 on MFMA.
+// Swaps are applied before any update of the current block touches the swapped rows outside
+// the block's columns, so both rows of a swap are always in the same state.
 template <typename T>
 __global__ void __launch_bounds__(kWG) k_front_panel(const int32_t* __restrict__ big_list, int step,
                                                     const int32_t* __restrict__ fsize, const int32_t* __restrict__ npiv,
@@ -84,18 +95,96 @@ __global__ void __launch_bounds__(kWG) k_front_panel(const int32_t* __restrict__
     const int f = big_list[blockIdx.x];
     const int m = fsize[f], p = npiv[f], k0 = step * kNB;
     if (k0 >= p) return;
-    wg_panel<T>(arena + front_off[f], m, m, p, k0, min(k0 + kNB, p), ipiv + first[f], tiny, nperturb, sh);
+    const int K0 = (k0 / kOB) * kOB, k1 = min(k0 + kNB, p);
+    wg_panel<T>(arena + front_off[f], m, m, p, k0, k1, ipiv + first[f], tiny, nperturb, sh, K0, k1, false);
 }
 
-// large fronts, trailing update after a panel step: one 64 x 64 tile per workgroup
 template <typename T>
-__global__ void __launch_bounds__(kWG) k_front_tiles(const int4* __restrict__ tiles, const int32_t* __restrict__ fsize,
-                                                    const int32_t* __restrict__ npiv, const int64_t* __restrict__ front_off,
-                                                    cx<T>* __restrict__ arena) {
-    __shared__ LuShared<T> sh;
-    const int4 tl = tiles[blockIdx.x];
-    const int f = tl.x, m = fsize[f], p = npiv[f];
-    wg_tile_update<T>(arena + front_off[f], m, m, tl.w, min(tl.w + kNB, p), tl.y, tl.z, sh);
+__global__ void __launch_bounds__(kWG) k_front_colstrip(const int32_t* __restrict__ big_list, int step,
+                                                       const int32_t* __restrict__ fsize, const int32_t* __restrict__ npiv,
+                                                       const int64_t* __restrict__ front_off, cx<T>* __restrict__ arena) {
+    __shared__ StripShared<T> sh;
+    const int f = big_list[blockIdx.y];
+    const int m = fsize[f], p = npiv[f], k0 = step * kNB;
+    if (k0 >= p) return;
+    const int K0 = (k0 / kOB) * kOB, k1 = min(k0 + kNB, p);
+    const int r0 = k0 + kOB * (int)blockIdx.x;
+    if (r0 >= m || K0 == k0) return;
+    wg_strip_update<T>(arena + front_off[f], m, r0, min(kOB, m - r0), k0, k1 - k0, K0, k0 - K0, sh);
+}
+
+template <typename T>
+struct RowStripShared {
+    StripShared<T> st;
+    cx<T> d[kNB][kNB + 1];   // unit-lower diagonal block of the panel
+};
+
+template <typename T>
+__global__ void __launch_bounds__(kWG) k_front_rowstrip(const int32_t* __restrict__ big_list, int step,
+                                                       const int32_t* __restrict__ fsize, const int32_t* __restrict__ npiv,
+                                                       const int32_t* __restrict__ first, const int64_t* __restrict__ front_off,
+                                                       const int32_t* __restrict__ ipiv, cx<T>* __restrict__ arena) {
+    __shared__ RowStripShared<T> sh;
+    const int f = big_list[blockIdx.y];
+    const int m = fsize[f], p = npiv[f], k0 = step * kNB;
+    if (k0 >= p) return;
+    const int K0 = (k0 / kOB) * kOB, k1 = min(k0 + kNB, p), nb = k1 - k0;
+    const int nright = (m - k1 + kOB - 1) / kOB, nleft = (K0 + kOB - 1) / kOB;
+    const int x = blockIdx.x;
+    if (x >= nright + nleft) return;
+    const bool right = x < nright;
+    const int c0 = right ? k1 + kOB * x : kOB * (x - nright);
+    const int nc = right ? min(kOB, m - c0) : min(kOB, K0 - c0);
+    cx<T>* A = arena + front_off[f];
+    const int32_t* pv = ipiv + first[f];
+    const int t = threadIdx.x;
+    // the panel's swaps, in order, on this tile's columns
+    if (t < nc) {
+        cx<T>* col = A + (size_t)(c0 + t) * m;
+        for (int k = k0; k < k1; ++k) {
+            const int r = pv[k];
+            if (r != k) { cx<T> a = col[k]; col[k] = col[r]; col[r] = a; }
+        }
+    }
+    if (!right) return;
+    __syncthreads();
+    if (K0 < k0) wg_strip_update<T>(A, m, k0, nb, c0, nc, K0, k0 - K0, sh.st);
+    for (int e = t; e < kNB * kNB; e += kWG) {
+        const int i = e % kNB, k = e / kNB;
+        sh.d[i][k] = (i < nb && k < nb) ? A[k0 + i + (size_t)(k0 + k) * m] : cx<T>{T(0), T(0)};
+    }
+    __syncthreads();
+    if (t < nc) {
+        cx<T>* col = A + (size_t)(c0 + t) * m;
+        cx<T> xv[kNB];
+#pragma unroll
+        for (int r = 0; r < kNB; ++r) xv[r] = r < nb ? col[k0 + r] : cx<T>{T(0), T(0)};
+#pragma unroll
+        for (int r = 1; r < kNB; ++r)
+#pragma unroll
+            for (int q = 0; q < r; ++q) xv[r] = cfms(xv[r], sh.d[r][q], xv[q]);
+#pragma unroll
+        for (int r = 0; r < kNB; ++r)
+            if (r < nb) col[k0 + r] = xv[r];
+    }
+}
+
+// large fronts, after 64-column block b: trailing GEMM S -= L21 U12 on MFMA, one 64 x 64 tile
+// per workgroup (blockIdx.y = front)
+template <typename T>
+__global__ void __launch_bounds__(kWG) k_front_gemm(const int32_t* __restrict__ big_list, int blk,
+                                                   const int32_t* __restrict__ fsize, const int32_t* __restrict__ npiv,
+                                                   const int64_t* __restrict__ front_off, cx<T>* __restrict__ arena) {
+    __shared__ GemmShared<T> sh;
+    const int f = big_list[blockIdx.y];
+    const int m = fsize[f], p = npiv[f], K0 = blk * kOB;
+    if (K0 >= p) return;
+    const int K1 = min(K0 + kOB, p);
+    if (K1 >= m) return;
+    const int nt = (m - K1 + kGT - 1) / kGT;
+    const int x = blockIdx.x;
+    if (x >= nt * nt) return;
+    wg_gemm_tile<T>(arena + front_off[f], m, m, K0, K1 - K0, K1 + kGT * (x % nt), K1 + kGT * (x / nt), sh);
 }
 
 // ------------------------------------------------------------------ solves
@@ -125,6 +214,7 @@ struct SolveShared {
 template <typename T>
 struct SolveArgs {
     const int32_t *fsize, *npiv, *first, *child_off, *child_list, *cmap, *idx, *parent, *ipiv;
+    const int32_t* huge;     // per front: 1 = triangular parts done by the multi-workgroup kernels
     const int64_t *front_off, *idx_off, *cmap_off;
     const cx<T>* arena;
     cx<T>* x;
@@ -175,6 +265,7 @@ __device__ void front_fwd(int f, const SolveArgs<T>& a, SolveShared<T>& sh) {
         }
     }
     __syncthreads();
+    if (a.huge[f]) return;
     for (int kb = 0; kb < p; kb += kSB) {
         const int nb = min(kSB, p - kb);
         for (int e = t; e < kSB * kSB; e += kWG) {
@@ -235,6 +326,7 @@ __device__ void front_bwd(int f, const SolveArgs<T>& a, SolveShared<T>& sh) {
         const int r = e % m, l = e / m;
         w[e] = x[ix[r] + (size_t)l * ldx];
     }
+    if (a.huge[f]) return;
     __syncthreads();
     // y_piv -= U12 x_cb, the contribution columns taken kSB at a time through LDS
     const int c = m - p;
@@ -324,6 +416,150 @@ __global__ void __launch_bounds__(kWG) k_front_bwd(const int32_t* __restrict__ l
     front_bwd<T>(level_fronts[blockIdx.x], a, sh);
 }
 
+// ---- the largest fronts: triangular solves by 64-pivot blocks with the rows spread over
+// workgroups (one launch per block). Every workgroup solves the block's diagonal system itself
+// from the unmodified work values (no workgroup writes them in that launch); workgroup 0 stores
+// the solved values to x; each workgroup then updates its own 64 rows of the work vector.
+
+// diagonal block of pivots [kb, kb + nb) into sh.d (lower = unit L, upper = U), the block's
+// solved values into sh.y (kSR right-hand sides starting at l0) and, for blockIdx.x == 0, x
+template <typename T>
+__device__ void huge_diag_solve(const cx<T>* F, int m, int kb, int nb, const cx<T>* w, int l0, int nr, bool upper,
+                                cx<T>* xout, int64_t ldx, SolveShared<T>& sh) {
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    for (int lr = wave; lr < nr; lr += kWG / 64) {
+        const cx<T>* wl = w + (size_t)(l0 + lr) * m;
+        cx<T> wi = lane < nb ? wl[kb + lane] : cx<T>{T(0), T(0)};
+        if (!upper) {
+            for (int k = 0; k < nb - 1; ++k) {
+                const cx<T> wk = shfl_cx(wi, k);
+                if (lane > k) wi = cfms(wi, sh.d[lane][k], wk);
+            }
+        } else {
+            for (int k = nb - 1; k >= 0; --k) {
+                if (lane == k) wi = cmul(wi, crecip(sh.d[k][k]));
+                const cx<T> xk = shfl_cx(wi, k);
+                if (lane < k) wi = cfms(wi, sh.d[lane][k], xk);
+            }
+        }
+        sh.y[lane][lr] = wi;
+        if (blockIdx.x == 0 && lane < nb) xout[kb + lane + (size_t)(l0 + lr) * ldx] = wi;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kWG) k_huge_fwd(const int32_t* __restrict__ huge_list, int kb, SolveArgs<T> a) {
+    __shared__ SolveShared<T> sh;
+    const int f = huge_list[blockIdx.y];
+    const int m = a.fsize[f], p = a.npiv[f];
+    if (kb >= p) return;
+    const int nb = min(kSB, p - kb), r0 = kb + nb + kSB * (int)blockIdx.x;
+    if (blockIdx.x > 0 && r0 >= m) return;
+    const cx<T>* F = a.arena + a.front_off[f];
+    cx<T>* w = a.work + a.idx_off[f] * a.nrhs;
+    const int t = threadIdx.x;
+    for (int e = t; e < kSB * kSB; e += kWG) {
+        const int i = e % kSB, k = e / kSB;
+        sh.d[i][k] = (i < nb && k < nb) ? F[kb + i + (size_t)(kb + k) * m] : cx<T>{T(0), T(0)};
+    }
+    for (int l0 = 0; l0 < a.nrhs; l0 += kSR) {
+        const int nr = min(kSR, a.nrhs - l0);
+        __syncthreads();
+        huge_diag_solve<T>(F, m, kb, nb, w, l0, nr, false, a.x + a.first[f], a.ldx, sh);
+        __syncthreads();
+        // rows [r0, r0 + 64): w[r] -= F[r, kb:kb+nb] y
+        const int rows = min(kSB, m - r0);
+        for (int e = t; e < rows * nr; e += kWG) {
+            const int r = r0 + e % rows, lr = e / rows;
+            cx<T> acc = w[r + (size_t)(l0 + lr) * m];
+            const cx<T>* Fr = F + r + (size_t)kb * m;
+#pragma unroll 16
+            for (int k = 0; k < nb; ++k) acc = cfms(acc, Fr[(size_t)k * m], sh.y[k][lr]);
+            w[r + (size_t)(l0 + lr) * m] = acc;
+        }
+    }
+}
+
+// y_piv -= U12 x_cb for 64 pivot rows per workgroup (all contribution columns)
+template <typename T>
+__global__ void __launch_bounds__(kWG) k_huge_bwd_cb(const int32_t* __restrict__ huge_list, SolveArgs<T> a) {
+    __shared__ SolveShared<T> sh;
+    const int f = huge_list[blockIdx.y];
+    const int m = a.fsize[f], p = a.npiv[f], c = m - p;
+    const int r0 = kSB * (int)blockIdx.x;
+    if (r0 >= p) return;
+    const int rows = min(kSB, p - r0);
+    const cx<T>* F = a.arena + a.front_off[f];
+    cx<T>* w = a.work + a.idx_off[f] * a.nrhs;
+    const int t = threadIdx.x;
+    for (int l0 = 0; l0 < a.nrhs; l0 += kSR) {
+        const int nr = min(kSR, a.nrhs - l0);
+        // each thread owns up to 4 (row, rhs) pairs of this workgroup's 64 x nr outputs
+        cx<T> acc[4];
+        for (int g = 0; g < 4; ++g) {
+            const int e = g * kWG + t;
+            acc[g] = e < rows * nr ? w[r0 + e % rows + (size_t)(l0 + e / rows) * m] : cx<T>{T(0), T(0)};
+        }
+        for (int s0 = 0; s0 < c; s0 += kSB) {
+            const int ns = min(kSB, c - s0);
+            __syncthreads();
+            for (int e = t; e < kSB * kSR; e += kWG) {
+                const int si = e % kSB, lr = e / kSB;
+                sh.y[si][lr] = (si < ns && lr < nr) ? w[p + s0 + si + (size_t)(l0 + lr) * m] : cx<T>{T(0), T(0)};
+            }
+            __syncthreads();
+            for (int g = 0; g < 4; ++g) {
+                const int e = g * kWG + t;
+                if (e >= rows * nr) break;
+                const int r = r0 + e % rows, lr = e / rows;
+                const cx<T>* Fr = F + r + (size_t)(p + s0) * m;
+                cx<T> v = acc[g];
+#pragma unroll 16
+                for (int k = 0; k < ns; ++k) v = cfms(v, Fr[(size_t)k * m], sh.y[k][lr]);
+                acc[g] = v;
+            }
+        }
+        for (int g = 0; g < 4; ++g) {
+            const int e = g * kWG + t;
+            if (e < rows * nr) w[r0 + e % rows + (size_t)(l0 + e / rows) * m] = acc[g];
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kWG) k_huge_bwd(const int32_t* __restrict__ huge_list, int kb, SolveArgs<T> a) {
+    __shared__ SolveShared<T> sh;
+    const int f = huge_list[blockIdx.y];
+    const int m = a.fsize[f], p = a.npiv[f];
+    if (kb >= p) return;
+    const int nb = min(kSB, p - kb), r0 = kSB * (int)blockIdx.x;
+    if (blockIdx.x > 0 && r0 >= kb) return;
+    const cx<T>* F = a.arena + a.front_off[f];
+    cx<T>* w = a.work + a.idx_off[f] * a.nrhs;
+    const int t = threadIdx.x;
+    for (int e = t; e < kSB * kSB; e += kWG) {
+        const int i = e % kSB, k = e / kSB;
+        sh.d[i][k] = (i < nb && k < nb) ? F[kb + i + (size_t)(kb + k) * m] : cx<T>{T(1), T(0)};
+    }
+    for (int l0 = 0; l0 < a.nrhs; l0 += kSR) {
+        const int nr = min(kSR, a.nrhs - l0);
+        __syncthreads();
+        huge_diag_solve<T>(F, m, kb, nb, w, l0, nr, true, a.x + a.first[f], a.ldx, sh);
+        __syncthreads();
+        // rows [r0, min(r0 + 64, kb)): w[r] -= F[r, kb:kb+nb] x_blk
+        const int rows = max(0, min(kSB, kb - r0));
+        for (int e = t; e < rows * nr; e += kWG) {
+            const int r = r0 + e % rows, lr = e / rows;
+            cx<T> acc = w[r + (size_t)(l0 + lr) * m];
+            const cx<T>* Fr = F + r + (size_t)kb * m;
+#pragma unroll 16
+            for (int k = 0; k < nb; ++k) acc = cfms(acc, Fr[(size_t)k * m], sh.y[k][lr]);
+            w[r + (size_t)(l0 + lr) * m] = acc;
+        }
+    }
+}
+
 // gather (with precision change) B (old numbering, n x nrhs FP64) -> xp (new numbering, T)
 template <typename T>
 __global__ void k_gather_perm(const zd* __restrict__ B, int64_t ldb, const int32_t* __restrict__ perm, int64_t n, int nrhs,
@@ -378,17 +614,46 @@ void run_factor(Factor& f, cr_sys sys, double sigma, cx<T>* arena, T tiny, hipSt
                                D.front_off.p, arena, f.ipiv.p, tiny, f.nperturb.p, D.big.p);
         }
         const int nbig = S.big_off[l + 1] - S.big_off[l];
+        const int32_t* bl = D.big_list.p + S.big_off[l];
         for (int j = 0; j < S.nsteps[l]; ++j) {
+            unsigned gcol = 0, grow = 0;
+            for (int q = S.big_off[l]; q < S.big_off[l + 1]; ++q) {
+                const int f = S.big_list[q], m = S.fsize[f], p = S.npiv[f], k0 = j * kNB;
+                if (k0 >= p) continue;
+                const int K0 = (k0 / kOB) * kOB, k1 = std::min(k0 + kNB, p);
+                gcol = std::max(gcol, (unsigned)((m - k0 + kOB - 1) / kOB));
+                grow = std::max(grow, (unsigned)((m - k1 + kOB - 1) / kOB + (K0 + kOB - 1) / kOB));
+            }
+            if (j % (kOB / kNB) != 0 && gcol) {
+                ProfScope ps(sys->ctx, "front_colstrip", s);
+                hipLaunchKernelGGL(k_front_colstrip<T>, dim3(gcol, nbig), dim3(kWG), 0, s, bl, j, D.fsize.p, D.npiv.p,
+                                   D.front_off.p, arena);
+            }
             {
                 ProfScope ps(sys->ctx, "front_panel", s);
-                hipLaunchKernelGGL(k_front_panel<T>, dim3(nbig), dim3(kWG), 0, s, D.big_list.p + S.big_off[l], j,
-                                   D.fsize.p, D.npiv.p, D.first.p, D.front_off.p, arena, f.ipiv.p, tiny, f.nperturb.p);
+                hipLaunchKernelGGL(k_front_panel<T>, dim3(nbig), dim3(kWG), 0, s, bl, j, D.fsize.p, D.npiv.p, D.first.p,
+                                   D.front_off.p, arena, f.ipiv.p, tiny, f.nperturb.p);
             }
-            const int64_t t0 = S.tile_off[S.step_off[l] + j], t1 = S.tile_off[S.step_off[l] + j + 1];
-            if (t1 > t0) {
-                ProfScope ps(sys->ctx, "front_tiles", s);
-                hipLaunchKernelGGL(k_front_tiles<T>, dim3((unsigned)(t1 - t0)), dim3(kWG), 0, s, D.tiles.p + t0,
-                                   D.fsize.p, D.npiv.p, D.front_off.p, arena);
+            if (grow) {
+                ProfScope ps(sys->ctx, "front_rowstrip", s);
+                hipLaunchKernelGGL(k_front_rowstrip<T>, dim3(grow, nbig), dim3(kWG), 0, s, bl, j, D.fsize.p, D.npiv.p,
+                                   D.first.p, D.front_off.p, f.ipiv.p, arena);
+            }
+            if (j % (kOB / kNB) == kOB / kNB - 1 || j == S.nsteps[l] - 1) {
+                const int blk = j / (kOB / kNB);
+                unsigned gx = 0;
+                for (int q = S.big_off[l]; q < S.big_off[l + 1]; ++q) {
+                    const int f = S.big_list[q], m = S.fsize[f], p = S.npiv[f], K0 = blk * kOB;
+                    if (K0 >= p) continue;
+                    const int K1 = std::min(K0 + kOB, p);
+                    const unsigned nt = (unsigned)((m - K1 + kGT - 1) / kGT);
+                    gx = std::max(gx, nt * nt);
+                }
+                if (gx) {
+                    ProfScope ps(sys->ctx, "front_gemm", s);
+                    hipLaunchKernelGGL(k_front_gemm<T>, dim3(gx, nbig), dim3(kWG), 0, s, bl, blk, D.fsize.p, D.npiv.p,
+                                       D.front_off.p, arena);
+                }
             }
         }
     }
@@ -410,6 +675,7 @@ void run_solve(const Factor& f, int nrhs, cx<T>* xp, cx<T>* work, hipStream_t s,
     a.idx = D.idx.p;
     a.parent = D.parent.p;
     a.ipiv = f.ipiv.p;
+    a.huge = D.huge.p;
     a.front_off = D.front_off.p;
     a.idx_off = D.idx_off.p;
     a.cmap_off = D.cmap_off.p;
@@ -421,13 +687,39 @@ void run_solve(const Factor& f, int nrhs, cx<T>* xp, cx<T>* work, hipStream_t s,
     {
         for (int l = 0; l < S.nlevel; ++l) {
             const int nf = S.level_off[l + 1] - S.level_off[l];
-            ProfScope ps(sys->ctx, "front_fwd", s);
-            hipLaunchKernelGGL(k_front_fwd<T>, dim3(nf), dim3(kWG), 0, s, D.level_fronts.p + S.level_off[l], a);
+            {
+                ProfScope ps(sys->ctx, "front_fwd", s);
+                hipLaunchKernelGGL(k_front_fwd<T>, dim3(nf), dim3(kWG), 0, s, D.level_fronts.p + S.level_off[l], a);
+            }
+            const int nh = S.huge_off[l + 1] - S.huge_off[l];
+            const int32_t* hl = D.huge_list.p + S.huge_off[l];
+            for (int kb = 0; kb < S.huge_piv[l]; kb += kSB) {
+                unsigned gx = 1;
+                for (int q = S.huge_off[l]; q < S.huge_off[l + 1]; ++q) {
+                    const int hf = S.huge_list[q], m = S.fsize[hf], p = S.npiv[hf];
+                    if (kb < p) gx = std::max(gx, (unsigned)((m - std::min(kb + kSB, p) + kSB - 1) / kSB));
+                }
+                ProfScope ps(sys->ctx, "front_fwd_huge", s);
+                hipLaunchKernelGGL(k_huge_fwd<T>, dim3(gx, nh), dim3(kWG), 0, s, hl, kb, a);
+            }
         }
         for (int l = S.nlevel - 1; l >= 0; --l) {
             const int nf = S.level_off[l + 1] - S.level_off[l];
-            ProfScope ps(sys->ctx, "front_bwd", s);
-            hipLaunchKernelGGL(k_front_bwd<T>, dim3(nf), dim3(kWG), 0, s, D.level_fronts.p + S.level_off[l], a);
+            {
+                ProfScope ps(sys->ctx, "front_bwd", s);
+                hipLaunchKernelGGL(k_front_bwd<T>, dim3(nf), dim3(kWG), 0, s, D.level_fronts.p + S.level_off[l], a);
+            }
+            const int nh = S.huge_off[l + 1] - S.huge_off[l];
+            if (nh == 0) continue;
+            const int32_t* hl = D.huge_list.p + S.huge_off[l];
+            {
+                ProfScope ps(sys->ctx, "front_bwd_huge", s);
+                hipLaunchKernelGGL(k_huge_bwd_cb<T>, dim3((S.huge_piv[l] + kSB - 1) / kSB, nh), dim3(kWG), 0, s, hl, a);
+            }
+            for (int kb = ((S.huge_piv[l] - 1) / kSB) * kSB; kb >= 0; kb -= kSB) {
+                ProfScope ps(sys->ctx, "front_bwd_huge", s);
+                hipLaunchKernelGGL(k_huge_bwd<T>, dim3(std::max(1, (kb + kSB - 1) / kSB), nh), dim3(kWG), 0, s, hl, kb, a);
+            }
         }
     }
     CR_HIP(hipGetLastError());
@@ -458,7 +750,8 @@ void upload_symbolic(cr_sys sys) {
     upload(D->iperm, S.iperm, s);
     upload(D->big, S.big, s);
     upload(D->big_list, S.big_list, s);
-    upload(D->tiles, S.tiles, s);
+    upload(D->huge, S.huge, s);
+    upload(D->huge_list, S.huge_list, s);
     CR_HIP(hipStreamSynchronize(s));
     sys->dsym = std::move(D);
 }

@@ -1,0 +1,182 @@
+// Blocked trailing updates of a large front's partial LU on the matrix cores.
+//
+// A large front is factored by outer blocks of kOB = 64 pivot columns, each made of four
+// 16-column panels (wg_panel). Inside an outer block the updates are deferred: before panel s
+// the L-shaped strip it needs -- its own 16 columns below the diagonal and its 16 rows to the
+// right -- receives the contributions of panels 0..s-1 of the block (wg_strip_update); after
+// the block the trailing matrix receives all 64 columns at once, S -= L21 U12 with K = 64
+// (wg_gemm_tile), a complex GEMM on MFMA: v_mfma_f32_16x16x4f32 for complex-FP32 fronts and
+// v_mfma_f64_16x16x4f64 for FP64 fronts, each complex product as four real products into
+// separate real and imaginary accumulators.
+//
+// MFMA 16x16x4 operand layout (lane l of a 64-wide wavefront, checked on gfx950): A[i][k] with
+// i = l % 16, k = l / 16; B[k][j] with j = l % 16, k = l / 16; the accumulator's item r is
+// D[4 (l / 16) + r][l % 16] for the FP32 instruction and D[l / 16 + 4 r][l % 16] for FP64.
+#pragma once
+
+#include "dense.cuh"
+
+namespace cr {
+
+constexpr int kOB = 64;      // outer block (pivot columns per trailing GEMM)
+constexpr int kGT = 64;      // GEMM output tile (kGT x kGT per workgroup, 32 x 32 per wave)
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct MfmaAcc;
+template <>
+struct MfmaAcc<float> {
+    typedef f32x4 type;
+    static __device__ __forceinline__ f32x4 mfma(float a, float b, f32x4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+template <>
+struct MfmaAcc<double> {
+    typedef f64x4 type;
+    static __device__ __forceinline__ f64x4 mfma(double a, double b, f64x4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+
+template <typename T>
+struct GemmShared {
+    static constexpr int KC = sizeof(T) == 4 ? 32 : 16;   // K chunk staged in LDS (~35 KB)
+    cx<T> a[KC][kGT + 4];   // L21 chunk, a[k][i]
+    cx<T> b[KC][kGT + 4];   // U12 chunk, b[k][j]
+};
+
+// C[i0:i0+64, j0:j0+64] -= A[i0:, k0:k0+K] A[k0:k0+K, j0:] inside the m x m column-major front
+// (rows and columns >= m are skipped). 256 threads; wave w owns the 32 x 32 quadrant
+// (32 (w & 1), 32 (w >> 1)) as 2 x 2 blocks of 16 x 16.
+template <typename T>
+__device__ void wg_gemm_tile(cx<T>* __restrict__ A, int lda, int m, int k0, int K, int i0, int j0,
+                             GemmShared<T>& sh) {
+    typedef typename MfmaAcc<T>::type acc_t;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int wi = 32 * (w & 1), wj = 32 * (w >> 1);
+    acc_t are[2][2], aim[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            are[a][b] = acc_t{0, 0, 0, 0};
+            aim[a][b] = acc_t{0, 0, 0, 0};
+        }
+    constexpr int KC = GemmShared<T>::KC;
+    for (int kc = 0; kc < K; kc += KC) {
+        const int nk = min(KC, K - kc);
+        __syncthreads();
+        // L21 chunk: 64 rows x KC columns, coalesced down the columns
+        for (int e = t; e < kGT * KC; e += kWG) {
+            const int i = e % kGT, k = e / kGT;
+            cx<T> v = {T(0), T(0)};
+            if (k < nk && i0 + i < m) v = A[i0 + i + (size_t)(k0 + kc + k) * lda];
+            sh.a[k][i] = v;
+        }
+        // U12 chunk: KC rows x 64 columns, coalesced down the columns
+        for (int e = t; e < kGT * KC; e += kWG) {
+            const int k = e % KC, j = e / KC;
+            cx<T> v = {T(0), T(0)};
+            if (k < nk && j0 + j < m) v = A[k0 + kc + k + (size_t)(j0 + j) * lda];
+            sh.b[k][j] = v;
+        }
+        __syncthreads();
+        const int li = lane & 15, lk = lane >> 4;
+        for (int kk = 0; kk < nk; kk += 4) {
+            cx<T> av[2], bv[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) av[a] = sh.a[kk + lk][wi + 16 * a + li];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) bv[b] = sh.b[kk + lk][wj + 16 * b + li];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    are[a][b] = MfmaAcc<T>::mfma(av[a].re, bv[b].re, are[a][b]);
+                    are[a][b] = MfmaAcc<T>::mfma(-av[a].im, bv[b].im, are[a][b]);
+                    aim[a][b] = MfmaAcc<T>::mfma(av[a].re, bv[b].im, aim[a][b]);
+                    aim[a][b] = MfmaAcc<T>::mfma(av[a].im, bv[b].re, aim[a][b]);
+                }
+        }
+    }
+    // epilogue: each lane owns 4 rows of one column per 16 x 16 block
+    const int lj = lane & 15;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int j = j0 + wj + 16 * b + lj;
+            if (j >= m) continue;
+            cx<T>* col = A + (size_t)j * lda;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = i0 + wi + 16 * a + MfmaAcc<T>::row(lane, r);
+                if (i < m) {
+                    cx<T> x = col[i];
+                    x.re -= are[a][b][r];
+                    x.im -= aim[a][b][r];
+                    col[i] = x;
+                }
+            }
+        }
+}
+
+template <typename T>
+struct StripShared {
+    cx<T> l[kOB][kNB + 1];    // rows x 16 (one panel of K)
+    cx<T> u[kNB][kOB + 1];    // 16 x columns
+};
+
+// C[r0:r0+nr, c0:c0+nc] -= A[r0:r0+nr, k0:k0+K] A[k0:k0+K, c0:c0+nc] with nr, nc <= 64,
+// nr * nc <= 1024 and K a multiple of 16 (the in-block updates before a panel).
+template <typename T>
+__device__ void wg_strip_update(cx<T>* __restrict__ A, int lda, int r0, int nr, int c0, int nc, int k0, int K,
+                                StripShared<T>& sh) {
+    const int t = threadIdx.x;
+    cx<T> acc[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) acc[g] = {T(0), T(0)};
+    for (int kc = 0; kc < K; kc += kNB) {
+        __syncthreads();
+        for (int e = t; e < nr * kNB; e += kWG) {
+            const int i = e % nr, k = e / nr;
+            sh.l[i][k] = A[r0 + i + (size_t)(k0 + kc + k) * lda];
+        }
+        for (int e = t; e < kNB * nc; e += kWG) {
+            const int k = e % kNB, j = e / kNB;
+            sh.u[k][j] = A[k0 + kc + k + (size_t)(c0 + j) * lda];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const int e = t + g * kWG;
+            if (e < nr * nc) {
+                const int i = e % nr, j = e / nr;
+                cx<T> a = acc[g];
+#pragma unroll
+                for (int k = 0; k < kNB; ++k) {
+                    a.re += sh.l[i][k].re * sh.u[k][j].re - sh.l[i][k].im * sh.u[k][j].im;
+                    a.im += sh.l[i][k].re * sh.u[k][j].im + sh.l[i][k].im * sh.u[k][j].re;
+                }
+                acc[g] = a;
+            }
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const int e = t + g * kWG;
+        if (e < nr * nc) {
+            const int i = e % nr, j = e / nr;
+            cx<T>& x = A[r0 + i + (size_t)(c0 + j) * lda];
+            x.re -= acc[g].re;
+            x.im -= acc[g].im;
+        }
+    }
+}
+
+}  // namespace cr

@@ -105,15 +105,15 @@ struct Symbolic {
     std::vector<int64_t> ent_src;    // csr position
     std::vector<int32_t> ent_dst;    // local row + local col * m (fits: m^2 < 2^31)
     int32_t max_front = 0, max_piv = 0, max_children = 0;
-    // large fronts are factored panel by panel with the trailing update spread over many
-    // workgroups: per level the list of large fronts, the panel steps, and per (level, step)
-    // the update tiles (front, row, column, first panel column)
+    // large fronts are factored panel by panel with the trailing updates spread over many
+    // workgroups: per level the list of large fronts and the number of 16-column panel steps
     std::vector<int32_t> big;                  // per front: 1 = large
     std::vector<int32_t> big_off, big_list;    // per level
     std::vector<int32_t> nsteps;               // per level
-    std::vector<int64_t> step_off;             // per level: offset into tile_off
-    std::vector<int64_t> tile_off;             // per (level, step): offset into tiles
-    std::vector<int4> tiles;
+    // the largest fronts are solved block by block with the rows spread over many workgroups
+    std::vector<int32_t> huge;                 // per front: 1 = multi-workgroup solve
+    std::vector<int32_t> huge_off, huge_list;  // per level
+    std::vector<int32_t> huge_piv;             // per level: max pivots of its huge fronts
     int64_t factor_entries = 0;
     double factor_flops = 0;
     double seconds = 0;
@@ -124,16 +124,22 @@ struct DevSymbolic {
     DevBuf<int32_t> first, npiv, fsize, parent, child_off, child_list, level_fronts, idx, cmap, ent_dst;
     DevBuf<int64_t> idx_off, front_off, cmap_off, ent_off, ent_src;
     DevBuf<int32_t> perm, iperm;
-    DevBuf<int32_t> big, big_list;
-    DevBuf<int4> tiles;
+    DevBuf<int32_t> big, big_list, huge, huge_list;
 };
 
 // scale, scaled device copies and norms of a freshly assembled or imported system
 void finalize_sys(cr_sys sys);
 
+// size thresholds of the front classes: m >= big_m factored with many workgroups, m >= huge_m
+// solved with many workgroups
+struct FrontClasses {
+    int32_t big_m = 192, huge_m = 1024;
+};
+
 std::unique_ptr<Symbolic> analyse_pattern(int64_t n, const std::vector<int64_t>& rowptr,
                                           const std::vector<int32_t>& col,
-                                          const std::vector<double>& coords /* n*3 or empty */);
+                                          const std::vector<double>& coords /* n*3 or empty */,
+                                          const FrontClasses& fc);
 
 }  // namespace cr
 
@@ -227,6 +233,7 @@ struct cr_sys_s {
     cr::DevBuf<int64_t> d_recv;
     cr::DevBuf<int32_t> d_flags;
     // analysis
+    cr::FrontClasses fclass;
     std::unique_ptr<cr::Symbolic> sym;
     std::unique_ptr<cr::DevSymbolic> dsym;
 };

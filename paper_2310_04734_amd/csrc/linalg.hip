@@ -9,6 +9,7 @@
 // so every result is bit-reproducible from run to run.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <complex>
 #include <cstring>
 
@@ -414,7 +415,11 @@ int solve_scaled(Factor& f, int nrhs, const zd* B, zd* X, int max_iter, double t
     }
     *berr = be;
     if (strict && !(be <= tol))
-        throw Error(CR_E_NOT_CONVERGED, "iterative refinement stopped at backward error " + std::to_string(be));
+    {
+        char buf[96];
+        std::snprintf(buf, sizeof(buf), "iterative refinement stopped at backward error %.3e after %d steps", be, it);
+        throw Error(CR_E_NOT_CONVERGED, buf);
+    }
     return it;
 }
 

@@ -171,7 +171,10 @@ def fuselage_workload(n_core=36, n_ring=18, h_z=0.04, n_loads=16, n_freq=2000, l
 def fuselage_variants(n_var=64, n_loads=16, n_core=6, n_ring=3, h_z=0.25):
     """Seeded fuselage variants for the learned proposer: length ~ U[2, 5] m, frame pitch
     ~ U[0.4, 0.8] m (frames at pitch (i + 1/2)), skin ~ U[1.5, 3] mm; coarse mesh; n_loads
-    random-phase skin pressures; greedy on 256 candidates 20..300 Hz with 2 blocks per point.
+    random-phase skin pressures; greedy on 256 candidates 20..300 Hz with 2 blocks per point to
+    a relative residual of 1e-3: with ||A|| ||x|| / ||f|| ~ 4e7 on these thin-skin models (after
+    Jacobi scaling) the residual relative to ||f|| stalls near 1e-4 once new Krylov columns fall
+    under the 1e-10 deflation ratio, so 1e-6 is out of reach.
     Returns a list of (Workload, geometry features) and the seeded train/test split (48 / 16)."""
     from .fuselage import fuselage
     rv = SplitMix64(stream_seed(LEARNED_ID, STREAM_VARIANT))
@@ -187,7 +190,7 @@ def fuselage_variants(n_var=64, n_loads=16, n_core=6, n_ring=3, h_z=0.25):
                         air=_air(), metal=plate)
         loads = _skin_loads(mesh, n_loads, stream_seed(LEARNED_ID, 3) * 1000 + 100 * m)
         rec = np.sort(SplitMix64(stream_seed(LEARNED_ID, STREAM_RECEIVERS) + m).sample(fluid_nodes(mesh), 50))
-        rom = dict(mode="greedy", band_hz=(20.0, 300.0), n_cand=256, blocks=2, tol=1e-6, max_shifts=40)
+        rom = dict(mode="greedy", band_hz=(20.0, 300.0), n_cand=256, blocks=2, tol=1e-3, max_shifts=40)
         geom = np.array([(length - 3.5) / 1.5, (pitch - 0.6) / 0.2, (skin - 2.25e-3) / 0.75e-3])
         out.append((Workload(f"fuselage_variant{m}", mesh, loads, rec, np.linspace(20.0, 300.0, 256), rom), geom))
     perm = SplitMix64(stream_seed(LEARNED_ID, STREAM_SPLIT)).sample(np.arange(n_var), n_var)
