@@ -57,7 +57,16 @@ def _roofline(name, launches, ms, an, n_fact, n_solves, elt):
                 "work_per_launch": f"{0.5 * an['factor_entries'] * elt / an['n_levels']:.4g} B "
                                    f"(factor triangle / tree levels)",
                 "launches": launches, "avg_launch_us": 1e3 * ms / launches}
-    if name in ("front_factor", "front_panel", "front_tiles"):
+    if name == "front_gemm":
+        # trailing GEMMs of the large fronts on the matrix cores: exact flops from the analysis
+        flops = an["gemm_flops"] * n_fact
+        peak = PEAK_FP32_TFLOPS if elt == 8 else PEAK_FP64_TFLOPS
+        ach = flops / (ms * 1e-3) / 1e12
+        return {"kernel": name, "bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                "frac": ach / peak, "traffic": None, "launches": launches, "avg_launch_us": 1e3 * ms / launches,
+                "work_per_launch": f"{an['gemm_flops'] * n_fact / launches:.4g} flop (8 (m - K1)^2 (K1 - K0) "
+                                   f"per 64-column block of every large front)"}
+    if name in ("front_factor", "front_panel", "front_colstrip", "front_rowstrip"):
         flops = an["factor_flops"] * n_fact
         peak = PEAK_FP32_TFLOPS if elt == 8 else PEAK_FP64_TFLOPS
         ach = flops / (ms * 1e-3) / 1e12
@@ -217,6 +226,8 @@ def main():
     n_solves = (prof.get("front_fwd", (0, 0))[0] // max(an["n_levels"], 1))
     elt = 16 if h["prec"] == P.CR_FP64 else 8
     roof = _roofline(dom, prof[dom][0], prof[dom][1], an, n_fact, n_solves, elt)
+    gemm = _roofline("front_gemm", prof["front_gemm"][0], prof["front_gemm"][1], an, n_fact, n_solves, elt) \
+        if "front_gemm" in prof else None
     ms_per_step = 1e3 * h["wall"] / a.steps
     out = {
         "metric": "FRF freq x load-cases/sec at rel err <=1e-6 vs FP64 oracle; ROM build time (s)",
@@ -247,6 +258,7 @@ def main():
                                         sorted(r["prof"].items(), key=lambda kv: -kv[1][1])}}
                      for k, r in runs.items()},
         "roofline": roof,
+        "frontal_gemm": gemm,
         "cpu_baseline": cpu,
     }
     if not a.no_batched:

@@ -147,6 +147,8 @@ typedef struct {
     int32_t n_fronts, n_levels, max_front, max_pivots;
     int64_t factor_entries;   /* stored L + U entries (complex)                           */
     double factor_flops;      /* real flops of one numeric factorisation (complex, 4M)    */
+    double gemm_flops;        /* the part of factor_flops done by the trailing GEMMs of the
+                                 large fronts (on the matrix cores)                        */
     double seconds;
 } cr_analysis_info;
 

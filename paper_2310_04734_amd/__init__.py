@@ -72,6 +72,7 @@ class cr_sys_dims(C.Structure):
 class cr_analysis_info(C.Structure):
     _fields_ = [("n_fronts", C.c_int32), ("n_levels", C.c_int32), ("max_front", C.c_int32),
                 ("max_pivots", C.c_int32), ("factor_entries", C.c_int64), ("factor_flops", C.c_double),
+                ("gemm_flops", C.c_double),
                 ("seconds", C.c_double)]
 
 

@@ -286,6 +286,11 @@ std::unique_ptr<Symbolic> analyse_pattern(int64_t n, const std::vector<int64_t>&
                 S.big[f] = 1;
                 S.big_list.push_back(f);
                 steps = std::max(steps, (S.npiv[f] + kPanel - 1) / kPanel);
+                // trailing GEMM after each 64-column block: 8 (m - K1)^2 (K1 - K0) real flops
+                for (int K0 = 0; K0 < S.npiv[f]; K0 += 64) {
+                    const double K1 = std::min(K0 + 64, S.npiv[f]), r = S.fsize[f] - K1;
+                    S.gemm_flops += 8.0 * r * r * (K1 - K0);
+                }
             }
             if (S.fsize[f] >= fc.huge_m && S.npiv[f] > 0) {
                 S.huge[f] = 1;

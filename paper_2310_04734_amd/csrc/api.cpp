@@ -403,6 +403,7 @@ cr_status cr_analyse(cr_sys sys, cr_analysis_info* info) {
             info->max_pivots = S.max_piv;
             info->factor_entries = S.factor_entries;
             info->factor_flops = S.factor_flops;
+            info->gemm_flops = S.gemm_flops;
             info->seconds = S.seconds;
         }
     });

@@ -25,6 +25,9 @@
 namespace cr {
 namespace {
 
+// Front assembly: zero the front, scatter A = K~ - sigma M~ (FP64, rounded once), add the
+// children's contribution blocks. gridDim.y workgroups share one front by owning the parent
+// columns j with j % gridDim.y == blockIdx.y, so no two workgroups touch the same entry.
 template <typename T>
 __global__ void __launch_bounds__(kWG) k_front_assemble(
     const int32_t* __restrict__ level_fronts, const int32_t* __restrict__ fsize, const int64_t* __restrict__ front_off,
@@ -34,15 +37,22 @@ __global__ void __launch_bounds__(kWG) k_front_assemble(
     const zd* __restrict__ M, double sigma, cx<T>* __restrict__ arena) {
     const int f = level_fronts[blockIdx.x];
     const int m = fsize[f];
+    const int S = gridDim.y, y = blockIdx.y, t = threadIdx.x;
     cx<T>* F = arena + front_off[f];
-    const int64_t mm = (int64_t)m * m;
-    for (int64_t e = threadIdx.x; e < mm; e += kWG) F[e] = {T(0), T(0)};
+    if (S == 1) {
+        const int64_t mm = (int64_t)m * m;
+        for (int64_t e = t; e < mm; e += kWG) F[e] = {T(0), T(0)};
+    } else {
+        for (int j = y; j < m; j += S)
+            for (int i = t; i < m; i += kWG) F[i + (size_t)j * m] = {T(0), T(0)};
+    }
     __syncthreads();
-    for (int64_t e = ent_off[f] + threadIdx.x; e < ent_off[f + 1]; e += kWG) {
+    for (int64_t e = ent_off[f] + t; e < ent_off[f + 1]; e += kWG) {
+        const int32_t d = ent_dst[e];
+        if (S > 1 && (d / m) % S != y) continue;
         const int64_t s = ent_src[e];
         const zd k = K[s], mv = M[s];
-        // A = K - sigma M in FP64, then rounded once
-        F[ent_dst[e]] = {T(k.re - sigma * mv.re), T(k.im - sigma * mv.im)};
+        F[d] = {T(k.re - sigma * mv.re), T(k.im - sigma * mv.im)};
     }
     __syncthreads();
     for (int ci = child_off[f]; ci < child_off[f + 1]; ++ci) {
@@ -50,12 +60,27 @@ __global__ void __launch_bounds__(kWG) k_front_assemble(
         const int mc = fsize[c], pc = npiv[c], nc = mc - pc;
         const cx<T>* C = arena + front_off[c];
         const int32_t* map = cmap + cmap_off[c];
-        for (int e = threadIdx.x; e < nc * nc; e += kWG) {
-            const int r = e % nc, s = e / nc;
-            const cx<T> v = C[(pc + r) + (size_t)(pc + s) * mc];
-            cx<T>& d = F[map[r] + (size_t)map[s] * m];
-            d.re += v.re;
-            d.im += v.im;
+        if (S == 1) {
+            for (int e = t; e < nc * nc; e += kWG) {
+                const int r = e % nc, s = e / nc;
+                const cx<T> v = C[(pc + r) + (size_t)(pc + s) * mc];
+                cx<T>& d = F[map[r] + (size_t)map[s] * m];
+                d.re += v.re;
+                d.im += v.im;
+            }
+        } else {
+            for (int s = 0; s < nc; ++s) {
+                const int js = map[s];
+                if (js % S != y) continue;
+                const cx<T>* Cs = C + pc + (size_t)(pc + s) * mc;
+                cx<T>* Fs = F + (size_t)js * m;
+                for (int r = t; r < nc; r += kWG) {
+                    const cx<T> v = Cs[r];
+                    cx<T>& d = Fs[map[r]];
+                    d.re += v.re;
+                    d.im += v.im;
+                }
+            }
         }
         __syncthreads();
     }
@@ -603,8 +628,12 @@ void run_factor(Factor& f, cr_sys sys, double sigma, cx<T>* arena, T tiny, hipSt
         const int nf = S.level_off[l + 1] - S.level_off[l];
         const int32_t* lf = D.level_fronts.p + S.level_off[l];
         {
+            // workgroups per front: one per 256 columns of the level's largest front, at most 64
+            int mmax = 0;
+            for (int q = S.level_off[l]; q < S.level_off[l + 1]; ++q) mmax = std::max(mmax, S.fsize[S.level_fronts[q]]);
+            const unsigned split = (unsigned)std::min(64, std::max(1, mmax / 256));
             ProfScope ps(sys->ctx, "front_assemble", s);
-            hipLaunchKernelGGL(k_front_assemble<T>, dim3(nf), dim3(kWG), 0, s, lf, D.fsize.p, D.front_off.p, D.child_off.p,
+            hipLaunchKernelGGL(k_front_assemble<T>, dim3(nf, split), dim3(kWG), 0, s, lf, D.fsize.p, D.front_off.p, D.child_off.p,
                                D.child_list.p, D.npiv.p, D.cmap_off.p, D.cmap.p, D.ent_off.p, D.ent_src.p, D.ent_dst.p,
                                sys->d_K.p, sys->d_M.p, sigma, arena);
         }

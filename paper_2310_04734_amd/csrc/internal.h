@@ -116,6 +116,7 @@ struct Symbolic {
     std::vector<int32_t> huge_piv;             // per level: max pivots of its huge fronts
     int64_t factor_entries = 0;
     double factor_flops = 0;
+    double gemm_flops = 0;         // trailing-GEMM part of factor_flops (large fronts)
     double seconds = 0;
 };
 

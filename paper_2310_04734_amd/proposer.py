@@ -130,8 +130,14 @@ def compare(ctx, variants, idx, net, prec=CR_FP64):
         s = build_system(ctx, w)
         tg, ig, dg = greedy_run(ctx, w, geom, prec=prec, sys_=s)
         tm, im, dm = greedy_run(ctx, w, geom, policy=CR_POLICY_MLP, mlp=net, prec=prec, sys_=s)
+        tol = w.rom["tol"]
         rows.append(dict(variant=int(m), greedy_shifts=int(len(tg["shift_idx"])), mlp_shifts=int(len(tm["shift_idx"])),
+                         greedy_converged=bool(tg["max_res"][-1] <= tol), mlp_converged=bool(tm["max_res"][-1] <= tol),
                          greedy_maxres=float(tg["max_res"][-1]), mlp_maxres=float(tm["max_res"][-1]),
+                         greedy_factorizations=int(len(tg["shift_idx"]) + ig["fp64_refactorizations"]),
+                         mlp_factorizations=int(len(tm["shift_idx"]) + im["fp64_refactorizations"]),
+                         greedy_block_solves=int(len(tg["shift_idx"]) * w.rom["blocks"]),
+                         mlp_block_solves=int(len(tm["shift_idx"]) * w.rom["blocks"]),
                          greedy_q=int(ig["q"]), mlp_q=int(im["q"]), mlp_accepted=int(tm["mlp_used"].sum()),
                          greedy_s=dg, mlp_s=dm))
         _log(f"compare variant {m}: greedy {rows[-1]['greedy_shifts']} shifts ({dg:.2f} s), proposer "
@@ -152,7 +158,7 @@ def main(argv=None):
     ap.add_argument("--out", required=True)
     ap.add_argument("--variants", type=int, default=64)
     ap.add_argument("--lookahead", type=int, default=8)
-    ap.add_argument("--epochs", type=int, default=300)
+    ap.add_argument("--epochs", type=int, default=150)
     ap.add_argument("--n-core", type=int, default=6)
     ap.add_argument("--n-ring", type=int, default=3)
     ap.add_argument("--h-z", type=float, default=0.25)
@@ -181,8 +187,9 @@ def main(argv=None):
                mesh=dict(n_core=a.n_core, n_ring=a.n_ring, h_z=a.h_z), lookahead=a.lookahead)
     with open(os.path.join(a.out, "proposer_eval.json"), "w") as f:
         json.dump(res, f, indent=1)
-    _log(f"test variants: greedy {res['greedy_shifts']} shifts, proposer {res['mlp_shifts']} shifts; "
-         f"train accuracy {acc:.3f}")
+    _log(f"test variants: greedy {res['greedy_shifts']} shifts, proposer {res['mlp_shifts']} shifts "
+         f"(converged {sum(r['greedy_converged'] for r in rows)} / {sum(r['mlp_converged'] for r in rows)} of "
+         f"{len(rows)}); train accuracy {acc:.3f}")
     return 0
 
 

@@ -24,3 +24,11 @@ def test_mlp_features_definition():
 def test_mlp_features_rejects_bad_arguments():
     with pytest.raises(P.CabinRomError):
         P.mlp_features(np.zeros(0), np.zeros(0, np.int32))
+
+
+def test_trained_proposer_weights_file():
+    import os
+    path = os.path.join(os.path.dirname(P.__file__), "data", "proposer_fuselage.npy")
+    p = np.load(path, allow_pickle=False)
+    n_params = 259 * 256 + 256 + 2 * (256 * 256 + 256) + 256 * 256 + 256
+    assert p.dtype == np.float32 and p.shape == (n_params,) and np.isfinite(p).all()
