@@ -79,22 +79,26 @@ struct LuShared {
 };
 
 // Panel step of the partial LU of the m x m column-major A (leading dimension lda): factor
-// columns [k0, k1) over rows [k0, m) with pivots searched among the fully-summed rows [k, p)
+// columns [k0, k1) over rows [k0, rend) with pivots searched among the fully-summed rows [k, p)
 // (ipiv[k] = row swapped with k; the swap is applied to columns [sw0, sw1) of the two rows),
 // then, when trsm is set, U12 rows [k0, k1) x columns [k1, m) = L_kk^{-1} A (unit lower).
+// rend = m factors the whole panel; rend = p leaves the rows [p, m), which never take part in
+// pivoting, to a separate triangular solve with the panel's U (wg_l21_rows).
+// Per column one pass over the rows scales the column, applies its rank-1 update to the rest
+// of the panel and takes the next column's pivot candidates on the way.
 // Pivots with cabs1 <= tiny (or NaN) are replaced by tiny in their own direction and counted
 // in *nperturb.
 template <typename T>
 __device__ void wg_panel(cx<T>* __restrict__ A, int lda, int m, int p, int k0, int k1, int* __restrict__ ipiv, T tiny,
-                         int* nperturb, LuShared<T>& sh, int sw0, int sw1, bool trsm) {
+                         int* nperturb, LuShared<T>& sh, int sw0, int sw1, bool trsm, int rend) {
     const int t = threadIdx.x;
+    T best = T(-1);
+    int bi = k0;
+    for (int i = k0 + t; i < p; i += kWG) {
+        const T v = cabs1(A[i + (size_t)k0 * lda]);
+        if (v > best) { best = v; bi = i; }
+    }
     for (int k = k0; k < k1; ++k) {
-        T best = T(-1);
-        int bi = k;
-        for (int i = k + t; i < p; i += kWG) {
-            T v = cabs1(A[i + (size_t)k * lda]);
-            if (v > best) { best = v; bi = i; }
-        }
         T pv;
         int pi;
         wg_argmax(best, bi, sh.red_v, sh.red_i, pv, pi);
@@ -116,17 +120,26 @@ __device__ void wg_panel(cx<T>* __restrict__ A, int lda, int m, int p, int k0, i
             if (t == 0) { A[k + (size_t)k * lda] = d; atomicAdd(nperturb, 1); }
         }
         const cx<T> r = crecip(d);
-        for (int i = k + 1 + t; i < m; i += kWG) {
-            cx<T>& x = A[i + (size_t)k * lda];
-            x = cmul(x, r);
-        }
-        __syncthreads();
         const int nc = k1 - k - 1;
-        if (nc > 0) {
-            const int rows = m - k - 1;
-            for (int e = t; e < rows * nc; e += kWG) {
-                int i = k + 1 + e % rows, j = k + 1 + e / rows;
-                A[i + (size_t)j * lda] = cfms(A[i + (size_t)j * lda], A[i + (size_t)k * lda], A[k + (size_t)j * lda]);
+        cx<T> u[kNB - 1];
+#pragma unroll
+        for (int jj = 0; jj < kNB - 1; ++jj) u[jj] = jj < nc ? A[k + (size_t)(k + 1 + jj) * lda] : cx<T>{T(0), T(0)};
+        best = T(-1);
+        bi = k + 1;
+        for (int i = k + 1 + t; i < rend; i += kWG) {
+            const cx<T> l = cmul(A[i + (size_t)k * lda], r);
+            A[i + (size_t)k * lda] = l;
+#pragma unroll
+            for (int jj = 0; jj < kNB - 1; ++jj) {
+                if (jj < nc) {
+                    cx<T>& x = A[i + (size_t)(k + 1 + jj) * lda];
+                    const cx<T> y = cfms(x, l, u[jj]);
+                    x = y;
+                    if (jj == 0 && i < p) {
+                        const T v = cabs1(y);
+                        if (v > best) { best = v; bi = i; }
+                    }
+                }
             }
         }
         __syncthreads();
@@ -211,7 +224,7 @@ __device__ void wg_getrf(cx<T>* __restrict__ A, int lda, int m, int p, int* __re
                          LuShared<T>& sh) {
     for (int k0 = 0; k0 < p; k0 += kNB) {
         const int k1 = min(k0 + kNB, p);
-        wg_panel<T>(A, lda, m, p, k0, k1, ipiv, tiny, nperturb, sh, 0, m, true);
+        wg_panel<T>(A, lda, m, p, k0, k1, ipiv, tiny, nperturb, sh, 0, m, true, m);
         if (k1 >= m) break;
         const int tiles = (m - k1 + kTile - 1) / kTile;
         for (int tile = 0; tile < tiles * tiles; ++tile)

@@ -102,11 +102,12 @@ __global__ void __launch_bounds__(kWG) k_front_factor(const int32_t* __restrict_
 // Large fronts are factored by 64-column blocks of four 16-column panels. Panel step j:
 //   k_front_colstrip  (not the block's first panel) the panel's columns, rows [k0, m), receive
 //                     the block's earlier panels (rows tiled over workgroups);
-//   k_front_panel     one workgroup per front: pivots, scaling and the in-panel updates, row
-//                     swaps applied inside the block's columns [K0, k1) only;
+//   k_front_panel     one workgroup per front: pivots, scaling and the in-panel updates of the
+//                     fully-summed rows [k0, p), row swaps inside the block's columns [K0, k1);
 //   k_front_rowstrip  columns tiled over workgroups: the panel's row swaps on columns [k1, m)
 //                     and [0, K0), then rows [k0, k1) of columns [k1, m) receive the block's
 //                     earlier panels and are solved with the panel's unit-lower diagonal block;
+//                     and rows [p, m) of the panel (one row per thread) solved with its U;
 //   k_front_gemm      after the block's last panel: trailing GEMM with K = 64 on MFMA.
 // Swaps are applied before any update of the current block touches the swapped rows outside
 // the block's columns, so both rows of a swap are always in the same state.
@@ -121,7 +122,7 @@ __global__ void __launch_bounds__(kWG) k_front_panel(const int32_t* __restrict__
     const int m = fsize[f], p = npiv[f], k0 = step * kNB;
     if (k0 >= p) return;
     const int K0 = (k0 / kOB) * kOB, k1 = min(k0 + kNB, p);
-    wg_panel<T>(arena + front_off[f], m, m, p, k0, k1, ipiv + first[f], tiny, nperturb, sh, K0, k1, false);
+    wg_panel<T>(arena + front_off[f], m, m, p, k0, k1, ipiv + first[f], tiny, nperturb, sh, K0, k1, false, p);
 }
 
 template <typename T>
@@ -141,7 +142,8 @@ __global__ void __launch_bounds__(kWG) k_front_colstrip(const int32_t* __restric
 template <typename T>
 struct RowStripShared {
     StripShared<T> st;
-    cx<T> d[kNB][kNB + 1];   // unit-lower diagonal block of the panel
+    cx<T> d[kNB][kNB + 1];   // diagonal block of the panel (unit-lower L and U)
+    cx<T> rd[kNB];           // reciprocals of U's diagonal
 };
 
 template <typename T>
@@ -155,14 +157,41 @@ __global__ void __launch_bounds__(kWG) k_front_rowstrip(const int32_t* __restric
     if (k0 >= p) return;
     const int K0 = (k0 / kOB) * kOB, k1 = min(k0 + kNB, p), nb = k1 - k0;
     const int nright = (m - k1 + kOB - 1) / kOB, nleft = (K0 + kOB - 1) / kOB;
+    const int nl21 = (m - p + kWG - 1) / kWG;
     const int x = blockIdx.x;
-    if (x >= nright + nleft) return;
+    if (x >= nright + nleft + nl21) return;
+    const int t = threadIdx.x;
+    cx<T>* A = arena + front_off[f];
+    if (x >= nright + nleft) {
+        // rows [p, m) of the panel: l_ik = (a_ik - sum_{k' < k} l_ik' u_k'k) / u_kk, in the
+        // order and rounding of the panel's own column steps
+        for (int e = t; e < kNB * kNB; e += kWG) {
+            const int i = e % kNB, k = e / kNB;
+            sh.d[i][k] = (i < nb && k < nb) ? A[k0 + i + (size_t)(k0 + k) * m] : cx<T>{T(1), T(0)};
+        }
+        __syncthreads();
+        if (t < kNB) sh.rd[t] = crecip(sh.d[t][t]);
+        __syncthreads();
+        const int i = p + kWG * (x - nright - nleft) + t;
+        if (i >= m) return;
+        cx<T> a[kNB];
+#pragma unroll
+        for (int k = 0; k < kNB; ++k) a[k] = k < nb ? A[i + (size_t)(k0 + k) * m] : cx<T>{T(0), T(0)};
+#pragma unroll
+        for (int k = 0; k < kNB; ++k) {
+            a[k] = cmul(a[k], sh.rd[k]);
+#pragma unroll
+            for (int j = k + 1; j < kNB; ++j) a[j] = cfms(a[j], a[k], sh.d[k][j]);
+        }
+#pragma unroll
+        for (int k = 0; k < kNB; ++k)
+            if (k < nb) A[i + (size_t)(k0 + k) * m] = a[k];
+        return;
+    }
     const bool right = x < nright;
     const int c0 = right ? k1 + kOB * x : kOB * (x - nright);
     const int nc = right ? min(kOB, m - c0) : min(kOB, K0 - c0);
-    cx<T>* A = arena + front_off[f];
     const int32_t* pv = ipiv + first[f];
-    const int t = threadIdx.x;
     // the panel's swaps, in order, on this tile's columns
     if (t < nc) {
         cx<T>* col = A + (size_t)(c0 + t) * m;
@@ -651,7 +680,8 @@ void run_factor(Factor& f, cr_sys sys, double sigma, cx<T>* arena, T tiny, hipSt
                 if (k0 >= p) continue;
                 const int K0 = (k0 / kOB) * kOB, k1 = std::min(k0 + kNB, p);
                 gcol = std::max(gcol, (unsigned)((m - k0 + kOB - 1) / kOB));
-                grow = std::max(grow, (unsigned)((m - k1 + kOB - 1) / kOB + (K0 + kOB - 1) / kOB));
+                grow = std::max(grow, (unsigned)((m - k1 + kOB - 1) / kOB + (K0 + kOB - 1) / kOB +
+                                                 (m - p + kWG - 1) / kWG));
             }
             if (j % (kOB / kNB) != 0 && gcol) {
                 ProfScope ps(sys->ctx, "front_colstrip", s);
