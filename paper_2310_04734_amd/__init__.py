@@ -233,13 +233,14 @@ class System:
         self.n, self.nnz, self.n_u, self.L, self.n_o = d.n, d.nnz, d.n_u, d.L, d.n_o
         self.analysis = None
 
-    def export(self):
-        """Unscaled host copies: rowptr, col, K, M (CSR values), F (n x L), flags, recv DoFs."""
+    def export(self, matrices=True):
+        """Unscaled host copies: rowptr, col, K, M (CSR values; None unless matrices), F (n x L),
+        flags, recv DoFs."""
         n, nnz = self.n, self.nnz
-        rowptr = np.empty(n + 1, np.int64)
-        col = np.empty(nnz, np.int32)
-        K = np.empty(nnz, np.complex128)
-        M = np.empty(nnz, np.complex128)
+        rowptr = np.empty(n + 1, np.int64) if matrices else None
+        col = np.empty(nnz, np.int32) if matrices else None
+        K = np.empty(nnz, np.complex128) if matrices else None
+        M = np.empty(nnz, np.complex128) if matrices else None
         F = np.empty((self.L, n), np.complex128)
         flags = np.empty(max(self.L, 1), np.int32)
         recv = np.empty(max(self.n_o, 1), np.int64)

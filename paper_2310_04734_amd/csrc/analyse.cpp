@@ -269,7 +269,7 @@ std::unique_ptr<Symbolic> analyse_pattern(int64_t n, const std::vector<int64_t>&
             S.ent_dst[k] = local(f, i) + local(f, j) * S.fsize[f];
         }
     S.piv_off.assign(S.first.begin(), S.first.end());
-    // large fronts: factored by 16-column panels with deferred 64-column trailing GEMMs spread
+    // large fronts: factored by 16-column panels with deferred 128-column trailing GEMMs spread
     // over many workgroups; per level the list of large fronts and the number of panel steps
     constexpr int kPanel = 16;
     S.big.assign(nf, 0);
@@ -286,9 +286,9 @@ std::unique_ptr<Symbolic> analyse_pattern(int64_t n, const std::vector<int64_t>&
                 S.big[f] = 1;
                 S.big_list.push_back(f);
                 steps = std::max(steps, (S.npiv[f] + kPanel - 1) / kPanel);
-                // trailing GEMM after each 64-column block: 8 (m - K1)^2 (K1 - K0) real flops
-                for (int K0 = 0; K0 < S.npiv[f]; K0 += 64) {
-                    const double K1 = std::min(K0 + 64, S.npiv[f]), r = S.fsize[f] - K1;
+                // trailing GEMM after each 128-column block (kOB of the GEMM kernel): 8 (m - K1)^2 (K1 - K0) flops
+                for (int K0 = 0; K0 < S.npiv[f]; K0 += 128) {
+                    const double K1 = std::min(K0 + 128, S.npiv[f]), r = S.fsize[f] - K1;
                     S.gemm_flops += 8.0 * r * r * (K1 - K0);
                 }
             }

@@ -52,7 +52,7 @@ struct cr_basis_s {
     int n_perturbed = 0;
     int fp64_refactorizations = 0;
     // scratch
-    DevBuf<zd> W, H, partial, RHS;
+    DevBuf<zd> W, H, Hn, partial, RHS;
     std::vector<zd> hH;
 };
 
@@ -134,7 +134,11 @@ int orthonormalise_append(cr_basis B, zd* W, int b) {
     cr_sys sys = B->sys;
     hipStream_t s = sys->ctx->stream;
     const int64_t n = sys->n;
-    std::vector<double> before = col_norms2(B, W, b);
+    // norms before orthogonalisation (diagonal of W^H W) stay on the device until the first
+    // column's norm after it is read, so that each column costs one host round trip
+    B->Hn.reserve((size_t)b * b + 1);
+    gram(n, b, b, W, n, W, n, B->Hn.p, b, 0, B->partial, s);
+    std::vector<double> before(b, 0.0);
     const int q0 = B->q;
     if (q0 > 0) {
         B->H.reserve((size_t)q0 * b);
@@ -155,7 +159,15 @@ int orthonormalise_append(cr_basis B, zd* W, int b) {
                 update(n, na, 1, B->V.p + n * q0, n, B->H.p, na, w, n, s);
             }
         }
-        const double after2 = col_norms2(B, w, 1)[0];
+        gram(n, 1, 1, w, n, w, n, B->Hn.p + (size_t)b * b, 1, 0, B->partial, s);
+        const size_t nread = c == 0 ? (size_t)b * b + 1 : 1;
+        B->hH.resize((size_t)b * b + 1);
+        CR_HIP(hipMemcpyAsync(B->hH.data() + (b * b + 1 - nread), B->Hn.p + (b * b + 1 - nread), nread * sizeof(zd),
+                              hipMemcpyDeviceToHost, s));
+        CR_HIP(hipStreamSynchronize(s));
+        if (c == 0)
+            for (int k = 0; k < b; ++k) before[k] = B->hH[(size_t)k * b + k].re;
+        const double after2 = B->hH[(size_t)b * b].re;
         const double ratio = std::sqrt(after2 / std::max(before[c], 1e-300));
         if (!(before[c] > 0) || !(ratio >= 1e-10)) {
             B->deflated++;

@@ -83,9 +83,9 @@ struct LuShared {
 // (ipiv[k] = row swapped with k; the swap is applied to columns [sw0, sw1) of the two rows),
 // then, when trsm is set, U12 rows [k0, k1) x columns [k1, m) = L_kk^{-1} A (unit lower).
 // rend = m factors the whole panel; rend = p leaves the rows [p, m), which never take part in
-// pivoting, to a separate triangular solve with the panel's U (wg_l21_rows).
-// Per column one pass over the rows scales the column, applies its rank-1 update to the rest
-// of the panel and takes the next column's pivot candidates on the way.
+// pivoting, to a separate triangular solve with the panel's U (the large-front row-strip
+// kernel). On long columns one pass over the rows scales the column, applies its rank-1
+// update to the rest of the panel and takes the next column's pivot candidates on the way.
 // Pivots with cabs1 <= tiny (or NaN) are replaced by tiny in their own direction and counted
 // in *nperturb.
 template <typename T>
@@ -94,11 +94,16 @@ __device__ void wg_panel(cx<T>* __restrict__ A, int lda, int m, int p, int k0, i
     const int t = threadIdx.x;
     T best = T(-1);
     int bi = k0;
-    for (int i = k0 + t; i < p; i += kWG) {
-        const T v = cabs1(A[i + (size_t)k0 * lda]);
-        if (v > best) { best = v; bi = i; }
-    }
+    bool have = false;   // pivot candidates of column k already taken by the previous pass
     for (int k = k0; k < k1; ++k) {
+        if (!have) {
+            best = T(-1);
+            bi = k;
+            for (int i = k + t; i < p; i += kWG) {
+                const T v = cabs1(A[i + (size_t)k * lda]);
+                if (v > best) { best = v; bi = i; }
+            }
+        }
         T pv;
         int pi;
         wg_argmax(best, bi, sh.red_v, sh.red_i, pv, pi);
@@ -121,25 +126,40 @@ __device__ void wg_panel(cx<T>* __restrict__ A, int lda, int m, int p, int k0, i
         }
         const cx<T> r = crecip(d);
         const int nc = k1 - k - 1;
-        cx<T> u[kNB - 1];
+        const int rows = rend - k - 1;
+        have = rows >= kWG;
+        if (have) {
+            // long columns: one pass per column, one row per thread at a time; the row of U is
+            // held in registers and the next column's pivot candidates are taken on the way
+            cx<T> u[kNB - 1];
 #pragma unroll
-        for (int jj = 0; jj < kNB - 1; ++jj) u[jj] = jj < nc ? A[k + (size_t)(k + 1 + jj) * lda] : cx<T>{T(0), T(0)};
-        best = T(-1);
-        bi = k + 1;
-        for (int i = k + 1 + t; i < rend; i += kWG) {
-            const cx<T> l = cmul(A[i + (size_t)k * lda], r);
-            A[i + (size_t)k * lda] = l;
+            for (int jj = 0; jj < kNB - 1; ++jj) u[jj] = jj < nc ? A[k + (size_t)(k + 1 + jj) * lda] : cx<T>{T(0), T(0)};
+            best = T(-1);
+            bi = k + 1;
+            for (int i = k + 1 + t; i < rend; i += kWG) {
+                const cx<T> l = cmul(A[i + (size_t)k * lda], r);
+                A[i + (size_t)k * lda] = l;
 #pragma unroll
-            for (int jj = 0; jj < kNB - 1; ++jj) {
-                if (jj < nc) {
-                    cx<T>& x = A[i + (size_t)(k + 1 + jj) * lda];
-                    const cx<T> y = cfms(x, l, u[jj]);
-                    x = y;
-                    if (jj == 0 && i < p) {
-                        const T v = cabs1(y);
-                        if (v > best) { best = v; bi = i; }
+                for (int jj = 0; jj < kNB - 1; ++jj) {
+                    if (jj < nc) {
+                        cx<T>& x = A[i + (size_t)(k + 1 + jj) * lda];
+                        const cx<T> y = cfms(x, l, u[jj]);
+                        x = y;
+                        if (jj == 0 && i < p) {
+                            const T v = cabs1(y);
+                            if (v > best) { best = v; bi = i; }
+                        }
                     }
                 }
+            }
+        } else {
+            // short columns (small fronts, reduced models): scale, then every (row, column) pair
+            // of the rank-1 update is one thread's work so that all threads stay busy
+            for (int i = k + 1 + t; i < rend; i += kWG) A[i + (size_t)k * lda] = cmul(A[i + (size_t)k * lda], r);
+            __syncthreads();
+            for (int e = t; e < rows * nc; e += kWG) {
+                const int i = k + 1 + e % rows, j = k + 1 + e / rows;
+                A[i + (size_t)j * lda] = cfms(A[i + (size_t)j * lda], A[i + (size_t)k * lda], A[k + (size_t)j * lda]);
             }
         }
         __syncthreads();
@@ -160,6 +180,62 @@ __device__ void wg_panel(cx<T>* __restrict__ A, int lda, int m, int p, int k0, i
 #pragma unroll
         for (int r = 0; r < kNB; ++r)
             if (k0 + r < k1) A[k0 + r + (size_t)j * lda] = x[r];
+    }
+    __syncthreads();
+}
+
+// Panel step as wg_panel with rend = p and no U12 solve, for panels whose fully-summed rows fit in
+// LDS (p - k0 <= R): the 16 columns are staged in LDS, factored there, and written back; the row
+// swaps reach the block's earlier columns [sw0, k0) in global memory. Same arithmetic, same order.
+template <typename T, int R>
+__device__ void wg_panel_lds(cx<T>* __restrict__ A, int lda, int p, int k0, int k1, int* __restrict__ ipiv, T tiny,
+                             int* nperturb, LuShared<T>& sh, cx<T> (*P)[kNB + 1], int sw0) {
+    const int t = threadIdx.x;
+    const int rows = p - k0, nb = k1 - k0;
+    for (int e = t; e < rows * nb; e += kWG) {
+        const int i = e % rows, c = e / rows;
+        P[i][c] = A[k0 + i + (size_t)(k0 + c) * lda];
+    }
+    __syncthreads();
+    for (int k = 0; k < nb; ++k) {
+        T best = T(-1);
+        int bi = k;
+        for (int i = k + t; i < rows; i += kWG) {
+            const T v = cabs1(P[i][k]);
+            if (v > best) { best = v; bi = i; }
+        }
+        T pv;
+        int pi;
+        wg_argmax(best, bi, sh.red_v, sh.red_i, pv, pi);
+        if (t == 0) ipiv[k0 + k] = k0 + pi;
+        if (pi != k) {
+            if (t < nb) { cx<T> x = P[k][t]; P[k][t] = P[pi][t]; P[pi][t] = x; }
+            for (int j = sw0 + t; j < k0; j += kWG) {
+                cx<T> x = A[k0 + k + (size_t)j * lda], y = A[k0 + pi + (size_t)j * lda];
+                A[k0 + k + (size_t)j * lda] = y;
+                A[k0 + pi + (size_t)j * lda] = x;
+            }
+            __syncthreads();
+        }
+        cx<T> d = P[k][k];
+        if (!(pv > tiny)) {
+            T mag = cabs1(d);
+            if (mag > T(0)) { d.re = d.re / mag * tiny; d.im = d.im / mag * tiny; }
+            else { d.re = tiny; d.im = T(0); }
+            __syncthreads();
+            if (t == 0) { P[k][k] = d; atomicAdd(nperturb, 1); }
+        }
+        const cx<T> r = crecip(d);
+        for (int i = k + 1 + t; i < rows; i += kWG) {
+            const cx<T> l = cmul(P[i][k], r);
+            P[i][k] = l;
+            for (int jj = k + 1; jj < nb; ++jj) P[i][jj] = cfms(P[i][jj], l, P[k][jj]);
+        }
+        __syncthreads();
+    }
+    for (int e = t; e < rows * nb; e += kWG) {
+        const int i = e % rows, c = e / rows;
+        A[k0 + i + (size_t)(k0 + c) * lda] = P[i][c];
     }
     __syncthreads();
 }

@@ -99,7 +99,7 @@ __global__ void __launch_bounds__(kWG) k_front_factor(const int32_t* __restrict_
     wg_getrf<T>(arena + front_off[f], m, m, p, ipiv + first[f], tiny, nperturb, sh);
 }
 
-// Large fronts are factored by 64-column blocks of four 16-column panels. Panel step j:
+// Large fronts are factored by 128-column blocks of eight 16-column panels. Panel step j:
 //   k_front_colstrip  (not the block's first panel) the panel's columns, rows [k0, m), receive
 //                     the block's earlier panels (rows tiled over workgroups);
 //   k_front_panel     one workgroup per front: pivots, scaling and the in-panel updates of the
@@ -108,21 +108,28 @@ __global__ void __launch_bounds__(kWG) k_front_factor(const int32_t* __restrict_
 //                     and [0, K0), then rows [k0, k1) of columns [k1, m) receive the block's
 //                     earlier panels and are solved with the panel's unit-lower diagonal block;
 //                     and rows [p, m) of the panel (one row per thread) solved with its U;
-//   k_front_gemm      after the block's last panel: trailing GEMM with K = 64 on MFMA.
+//   k_front_gemm      after the block's last panel: trailing GEMM with K = 128 on MFMA.
 // Swaps are applied before any update of the current block touches the swapped rows outside
 // the block's columns, so both rows of a swap are always in the same state.
+constexpr int kPanelLdsBytes = 96 * 1024;   // LDS for a panel's fully-summed rows (16 columns)
+
 template <typename T>
 __global__ void __launch_bounds__(kWG) k_front_panel(const int32_t* __restrict__ big_list, int step,
                                                     const int32_t* __restrict__ fsize, const int32_t* __restrict__ npiv,
                                                     const int32_t* __restrict__ first, const int64_t* __restrict__ front_off,
                                                     cx<T>* __restrict__ arena, int32_t* __restrict__ ipiv, T tiny,
                                                     int32_t* nperturb) {
+    constexpr int R = kPanelLdsBytes / (int)sizeof(cx<T>) / (kNB + 1);
     __shared__ LuShared<T> sh;
+    __shared__ cx<T> pl[R][kNB + 1];
     const int f = big_list[blockIdx.x];
     const int m = fsize[f], p = npiv[f], k0 = step * kNB;
     if (k0 >= p) return;
     const int K0 = (k0 / kOB) * kOB, k1 = min(k0 + kNB, p);
-    wg_panel<T>(arena + front_off[f], m, m, p, k0, k1, ipiv + first[f], tiny, nperturb, sh, K0, k1, false, p);
+    if (p - k0 <= R)
+        wg_panel_lds<T, R>(arena + front_off[f], m, p, k0, k1, ipiv + first[f], tiny, nperturb, sh, pl, K0);
+    else
+        wg_panel<T>(arena + front_off[f], m, m, p, k0, k1, ipiv + first[f], tiny, nperturb, sh, K0, k1, false, p);
 }
 
 template <typename T>
@@ -134,9 +141,9 @@ __global__ void __launch_bounds__(kWG) k_front_colstrip(const int32_t* __restric
     const int m = fsize[f], p = npiv[f], k0 = step * kNB;
     if (k0 >= p) return;
     const int K0 = (k0 / kOB) * kOB, k1 = min(k0 + kNB, p);
-    const int r0 = k0 + kOB * (int)blockIdx.x;
+    const int r0 = k0 + kST * (int)blockIdx.x;
     if (r0 >= m || K0 == k0) return;
-    wg_strip_update<T>(arena + front_off[f], m, r0, min(kOB, m - r0), k0, k1 - k0, K0, k0 - K0, sh);
+    wg_strip_update<T>(arena + front_off[f], m, r0, min(kST, m - r0), k0, k1 - k0, K0, k0 - K0, sh);
 }
 
 template <typename T>
@@ -156,7 +163,7 @@ __global__ void __launch_bounds__(kWG) k_front_rowstrip(const int32_t* __restric
     const int m = fsize[f], p = npiv[f], k0 = step * kNB;
     if (k0 >= p) return;
     const int K0 = (k0 / kOB) * kOB, k1 = min(k0 + kNB, p), nb = k1 - k0;
-    const int nright = (m - k1 + kOB - 1) / kOB, nleft = (K0 + kOB - 1) / kOB;
+    const int nright = (m - k1 + kST - 1) / kST, nleft = (K0 + kST - 1) / kST;
     const int nl21 = (m - p + kWG - 1) / kWG;
     const int x = blockIdx.x;
     if (x >= nright + nleft + nl21) return;
@@ -189,8 +196,8 @@ __global__ void __launch_bounds__(kWG) k_front_rowstrip(const int32_t* __restric
         return;
     }
     const bool right = x < nright;
-    const int c0 = right ? k1 + kOB * x : kOB * (x - nright);
-    const int nc = right ? min(kOB, m - c0) : min(kOB, K0 - c0);
+    const int c0 = right ? k1 + kST * x : kST * (x - nright);
+    const int nc = right ? min(kST, m - c0) : min(kST, K0 - c0);
     const int32_t* pv = ipiv + first[f];
     // the panel's swaps, in order, on this tile's columns
     if (t < nc) {
@@ -223,7 +230,7 @@ __global__ void __launch_bounds__(kWG) k_front_rowstrip(const int32_t* __restric
     }
 }
 
-// large fronts, after 64-column block b: trailing GEMM S -= L21 U12 on MFMA, one 64 x 64 tile
+// large fronts, after 128-column block b: trailing GEMM S -= L21 U12 on MFMA, one 64 x 64 tile
 // per workgroup (blockIdx.y = front)
 template <typename T>
 __global__ void __launch_bounds__(kWG) k_front_gemm(const int32_t* __restrict__ big_list, int blk,
@@ -262,6 +269,26 @@ struct SolveShared {
     cx<T> y[kSB][kSR];       // solved block values
 };
 
+// acc - sum_{k < nb} Fr[k m] y[k][lr] for nb <= 64, summed in k order; the panel's entries of the
+// row are loaded 32 at a time with all loads of a batch in flight before the first product
+template <typename T>
+__device__ __forceinline__ cx<T> row_panel_fms(cx<T> acc, const cx<T>* __restrict__ Fr, int64_t m, int nb,
+                                               const cx<T> (*y)[kSR], int lr) {
+#pragma unroll
+    for (int h = 0; h < kSB; h += 32) {
+        if (h >= nb) break;
+        // unconditional loads (past nb the last column is read again and not used), so that
+        // the batch is issued without branches
+        cx<T> f[32];
+#pragma unroll
+        for (int k = 0; k < 32; ++k) f[k] = Fr[(size_t)min(h + k, nb - 1) * m];
+#pragma unroll
+        for (int k = 0; k < 32; ++k)
+            if (h + k < nb) acc = cfms(acc, f[k], y[h + k][lr]);
+    }
+    return acc;
+}
+
 // Forward: per front, w (m x nrhs, column stride m) = [b_piv ; 0] + children's contributions,
 // row swaps on the pivot part, y = L11^{-1} w_piv, w_cb -= L21 y; y is written to x (new
 // numbering) and w_cb stays in the front's work slot for the parent.
@@ -269,6 +296,7 @@ template <typename T>
 struct SolveArgs {
     const int32_t *fsize, *npiv, *first, *child_off, *child_list, *cmap, *idx, *parent, *ipiv;
     const int32_t* huge;     // per front: 1 = triangular parts done by the multi-workgroup kernels
+    const int32_t* psrc;     // per pivot: source row of the front's composed row swaps
     const int64_t *front_off, *idx_off, *cmap_off;
     const cx<T>* arena;
     cx<T>* x;
@@ -311,12 +339,17 @@ __device__ void front_fwd(int f, const SolveArgs<T>& a, SolveShared<T>& sh) {
         __syncthreads();
     }
     if (p == 0) return;
-    for (int l = t; l < nrhs; l += kWG) {
-        cx<T>* wl = w + (size_t)l * m;
-        for (int k = 0; k < p; ++k) {
-            const int r = ipiv[f0 + k];
-            if (r != k) { cx<T> a = wl[k]; wl[k] = wl[r]; wl[r] = a; }
-        }
+    // the front's row swaps as one gather, w_piv[k] <- w_piv[psrc[k]], staged through the
+    // front's own (not yet written) pivot slots of x
+    const int32_t* src = a.psrc + f0;
+    for (int e = t; e < p * nrhs; e += kWG) {
+        const int r = e % p, l = e / p;
+        x[f0 + r + (size_t)l * ldx] = w[r + (size_t)l * m];
+    }
+    __syncthreads();
+    for (int e = t; e < p * nrhs; e += kWG) {
+        const int r = e % p, l = e / p;
+        w[r + (size_t)l * m] = x[f0 + src[r] + (size_t)l * ldx];
     }
     __syncthreads();
     if (a.huge[f]) return;
@@ -347,8 +380,7 @@ __device__ void front_fwd(int f, const SolveArgs<T>& a, SolveShared<T>& sh) {
                 const int r = r0 + e % rows, lr = e / rows;
                 cx<T> acc = w[r + (size_t)(l0 + lr) * m];
                 const cx<T>* Fr = F + r + (size_t)kb * m;
-#pragma unroll 16
-                for (int k = 0; k < nb; ++k) acc = cfms(acc, Fr[(size_t)k * m], sh.y[k][lr]);
+                acc = row_panel_fms<T>(acc, Fr, m, nb, sh.y, lr);
                 w[r + (size_t)(l0 + lr) * m] = acc;
             }
         }
@@ -406,8 +438,7 @@ __device__ void front_bwd(int f, const SolveArgs<T>& a, SolveShared<T>& sh) {
                     const int r = e % p, lr = e / p;
                     const cx<T>* Fr = F + r + (size_t)(p + s0) * m;
                     cx<T> a = acc[g];
-#pragma unroll 16
-                    for (int k = 0; k < ns; ++k) a = cfms(a, Fr[(size_t)k * m], sh.y[k][lr]);
+                    a = row_panel_fms<T>(a, Fr, m, ns, sh.y, lr);
                     acc[g] = a;
                 }
             }
@@ -445,8 +476,7 @@ __device__ void front_bwd(int f, const SolveArgs<T>& a, SolveShared<T>& sh) {
                 const int r = e % kb, lr = e / kb;
                 cx<T> acc = w[r + (size_t)(l0 + lr) * m];
                 const cx<T>* Fr = F + r + (size_t)kb * m;
-#pragma unroll 16
-                for (int k = 0; k < nb; ++k) acc = cfms(acc, Fr[(size_t)k * m], sh.y[k][lr]);
+                acc = row_panel_fms<T>(acc, Fr, m, nb, sh.y, lr);
                 w[r + (size_t)(l0 + lr) * m] = acc;
             }
         }
@@ -527,8 +557,7 @@ __global__ void __launch_bounds__(kWG) k_huge_fwd(const int32_t* __restrict__ hu
             const int r = r0 + e % rows, lr = e / rows;
             cx<T> acc = w[r + (size_t)(l0 + lr) * m];
             const cx<T>* Fr = F + r + (size_t)kb * m;
-#pragma unroll 16
-            for (int k = 0; k < nb; ++k) acc = cfms(acc, Fr[(size_t)k * m], sh.y[k][lr]);
+            acc = row_panel_fms<T>(acc, Fr, m, nb, sh.y, lr);
             w[r + (size_t)(l0 + lr) * m] = acc;
         }
     }
@@ -568,8 +597,7 @@ __global__ void __launch_bounds__(kWG) k_huge_bwd_cb(const int32_t* __restrict__
                 const int r = r0 + e % rows, lr = e / rows;
                 const cx<T>* Fr = F + r + (size_t)(p + s0) * m;
                 cx<T> v = acc[g];
-#pragma unroll 16
-                for (int k = 0; k < ns; ++k) v = cfms(v, Fr[(size_t)k * m], sh.y[k][lr]);
+                v = row_panel_fms<T>(v, Fr, m, ns, sh.y, lr);
                 acc[g] = v;
             }
         }
@@ -607,8 +635,7 @@ __global__ void __launch_bounds__(kWG) k_huge_bwd(const int32_t* __restrict__ hu
             const int r = r0 + e % rows, lr = e / rows;
             cx<T> acc = w[r + (size_t)(l0 + lr) * m];
             const cx<T>* Fr = F + r + (size_t)kb * m;
-#pragma unroll 16
-            for (int k = 0; k < nb; ++k) acc = cfms(acc, Fr[(size_t)k * m], sh.y[k][lr]);
+            acc = row_panel_fms<T>(acc, Fr, m, nb, sh.y, lr);
             w[r + (size_t)(l0 + lr) * m] = acc;
         }
     }
@@ -649,6 +676,42 @@ __global__ void k_maxabs_entries(const zd* __restrict__ K, const zd* __restrict_
     if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(m));
 }
 
+// Per front, the composition of its row swaps (ipiv[k] swapped with k, k = 0..p-1) as a gather
+// map: psrc[k] = the row whose value ends at k. Done once per factorisation so that every solve
+// applies the swaps in one parallel gather; the sequential composition runs in LDS.
+constexpr int kComposeLds = 16384;   // pivots composed in LDS (64 KB); larger fronts use global memory
+__global__ void __launch_bounds__(kWG) k_compose_pivots(const int32_t* __restrict__ npiv, const int32_t* __restrict__ first,
+                                                       const int32_t* __restrict__ ipiv, int32_t* __restrict__ psrc) {
+    __shared__ int32_t perm[kComposeLds];
+    const int f = blockIdx.x;
+    const int p = npiv[f], f0 = first[f];
+    const int32_t* iv = ipiv + f0;
+    int32_t* out = psrc + f0;
+    if (p <= kComposeLds) {
+        for (int k = threadIdx.x; k < p; k += kWG) perm[k] = k;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int k = 0; k < p; ++k) {
+                const int r = iv[k];
+                const int32_t tmp = perm[k];
+                perm[k] = perm[r];
+                perm[r] = tmp;
+            }
+        __syncthreads();
+        for (int k = threadIdx.x; k < p; k += kWG) out[k] = perm[k];
+    } else {
+        for (int k = threadIdx.x; k < p; k += kWG) out[k] = k;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int k = 0; k < p; ++k) {
+                const int r = iv[k];
+                const int32_t tmp = out[k];
+                out[k] = out[r];
+                out[r] = tmp;
+            }
+    }
+}
+
 template <typename T>
 void run_factor(Factor& f, cr_sys sys, double sigma, cx<T>* arena, T tiny, hipStream_t s) {
     const Symbolic& S = *sys->sym;
@@ -657,10 +720,10 @@ void run_factor(Factor& f, cr_sys sys, double sigma, cx<T>* arena, T tiny, hipSt
         const int nf = S.level_off[l + 1] - S.level_off[l];
         const int32_t* lf = D.level_fronts.p + S.level_off[l];
         {
-            // workgroups per front: one per 256 columns of the level's largest front, at most 64
+            // workgroups per front: one per 32 columns of the level's largest front, at most 64
             int mmax = 0;
             for (int q = S.level_off[l]; q < S.level_off[l + 1]; ++q) mmax = std::max(mmax, S.fsize[S.level_fronts[q]]);
-            const unsigned split = (unsigned)std::min(64, std::max(1, mmax / 256));
+            const unsigned split = (unsigned)std::min(64, std::max(1, mmax / 32));
             ProfScope ps(sys->ctx, "front_assemble", s);
             hipLaunchKernelGGL(k_front_assemble<T>, dim3(nf, split), dim3(kWG), 0, s, lf, D.fsize.p, D.front_off.p, D.child_off.p,
                                D.child_list.p, D.npiv.p, D.cmap_off.p, D.cmap.p, D.ent_off.p, D.ent_src.p, D.ent_dst.p,
@@ -679,8 +742,8 @@ void run_factor(Factor& f, cr_sys sys, double sigma, cx<T>* arena, T tiny, hipSt
                 const int f = S.big_list[q], m = S.fsize[f], p = S.npiv[f], k0 = j * kNB;
                 if (k0 >= p) continue;
                 const int K0 = (k0 / kOB) * kOB, k1 = std::min(k0 + kNB, p);
-                gcol = std::max(gcol, (unsigned)((m - k0 + kOB - 1) / kOB));
-                grow = std::max(grow, (unsigned)((m - k1 + kOB - 1) / kOB + (K0 + kOB - 1) / kOB +
+                gcol = std::max(gcol, (unsigned)((m - k0 + kST - 1) / kST));
+                grow = std::max(grow, (unsigned)((m - k1 + kST - 1) / kST + (K0 + kST - 1) / kST +
                                                  (m - p + kWG - 1) / kWG));
             }
             if (j % (kOB / kNB) != 0 && gcol) {
@@ -716,6 +779,7 @@ void run_factor(Factor& f, cr_sys sys, double sigma, cx<T>* arena, T tiny, hipSt
             }
         }
     }
+    hipLaunchKernelGGL(k_compose_pivots, dim3(S.nfront), dim3(kWG), 0, s, D.npiv.p, D.first.p, f.ipiv.p, f.psrc.p);
     CR_HIP(hipGetLastError());
 }
 
@@ -735,6 +799,7 @@ void run_solve(const Factor& f, int nrhs, cx<T>* xp, cx<T>* work, hipStream_t s,
     a.parent = D.parent.p;
     a.ipiv = f.ipiv.p;
     a.huge = D.huge.p;
+    a.psrc = f.psrc.p;
     a.front_off = D.front_off.p;
     a.idx_off = D.idx_off.p;
     a.cmap_off = D.cmap_off.p;
@@ -822,6 +887,7 @@ void numeric_factor(Factor& f, cr_sys sys, double omega, cr_precision prec, hipS
     f.omega = omega;
     f.prec = prec;
     f.ipiv.reserve(S.n);
+    f.psrc.reserve(S.n);
     f.nperturb.reserve(2);
     const double sigma = omega * omega;
     // largest |entry| of the shifted matrix sets the perturbation threshold

@@ -1,10 +1,10 @@
 // Blocked trailing updates of a large front's partial LU on the matrix cores.
 //
-// A large front is factored by outer blocks of kOB = 64 pivot columns, each made of four
+// A large front is factored by outer blocks of kOB = 128 pivot columns, each made of eight
 // 16-column panels (wg_panel). Inside an outer block the updates are deferred: before panel s
 // the L-shaped strip it needs -- its own 16 columns below the diagonal and its 16 rows to the
 // right -- receives the contributions of panels 0..s-1 of the block (wg_strip_update); after
-// the block the trailing matrix receives all 64 columns at once, S -= L21 U12 with K = 64
+// the block the trailing matrix receives all 128 columns at once, S -= L21 U12 with K = 128
 // (wg_gemm_tile), a complex GEMM on MFMA: v_mfma_f32_16x16x4f32 for complex-FP32 fronts and
 // v_mfma_f64_16x16x4f64 for FP64 fronts, each complex product as four real products into
 // separate real and imaginary accumulators.
@@ -18,7 +18,8 @@
 
 namespace cr {
 
-constexpr int kOB = 64;      // outer block (pivot columns per trailing GEMM)
+constexpr int kOB = 128;     // outer block (pivot columns per trailing GEMM)
+constexpr int kST = 64;      // strip update tile (rows or columns per workgroup)
 constexpr int kGT = 64;      // GEMM output tile (kGT x kGT per workgroup, 32 x 32 per wave)
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -128,8 +129,8 @@ __device__ void wg_gemm_tile(cx<T>* __restrict__ A, int lda, int m, int k0, int 
 
 template <typename T>
 struct StripShared {
-    cx<T> l[kOB][kNB + 1];    // rows x 16 (one panel of K)
-    cx<T> u[kNB][kOB + 1];    // 16 x columns
+    cx<T> l[kST][kNB + 1];    // rows x 16 (one panel of K)
+    cx<T> u[kNB][kST + 1];    // 16 x columns
 };
 
 // C[r0:r0+nr, c0:c0+nc] -= A[r0:r0+nr, k0:k0+K] A[k0:k0+K, c0:c0+nc] with nr, nc <= 64,

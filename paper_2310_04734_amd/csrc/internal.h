@@ -249,6 +249,7 @@ struct Factor {
     DevBuf<zd> arena64;   // complex128 fronts (FP64)
     DevBuf<zf> arena32;   // complex64 fronts (MIXED)
     DevBuf<int32_t> ipiv; // local pivot row per pivot (n)
+    DevBuf<int32_t> psrc; // per pivot: source row of the front's composed swaps (n)
     DevBuf<int32_t> nperturb;
     DevBuf<unsigned long long> amax;
     int32_t n_perturbed = 0;

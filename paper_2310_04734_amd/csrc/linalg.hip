@@ -430,33 +430,36 @@ constexpr int kGramRows = 256;   // rows per workgroup chunk
 constexpr int kGramB = 16;       // max columns of the staged operand
 
 // partial[chunk][k][c] = sum_{i in chunk} conj(A[i,k]) B[i,c],  k < qa, c < b (b <= 16)
+// B = the staged column count rounded up (1, 4 or 16) so that narrow blocks do no padded work;
+// blockIdx.y strides over the columns of A so that short tall matrices still fill the chip
+template <int B>
 __global__ void __launch_bounds__(256) k_gram_partial(int64_t n, int qa, int b, const zd* __restrict__ A, int64_t lda,
                                                       const zd* __restrict__ Bm, int64_t ldb, zd* __restrict__ partial) {
-    __shared__ zd sb[kGramRows][kGramB];
+    __shared__ zd sb[kGramRows][B];
     const int64_t i0 = (int64_t)blockIdx.x * kGramRows;
     const int rows = (int)std::min<int64_t>(kGramRows, n - i0);
-    for (int e = threadIdx.x; e < kGramRows * kGramB; e += 256) {
+    for (int e = threadIdx.x; e < kGramRows * B; e += 256) {
         const int r = e % kGramRows, c = e / kGramRows;
         sb[r][c] = (r < rows && c < b) ? Bm[i0 + r + c * ldb] : zd{0, 0};
     }
     __syncthreads();
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     zd* out = partial + (size_t)blockIdx.x * qa * b;
-    for (int k = wave; k < qa; k += 4) {
-        double ar[kGramB], ai[kGramB];
+    for (int k = blockIdx.y * 4 + wave; k < qa; k += 4 * gridDim.y) {
+        double ar[B], ai[B];
 #pragma unroll
-        for (int c = 0; c < kGramB; ++c) ar[c] = ai[c] = 0;
+        for (int c = 0; c < B; ++c) ar[c] = ai[c] = 0;
         for (int r = lane; r < rows; r += 64) {
             const zd a = A[i0 + r + k * lda];
 #pragma unroll
-            for (int c = 0; c < kGramB; ++c) {
+            for (int c = 0; c < B; ++c) {
                 const zd v = sb[r][c];
                 ar[c] += a.re * v.re + a.im * v.im;   // conj(a) * v
                 ai[c] += a.re * v.im - a.im * v.re;
             }
         }
 #pragma unroll
-        for (int c = 0; c < kGramB; ++c)
+        for (int c = 0; c < B; ++c)
             for (int off = 32; off > 0; off >>= 1) {
                 ar[c] += __shfl_xor(ar[c], off);
                 ai[c] += __shfl_xor(ai[c], off);
@@ -547,8 +550,18 @@ void gram(int64_t n, int qa, int b, const zd* A, int64_t lda, const zd* B, int64
     for (int c0 = 0; c0 < b; c0 += kGramB) {
         const int bc = std::min(kGramB, b - c0);
         partial.reserve((size_t)nchunk * qa * bc);
-        hipLaunchKernelGGL(k_gram_partial, dim3(nchunk), dim3(256), 0, s, n, qa, bc, A, lda, B + (int64_t)c0 * ldb, ldb,
-                           partial.p);
+        // at least ~1024 workgroups when the columns of A allow it
+        const unsigned gy = (unsigned)std::max(1, std::min((qa + 3) / 4, (1024 + nchunk - 1) / nchunk));
+        const dim3 grid(nchunk, gy);
+        if (bc == 1)
+            hipLaunchKernelGGL(k_gram_partial<1>, grid, dim3(256), 0, s, n, qa, bc, A, lda, B + (int64_t)c0 * ldb, ldb,
+                               partial.p);
+        else if (bc <= 4)
+            hipLaunchKernelGGL(k_gram_partial<4>, grid, dim3(256), 0, s, n, qa, bc, A, lda, B + (int64_t)c0 * ldb, ldb,
+                               partial.p);
+        else
+            hipLaunchKernelGGL(k_gram_partial<kGramB>, grid, dim3(256), 0, s, n, qa, bc, A, lda, B + (int64_t)c0 * ldb,
+                               ldb, partial.p);
         zd* Hc = conj_t ? H + c0 : H + (int64_t)c0 * ldh;
         hipLaunchKernelGGL(k_gram_reduce, dim3((qa * bc + 255) / 256), dim3(256), 0, s, nchunk, qa, bc, partial.p, Hc, ldh,
                            conj_t);
