@@ -278,6 +278,7 @@ std::unique_ptr<Symbolic> analyse_pattern(int64_t n, const std::vector<int64_t>&
     S.huge.assign(nf, 0);
     S.huge_off.assign(S.nlevel + 1, 0);
     S.huge_piv.assign(S.nlevel, 0);
+    S.wide_solve.clear();
     for (int l = 0; l < S.nlevel; ++l) {
         int steps = 0;
         for (int q = S.level_off[l]; q < S.level_off[l + 1]; ++q) {
@@ -301,6 +302,13 @@ std::unique_ptr<Symbolic> analyse_pattern(int64_t n, const std::vector<int64_t>&
         S.big_off[l + 1] = (int32_t)S.big_list.size();
         S.huge_off[l + 1] = (int32_t)S.huge_list.size();
         S.nsteps[l] = steps;
+        // levels whose one-workgroup solves carry large triangles get 1024-thread workgroups
+        double work = 0;
+        for (int q = S.level_off[l]; q < S.level_off[l + 1]; ++q) {
+            const int f = S.level_fronts[q];
+            if (!S.huge[f]) work = std::max(work, (double)S.fsize[f] * S.npiv[f]);
+        }
+        S.wide_solve.push_back(work >= 32768.0 ? 1 : 0);
     }
     S.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return sym;

@@ -230,22 +230,22 @@ __global__ void __launch_bounds__(kWG) k_front_rowstrip(const int32_t* __restric
     }
 }
 
-// large fronts, after 128-column block b: trailing GEMM S -= L21 U12 on MFMA, one 64 x 64 tile
+// large fronts, after 128-column block b: trailing GEMM S -= L21 U12 on MFMA, one TW x TW tile
 // per workgroup (blockIdx.y = front)
-template <typename T>
+template <typename T, int TW>
 __global__ void __launch_bounds__(kWG) k_front_gemm(const int32_t* __restrict__ big_list, int blk,
                                                    const int32_t* __restrict__ fsize, const int32_t* __restrict__ npiv,
                                                    const int64_t* __restrict__ front_off, cx<T>* __restrict__ arena) {
-    __shared__ GemmShared<T> sh;
+    __shared__ GemmShared<T, TW> sh;
     const int f = big_list[blockIdx.y];
     const int m = fsize[f], p = npiv[f], K0 = blk * kOB;
     if (K0 >= p) return;
     const int K1 = min(K0 + kOB, p);
     if (K1 >= m) return;
-    const int nt = (m - K1 + kGT - 1) / kGT;
+    const int nt = (m - K1 + TW - 1) / TW;
     const int x = blockIdx.x;
     if (x >= nt * nt) return;
-    wg_gemm_tile<T>(arena + front_off[f], m, m, K0, K1 - K0, K1 + kGT * (x % nt), K1 + kGT * (x / nt), sh);
+    wg_gemm_tile<T, TW>(arena + front_off[f], m, m, K0, K1 - K0, K1 + TW * (x % nt), K1 + TW * (x / nt), sh);
 }
 
 // ------------------------------------------------------------------ solves
@@ -255,6 +255,7 @@ __global__ void __launch_bounds__(kWG) k_front_gemm(const int32_t* __restrict__ 
 // front vector is updated by the whole workgroup with the block's column panel, whose loads
 // are independent of each other (unrolled). Two barriers per 64 pivots.
 
+constexpr int kWideSolve = 1024;   // threads per workgroup for the solve levels with large fronts
 constexpr int kSB = 64;     // solve block (= wavefront size)
 constexpr int kSR = 16;     // right-hand sides per pass
 
@@ -267,23 +268,24 @@ template <typename T>
 struct SolveShared {
     cx<T> d[kSB][kSB + 1];   // diagonal block
     cx<T> y[kSB][kSR];       // solved block values
+    cx<T> rd[kSB];           // reciprocals of U's diagonal in the block (backward solves)
 };
 
 // acc - sum_{k < nb} Fr[k m] y[k][lr] for nb <= 64, summed in k order; the panel's entries of the
 // row are loaded 32 at a time with all loads of a batch in flight before the first product
-template <typename T>
+template <typename T, int BATCH = 32>
 __device__ __forceinline__ cx<T> row_panel_fms(cx<T> acc, const cx<T>* __restrict__ Fr, int64_t m, int nb,
                                                const cx<T> (*y)[kSR], int lr) {
 #pragma unroll
-    for (int h = 0; h < kSB; h += 32) {
+    for (int h = 0; h < kSB; h += BATCH) {
         if (h >= nb) break;
         // unconditional loads (past nb the last column is read again and not used), so that
         // the batch is issued without branches
-        cx<T> f[32];
+        cx<T> f[BATCH];
 #pragma unroll
-        for (int k = 0; k < 32; ++k) f[k] = Fr[(size_t)min(h + k, nb - 1) * m];
+        for (int k = 0; k < BATCH; ++k) f[k] = Fr[(size_t)min(h + k, nb - 1) * m];
 #pragma unroll
-        for (int k = 0; k < 32; ++k)
+        for (int k = 0; k < BATCH; ++k)
             if (h + k < nb) acc = cfms(acc, f[k], y[h + k][lr]);
     }
     return acc;
@@ -305,7 +307,7 @@ struct SolveArgs {
     cx<T>* work;
 };
 
-template <typename T>
+template <typename T, int NT>
 __device__ void front_fwd(int f, const SolveArgs<T>& a, SolveShared<T>& sh) {
     const int32_t *fsize = a.fsize, *npiv = a.npiv, *first = a.first, *child_off = a.child_off,
                   *child_list = a.child_list, *cmap = a.cmap, *ipiv = a.ipiv;
@@ -319,7 +321,7 @@ __device__ void front_fwd(int f, const SolveArgs<T>& a, SolveShared<T>& sh) {
     const cx<T>* F = arena + front_off[f];
     cx<T>* w = work + idx_off[f] * nrhs;   // m x nrhs
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    for (int e = t; e < m * nrhs; e += kWG) {
+    for (int e = t; e < m * nrhs; e += NT) {
         const int r = e % m, l = e / m;
         w[e] = r < p ? x[f0 + r + (size_t)l * ldx] : cx<T>{T(0), T(0)};
     }
@@ -329,7 +331,7 @@ __device__ void front_fwd(int f, const SolveArgs<T>& a, SolveShared<T>& sh) {
         const int mc = fsize[c], pc = npiv[c], nc = mc - pc;
         const cx<T>* wc = work + idx_off[c] * nrhs;
         const int32_t* map = cmap + cmap_off[c];
-        for (int e = t; e < nc * nrhs; e += kWG) {
+        for (int e = t; e < nc * nrhs; e += NT) {
             const int r = e % nc, l = e / nc;
             const cx<T> v = wc[pc + r + (size_t)l * mc];
             cx<T>& d = w[map[r] + (size_t)l * m];
@@ -342,12 +344,12 @@ __device__ void front_fwd(int f, const SolveArgs<T>& a, SolveShared<T>& sh) {
     // the front's row swaps as one gather, w_piv[k] <- w_piv[psrc[k]], staged through the
     // front's own (not yet written) pivot slots of x
     const int32_t* src = a.psrc + f0;
-    for (int e = t; e < p * nrhs; e += kWG) {
+    for (int e = t; e < p * nrhs; e += NT) {
         const int r = e % p, l = e / p;
         x[f0 + r + (size_t)l * ldx] = w[r + (size_t)l * m];
     }
     __syncthreads();
-    for (int e = t; e < p * nrhs; e += kWG) {
+    for (int e = t; e < p * nrhs; e += NT) {
         const int r = e % p, l = e / p;
         w[r + (size_t)l * m] = x[f0 + src[r] + (size_t)l * ldx];
     }
@@ -355,7 +357,7 @@ __device__ void front_fwd(int f, const SolveArgs<T>& a, SolveShared<T>& sh) {
     if (a.huge[f]) return;
     for (int kb = 0; kb < p; kb += kSB) {
         const int nb = min(kSB, p - kb);
-        for (int e = t; e < kSB * kSB; e += kWG) {
+        for (int e = t; e < kSB * kSB; e += NT) {
             const int i = e % kSB, k = e / kSB;
             sh.d[i][k] = (i < nb && k < nb) ? F[kb + i + (size_t)(kb + k) * m] : cx<T>{T(0), T(0)};
         }
@@ -363,7 +365,7 @@ __device__ void front_fwd(int f, const SolveArgs<T>& a, SolveShared<T>& sh) {
             const int nr = min(kSR, nrhs - l0);
             __syncthreads();
             // diagonal block: unit lower triangular, one wave per right-hand side
-            for (int lr = wave; lr < nr; lr += kWG / 64) {
+            for (int lr = wave; lr < nr; lr += NT / 64) {
                 cx<T>* wl = w + (size_t)(l0 + lr) * m;
                 cx<T> wi = lane < nb ? wl[kb + lane] : cx<T>{T(0), T(0)};
                 for (int k = 0; k < nb - 1; ++k) {
@@ -376,24 +378,24 @@ __device__ void front_fwd(int f, const SolveArgs<T>& a, SolveShared<T>& sh) {
             __syncthreads();
             // rows below the block: w[r] -= F[r, kb:kb+nb] y
             const int r0 = kb + nb, rows = m - r0;
-            for (int e = t; e < rows * nr; e += kWG) {
+            for (int e = t; e < rows * nr; e += NT) {
                 const int r = r0 + e % rows, lr = e / rows;
                 cx<T> acc = w[r + (size_t)(l0 + lr) * m];
                 const cx<T>* Fr = F + r + (size_t)kb * m;
-                acc = row_panel_fms<T>(acc, Fr, m, nb, sh.y, lr);
+                acc = row_panel_fms<T, (NT > 256 ? 16 : 32)>(acc, Fr, m, nb, sh.y, lr);
                 w[r + (size_t)(l0 + lr) * m] = acc;
             }
         }
         __syncthreads();
     }
-    for (int e = t; e < p * nrhs; e += kWG) {
+    for (int e = t; e < p * nrhs; e += NT) {
         const int r = e % p, l = e / p;
         x[f0 + r + (size_t)l * ldx] = w[r + (size_t)l * m];
     }
 }
 
 // Backward: x_piv = U11^{-1} (y - U12 x_cb), x_cb gathered from already-solved ancestors.
-template <typename T>
+template <typename T, int NT>
 __device__ void front_bwd(int f, const SolveArgs<T>& a, SolveShared<T>& sh) {
     const int32_t *fsize = a.fsize, *npiv = a.npiv, *first = a.first, *idx = a.idx;
     const int64_t *front_off = a.front_off, *idx_off = a.idx_off;
@@ -408,7 +410,7 @@ __device__ void front_bwd(int f, const SolveArgs<T>& a, SolveShared<T>& sh) {
     const int32_t* ix = idx + idx_off[f];
     cx<T>* w = work + idx_off[f] * nrhs;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    for (int e = t; e < m * nrhs; e += kWG) {
+    for (int e = t; e < m * nrhs; e += NT) {
         const int r = e % m, l = e / m;
         w[e] = x[ix[r] + (size_t)l * ldx];
     }
@@ -418,33 +420,34 @@ __device__ void front_bwd(int f, const SolveArgs<T>& a, SolveShared<T>& sh) {
     const int c = m - p;
     for (int l0 = 0; l0 < nrhs; l0 += kSR) {
         const int nr = min(kSR, nrhs - l0);
-        for (int base = 0; base < p * nr; base += 4 * kWG) {
+        for (int base = 0; base < p * nr; base += 4 * NT) {
             cx<T> acc[4];
             for (int g = 0; g < 4; ++g) {
-                const int e = base + g * kWG + t;
+                const int e = base + g * NT + t;
                 acc[g] = e < p * nr ? w[e % p + (size_t)(l0 + e / p) * m] : cx<T>{T(0), T(0)};
             }
             for (int s0 = 0; s0 < c; s0 += kSB) {
                 const int ns = min(kSB, c - s0);
                 __syncthreads();
-                for (int e = t; e < kSB * kSR; e += kWG) {
+                for (int e = t; e < kSB * kSR; e += NT) {
                     const int sidx = e % kSB, lr = e / kSB;
                     sh.y[sidx][lr] = (sidx < ns && lr < nr) ? w[p + s0 + sidx + (size_t)(l0 + lr) * m] : cx<T>{T(0), T(0)};
                 }
                 __syncthreads();
                 for (int g = 0; g < 4; ++g) {
-                    const int e = base + g * kWG + t;
+                    const int e = base + g * NT + t;
                     if (e >= p * nr) break;
                     const int r = e % p, lr = e / p;
                     const cx<T>* Fr = F + r + (size_t)(p + s0) * m;
                     cx<T> a = acc[g];
-                    a = row_panel_fms<T>(a, Fr, m, ns, sh.y, lr);
+#pragma unroll 16
+                    for (int k = 0; k < ns; ++k) a = cfms(a, Fr[(size_t)k * m], sh.y[k][lr]);
                     acc[g] = a;
                 }
             }
             __syncthreads();
             for (int g = 0; g < 4; ++g) {
-                const int e = base + g * kWG + t;
+                const int e = base + g * NT + t;
                 if (e < p * nr) w[e % p + (size_t)(l0 + e / p) * m] = acc[g];
             }
         }
@@ -452,18 +455,20 @@ __device__ void front_bwd(int f, const SolveArgs<T>& a, SolveShared<T>& sh) {
     __syncthreads();
     for (int kb = ((p - 1) / kSB) * kSB; kb >= 0; kb -= kSB) {
         const int nb = min(kSB, p - kb);
-        for (int e = t; e < kSB * kSB; e += kWG) {
+        for (int e = t; e < kSB * kSB; e += NT) {
             const int i = e % kSB, k = e / kSB;
             sh.d[i][k] = (i < nb && k < nb) ? F[kb + i + (size_t)(kb + k) * m] : cx<T>{T(1), T(0)};
         }
+        // the divisions leave the sequential chain: all reciprocals of the block's diagonal at once
+        if (t < kSB) sh.rd[t] = t < nb ? crecip(F[kb + t + (size_t)(kb + t) * m]) : cx<T>{T(1), T(0)};
         for (int l0 = 0; l0 < nrhs; l0 += kSR) {
             const int nr = min(kSR, nrhs - l0);
             __syncthreads();
-            for (int lr = wave; lr < nr; lr += kWG / 64) {
+            for (int lr = wave; lr < nr; lr += NT / 64) {
                 cx<T>* wl = w + (size_t)(l0 + lr) * m;
                 cx<T> wi = lane < nb ? wl[kb + lane] : cx<T>{T(0), T(0)};
                 for (int k = nb - 1; k >= 0; --k) {
-                    if (lane == k) wi = cmul(wi, crecip(sh.d[k][k]));
+                    if (lane == k) wi = cmul(wi, sh.rd[k]);
                     const cx<T> xk = shfl_cx(wi, k);
                     if (lane < k) wi = cfms(wi, sh.d[lane][k], xk);
                 }
@@ -472,32 +477,33 @@ __device__ void front_bwd(int f, const SolveArgs<T>& a, SolveShared<T>& sh) {
             }
             __syncthreads();
             // rows above the block: w[r] -= F[r, kb:kb+nb] x_blk
-            for (int e = t; e < kb * nr; e += kWG) {
+            for (int e = t; e < kb * nr; e += NT) {
                 const int r = e % kb, lr = e / kb;
                 cx<T> acc = w[r + (size_t)(l0 + lr) * m];
                 const cx<T>* Fr = F + r + (size_t)kb * m;
-                acc = row_panel_fms<T>(acc, Fr, m, nb, sh.y, lr);
+#pragma unroll 16
+                for (int k = 0; k < nb; ++k) acc = cfms(acc, Fr[(size_t)k * m], sh.y[k][lr]);
                 w[r + (size_t)(l0 + lr) * m] = acc;
             }
         }
         __syncthreads();
     }
-    for (int e = t; e < p * nrhs; e += kWG) {
+    for (int e = t; e < p * nrhs; e += NT) {
         const int r = e % p, l = e / p;
         x[f0 + r + (size_t)l * ldx] = w[r + (size_t)l * m];
     }
 }
 
 // One launch per tree level and direction; every front of the level is one workgroup.
-template <typename T>
-__global__ void __launch_bounds__(kWG) k_front_fwd(const int32_t* __restrict__ level_fronts, SolveArgs<T> a) {
+template <typename T, int NT>
+__global__ void __launch_bounds__(NT) k_front_fwd(const int32_t* __restrict__ level_fronts, SolveArgs<T> a) {
     __shared__ SolveShared<T> sh;
-    front_fwd<T>(level_fronts[blockIdx.x], a, sh);
+    front_fwd<T, NT>(level_fronts[blockIdx.x], a, sh);
 }
-template <typename T>
-__global__ void __launch_bounds__(kWG) k_front_bwd(const int32_t* __restrict__ level_fronts, SolveArgs<T> a) {
+template <typename T, int NT>
+__global__ void __launch_bounds__(NT) k_front_bwd(const int32_t* __restrict__ level_fronts, SolveArgs<T> a) {
     __shared__ SolveShared<T> sh;
-    front_bwd<T>(level_fronts[blockIdx.x], a, sh);
+    front_bwd<T, NT>(level_fronts[blockIdx.x], a, sh);
 }
 
 // ---- the largest fronts: triangular solves by 64-pivot blocks with the rows spread over
@@ -521,7 +527,7 @@ __device__ void huge_diag_solve(const cx<T>* F, int m, int kb, int nb, const cx<
             }
         } else {
             for (int k = nb - 1; k >= 0; --k) {
-                if (lane == k) wi = cmul(wi, crecip(sh.d[k][k]));
+                if (lane == k) wi = cmul(wi, sh.rd[k]);
                 const cx<T> xk = shfl_cx(wi, k);
                 if (lane < k) wi = cfms(wi, sh.d[lane][k], xk);
             }
@@ -557,7 +563,8 @@ __global__ void __launch_bounds__(kWG) k_huge_fwd(const int32_t* __restrict__ hu
             const int r = r0 + e % rows, lr = e / rows;
             cx<T> acc = w[r + (size_t)(l0 + lr) * m];
             const cx<T>* Fr = F + r + (size_t)kb * m;
-            acc = row_panel_fms<T>(acc, Fr, m, nb, sh.y, lr);
+#pragma unroll 16
+            for (int k = 0; k < nb; ++k) acc = cfms(acc, Fr[(size_t)k * m], sh.y[k][lr]);
             w[r + (size_t)(l0 + lr) * m] = acc;
         }
     }
@@ -597,7 +604,8 @@ __global__ void __launch_bounds__(kWG) k_huge_bwd_cb(const int32_t* __restrict__
                 const int r = r0 + e % rows, lr = e / rows;
                 const cx<T>* Fr = F + r + (size_t)(p + s0) * m;
                 cx<T> v = acc[g];
-                v = row_panel_fms<T>(v, Fr, m, ns, sh.y, lr);
+#pragma unroll 16
+                for (int k = 0; k < ns; ++k) v = cfms(v, Fr[(size_t)k * m], sh.y[k][lr]);
                 acc[g] = v;
             }
         }
@@ -624,6 +632,7 @@ __global__ void __launch_bounds__(kWG) k_huge_bwd(const int32_t* __restrict__ hu
         const int i = e % kSB, k = e / kSB;
         sh.d[i][k] = (i < nb && k < nb) ? F[kb + i + (size_t)(kb + k) * m] : cx<T>{T(1), T(0)};
     }
+    if (t < kSB) sh.rd[t] = t < nb ? crecip(F[kb + t + (size_t)(kb + t) * m]) : cx<T>{T(1), T(0)};
     for (int l0 = 0; l0 < a.nrhs; l0 += kSR) {
         const int nr = min(kSR, a.nrhs - l0);
         __syncthreads();
@@ -635,7 +644,8 @@ __global__ void __launch_bounds__(kWG) k_huge_bwd(const int32_t* __restrict__ hu
             const int r = r0 + e % rows, lr = e / rows;
             cx<T> acc = w[r + (size_t)(l0 + lr) * m];
             const cx<T>* Fr = F + r + (size_t)kb * m;
-            acc = row_panel_fms<T>(acc, Fr, m, nb, sh.y, lr);
+#pragma unroll 16
+            for (int k = 0; k < nb; ++k) acc = cfms(acc, Fr[(size_t)k * m], sh.y[k][lr]);
             w[r + (size_t)(l0 + lr) * m] = acc;
         }
     }
@@ -763,18 +773,19 @@ void run_factor(Factor& f, cr_sys sys, double sigma, cx<T>* arena, T tiny, hipSt
             }
             if (j % (kOB / kNB) == kOB / kNB - 1 || j == S.nsteps[l] - 1) {
                 const int blk = j / (kOB / kNB);
-                unsigned gx = 0;
+                int rmax = 0;   // largest trailing order of the level's fronts after this block
                 for (int q = S.big_off[l]; q < S.big_off[l + 1]; ++q) {
                     const int f = S.big_list[q], m = S.fsize[f], p = S.npiv[f], K0 = blk * kOB;
                     if (K0 >= p) continue;
-                    const int K1 = std::min(K0 + kOB, p);
-                    const unsigned nt = (unsigned)((m - K1 + kGT - 1) / kGT);
-                    gx = std::max(gx, nt * nt);
+                    rmax = std::max(rmax, m - std::min(K0 + kOB, p));
                 }
-                if (gx) {
+                if (rmax > 0) {
+                    // 64 x 64 tiles: 128 x 128 tiles (one wave per SIMD for their accumulators) were
+                    // measured slower on the fuselage fronts
+                    const unsigned nt = (unsigned)((rmax + kGT - 1) / kGT);
                     ProfScope ps(sys->ctx, "front_gemm", s);
-                    hipLaunchKernelGGL(k_front_gemm<T>, dim3(gx, nbig), dim3(kWG), 0, s, bl, blk, D.fsize.p, D.npiv.p,
-                                       D.front_off.p, arena);
+                    hipLaunchKernelGGL((k_front_gemm<T, kGT>), dim3(nt * nt, nbig), dim3(kWG), 0, s, bl, blk, D.fsize.p,
+                                       D.npiv.p, D.front_off.p, arena);
                 }
             }
         }
@@ -813,7 +824,11 @@ void run_solve(const Factor& f, int nrhs, cx<T>* xp, cx<T>* work, hipStream_t s,
             const int nf = S.level_off[l + 1] - S.level_off[l];
             {
                 ProfScope ps(sys->ctx, "front_fwd", s);
-                hipLaunchKernelGGL(k_front_fwd<T>, dim3(nf), dim3(kWG), 0, s, D.level_fronts.p + S.level_off[l], a);
+                if (S.wide_solve[l])
+                    hipLaunchKernelGGL((k_front_fwd<T, kWideSolve>), dim3(nf), dim3(kWideSolve), 0, s,
+                                       D.level_fronts.p + S.level_off[l], a);
+                else
+                    hipLaunchKernelGGL((k_front_fwd<T, kWG>), dim3(nf), dim3(kWG), 0, s, D.level_fronts.p + S.level_off[l], a);
             }
             const int nh = S.huge_off[l + 1] - S.huge_off[l];
             const int32_t* hl = D.huge_list.p + S.huge_off[l];
@@ -831,7 +846,11 @@ void run_solve(const Factor& f, int nrhs, cx<T>* xp, cx<T>* work, hipStream_t s,
             const int nf = S.level_off[l + 1] - S.level_off[l];
             {
                 ProfScope ps(sys->ctx, "front_bwd", s);
-                hipLaunchKernelGGL(k_front_bwd<T>, dim3(nf), dim3(kWG), 0, s, D.level_fronts.p + S.level_off[l], a);
+                if (S.wide_solve[l])
+                    hipLaunchKernelGGL((k_front_bwd<T, kWideSolve>), dim3(nf), dim3(kWideSolve), 0, s,
+                                       D.level_fronts.p + S.level_off[l], a);
+                else
+                    hipLaunchKernelGGL((k_front_bwd<T, kWG>), dim3(nf), dim3(kWG), 0, s, D.level_fronts.p + S.level_off[l], a);
             }
             const int nh = S.huge_off[l + 1] - S.huge_off[l];
             if (nh == 0) continue;

@@ -44,43 +44,46 @@ struct MfmaAcc<double> {
     static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
 };
 
-template <typename T>
+template <typename T, int TW = kGT>
 struct GemmShared {
-    static constexpr int KC = sizeof(T) == 4 ? 32 : 16;   // K chunk staged in LDS (~35 KB)
-    cx<T> a[KC][kGT + 4];   // L21 chunk, a[k][i]
-    cx<T> b[KC][kGT + 4];   // U12 chunk, b[k][j]
+    static constexpr int KC = sizeof(T) == 4 ? 32 : 16;   // K chunk staged in LDS (35 KB at TW = 64, 68 KB at 128)
+    cx<T> a[KC][TW + 4];   // L21 chunk, a[k][i]
+    // U12 chunk, b[k][j]; it is written along k (one column of U12 per lane run), so an odd row
+    // pitch spreads those writes over the LDS banks
+    cx<T> b[KC][TW + 1];
 };
 
-// C[i0:i0+64, j0:j0+64] -= A[i0:, k0:k0+K] A[k0:k0+K, j0:] inside the m x m column-major front
-// (rows and columns >= m are skipped). 256 threads; wave w owns the 32 x 32 quadrant
-// (32 (w & 1), 32 (w >> 1)) as 2 x 2 blocks of 16 x 16.
-template <typename T>
+// C[i0:i0+TW, j0:j0+TW] -= A[i0:, k0:k0+K] A[k0:k0+K, j0:] inside the m x m column-major front
+// (rows and columns >= m are skipped). 256 threads; wave w owns the (TW/2) x (TW/2) quadrant
+// ((TW/2) (w & 1), (TW/2) (w >> 1)) as BI x BI blocks of 16 x 16 (BI = TW / 32).
+template <typename T, int TW = kGT>
 __device__ void wg_gemm_tile(cx<T>* __restrict__ A, int lda, int m, int k0, int K, int i0, int j0,
-                             GemmShared<T>& sh) {
+                             GemmShared<T, TW>& sh) {
     typedef typename MfmaAcc<T>::type acc_t;
+    constexpr int BI = TW / 32;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int wi = 32 * (w & 1), wj = 32 * (w >> 1);
-    acc_t are[2][2], aim[2][2];
+    const int wi = (TW / 2) * (w & 1), wj = (TW / 2) * (w >> 1);
+    acc_t are[BI][BI], aim[BI][BI];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < BI; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
+        for (int b = 0; b < BI; ++b) {
             are[a][b] = acc_t{0, 0, 0, 0};
             aim[a][b] = acc_t{0, 0, 0, 0};
         }
-    constexpr int KC = GemmShared<T>::KC;
+    constexpr int KC = GemmShared<T, TW>::KC;
     for (int kc = 0; kc < K; kc += KC) {
         const int nk = min(KC, K - kc);
         __syncthreads();
-        // L21 chunk: 64 rows x KC columns, coalesced down the columns
-        for (int e = t; e < kGT * KC; e += kWG) {
-            const int i = e % kGT, k = e / kGT;
+        // L21 chunk: TW rows x KC columns, coalesced down the columns
+        for (int e = t; e < TW * KC; e += kWG) {
+            const int i = e % TW, k = e / TW;
             cx<T> v = {T(0), T(0)};
             if (k < nk && i0 + i < m) v = A[i0 + i + (size_t)(k0 + kc + k) * lda];
             sh.a[k][i] = v;
         }
-        // U12 chunk: KC rows x 64 columns, coalesced down the columns
-        for (int e = t; e < kGT * KC; e += kWG) {
+        // U12 chunk: KC rows x TW columns, coalesced down the columns
+        for (int e = t; e < TW * KC; e += kWG) {
             const int k = e % KC, j = e / KC;
             cx<T> v = {T(0), T(0)};
             if (k < nk && j0 + j < m) v = A[k0 + kc + k + (size_t)(j0 + j) * lda];
@@ -89,15 +92,15 @@ __device__ void wg_gemm_tile(cx<T>* __restrict__ A, int lda, int m, int k0, int 
         __syncthreads();
         const int li = lane & 15, lk = lane >> 4;
         for (int kk = 0; kk < nk; kk += 4) {
-            cx<T> av[2], bv[2];
+            cx<T> av[BI], bv[BI];
 #pragma unroll
-            for (int a = 0; a < 2; ++a) av[a] = sh.a[kk + lk][wi + 16 * a + li];
+            for (int a = 0; a < BI; ++a) av[a] = sh.a[kk + lk][wi + 16 * a + li];
 #pragma unroll
-            for (int b = 0; b < 2; ++b) bv[b] = sh.b[kk + lk][wj + 16 * b + li];
+            for (int b = 0; b < BI; ++b) bv[b] = sh.b[kk + lk][wj + 16 * b + li];
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
+            for (int a = 0; a < BI; ++a)
 #pragma unroll
-                for (int b = 0; b < 2; ++b) {
+                for (int b = 0; b < BI; ++b) {
                     are[a][b] = MfmaAcc<T>::mfma(av[a].re, bv[b].re, are[a][b]);
                     are[a][b] = MfmaAcc<T>::mfma(-av[a].im, bv[b].im, are[a][b]);
                     aim[a][b] = MfmaAcc<T>::mfma(av[a].re, bv[b].im, aim[a][b]);
@@ -108,9 +111,9 @@ __device__ void wg_gemm_tile(cx<T>* __restrict__ A, int lda, int m, int k0, int 
     // epilogue: each lane owns 4 rows of one column per 16 x 16 block
     const int lj = lane & 15;
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < BI; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
+        for (int b = 0; b < BI; ++b) {
             const int j = j0 + wj + 16 * b + lj;
             if (j >= m) continue;
             cx<T>* col = A + (size_t)j * lda;
