@@ -50,6 +50,35 @@ def _args():
     return ap.parse_args()
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_plate_cavity.txt")
+TRAFFIC_SOURCES = ["paper_2310_04734_amd/csrc/factor.hip", "paper_2310_04734_amd/csrc/dense.cuh",
+                   "paper_2310_04734_amd/csrc/gemm.cuh"]
+
+
+def _measured_traffic(kernel, elt):
+    """HBM bytes per dispatch of a front kernel from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE scaled by a plain copy of known size), or None when the summary is missing or the
+    kernel sources changed since the counters were taken."""
+    import hashlib
+    try:
+        lines = open(TRAFFIC_FILE).read().splitlines()
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for p in TRAFFIC_SOURCES:
+        h.update(open(os.path.join(ROOT, p), "rb").read())
+    kv = dict(ln.split(" = ", 1) for ln in lines if " = " in ln and not ln.startswith("#"))
+    if kv.get("source_sha256_16") != h.hexdigest()[:16]:
+        return None
+    full = f"k_{kernel}<{'double' if elt == 16 else 'float'}>"
+    for ln in lines:
+        if ln.startswith(full + " "):
+            for tok in ln.split():
+                if tok.startswith("bytes_per_dispatch="):
+                    return float(tok.split("=", 1)[1])
+    return None
+
+
 def _roofline(name, launches, ms, an, n_fact, n_solves, elt):
     """Achieved rate of one kernel from the algorithmic work its launches did."""
     if name in ("front_fwd", "front_bwd"):
@@ -57,7 +86,7 @@ def _roofline(name, launches, ms, an, n_fact, n_solves, elt):
         byts = 0.5 * an["factor_entries"] * elt * n_solves
         ach = byts / (ms * 1e-3) / 1e9
         return {"kernel": name, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": ach / PEAK_HBM_GBS, "traffic": None,
+                "frac": ach / PEAK_HBM_GBS, "traffic": _measured_traffic(name, elt),
                 "work_per_launch": f"{0.5 * an['factor_entries'] * elt / an['n_levels']:.4g} B "
                                    f"(factor triangle / tree levels)",
                 "launches": launches, "avg_launch_us": 1e3 * ms / launches}

@@ -72,24 +72,33 @@ __device__ void wg_gemm_tile(cx<T>* __restrict__ A, int lda, int m, int k0, int 
             aim[a][b] = acc_t{0, 0, 0, 0};
         }
     constexpr int KC = GemmShared<T, TW>::KC;
+    constexpr int PER = TW * KC / kWG;   // entries of each operand chunk per thread
+    // software pipeline: chunk c + 1 is fetched into registers (all loads in flight together)
+    // while chunk c is multiplied from LDS
+    cx<T> ra[PER], rb[PER];
+    auto fetch = [&](int kc) {
+        const int nk = min(KC, K - kc);
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = t + q * kWG;
+            const int i = e % TW, k = e / TW;
+            ra[q] = (k < nk && i0 + i < m) ? A[i0 + i + (size_t)(k0 + kc + k) * lda] : cx<T>{T(0), T(0)};
+            const int k2 = e % KC, j = e / KC;
+            rb[q] = (k2 < nk && j0 + j < m) ? A[k0 + kc + k2 + (size_t)(j0 + j) * lda] : cx<T>{T(0), T(0)};
+        }
+    };
+    fetch(0);
     for (int kc = 0; kc < K; kc += KC) {
         const int nk = min(KC, K - kc);
         __syncthreads();
-        // L21 chunk: TW rows x KC columns, coalesced down the columns
-        for (int e = t; e < TW * KC; e += kWG) {
-            const int i = e % TW, k = e / TW;
-            cx<T> v = {T(0), T(0)};
-            if (k < nk && i0 + i < m) v = A[i0 + i + (size_t)(k0 + kc + k) * lda];
-            sh.a[k][i] = v;
-        }
-        // U12 chunk: KC rows x TW columns, coalesced down the columns
-        for (int e = t; e < TW * KC; e += kWG) {
-            const int k = e % KC, j = e / KC;
-            cx<T> v = {T(0), T(0)};
-            if (k < nk && j0 + j < m) v = A[k0 + kc + k + (size_t)(j0 + j) * lda];
-            sh.b[k][j] = v;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = t + q * kWG;
+            sh.a[e / TW][e % TW] = ra[q];   // L21 chunk, coalesced down the columns
+            sh.b[e % KC][e / KC] = rb[q];   // U12 chunk, coalesced down the columns
         }
         __syncthreads();
+        if (kc + KC < K) fetch(kc + KC);
         const int li = lane & 15, lk = lane >> 4;
         for (int kk = 0; kk < nk; kk += 4) {
             cx<T> av[BI], bv[BI];
@@ -108,23 +117,36 @@ __device__ void wg_gemm_tile(cx<T>* __restrict__ A, int lda, int m, int k0, int 
                 }
         }
     }
-    // epilogue: each lane owns 4 rows of one column per 16 x 16 block
+    // epilogue: each lane owns 4 rows of one column per 16 x 16 block; all of the lane's C
+    // entries are loaded before the first store, so the read-modify-write pays one memory
+    // latency instead of one per entry (entries outside the front read a clamped address and
+    // are not stored)
     const int lj = lane & 15;
+    cx<T> cv[BI][BI][4];
+#pragma unroll
+    for (int a = 0; a < BI; ++a)
+#pragma unroll
+        for (int b = 0; b < BI; ++b) {
+            const int j = min(j0 + wj + 16 * b + lj, m - 1);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = min(i0 + wi + 16 * a + MfmaAcc<T>::row(lane, r), m - 1);
+                cv[a][b][r] = A[i + (size_t)j * lda];
+            }
+        }
 #pragma unroll
     for (int a = 0; a < BI; ++a)
 #pragma unroll
         for (int b = 0; b < BI; ++b) {
             const int j = j0 + wj + 16 * b + lj;
-            if (j >= m) continue;
-            cx<T>* col = A + (size_t)j * lda;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int i = i0 + wi + 16 * a + MfmaAcc<T>::row(lane, r);
-                if (i < m) {
-                    cx<T> x = col[i];
+                if (i < m && j < m) {
+                    cx<T> x = cv[a][b][r];
                     x.re -= are[a][b][r];
                     x.im -= aim[a][b][r];
-                    col[i] = x;
+                    A[i + (size_t)j * lda] = x;
                 }
             }
         }
@@ -145,15 +167,22 @@ __device__ void wg_strip_update(cx<T>* __restrict__ A, int lda, int r0, int nr, 
     cx<T> acc[4];
 #pragma unroll
     for (int g = 0; g < 4; ++g) acc[g] = {T(0), T(0)};
+    constexpr int PER = kST * kNB / kWG;   // staged entries of each operand per thread
     for (int kc = 0; kc < K; kc += kNB) {
-        __syncthreads();
-        for (int e = t; e < nr * kNB; e += kWG) {
-            const int i = e % nr, k = e / nr;
-            sh.l[i][k] = A[r0 + i + (size_t)(k0 + kc + k) * lda];
+        // all loads of the chunk in flight before the first LDS store
+        cx<T> rl[PER], ru[PER];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = t + q * kWG;
+            rl[q] = e < nr * kNB ? A[r0 + e % nr + (size_t)(k0 + kc + e / nr) * lda] : cx<T>{T(0), T(0)};
+            ru[q] = e < kNB * nc ? A[k0 + kc + e % kNB + (size_t)(c0 + e / kNB) * lda] : cx<T>{T(0), T(0)};
         }
-        for (int e = t; e < kNB * nc; e += kWG) {
-            const int k = e % kNB, j = e / kNB;
-            sh.u[k][j] = A[k0 + kc + k + (size_t)(c0 + j) * lda];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = t + q * kWG;
+            if (e < nr * kNB) sh.l[e % nr][e / nr] = rl[q];
+            if (e < kNB * nc) sh.u[e % kNB][e / kNB] = ru[q];
         }
         __syncthreads();
 #pragma unroll
@@ -171,14 +200,19 @@ __device__ void wg_strip_update(cx<T>* __restrict__ A, int lda, int r0, int nr, 
             }
         }
     }
+    cx<T> cv[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const int e = t + g * kWG;
+        cv[g] = e < nr * nc ? A[r0 + e % nr + (size_t)(c0 + e / nr) * lda] : cx<T>{T(0), T(0)};
+    }
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
         const int e = t + g * kWG;
         if (e < nr * nc) {
-            const int i = e % nr, j = e / nr;
-            cx<T>& x = A[r0 + i + (size_t)(c0 + j) * lda];
-            x.re -= acc[g].re;
-            x.im -= acc[g].im;
+            cv[g].re -= acc[g].re;
+            cv[g].im -= acc[g].im;
+            A[r0 + e % nr + (size_t)(c0 + e / nr) * lda] = cv[g];
         }
     }
 }
