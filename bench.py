@@ -40,7 +40,8 @@ def _args():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", choices=["fp64", "mixed"], default=None, help="time one configuration only")
+    ap.add_argument("--only", choices=["fp64", "mixed", "fuselage", "batched"], default=None,
+                    help="time one configuration only (fuselage / batched: only that section, for profiling)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-sweep measurement")
     ap.add_argument("--batched-roms", type=int, default=256)
     ap.add_argument("--no-fuselage", action="store_true", help="skip the 529k-DoF fuselage measurement")
@@ -274,6 +275,12 @@ def main():
     import workloads as W
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if a.only == "fuselage":
+        print(json.dumps({"fuselage": bench_fuselage(P, W, P.Context(0), a.fuselage_shifts)}))
+        return
+    if a.only == "batched":
+        print(json.dumps({"batched_sweep": bench_batched(P, W, P.Context(0), max(1, a.steps), n_rom=a.batched_roms)}))
+        return
     w = W.plate_cavity_workload()
     rp = w.rom
     ctx = P.Context(0)

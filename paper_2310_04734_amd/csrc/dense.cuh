@@ -44,6 +44,28 @@ constexpr int kWG = 256;     // threads per workgroup (4 wavefronts)
 constexpr int kNB = 16;      // panel width
 constexpr int kTile = 64;    // trailing-update tile (64 x 64, 4 x 4 per thread)
 
+// Element loop over [0, n) with stride NT in batches of U iterations: the loads of all U
+// iterations are issued before any of their stores. The callers' iterations touch disjoint
+// addresses, which the compiler cannot prove, so without the batching every iteration would
+// wait for its own loads.
+template <int NT, int U, typename Load, typename Store>
+__device__ __forceinline__ void batched_for(int n, Load ld, Store st) {
+    using V = decltype(ld(0));
+    for (int base = threadIdx.x; base < n; base += NT * U) {
+        V v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = base + u * NT;
+            if (e < n) v[u] = ld(e);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = base + u * NT;
+            if (e < n) st(e, v[u]);
+        }
+    }
+}
+
 // Workgroup max-reduction of (value, index); lowest index wins ties. Uses red_v/red_i in LDS
 // (kWG / 64 + 1 entries each). All threads receive the result.
 template <typename T>
@@ -88,7 +110,9 @@ struct LuShared {
 // update to the rest of the panel and takes the next column's pivot candidates on the way.
 // Pivots with cabs1 <= tiny (or NaN) are replaced by tiny in their own direction and counted
 // in *nperturb.
-template <typename T>
+// LEAN = true keeps every loop register-light (one row or entry in flight per thread) for
+// callers whose occupancy matters more than memory-level parallelism (the reduced-model sweep).
+template <typename T, bool LEAN = false>
 __device__ void wg_panel(cx<T>* __restrict__ A, int lda, int m, int p, int k0, int k1, int* __restrict__ ipiv, T tiny,
                          int* nperturb, LuShared<T>& sh, int sw0, int sw1, bool trsm, int rend) {
     const int t = threadIdx.x;
@@ -137,14 +161,36 @@ __device__ void wg_panel(cx<T>* __restrict__ A, int lda, int m, int p, int k0, i
             best = T(-1);
             bi = k + 1;
             for (int i = k + 1 + t; i < rend; i += kWG) {
-                const cx<T> l = cmul(A[i + (size_t)k * lda], r);
+                if constexpr (LEAN) {
+                    const cx<T> l = cmul(A[i + (size_t)k * lda], r);
+                    A[i + (size_t)k * lda] = l;
+#pragma unroll
+                    for (int jj = 0; jj < kNB - 1; ++jj) {
+                        if (jj < nc) {
+                            cx<T>& x = A[i + (size_t)(k + 1 + jj) * lda];
+                            const cx<T> y = cfms(x, l, u[jj]);
+                            x = y;
+                            if (jj == 0 && i < p) {
+                                const T v = cabs1(y);
+                                if (v > best) { best = v; bi = i; }
+                            }
+                        }
+                    }
+                    continue;
+                }
+                // the row's entries are all loaded before any store (one memory latency per row)
+                const cx<T> a0 = A[i + (size_t)k * lda];
+                cx<T> xv[kNB - 1];
+#pragma unroll
+                for (int jj = 0; jj < kNB - 1; ++jj)
+                    xv[jj] = jj < nc ? A[i + (size_t)(k + 1 + jj) * lda] : cx<T>{T(0), T(0)};
+                const cx<T> l = cmul(a0, r);
                 A[i + (size_t)k * lda] = l;
 #pragma unroll
                 for (int jj = 0; jj < kNB - 1; ++jj) {
                     if (jj < nc) {
-                        cx<T>& x = A[i + (size_t)(k + 1 + jj) * lda];
-                        const cx<T> y = cfms(x, l, u[jj]);
-                        x = y;
+                        const cx<T> y = cfms(xv[jj], l, u[jj]);
+                        A[i + (size_t)(k + 1 + jj) * lda] = y;
                         if (jj == 0 && i < p) {
                             const T v = cabs1(y);
                             if (v > best) { best = v; bi = i; }
@@ -157,10 +203,12 @@ __device__ void wg_panel(cx<T>* __restrict__ A, int lda, int m, int p, int k0, i
             // of the rank-1 update is one thread's work so that all threads stay busy
             for (int i = k + 1 + t; i < rend; i += kWG) A[i + (size_t)k * lda] = cmul(A[i + (size_t)k * lda], r);
             __syncthreads();
-            for (int e = t; e < rows * nc; e += kWG) {
-                const int i = k + 1 + e % rows, j = k + 1 + e / rows;
-                A[i + (size_t)j * lda] = cfms(A[i + (size_t)j * lda], A[i + (size_t)k * lda], A[k + (size_t)j * lda]);
-            }
+            batched_for<kWG, LEAN ? 1 : 4>(rows * nc,
+                [&](int e) {
+                    const int i = k + 1 + e % rows, j = k + 1 + e / rows;
+                    return cfms(A[i + (size_t)j * lda], A[i + (size_t)k * lda], A[k + (size_t)j * lda]);
+                },
+                [&](int e, cx<T> v) { A[k + 1 + e % rows + (size_t)(k + 1 + e / rows) * lda] = v; });
         }
         __syncthreads();
     }
@@ -242,7 +290,7 @@ __device__ void wg_panel_lds(cx<T>* __restrict__ A, int lda, int p, int k0, int 
 
 // One 64 x 64 tile (rows i0.., columns j0..) of the trailing update
 // A[k1:m, k1:m] -= A[k1:m, k0:k1] A[k0:k1, k1:m], with k1 - k0 <= kNB.
-template <typename T>
+template <typename T, bool LEAN = false>
 __device__ void wg_tile_update(cx<T>* __restrict__ A, int lda, int m, int k0, int k1, int i0, int j0, LuShared<T>& sh) {
     const int t = threadIdx.x;
     const int nbk = k1 - k0;
@@ -279,32 +327,52 @@ __device__ void wg_tile_update(cx<T>* __restrict__ A, int lda, int m, int k0, in
                 acc[a][b].im += av[a].re * bv[b].im + av[a].im * bv[b].re;
             }
     }
+    if constexpr (LEAN) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int i = i0 + tx + 16 * a, j = j0 + ty + 16 * b;
+                if (i < m && j < m) {
+                    cx<T>& x = A[i + (size_t)j * lda];
+                    x.re -= acc[a][b].re;
+                    x.im -= acc[a][b].im;
+                }
+            }
+        __syncthreads();
+        return;
+    }
+    // all 16 entries of the thread are loaded before the first store (one memory latency)
+    cx<T> cv[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            int i = i0 + tx + 16 * a, j = j0 + ty + 16 * b;
-            if (i < m && j < m) {
-                cx<T>& x = A[i + (size_t)j * lda];
-                x.re -= acc[a][b].re;
-                x.im -= acc[a][b].im;
-            }
+            const int i = i0 + tx + 16 * a, j = j0 + ty + 16 * b;
+            cv[a][b] = (i < m && j < m) ? A[i + (size_t)j * lda] : cx<T>{T(0), T(0)};
+        }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int i = i0 + tx + 16 * a, j = j0 + ty + 16 * b;
+            if (i < m && j < m) A[i + (size_t)j * lda] = {cv[a][b].re - acc[a][b].re, cv[a][b].im - acc[a][b].im};
         }
     __syncthreads();
 }
 
 // Whole partial LU inside one workgroup: P A = L U on the leading p columns with the trailing
 // (m-p) x (m-p) block replaced by its Schur complement.
-template <typename T>
+template <typename T, bool LEAN = false>
 __device__ void wg_getrf(cx<T>* __restrict__ A, int lda, int m, int p, int* __restrict__ ipiv, T tiny, int* nperturb,
                          LuShared<T>& sh) {
     for (int k0 = 0; k0 < p; k0 += kNB) {
         const int k1 = min(k0 + kNB, p);
-        wg_panel<T>(A, lda, m, p, k0, k1, ipiv, tiny, nperturb, sh, 0, m, true, m);
+        wg_panel<T, LEAN>(A, lda, m, p, k0, k1, ipiv, tiny, nperturb, sh, 0, m, true, m);
         if (k1 >= m) break;
         const int tiles = (m - k1 + kTile - 1) / kTile;
         for (int tile = 0; tile < tiles * tiles; ++tile)
-            wg_tile_update<T>(A, lda, m, k0, k1, k1 + (tile % tiles) * kTile, k1 + (tile / tiles) * kTile, sh);
+            wg_tile_update<T, LEAN>(A, lda, m, k0, k1, k1 + (tile % tiles) * kTile, k1 + (tile / tiles) * kTile, sh);
     }
     __syncthreads();
 }

@@ -47,13 +47,21 @@ __global__ void __launch_bounds__(kWG) k_front_assemble(
             for (int i = t; i < m; i += kWG) F[i + (size_t)j * m] = {T(0), T(0)};
     }
     __syncthreads();
-    for (int64_t e = ent_off[f] + t; e < ent_off[f + 1]; e += kWG) {
-        const int32_t d = ent_dst[e];
-        if (S > 1 && (d / m) % S != y) continue;
-        const int64_t s = ent_src[e];
-        const zd k = K[s], mv = M[s];
-        F[d] = {T(k.re - sigma * mv.re), T(k.im - sigma * mv.im)};
-    }
+    const int64_t e0 = ent_off[f];
+    const int ne = (int)(ent_off[f + 1] - e0);
+    auto mine = [&](int32_t d) { return S == 1 || (d / m) % S == y; };
+    batched_for<kWG, 4>(ne,
+        [&](int e) {
+            const int32_t d = ent_dst[e0 + e];
+            if (!mine(d)) return cx<T>{T(0), T(0)};
+            const int64_t s = ent_src[e0 + e];
+            const zd k = K[s], mv = M[s];
+            return cx<T>{T(k.re - sigma * mv.re), T(k.im - sigma * mv.im)};   // FP64, rounded once
+        },
+        [&](int e, cx<T> v) {
+            const int32_t d = ent_dst[e0 + e];
+            if (mine(d)) F[d] = v;
+        });
     __syncthreads();
     for (int ci = child_off[f]; ci < child_off[f + 1]; ++ci) {
         const int c = child_list[ci];
@@ -61,25 +69,25 @@ __global__ void __launch_bounds__(kWG) k_front_assemble(
         const cx<T>* C = arena + front_off[c];
         const int32_t* map = cmap + cmap_off[c];
         if (S == 1) {
-            for (int e = t; e < nc * nc; e += kWG) {
-                const int r = e % nc, s = e / nc;
-                const cx<T> v = C[(pc + r) + (size_t)(pc + s) * mc];
-                cx<T>& d = F[map[r] + (size_t)map[s] * m];
-                d.re += v.re;
-                d.im += v.im;
-            }
+            batched_for<kWG, 4>(nc * nc,
+                [&](int e) {
+                    const int r = e % nc, s = e / nc;
+                    const cx<T> v = C[(pc + r) + (size_t)(pc + s) * mc], d = F[map[r] + (size_t)map[s] * m];
+                    return cx<T>{d.re + v.re, d.im + v.im};
+                },
+                [&](int e, cx<T> v) { F[map[e % nc] + (size_t)map[e / nc] * m] = v; });
         } else {
             for (int s = 0; s < nc; ++s) {
                 const int js = map[s];
                 if (js % S != y) continue;
                 const cx<T>* Cs = C + pc + (size_t)(pc + s) * mc;
                 cx<T>* Fs = F + (size_t)js * m;
-                for (int r = t; r < nc; r += kWG) {
-                    const cx<T> v = Cs[r];
-                    cx<T>& d = Fs[map[r]];
-                    d.re += v.re;
-                    d.im += v.im;
-                }
+                batched_for<kWG, 4>(nc,
+                    [&](int r) {
+                        const cx<T> v = Cs[r], d = Fs[map[r]];
+                        return cx<T>{d.re + v.re, d.im + v.im};
+                    },
+                    [&](int r, cx<T> v) { Fs[map[r]] = v; });
             }
         }
         __syncthreads();
@@ -321,38 +329,33 @@ __device__ void front_fwd(int f, const SolveArgs<T>& a, SolveShared<T>& sh) {
     const cx<T>* F = arena + front_off[f];
     cx<T>* w = work + idx_off[f] * nrhs;   // m x nrhs
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    for (int e = t; e < m * nrhs; e += NT) {
-        const int r = e % m, l = e / m;
-        w[e] = r < p ? x[f0 + r + (size_t)l * ldx] : cx<T>{T(0), T(0)};
-    }
+    batched_for<NT, 4>(m * nrhs,
+        [&](int e) { const int r = e % m, l = e / m; return r < p ? x[f0 + r + (size_t)l * ldx] : cx<T>{T(0), T(0)}; },
+        [&](int e, cx<T> v) { w[e] = v; });
     __syncthreads();
     for (int ci = child_off[f]; ci < child_off[f + 1]; ++ci) {
         const int c = child_list[ci];
         const int mc = fsize[c], pc = npiv[c], nc = mc - pc;
         const cx<T>* wc = work + idx_off[c] * nrhs;
         const int32_t* map = cmap + cmap_off[c];
-        for (int e = t; e < nc * nrhs; e += NT) {
-            const int r = e % nc, l = e / nc;
-            const cx<T> v = wc[pc + r + (size_t)l * mc];
-            cx<T>& d = w[map[r] + (size_t)l * m];
-            d.re += v.re;
-            d.im += v.im;
-        }
+        batched_for<NT, 4>(nc * nrhs,
+            [&](int e) {
+                const int r = e % nc, l = e / nc;
+                const cx<T> v = wc[pc + r + (size_t)l * mc], d = w[map[r] + (size_t)l * m];
+                return cx<T>{d.re + v.re, d.im + v.im};
+            },
+            [&](int e, cx<T> v) { w[map[e % nc] + (size_t)(e / nc) * m] = v; });
         __syncthreads();
     }
     if (p == 0) return;
     // the front's row swaps as one gather, w_piv[k] <- w_piv[psrc[k]], staged through the
     // front's own (not yet written) pivot slots of x
     const int32_t* src = a.psrc + f0;
-    for (int e = t; e < p * nrhs; e += NT) {
-        const int r = e % p, l = e / p;
-        x[f0 + r + (size_t)l * ldx] = w[r + (size_t)l * m];
-    }
+    batched_for<NT, 4>(p * nrhs, [&](int e) { return w[e % p + (size_t)(e / p) * m]; },
+                       [&](int e, cx<T> v) { x[f0 + e % p + (size_t)(e / p) * ldx] = v; });
     __syncthreads();
-    for (int e = t; e < p * nrhs; e += NT) {
-        const int r = e % p, l = e / p;
-        w[r + (size_t)l * m] = x[f0 + src[r] + (size_t)l * ldx];
-    }
+    batched_for<NT, 4>(p * nrhs, [&](int e) { return x[f0 + src[e % p] + (size_t)(e / p) * ldx]; },
+                       [&](int e, cx<T> v) { w[e % p + (size_t)(e / p) * m] = v; });
     __syncthreads();
     if (a.huge[f]) return;
     for (int kb = 0; kb < p; kb += kSB) {
@@ -388,10 +391,8 @@ __device__ void front_fwd(int f, const SolveArgs<T>& a, SolveShared<T>& sh) {
         }
         __syncthreads();
     }
-    for (int e = t; e < p * nrhs; e += NT) {
-        const int r = e % p, l = e / p;
-        x[f0 + r + (size_t)l * ldx] = w[r + (size_t)l * m];
-    }
+    batched_for<NT, 4>(p * nrhs, [&](int e) { return w[e % p + (size_t)(e / p) * m]; },
+                       [&](int e, cx<T> v) { x[f0 + e % p + (size_t)(e / p) * ldx] = v; });
 }
 
 // Backward: x_piv = U11^{-1} (y - U12 x_cb), x_cb gathered from already-solved ancestors.
@@ -410,10 +411,8 @@ __device__ void front_bwd(int f, const SolveArgs<T>& a, SolveShared<T>& sh) {
     const int32_t* ix = idx + idx_off[f];
     cx<T>* w = work + idx_off[f] * nrhs;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    for (int e = t; e < m * nrhs; e += NT) {
-        const int r = e % m, l = e / m;
-        w[e] = x[ix[r] + (size_t)l * ldx];
-    }
+    batched_for<NT, 4>(m * nrhs, [&](int e) { return x[ix[e % m] + (size_t)(e / m) * ldx]; },
+                       [&](int e, cx<T> v) { w[e] = v; });
     if (a.huge[f]) return;
     __syncthreads();
     // y_piv -= U12 x_cb, the contribution columns taken kSB at a time through LDS
@@ -488,10 +487,8 @@ __device__ void front_bwd(int f, const SolveArgs<T>& a, SolveShared<T>& sh) {
         }
         __syncthreads();
     }
-    for (int e = t; e < p * nrhs; e += NT) {
-        const int r = e % p, l = e / p;
-        x[f0 + r + (size_t)l * ldx] = w[r + (size_t)l * m];
-    }
+    batched_for<NT, 4>(p * nrhs, [&](int e) { return w[e % p + (size_t)(e / p) * m]; },
+                       [&](int e, cx<T> v) { x[f0 + e % p + (size_t)(e / p) * ldx] = v; });
 }
 
 // One launch per tree level and direction; every front of the level is one workgroup.

@@ -103,7 +103,7 @@ __device__ bool solve_item(const RomDesc& rd, double w, cx<T>* __restrict__ A, i
     if (t == 0) *s_perturb = 0;
     __syncthreads();
     const T tiny = sizeof(T) == 4 ? T(3e-4 * amax) : T(1e-8 * amax);
-    wg_getrf<T>(A, q, q, q, ipiv, tiny, s_perturb, sh);
+    wg_getrf<T, true>(A, q, q, q, ipiv, tiny, s_perturb, sh);
     int its = 0;
     double prev = 1e300;
     bool conv = false;
