@@ -92,17 +92,71 @@ __device__ __forceinline__ void wg_argmax(T v, int i, T* red_v, int* red_i, T& o
     __syncthreads();
 }
 
+// Composite permutation of one panel's row swaps (at most 2 kNB rows are touched).
+struct SwapShared {
+    int row[2 * kNB], src[2 * kNB], n;
+};
+
 template <typename T>
 struct LuShared {
     cx<T> a[kTile][kNB + 1];     // trailing update: L panel tile
     cx<T> b[kNB][kTile + 1];     // trailing update: U panel tile
     T red_v[kWG / 64 + 1];
     int red_i[kWG / 64 + 1];
+    SwapShared sw;
 };
+
+// The row swaps ipiv[k0..k1) (row k exchanged with row ipiv[k], in order; absolute row indices)
+// applied to columns [ca, cb) of A as one gather: thread 0 composes them into "row r now holds
+// old row src(r)" for the touched rows, then every moved entry is read before any is written
+// (a barrier between), so a panel's swaps cost one memory round trip on these columns instead
+// of one per swap. Same result as the swaps one by one. Called by the whole workgroup; ipiv
+// entries must be visible to thread 0 (it wrote them, or they come from an earlier kernel).
+template <typename T, int U = 4>
+__device__ void wg_apply_swaps(cx<T>* __restrict__ A, int lda, const int* ipiv, int k0, int k1, int ca, int cb,
+                               SwapShared& sw) {
+    const int t = threadIdx.x;
+    if (t == 0) {
+        int n = 0;
+        for (int k = k0; k < k1; ++k) {
+            const int r = ipiv[k];
+            if (r == k) continue;
+            int a = -1, b = -1;
+            for (int q = 0; q < n; ++q) {
+                if (sw.row[q] == k) a = q;
+                if (sw.row[q] == r) b = q;
+            }
+            if (a < 0) { sw.row[n] = k; sw.src[n] = k; a = n++; }
+            if (b < 0) { sw.row[n] = r; sw.src[n] = r; b = n++; }
+            const int x = sw.src[a];
+            sw.src[a] = sw.src[b];
+            sw.src[b] = x;
+        }
+        sw.n = n;
+    }
+    __syncthreads();
+    const int n = sw.n, total = n * max(cb - ca, 0);
+    for (int base = 0; base < total; base += U * kWG) {
+        cx<T> v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = base + u * kWG + t;
+            if (e < total) v[u] = A[sw.src[e % n] + (size_t)(ca + e / n) * lda];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = base + u * kWG + t;
+            if (e < total) A[sw.row[e % n] + (size_t)(ca + e / n) * lda] = v[u];
+        }
+        __syncthreads();
+    }
+}
 
 // Panel step of the partial LU of the m x m column-major A (leading dimension lda): factor
 // columns [k0, k1) over rows [k0, rend) with pivots searched among the fully-summed rows [k, p)
-// (ipiv[k] = row swapped with k; the swap is applied to columns [sw0, sw1) of the two rows),
+// (ipiv[k] = row swapped with k; the swap is applied to columns [sw0, sw1) of the two rows: the
+// panel's own columns at once, the others composed into one gather after the panel),
 // then, when trsm is set, U12 rows [k0, k1) x columns [k1, m) = L_kk^{-1} A (unit lower).
 // rend = m factors the whole panel; rend = p leaves the rows [p, m), which never take part in
 // pivoting, to a separate triangular solve with the panel's U (the large-front row-strip
@@ -113,7 +167,7 @@ struct LuShared {
 // LEAN = true keeps every loop register-light (one row or entry in flight per thread) for
 // callers whose occupancy matters more than memory-level parallelism (the reduced-model sweep).
 template <typename T, bool LEAN = false>
-__device__ void wg_panel(cx<T>* __restrict__ A, int lda, int m, int p, int k0, int k1, int* __restrict__ ipiv, T tiny,
+__device__ __forceinline__ void wg_panel(cx<T>* __restrict__ A, int lda, int m, int p, int k0, int k1, int* __restrict__ ipiv, T tiny,
                          int* nperturb, LuShared<T>& sh, int sw0, int sw1, bool trsm, int rend) {
     const int t = threadIdx.x;
     T best = T(-1);
@@ -133,7 +187,8 @@ __device__ void wg_panel(cx<T>* __restrict__ A, int lda, int m, int p, int k0, i
         wg_argmax(best, bi, sh.red_v, sh.red_i, pv, pi);
         if (t == 0) ipiv[k] = pi;
         if (pi != k) {
-            for (int j = sw0 + t; j < sw1; j += kWG) {
+            // the panel's own columns now; the other columns of [sw0, sw1) after the panel
+            for (int j = max(sw0, k0) + t; j < min(sw1, k1); j += kWG) {
                 cx<T> x = A[k + (size_t)j * lda], y = A[pi + (size_t)j * lda];
                 A[k + (size_t)j * lda] = y;
                 A[pi + (size_t)j * lda] = x;
@@ -212,6 +267,8 @@ __device__ void wg_panel(cx<T>* __restrict__ A, int lda, int m, int p, int k0, i
         }
         __syncthreads();
     }
+    wg_apply_swaps<T, LEAN ? 1 : 4>(A, lda, ipiv, k0, k1, sw0, min(sw1, k0), sh.sw);
+    wg_apply_swaps<T, LEAN ? 1 : 4>(A, lda, ipiv, k0, k1, max(sw0, k1), sw1, sh.sw);
     if (!trsm || k1 >= m) return;
     // U12 block: solve L_kk X = A[k0:k1, k1:m] (unit lower)
     for (int j = k1 + t; j < m; j += kWG) {
@@ -234,7 +291,8 @@ __device__ void wg_panel(cx<T>* __restrict__ A, int lda, int m, int p, int k0, i
 
 // Panel step as wg_panel with rend = p and no U12 solve, for panels whose fully-summed rows fit in
 // LDS (p - k0 <= R): the 16 columns are staged in LDS, factored there, and written back; the row
-// swaps reach the block's earlier columns [sw0, k0) in global memory. Same arithmetic, same order.
+// swaps reach the block's earlier columns [sw0, k0) in global memory after the panel, composed
+// into one gather. Same arithmetic, same order.
 template <typename T, int R>
 __device__ void wg_panel_lds(cx<T>* __restrict__ A, int lda, int p, int k0, int k1, int* __restrict__ ipiv, T tiny,
                              int* nperturb, LuShared<T>& sh, cx<T> (*P)[kNB + 1], int sw0) {
@@ -258,11 +316,6 @@ __device__ void wg_panel_lds(cx<T>* __restrict__ A, int lda, int p, int k0, int 
         if (t == 0) ipiv[k0 + k] = k0 + pi;
         if (pi != k) {
             if (t < nb) { cx<T> x = P[k][t]; P[k][t] = P[pi][t]; P[pi][t] = x; }
-            for (int j = sw0 + t; j < k0; j += kWG) {
-                cx<T> x = A[k0 + k + (size_t)j * lda], y = A[k0 + pi + (size_t)j * lda];
-                A[k0 + k + (size_t)j * lda] = y;
-                A[k0 + pi + (size_t)j * lda] = x;
-            }
             __syncthreads();
         }
         cx<T> d = P[k][k];
@@ -285,7 +338,8 @@ __device__ void wg_panel_lds(cx<T>* __restrict__ A, int lda, int p, int k0, int 
         const int i = e % rows, c = e / rows;
         A[k0 + i + (size_t)(k0 + c) * lda] = P[i][c];
     }
-    __syncthreads();
+    // the swaps reach the block's earlier columns once, after the panel
+    wg_apply_swaps<T>(A, lda, ipiv, k0, k1, sw0, k0, sh.sw);
 }
 
 // One 64 x 64 tile (rows i0.., columns j0..) of the trailing update

@@ -159,6 +159,7 @@ struct RowStripShared {
     StripShared<T> st;
     cx<T> d[kNB][kNB + 1];   // diagonal block of the panel (unit-lower L and U)
     cx<T> rd[kNB];           // reciprocals of U's diagonal
+    SwapShared sw;
 };
 
 template <typename T>
@@ -207,16 +208,9 @@ __global__ void __launch_bounds__(kWG) k_front_rowstrip(const int32_t* __restric
     const int c0 = right ? k1 + kST * x : kST * (x - nright);
     const int nc = right ? min(kST, m - c0) : min(kST, K0 - c0);
     const int32_t* pv = ipiv + first[f];
-    // the panel's swaps, in order, on this tile's columns
-    if (t < nc) {
-        cx<T>* col = A + (size_t)(c0 + t) * m;
-        for (int k = k0; k < k1; ++k) {
-            const int r = pv[k];
-            if (r != k) { cx<T> a = col[k]; col[k] = col[r]; col[r] = a; }
-        }
-    }
+    // the panel's swaps on this tile's columns, composed into one gather
+    wg_apply_swaps<T>(A, m, pv, k0, k1, c0, c0 + nc, sh.sw);
     if (!right) return;
-    __syncthreads();
     if (K0 < k0) wg_strip_update<T>(A, m, k0, nb, c0, nc, K0, k0 - K0, sh.st);
     for (int e = t; e < kNB * kNB; e += kWG) {
         const int i = e % kNB, k = e / kNB;
@@ -258,8 +252,8 @@ __global__ void __launch_bounds__(kWG) k_front_gemm(const int32_t* __restrict__ 
 
 // ------------------------------------------------------------------ solves
 // Both solves are blocked by 64 pivots (one wavefront): the 64 x 64 diagonal block is staged in
-// LDS and solved by one wave per right-hand side with one row per lane (values exchanged by
-// cross-lane shuffles, no barriers); the solved values are staged in LDS and the rest of the
+// LDS and solved by one wave per right-hand side with one row per lane (each solved value is
+// broadcast from its lane with v_readlane, no barriers); the solved values are staged in LDS and the rest of the
 // front vector is updated by the whole workgroup with the block's column panel, whose loads
 // are independent of each other (unrolled). Two barriers per 64 pivots.
 
@@ -267,17 +261,94 @@ constexpr int kWideSolve = 1024;   // threads per workgroup for the solve levels
 constexpr int kSB = 64;     // solve block (= wavefront size)
 constexpr int kSR = 16;     // right-hand sides per pass
 
-template <typename T>
-__device__ __forceinline__ cx<T> shfl_cx(cx<T> v, int src) {
-    return {__shfl(v.re, src), __shfl(v.im, src)};
+// The value of lane k (k wave-uniform) in every lane: v_readlane into a scalar register, which
+// costs a few cycles where a shuffle takes an LDS-crossbar round trip per 32-bit half; the
+// diagonal-block chains take one such broadcast per pivot.
+__device__ __forceinline__ float lane_value(float v, int k) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
 }
+__device__ __forceinline__ double lane_value(double v, int k) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned int lo = (unsigned int)__builtin_amdgcn_readlane((int)(unsigned int)b, k);
+    const unsigned int hi = (unsigned int)__builtin_amdgcn_readlane((int)(unsigned int)(b >> 32), k);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+template <typename T>
+__device__ __forceinline__ cx<T> lane_cx(cx<T> v, int k) {
+    return {lane_value(v.re, k), lane_value(v.im, k)};
+}
+
 
 template <typename T>
 struct SolveShared {
     cx<T> d[kSB][kSB + 1];   // diagonal block
     cx<T> y[kSB][kSR];       // solved block values
     cx<T> rd[kSB];           // reciprocals of U's diagonal in the block (backward solves)
+    cx<T> red[kWideSolve];   // partial sums of the column-split panel products
 };
+
+// Diagonal-block solves by one wave, lane i holding row i of the right-hand side. The lane's
+// entries of the block are read from LDS kChain at a time into registers ahead of the dependent
+// chain (one LDS wait per kChain steps), and the lane's update is a select rather than a branch.
+// Unit lower: wi <- L^{-1} wi over nb pivots.
+constexpr int kChain = 4;   // (8 trips a code-generation error in this compiler release)
+template <typename T>
+__device__ __forceinline__ cx<T> wave_lower_solve(cx<T> wi, const SolveShared<T>& sh, int nb, int lane) {
+    for (int k0 = 0; k0 < nb - 1; k0 += kChain) {
+        cx<T> dr[kChain];
+#pragma unroll
+        for (int j = 0; j < kChain; ++j) dr[j] = sh.d[lane][min(k0 + j, kSB - 1)];
+#pragma unroll
+        for (int j = 0; j < kChain; ++j) {
+            const int k = k0 + j;
+            if (k < nb - 1) {
+                const cx<T> wk = lane_cx(wi, k);
+                const cx<T> u = cfms(wi, dr[j], wk);
+                const bool upd = lane > k;
+                wi.re = upd ? u.re : wi.re;   // per component: a select of the values
+                wi.im = upd ? u.im : wi.im;
+            }
+        }
+    }
+    return wi;
+}
+// Upper: wi <- U^{-1} wi, sh.rd holding the reciprocals of U's diagonal.
+template <typename T>
+__device__ __forceinline__ cx<T> wave_upper_solve(cx<T> wi, const SolveShared<T>& sh, int nb, int lane) {
+    for (int k1 = nb - 1; k1 >= 0; k1 -= kChain) {
+        cx<T> dr[kChain], rr[kChain];
+#pragma unroll
+        for (int j = 0; j < kChain; ++j) {
+            dr[j] = sh.d[lane][max(k1 - j, 0)];
+            rr[j] = sh.rd[max(k1 - j, 0)];
+        }
+#pragma unroll
+        for (int j = 0; j < kChain; ++j) {
+            const int k = k1 - j;
+            if (k >= 0) {
+                const cx<T> xk = cmul(lane_cx(wi, k), rr[j]);
+                const cx<T> u = cfms(wi, dr[j], xk);
+                const bool piv = lane == k, upd = lane < k;
+                wi.re = piv ? xk.re : (upd ? u.re : wi.re);
+                wi.im = piv ? xk.im : (upd ? u.im : wi.im);
+            }
+        }
+    }
+    return wi;
+}
+
+// Column split of a panel product over few rows: with ne = rows x right-hand sides entries and
+// NT threads, the workgroup forms G groups of NT / G threads (G a power of two, at most 16, and
+// 1 when the entries fill half the workgroup); group g sums its own contiguous share of the
+// panel's columns, so a thread issues ncols / G loads instead of ncols, and the G partial sums
+// are added through LDS.
+template <int NT>
+__device__ __forceinline__ int split_groups(int ne) {
+    const int r = (ne + 63) & ~63;
+    int G = 1;
+    while (G < 16 && 2 * G * r <= NT) G *= 2;
+    return G;
+}
 
 // acc - sum_{k < nb} Fr[k m] y[k][lr] for nb <= 64, summed in k order; the panel's entries of the
 // row are loaded 32 at a time with all loads of a batch in flight before the first product
@@ -299,6 +370,149 @@ __device__ __forceinline__ cx<T> row_panel_fms(cx<T> acc, const cx<T>* __restric
     return acc;
 }
 
+// Partial product of group g (of G) over columns [0, ncols <= 64) of a panel: returns
+// -sum_{k in group's share} Fr[k m] y[k][lr]; the share is wave-uniform, so the loads of a
+// share are issued together under scalar branches, at most BATCH at a time (register budget of
+// the 1024-thread workgroups).
+template <typename T, int BATCH>
+__device__ __forceinline__ cx<T> group_panel_partial(const cx<T>* __restrict__ Fr, int64_t m, int ncols, int g,
+                                                     int G, const cx<T> (*y)[kSR], int lr) {
+    const int per = (ncols + G - 1) / G, ka = g * per, cnt = min(per, ncols - ka);
+    cx<T> acc = {T(0), T(0)};
+#pragma unroll
+    for (int h = 0; h < kSB / 2; h += BATCH) {
+        if (h >= cnt) break;
+        cx<T> f[BATCH];
+#pragma unroll
+        for (int k = 0; k < BATCH; ++k)
+            if (h + k < cnt) f[k] = Fr[(size_t)(ka + h + k) * m];
+#pragma unroll
+        for (int k = 0; k < BATCH; ++k)
+            if (h + k < cnt) acc = cfms(acc, f[k], y[ka + h + k][lr]);
+    }
+    return acc;
+}
+
+// ---- multi-RHS panel products on the matrix cores: W[rows, nr] -= F[rows, ncols] Y[ncols, nr]
+// for nr <= 16 as 16 x 16 output tiles (one per wave at a time), each complex product as four
+// real MFMA 16x16x4 products; every panel entry is loaded once (not once per right-hand side).
+// Lane l supplies the A operand F[row0 + l % 16][k0 + l / 16] and the B operand
+// Y[k0 + l / 16][l % 16] (zero past ncols or nr); item r of the accumulators is row
+// MfmaAcc<T>::row(l, r), column l % 16 of the tile.
+constexpr int kMfmaRhs = 4;   // right-hand sides from which the panel products use the matrix cores
+
+template <typename T>
+__device__ __forceinline__ void mfma_panel_accum(typename MfmaAcc<T>::type& dre, typename MfmaAcc<T>::type& dim,
+                                                 const cx<T>* __restrict__ Frow, int64_t ldf, bool rok, int ncols,
+                                                 const cx<T> (*y)[kSR], int nr) {
+    const int lane = threadIdx.x & 63, i = lane & 15, kk = lane >> 4;
+    constexpr int H = 8;   // K steps whose loads are issued together
+#pragma unroll
+    for (int s0 = 0; s0 < kSB / 4; s0 += H) {
+        if (4 * s0 >= ncols) break;
+        cx<T> av[H];
+#pragma unroll
+        for (int s = 0; s < H; ++s) {
+            const int k = 4 * (s0 + s) + kk;
+            av[s] = (rok && k < ncols) ? Frow[(size_t)k * ldf] : cx<T>{T(0), T(0)};
+        }
+#pragma unroll
+        for (int s = 0; s < H; ++s) {
+            const int k = 4 * (s0 + s) + kk;
+            const cx<T> b = (k < ncols && i < nr) ? y[k][i] : cx<T>{T(0), T(0)};
+            dre = MfmaAcc<T>::mfma(av[s].re, b.re, dre);
+            dre = MfmaAcc<T>::mfma(-av[s].im, b.im, dre);
+            dim = MfmaAcc<T>::mfma(av[s].re, b.im, dim);
+            dim = MfmaAcc<T>::mfma(av[s].im, b.re, dim);
+        }
+    }
+}
+
+// w[tr0 + row + j ldw] -= D[row][j] for row < trows, j < nr (one wave)
+template <typename T>
+__device__ __forceinline__ void mfma_tile_sub(cx<T>* w, int64_t ldw, int tr0, int trows, int nr,
+                                              const typename MfmaAcc<T>::type& dre,
+                                              const typename MfmaAcc<T>::type& dim) {
+    const int lane = threadIdx.x & 63, j = lane & 15;
+    cx<T> cv[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int ro = MfmaAcc<T>::row(lane, r);
+        cv[r] = (ro < trows && j < nr) ? w[tr0 + ro + (size_t)j * ldw] : cx<T>{T(0), T(0)};
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int ro = MfmaAcc<T>::row(lane, r);
+        if (ro < trows && j < nr) {
+            cv[r].re -= dre[r];
+            cv[r].im -= dim[r];
+            w[tr0 + ro + (size_t)j * ldw] = cv[r];
+        }
+    }
+}
+
+// w[r + j ldw] -= sum_{k < ncols} Fc[r + k ldf] y[k][j] for r in [r0, r0 + rows), j < nr
+template <typename T, int NT>
+__device__ __forceinline__ void mfma_rows_update(cx<T>* w, int64_t ldw, int r0, int rows, int nr, const cx<T>* Fc, int64_t ldf,
+                                 int ncols, const cx<T> (*y)[kSR]) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, i = lane & 15;
+    const int ntile = rows > 0 ? (rows + 15) / 16 : 0;
+    for (int tile = wave; tile < ntile; tile += NT / 64) {
+        typename MfmaAcc<T>::type dre = {0, 0, 0, 0}, dim = {0, 0, 0, 0};
+        const int tr0 = r0 + 16 * tile, trows = min(16, rows - 16 * tile);
+        mfma_panel_accum<T>(dre, dim, Fc + tr0 + i, ldf, i < trows, ncols, y, nr);
+        mfma_tile_sub<T>(w, ldw, tr0, trows, nr, dre, dim);
+    }
+}
+
+// w[r0 + i + lr m] -= sum_{k < ncols} Fc[r0 + i + k m] y[k][lr] for i < rows, lr < nr
+// (ncols <= 64, y in LDS); column-split over thread groups when the rows are few. The caller
+// synchronises before y or w is reused.
+// MR (kernels built for several right-hand sides): from kMfmaRhs of them the product runs on the
+// matrix cores; single right-hand-side kernels carry no MFMA code (lower register pressure).
+template <typename T, int NT, int BATCH, bool MR>
+__device__ __forceinline__ void panel_fms(cx<T>* __restrict__ w, int64_t m, int r0, int rows, int nr, const cx<T>* __restrict__ Fc,
+                          int ncols, SolveShared<T>& sh) {
+    const int t = threadIdx.x, ne = rows * nr;
+    if (ne == 0) return;
+    if constexpr (MR) {
+        if (nr >= kMfmaRhs) {
+            mfma_rows_update<T, NT>(w, m, r0, rows, nr, Fc, m, ncols, sh.y);
+            return;
+        }
+    }
+    const int G = split_groups<NT>(ne);
+    if (G == 1) {
+        for (int e = t; e < ne; e += NT) {
+            const int r = r0 + e % rows, lr = e / rows;
+            cx<T> acc = w[r + (size_t)lr * m];
+            const cx<T>* Fr = Fc + r;
+            if (BATCH > 0) {
+                acc = row_panel_fms<T, (BATCH > 0 ? BATCH : 32)>(acc, Fr, m, ncols, sh.y, lr);
+            } else {
+#pragma unroll 16
+                for (int k = 0; k < ncols; ++k) acc = cfms(acc, Fr[(size_t)k * m], sh.y[k][lr]);
+            }
+            w[r + (size_t)lr * m] = acc;
+        }
+        return;
+    }
+    const int S = NT / G, g = t / S, e = t % S;
+    cx<T> part = {T(0), T(0)};
+    if (e < ne) part = group_panel_partial<T, (NT > 256 ? 16 : 32)>(Fc + r0 + e % rows, m, ncols, g, G, sh.y, e / rows);
+    sh.red[t] = part;
+    __syncthreads();
+    if (g == 0 && e < ne) {
+        const int r = r0 + e % rows, lr = e / rows;
+        cx<T> acc = w[r + (size_t)lr * m];
+        for (int h = 0; h < G; ++h) {
+            acc.re += sh.red[h * S + e].re;
+            acc.im += sh.red[h * S + e].im;
+        }
+        w[r + (size_t)lr * m] = acc;
+    }
+}
+
 // Forward: per front, w (m x nrhs, column stride m) = [b_piv ; 0] + children's contributions,
 // row swaps on the pivot part, y = L11^{-1} w_piv, w_cb -= L21 y; y is written to x (new
 // numbering) and w_cb stays in the front's work slot for the parent.
@@ -315,10 +529,10 @@ struct SolveArgs {
     cx<T>* work;
 };
 
-template <typename T, int NT>
-__device__ void front_fwd(int f, const SolveArgs<T>& a, SolveShared<T>& sh) {
+template <typename T, int NT, bool MR>
+__device__ void front_fwd_body(int f, const SolveArgs<T>& a, SolveShared<T>& sh) {
     const int32_t *fsize = a.fsize, *npiv = a.npiv, *first = a.first, *child_off = a.child_off,
-                  *child_list = a.child_list, *cmap = a.cmap, *ipiv = a.ipiv;
+                  *child_list = a.child_list, *cmap = a.cmap;
     const int64_t *front_off = a.front_off, *idx_off = a.idx_off, *cmap_off = a.cmap_off;
     const cx<T>* arena = a.arena;
     cx<T>* x = a.x;
@@ -371,23 +585,14 @@ __device__ void front_fwd(int f, const SolveArgs<T>& a, SolveShared<T>& sh) {
             for (int lr = wave; lr < nr; lr += NT / 64) {
                 cx<T>* wl = w + (size_t)(l0 + lr) * m;
                 cx<T> wi = lane < nb ? wl[kb + lane] : cx<T>{T(0), T(0)};
-                for (int k = 0; k < nb - 1; ++k) {
-                    const cx<T> wk = shfl_cx(wi, k);
-                    if (lane > k) wi = cfms(wi, sh.d[lane][k], wk);
-                }
+                wi = wave_lower_solve<T>(wi, sh, nb, lane);
                 if (lane < nb) wl[kb + lane] = wi;
                 sh.y[lane][lr] = wi;
             }
             __syncthreads();
             // rows below the block: w[r] -= F[r, kb:kb+nb] y
-            const int r0 = kb + nb, rows = m - r0;
-            for (int e = t; e < rows * nr; e += NT) {
-                const int r = r0 + e % rows, lr = e / rows;
-                cx<T> acc = w[r + (size_t)(l0 + lr) * m];
-                const cx<T>* Fr = F + r + (size_t)kb * m;
-                acc = row_panel_fms<T, (NT > 256 ? 16 : 32)>(acc, Fr, m, nb, sh.y, lr);
-                w[r + (size_t)(l0 + lr) * m] = acc;
-            }
+            panel_fms<T, NT, (NT > 256 ? 16 : 32), MR>(w + (size_t)l0 * m, m, kb + nb, m - kb - nb, nr,
+                                                   F + (size_t)kb * m, nb, sh);
         }
         __syncthreads();
     }
@@ -395,21 +600,21 @@ __device__ void front_fwd(int f, const SolveArgs<T>& a, SolveShared<T>& sh) {
                        [&](int e, cx<T> v) { x[f0 + e % p + (size_t)(e / p) * ldx] = v; });
 }
 
+
 // Backward: x_piv = U11^{-1} (y - U12 x_cb), x_cb gathered from already-solved ancestors.
-template <typename T, int NT>
-__device__ void front_bwd(int f, const SolveArgs<T>& a, SolveShared<T>& sh) {
+template <typename T, int NT, bool MR>
+__device__ void front_bwd_body(int f, const SolveArgs<T>& a, SolveShared<T>& sh) {
     const int32_t *fsize = a.fsize, *npiv = a.npiv, *first = a.first, *idx = a.idx;
     const int64_t *front_off = a.front_off, *idx_off = a.idx_off;
     const cx<T>* arena = a.arena;
     cx<T>* x = a.x;
-    cx<T>* work = a.work;
     const int64_t ldx = a.ldx;
     const int nrhs = a.nrhs;
     const int m = fsize[f], p = npiv[f], f0 = first[f];
     if (p == 0) return;
     const cx<T>* F = arena + front_off[f];
     const int32_t* ix = idx + idx_off[f];
-    cx<T>* w = work + idx_off[f] * nrhs;
+    cx<T>* w = a.work + idx_off[f] * nrhs;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     batched_for<NT, 4>(m * nrhs, [&](int e) { return x[ix[e % m] + (size_t)(e / m) * ldx]; },
                        [&](int e, cx<T> v) { w[e] = v; });
@@ -417,8 +622,66 @@ __device__ void front_bwd(int f, const SolveArgs<T>& a, SolveShared<T>& sh) {
     __syncthreads();
     // y_piv -= U12 x_cb, the contribution columns taken kSB at a time through LDS
     const int c = m - p;
-    for (int l0 = 0; l0 < nrhs; l0 += kSR) {
+    for (int l0 = 0; l0 < nrhs && c > 0; l0 += kSR) {
         const int nr = min(kSR, nrhs - l0);
+        if constexpr (MR) {
+            if (nr >= kMfmaRhs) {
+                // 16-row tiles of the pivot rows on the matrix cores, accumulated over all columns
+                const int ntile = (p + 15) / 16, nw = NT / 64, i = lane & 15;
+                for (int pass = 0; pass < (ntile + nw - 1) / nw; ++pass) {
+                    const int tile = pass * nw + wave, tr0 = 16 * tile;
+                    const int trows = tile < ntile ? min(16, p - tr0) : 0;
+                    typename MfmaAcc<T>::type dre = {0, 0, 0, 0}, dim = {0, 0, 0, 0};
+                    for (int s0 = 0; s0 < c; s0 += kSB) {
+                        const int ns = min(kSB, c - s0);
+                        __syncthreads();
+                        for (int q = t; q < kSB * kSR; q += NT) {
+                            const int sidx = q % kSB, lr = q / kSB;
+                            sh.y[sidx][lr] =
+                                (sidx < ns && lr < nr) ? w[p + s0 + sidx + (size_t)(l0 + lr) * m] : cx<T>{T(0), T(0)};
+                        }
+                        __syncthreads();
+                        if (trows > 0)
+                            mfma_panel_accum<T>(dre, dim, F + tr0 + i + (size_t)(p + s0) * m, m, i < trows, ns, sh.y, nr);
+                    }
+                    if (trows > 0) mfma_tile_sub<T>(w + (size_t)l0 * m, m, tr0, trows, nr, dre, dim);
+                }
+                continue;
+            }
+        }
+        const int G = split_groups<NT>(p * nr);
+        if (G > 1) {
+            // few pivot rows: the contribution columns are split over G thread groups
+            const int S = NT / G, g = t / S, e = t % S;
+            cx<T> part = {T(0), T(0)};
+            for (int s0 = 0; s0 < c; s0 += kSB) {
+                const int ns = min(kSB, c - s0);
+                __syncthreads();
+                for (int q = t; q < kSB * kSR; q += NT) {
+                    const int sidx = q % kSB, lr = q / kSB;
+                    sh.y[sidx][lr] = (sidx < ns && lr < nr) ? w[p + s0 + sidx + (size_t)(l0 + lr) * m] : cx<T>{T(0), T(0)};
+                }
+                __syncthreads();
+                if (e < p * nr) {
+                    const cx<T> d = group_panel_partial<T, (NT > 256 ? 16 : 32)>(F + e % p + (size_t)(p + s0) * m, m, ns,
+                                                                                 g, G, sh.y, e / p);
+                    part.re += d.re;
+                    part.im += d.im;
+                }
+            }
+            sh.red[t] = part;
+            __syncthreads();
+            if (g == 0 && e < p * nr) {
+                cx<T>* wr = w + e % p + (size_t)(l0 + e / p) * m;
+                cx<T> acc = *wr;
+                for (int h = 0; h < G; ++h) {
+                    acc.re += sh.red[h * S + e].re;
+                    acc.im += sh.red[h * S + e].im;
+                }
+                *wr = acc;
+            }
+            continue;
+        }
         for (int base = 0; base < p * nr; base += 4 * NT) {
             cx<T> acc[4];
             for (int g = 0; g < 4; ++g) {
@@ -466,24 +729,13 @@ __device__ void front_bwd(int f, const SolveArgs<T>& a, SolveShared<T>& sh) {
             for (int lr = wave; lr < nr; lr += NT / 64) {
                 cx<T>* wl = w + (size_t)(l0 + lr) * m;
                 cx<T> wi = lane < nb ? wl[kb + lane] : cx<T>{T(0), T(0)};
-                for (int k = nb - 1; k >= 0; --k) {
-                    if (lane == k) wi = cmul(wi, sh.rd[k]);
-                    const cx<T> xk = shfl_cx(wi, k);
-                    if (lane < k) wi = cfms(wi, sh.d[lane][k], xk);
-                }
+                wi = wave_upper_solve<T>(wi, sh, nb, lane);
                 if (lane < nb) wl[kb + lane] = wi;
                 sh.y[lane][lr] = wi;
             }
             __syncthreads();
             // rows above the block: w[r] -= F[r, kb:kb+nb] x_blk
-            for (int e = t; e < kb * nr; e += NT) {
-                const int r = e % kb, lr = e / kb;
-                cx<T> acc = w[r + (size_t)(l0 + lr) * m];
-                const cx<T>* Fr = F + r + (size_t)kb * m;
-#pragma unroll 16
-                for (int k = 0; k < nb; ++k) acc = cfms(acc, Fr[(size_t)k * m], sh.y[k][lr]);
-                w[r + (size_t)(l0 + lr) * m] = acc;
-            }
+            panel_fms<T, NT, 0, MR>(w + (size_t)l0 * m, m, 0, kb, nr, F + (size_t)kb * m, nb, sh);
         }
         __syncthreads();
     }
@@ -492,15 +744,15 @@ __device__ void front_bwd(int f, const SolveArgs<T>& a, SolveShared<T>& sh) {
 }
 
 // One launch per tree level and direction; every front of the level is one workgroup.
-template <typename T, int NT>
+template <typename T, int NT, bool MR>
 __global__ void __launch_bounds__(NT) k_front_fwd(const int32_t* __restrict__ level_fronts, SolveArgs<T> a) {
     __shared__ SolveShared<T> sh;
-    front_fwd<T, NT>(level_fronts[blockIdx.x], a, sh);
+    front_fwd_body<T, NT, MR>(level_fronts[blockIdx.x], a, sh);
 }
-template <typename T, int NT>
+template <typename T, int NT, bool MR>
 __global__ void __launch_bounds__(NT) k_front_bwd(const int32_t* __restrict__ level_fronts, SolveArgs<T> a) {
     __shared__ SolveShared<T> sh;
-    front_bwd<T, NT>(level_fronts[blockIdx.x], a, sh);
+    front_bwd_body<T, NT, MR>(level_fronts[blockIdx.x], a, sh);
 }
 
 // ---- the largest fronts: triangular solves by 64-pivot blocks with the rows spread over
@@ -517,18 +769,10 @@ __device__ void huge_diag_solve(const cx<T>* F, int m, int kb, int nb, const cx<
     for (int lr = wave; lr < nr; lr += kWG / 64) {
         const cx<T>* wl = w + (size_t)(l0 + lr) * m;
         cx<T> wi = lane < nb ? wl[kb + lane] : cx<T>{T(0), T(0)};
-        if (!upper) {
-            for (int k = 0; k < nb - 1; ++k) {
-                const cx<T> wk = shfl_cx(wi, k);
-                if (lane > k) wi = cfms(wi, sh.d[lane][k], wk);
-            }
-        } else {
-            for (int k = nb - 1; k >= 0; --k) {
-                if (lane == k) wi = cmul(wi, sh.rd[k]);
-                const cx<T> xk = shfl_cx(wi, k);
-                if (lane < k) wi = cfms(wi, sh.d[lane][k], xk);
-            }
-        }
+        if (upper)
+            wi = wave_upper_solve<T>(wi, sh, nb, lane);
+        else
+            wi = wave_lower_solve<T>(wi, sh, nb, lane);
         sh.y[lane][lr] = wi;
         if (blockIdx.x == 0 && lane < nb) xout[kb + lane + (size_t)(l0 + lr) * ldx] = wi;
     }
@@ -556,6 +800,10 @@ __global__ void __launch_bounds__(kWG) k_huge_fwd(const int32_t* __restrict__ hu
         __syncthreads();
         // rows [r0, r0 + 64): w[r] -= F[r, kb:kb+nb] y
         const int rows = min(kSB, m - r0);
+        if (nr >= kMfmaRhs) {
+            mfma_rows_update<T, kWG>(w + (size_t)l0 * m, m, r0, rows, nr, F + (size_t)kb * m, m, nb, sh.y);
+            continue;
+        }
         for (int e = t; e < rows * nr; e += kWG) {
             const int r = r0 + e % rows, lr = e / rows;
             cx<T> acc = w[r + (size_t)(l0 + lr) * m];
@@ -579,8 +827,28 @@ __global__ void __launch_bounds__(kWG) k_huge_bwd_cb(const int32_t* __restrict__
     const cx<T>* F = a.arena + a.front_off[f];
     cx<T>* w = a.work + a.idx_off[f] * a.nrhs;
     const int t = threadIdx.x;
+    const int lane = t & 63, wave = t >> 6;
     for (int l0 = 0; l0 < a.nrhs; l0 += kSR) {
         const int nr = min(kSR, a.nrhs - l0);
+        if (nr >= kMfmaRhs) {
+            // wave w: rows [r0 + 16 w, +16) on the matrix cores, accumulated over all columns
+            const int tr0 = r0 + 16 * wave, trows = min(16, rows - 16 * wave), i = lane & 15;
+            typename MfmaAcc<T>::type dre = {0, 0, 0, 0}, dim = {0, 0, 0, 0};
+            for (int s0 = 0; s0 < c; s0 += kSB) {
+                const int ns = min(kSB, c - s0);
+                __syncthreads();
+                for (int e = t; e < kSB * kSR; e += kWG) {
+                    const int si = e % kSB, lr = e / kSB;
+                    sh.y[si][lr] = (si < ns && lr < nr) ? w[p + s0 + si + (size_t)(l0 + lr) * m] : cx<T>{T(0), T(0)};
+                }
+                __syncthreads();
+                if (trows > 0)
+                    mfma_panel_accum<T>(dre, dim, F + tr0 + i + (size_t)(p + s0) * m, m, i < trows, ns, sh.y, nr);
+            }
+            if (trows > 0) mfma_tile_sub<T>(w + (size_t)l0 * m, m, tr0, trows, nr, dre, dim);
+            __syncthreads();
+            continue;
+        }
         // each thread owns up to 4 (row, rhs) pairs of this workgroup's 64 x nr outputs
         cx<T> acc[4];
         for (int g = 0; g < 4; ++g) {
@@ -637,6 +905,10 @@ __global__ void __launch_bounds__(kWG) k_huge_bwd(const int32_t* __restrict__ hu
         __syncthreads();
         // rows [r0, min(r0 + 64, kb)): w[r] -= F[r, kb:kb+nb] x_blk
         const int rows = max(0, min(kSB, kb - r0));
+        if (nr >= kMfmaRhs) {
+            mfma_rows_update<T, kWG>(w + (size_t)l0 * m, m, r0, rows, nr, F + (size_t)kb * m, m, nb, sh.y);
+            continue;
+        }
         for (int e = t; e < rows * nr; e += kWG) {
             const int r = r0 + e % rows, lr = e / rows;
             cx<T> acc = w[r + (size_t)(l0 + lr) * m];
@@ -791,6 +1063,18 @@ void run_factor(Factor& f, cr_sys sys, double sigma, cx<T>* arena, T tiny, hipSt
     CR_HIP(hipGetLastError());
 }
 
+// one solve level: the kernel variant for the right-hand-side count (MR)
+template <typename T, int NT>
+void launch_level(bool fwd, bool mr, int nf, hipStream_t s, const int32_t* lf, const SolveArgs<T>& a) {
+    if (fwd) {
+        if (mr) hipLaunchKernelGGL((k_front_fwd<T, NT, true>), dim3(nf), dim3(NT), 0, s, lf, a);
+        else hipLaunchKernelGGL((k_front_fwd<T, NT, false>), dim3(nf), dim3(NT), 0, s, lf, a);
+    } else {
+        if (mr) hipLaunchKernelGGL((k_front_bwd<T, NT, true>), dim3(nf), dim3(NT), 0, s, lf, a);
+        else hipLaunchKernelGGL((k_front_bwd<T, NT, false>), dim3(nf), dim3(NT), 0, s, lf, a);
+    }
+}
+
 template <typename T>
 void run_solve(const Factor& f, int nrhs, cx<T>* xp, cx<T>* work, hipStream_t s, const cx<T>* arena) {
     cr_sys sys = f.sys;
@@ -821,11 +1105,10 @@ void run_solve(const Factor& f, int nrhs, cx<T>* xp, cx<T>* work, hipStream_t s,
             const int nf = S.level_off[l + 1] - S.level_off[l];
             {
                 ProfScope ps(sys->ctx, "front_fwd", s);
-                if (S.wide_solve[l])
-                    hipLaunchKernelGGL((k_front_fwd<T, kWideSolve>), dim3(nf), dim3(kWideSolve), 0, s,
-                                       D.level_fronts.p + S.level_off[l], a);
-                else
-                    hipLaunchKernelGGL((k_front_fwd<T, kWG>), dim3(nf), dim3(kWG), 0, s, D.level_fronts.p + S.level_off[l], a);
+                const int32_t* lf = D.level_fronts.p + S.level_off[l];
+                const bool mr = nrhs >= kMfmaRhs;
+                if (S.wide_solve[l]) launch_level<T, kWideSolve>(true, mr, nf, s, lf, a);
+                else launch_level<T, kWG>(true, mr, nf, s, lf, a);
             }
             const int nh = S.huge_off[l + 1] - S.huge_off[l];
             const int32_t* hl = D.huge_list.p + S.huge_off[l];
@@ -843,11 +1126,10 @@ void run_solve(const Factor& f, int nrhs, cx<T>* xp, cx<T>* work, hipStream_t s,
             const int nf = S.level_off[l + 1] - S.level_off[l];
             {
                 ProfScope ps(sys->ctx, "front_bwd", s);
-                if (S.wide_solve[l])
-                    hipLaunchKernelGGL((k_front_bwd<T, kWideSolve>), dim3(nf), dim3(kWideSolve), 0, s,
-                                       D.level_fronts.p + S.level_off[l], a);
-                else
-                    hipLaunchKernelGGL((k_front_bwd<T, kWG>), dim3(nf), dim3(kWG), 0, s, D.level_fronts.p + S.level_off[l], a);
+                const int32_t* lf = D.level_fronts.p + S.level_off[l];
+                const bool mr = nrhs >= kMfmaRhs;
+                if (S.wide_solve[l]) launch_level<T, kWideSolve>(false, mr, nf, s, lf, a);
+                else launch_level<T, kWG>(false, mr, nf, s, lf, a);
             }
             const int nh = S.huge_off[l + 1] - S.huge_off[l];
             if (nh == 0) continue;

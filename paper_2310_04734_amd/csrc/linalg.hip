@@ -429,60 +429,194 @@ namespace {
 constexpr int kGramRows = 256;   // rows per workgroup chunk
 constexpr int kGramB = 16;       // max columns of the staged operand
 
+// Sum over the 64 lanes of a wave of V doubles per lane (V a power of two <= 64), as a
+// reduce-scatter: each exchange step sends half of the values still held to the partner lane and
+// keeps the other half, so the wave does V - 1 + (6 - log2 V) shuffles instead of 6 V. On return
+// v[0] of lane l is the wave's total of value wave_sum_index<V>(l); every value has 64 / V lanes
+// holding it, the one with wave_sum_writer<V>(l) true writes it.
+template <int V, int H = V / 2, int D = 32>
+__device__ __forceinline__ void wave_sum_scatter(double (&v)[V], int lane) {
+    if constexpr (H >= 1) {
+        const bool up = lane & D;
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+            const double send = up ? v[i] : v[i + H];
+            const double keep = up ? v[i + H] : v[i];
+            v[i] = keep + __shfl_xor(send, D);
+        }
+        wave_sum_scatter<V, H / 2, D / 2>(v, lane);
+    } else {
+        // distances below the last halving step: plain sums
+#pragma unroll
+        for (int d = D; d >= 1; d /= 2) v[0] += __shfl_xor(v[0], d);
+    }
+}
+template <int V>
+__device__ __forceinline__ int wave_sum_index(int lane) {
+    int idx = 0;
+    for (int h = V / 2, d = 32; h >= 1; h /= 2, d /= 2)
+        if (lane & d) idx += h;
+    return idx;
+}
+template <int V>
+__device__ __forceinline__ bool wave_sum_writer(int lane) {
+    return (lane & (64 / V - 1)) == 0;
+}
+
 // partial[chunk][k][c] = sum_{i in chunk} conj(A[i,k]) B[i,c],  k < qa, c < b (b <= 16)
-// B = the staged column count rounded up (1, 4 or 16) so that narrow blocks do no padded work;
-// blockIdx.y strides over the columns of A so that short tall matrices still fill the chip
+// B = the staged column count rounded up (1 or 4; wider blocks go to the matrix-core kernel below);
+// blockIdx.y strides over the columns of A so that short tall matrices still fill the chip.
+// The chunk of B is staged column by column (lane-consecutive rows: no LDS bank conflicts).
 template <int B>
 __global__ void __launch_bounds__(256) k_gram_partial(int64_t n, int qa, int b, const zd* __restrict__ A, int64_t lda,
                                                       const zd* __restrict__ Bm, int64_t ldb, zd* __restrict__ partial) {
-    __shared__ zd sb[kGramRows][B];
+    __shared__ zd sb[B][kGramRows];
     const int64_t i0 = (int64_t)blockIdx.x * kGramRows;
     const int rows = (int)std::min<int64_t>(kGramRows, n - i0);
     for (int e = threadIdx.x; e < kGramRows * B; e += 256) {
         const int r = e % kGramRows, c = e / kGramRows;
-        sb[r][c] = (r < rows && c < b) ? Bm[i0 + r + c * ldb] : zd{0, 0};
+        sb[c][r] = (r < rows && c < b) ? Bm[i0 + r + c * ldb] : zd{0, 0};
     }
     __syncthreads();
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     zd* out = partial + (size_t)blockIdx.x * qa * b;
     for (int k = blockIdx.y * 4 + wave; k < qa; k += 4 * gridDim.y) {
-        double ar[B], ai[B];
+        double v[2 * B];
 #pragma unroll
-        for (int c = 0; c < B; ++c) ar[c] = ai[c] = 0;
-        for (int r = lane; r < rows; r += 64) {
-            const zd a = A[i0 + r + k * lda];
+        for (int c = 0; c < 2 * B; ++c) v[c] = 0;
+        zd a[kGramRows / 64];
 #pragma unroll
-            for (int c = 0; c < B; ++c) {
-                const zd v = sb[r][c];
-                ar[c] += a.re * v.re + a.im * v.im;   // conj(a) * v
-                ai[c] += a.re * v.im - a.im * v.re;
-            }
+        for (int j = 0; j < kGramRows / 64; ++j) {
+            const int r = lane + 64 * j;
+            a[j] = r < rows ? A[i0 + r + k * lda] : zd{0, 0};
         }
 #pragma unroll
-        for (int c = 0; c < B; ++c)
-            for (int off = 32; off > 0; off >>= 1) {
-                ar[c] += __shfl_xor(ar[c], off);
-                ai[c] += __shfl_xor(ai[c], off);
+        for (int j = 0; j < kGramRows / 64; ++j) {
+            const int r = lane + 64 * j;
+#pragma unroll
+            for (int c = 0; c < B; ++c) {
+                const zd w = sb[c][r];
+                v[2 * c] += a[j].re * w.re + a[j].im * w.im;   // conj(a) * w
+                v[2 * c + 1] += a[j].re * w.im - a[j].im * w.re;
             }
-        if (lane == 0)
-            for (int c = 0; c < b; ++c) out[k + (size_t)c * qa] = {ar[c], ai[c]};
+        }
+        wave_sum_scatter<2 * B>(v, lane);
+        const int idx = wave_sum_index<2 * B>(lane), c = idx / 2;
+        if (wave_sum_writer<2 * B>(lane) && c < b) {
+            double* o = reinterpret_cast<double*>(out + k + (size_t)c * qa);
+            o[idx & 1] = v[0];
+        }
     }
 }
 
-// H[k + c*ldh] = sum over chunks (fixed order); conj_t: store conj into H[c + k*ldh] instead
-__global__ void k_gram_reduce(int nchunk, int qa, int b, const zd* __restrict__ partial, zd* __restrict__ H, int64_t ldh,
-                              int conj_t) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= qa * b) return;
-    const int k = e % qa, c = e / qa;
-    double r = 0, i = 0;
-    for (int ch = 0; ch < nchunk; ++ch) {
-        const zd v = partial[(size_t)ch * qa * b + k + (size_t)c * qa];
-        r += v.re;
-        i += v.im;
+constexpr int kGramRowsM = 512;   // rows per wave of the matrix-core Gram
+constexpr int kGramTPW = 4;        // 16-column tiles of A per wave
+
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+
+// partial[chunk][k][c] as k_gram_partial, for blocks of 5..16 columns, on the matrix cores
+// (v_mfma_f64_16x16x4f64): one wave per (chunk of kGramRowsM rows, group of kGramTPW 16-column
+// tiles of A), no LDS and no barrier. A step takes 4 rows; lane l supplies the A operand
+// A[row][k0 + l % 16] and the B operand B[row][l % 16] of row r0 + l / 16, and conj(A)^T B is
+// formed as four real products into separate real and imaginary accumulators, which stay in
+// registers over the whole chunk (item r of lane l holds k = k0 + l / 16 + 4 r, c = l % 16).
+__global__ void __launch_bounds__(256) k_gram_mfma(int64_t n, int qa, int b, const zd* __restrict__ A, int64_t lda,
+                                                   const zd* __restrict__ Bm, int64_t ldb, zd* __restrict__ partial,
+                                                   int nchunk, int ntg) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wid = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wid >= (int64_t)nchunk * ntg) return;
+    const int chunk = (int)(wid % nchunk), tg = (int)(wid / nchunk);
+    const int64_t rb = (int64_t)chunk * kGramRowsM, rend = std::min<int64_t>(n, rb + kGramRowsM);
+    const int i = lane & 15, kk = lane >> 4, kbase = tg * kGramTPW * 16;
+    f64x4_t hre[kGramTPW], him[kGramTPW];
+#pragma unroll
+    for (int t = 0; t < kGramTPW; ++t) {
+        hre[t] = f64x4_t{0, 0, 0, 0};
+        him[t] = f64x4_t{0, 0, 0, 0};
     }
-    if (conj_t) H[c + (size_t)k * ldh] = {r, -i};
-    else H[k + (size_t)c * ldh] = {r, i};
+    constexpr int U = 4;   // 4-row steps whose loads are issued together
+    for (int64_t r0 = rb; r0 < rend; r0 += 4 * U) {
+        zd bv[U], av[U][kGramTPW];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t row = r0 + 4 * u + kk;
+            const bool ok = row < rend;
+            bv[u] = (ok && i < b) ? Bm[row + (int64_t)i * ldb] : zd{0, 0};
+#pragma unroll
+            for (int t = 0; t < kGramTPW; ++t) {
+                const int col = kbase + 16 * t + i;
+                av[u][t] = (ok && col < qa) ? A[row + (int64_t)col * lda] : zd{0, 0};
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int t = 0; t < kGramTPW; ++t) {
+                // conj(a) b = (ar br + ai bi) + i (ar bi - ai br)
+                hre[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][t].re, bv[u].re, hre[t], 0, 0, 0);
+                hre[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][t].im, bv[u].im, hre[t], 0, 0, 0);
+                him[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][t].re, bv[u].im, him[t], 0, 0, 0);
+                him[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[u][t].im, bv[u].re, him[t], 0, 0, 0);
+            }
+    }
+    zd* out = partial + (size_t)chunk * qa * b;
+#pragma unroll
+    for (int t = 0; t < kGramTPW; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int k = kbase + 16 * t + kk + 4 * r;
+            if (k < qa && i < b) out[k + (size_t)i * qa] = {hre[t][r], him[t][r]};
+        }
+}
+
+// H[k + c*ldh] = sum of the nchunk partials of output o = k + c qa (conj_t: conj into
+// H[c + k*ldh]), in a fixed order: thread t takes output o0 + t % OB and the chunks
+// ch = t / OB (mod 1024 / OB) in increasing order, four running sums; the 1024 / OB sums of an
+// output are then added by a fixed tree in LDS.
+template <int OB>
+__global__ void __launch_bounds__(1024) k_gram_reduce(int nchunk, int qa, int b, const zd* __restrict__ partial,
+                                                      zd* __restrict__ H, int64_t ldh, int conj_t) {
+    constexpr int NS = 1024 / OB;
+    __shared__ zd red[1024];
+    const int t = threadIdx.x, lo = t % OB, sg = t / OB;
+    const int no = qa * b, o = blockIdx.x * OB + lo;
+    zd acc = {0, 0};
+    if (o < no) {
+        zd s4[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+        int ch = sg;
+        for (; ch + 3 * NS < nchunk; ch += 4 * NS) {
+            zd v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = partial[(size_t)(ch + u * NS) * no + o];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                s4[u].re += v[u].re;
+                s4[u].im += v[u].im;
+            }
+        }
+        for (; ch < nchunk; ch += NS) {
+            const zd v = partial[(size_t)ch * no + o];
+            s4[0].re += v.re;
+            s4[0].im += v.im;
+        }
+        acc = {(s4[0].re + s4[1].re) + (s4[2].re + s4[3].re), (s4[0].im + s4[1].im) + (s4[2].im + s4[3].im)};
+    }
+    red[t] = acc;
+    __syncthreads();
+#pragma unroll
+    for (int h = NS / 2; h >= 1; h /= 2) {
+        if (sg < h) {
+            red[t].re += red[t + h * OB].re;
+            red[t].im += red[t + h * OB].im;
+        }
+        __syncthreads();
+    }
+    if (sg == 0 && o < no) {
+        const int k = o % qa, c = o / qa;
+        if (conj_t) H[c + (size_t)k * ldh] = {red[t].re, -red[t].im};
+        else H[k + (size_t)c * ldh] = red[t];
+    }
 }
 
 // W[:, c] -= V[:, 0:q] H[0:q, c] for c < b (b <= 16); H staged through LDS in chunks of 64 rows
@@ -546,25 +680,34 @@ __global__ void k_scale_cols(int64_t n, int b, zd* __restrict__ W, int64_t ldw, 
 void gram(int64_t n, int qa, int b, const zd* A, int64_t lda, const zd* B, int64_t ldb, zd* H, int64_t ldh, int conj_t,
           DevBuf<zd>& partial, hipStream_t s) {
     if (qa <= 0 || b <= 0) return;
-    const int nchunk = (int)((n + kGramRows - 1) / kGramRows);
     for (int c0 = 0; c0 < b; c0 += kGramB) {
         const int bc = std::min(kGramB, b - c0);
+        const bool mat = bc > 4;   // wide blocks on the matrix cores
+        const int nchunk = (int)((n + (mat ? kGramRowsM : kGramRows) - 1) / (mat ? kGramRowsM : kGramRows));
         partial.reserve((size_t)nchunk * qa * bc);
         // at least ~1024 workgroups when the columns of A allow it
         const unsigned gy = (unsigned)std::max(1, std::min((qa + 3) / 4, (1024 + nchunk - 1) / nchunk));
         const dim3 grid(nchunk, gy);
-        if (bc == 1)
+        if (mat) {
+            const int ntg = (qa + 16 * kGramTPW - 1) / (16 * kGramTPW);
+            const int64_t waves = (int64_t)nchunk * ntg;
+            hipLaunchKernelGGL(k_gram_mfma, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, n, qa, bc, A, lda,
+                               B + (int64_t)c0 * ldb, ldb, partial.p, nchunk, ntg);
+        } else if (bc == 1)
             hipLaunchKernelGGL(k_gram_partial<1>, grid, dim3(256), 0, s, n, qa, bc, A, lda, B + (int64_t)c0 * ldb, ldb,
                                partial.p);
-        else if (bc <= 4)
+        else
             hipLaunchKernelGGL(k_gram_partial<4>, grid, dim3(256), 0, s, n, qa, bc, A, lda, B + (int64_t)c0 * ldb, ldb,
                                partial.p);
-        else
-            hipLaunchKernelGGL(k_gram_partial<kGramB>, grid, dim3(256), 0, s, n, qa, bc, A, lda, B + (int64_t)c0 * ldb,
-                               ldb, partial.p);
         zd* Hc = conj_t ? H + c0 : H + (int64_t)c0 * ldh;
-        hipLaunchKernelGGL(k_gram_reduce, dim3((qa * bc + 255) / 256), dim3(256), 0, s, nchunk, qa, bc, partial.p, Hc, ldh,
-                           conj_t);
+        const int no = qa * bc;
+        if (no == 1)
+            hipLaunchKernelGGL(k_gram_reduce<1>, dim3(1), dim3(1024), 0, s, nchunk, qa, bc, partial.p, Hc, ldh, conj_t);
+        else if (no <= 16)
+            hipLaunchKernelGGL(k_gram_reduce<16>, dim3(1), dim3(1024), 0, s, nchunk, qa, bc, partial.p, Hc, ldh, conj_t);
+        else
+            hipLaunchKernelGGL(k_gram_reduce<64>, dim3((no + 63) / 64), dim3(1024), 0, s, nchunk, qa, bc, partial.p, Hc,
+                               ldh, conj_t);
     }
 }
 

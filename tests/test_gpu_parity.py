@@ -150,6 +150,32 @@ def test_basis_fixed_box(P, ctx):
         assert _rel(Y, Yo).max() <= 1e-6
 
 
+def test_basis_partial_blocks(P, ctx):
+    """13 loads of which 3 repeat earlier ones: the first block at each point deflates, so the
+    Gram products run on blocks of 13 and 10 columns (the matrix-core path for 5..16 columns with
+    a ragged column count), and the box's 528 rows leave a ragged last row chunk."""
+    _flush("basis partial blocks")
+    w = W.box()
+    fn = W.fluid_nodes(w.mesh)
+    nodes = [int(v) for v in W.SplitMix64(W.stream_seed(9, 1)).sample(fn, 10)]
+    nodes += nodes[:3]
+    w.loads = [W.Load(kind=W.LOAD_VOLUME_VELOCITY, node=nd, value=1.0 + 0.0j) for nd in nodes]
+    shifts, blocks = 2 * np.pi * np.array([80.0, 200.0, 320.0]), 3
+    s = assembly.assemble(w.mesh, w.loads, w.receivers)
+    ss = krylov.jacobi_scaled(s)
+    rb = krylov.build_basis(ss, shifts, blocks)
+    r = krylov.project(ss, rb.basis)
+    assert rb.deflated >= 3
+    g = P.assemble(ctx, w.mesh, w.loads, w.receivers)
+    g.analyse()
+    B = g.basis(shifts, blocks, prec=P.CR_FP64)
+    assert B.q == rb.q and B.info["deflated"] == rb.deflated
+    V = B.V().cpu().numpy()
+    assert np.abs(V.conj().T @ V - np.eye(B.q)).max() < 1e-12
+    Y = B.project().sweep(w.omegas, prec=P.CR_FP64).cpu().numpy()
+    assert _rel(Y, rom.sweep(r, w.omegas)).max() <= 1e-6
+
+
 def test_greedy_plate_cavity(P, ctx):
     _flush("greedy plate_cavity")
     w = W.plate_cavity_workload()
