@@ -116,6 +116,7 @@ template <typename T, int U = 4>
 __device__ void wg_apply_swaps(cx<T>* __restrict__ A, int lda, const int* ipiv, int k0, int k1, int ca, int cb,
                                SwapShared& sw) {
     const int t = threadIdx.x;
+    __syncthreads();   // an earlier call's readers of sw are done
     if (t == 0) {
         int n = 0;
         for (int k = k0; k < k1; ++k) {
@@ -135,19 +136,24 @@ __device__ void wg_apply_swaps(cx<T>* __restrict__ A, int lda, const int* ipiv, 
         sw.n = n;
     }
     __syncthreads();
-    const int n = sw.n, total = n * max(cb - ca, 0);
-    for (int base = 0; base < total; base += U * kWG) {
+    const int n = sw.n;
+    if (n == 0) return;
+    // whole columns per pass: every source row of a column is read before any row of that column
+    // is written
+    const int cpi = (U * kWG) / n;
+    for (int c0 = ca; c0 < cb; c0 += cpi) {
+        const int tot = n * min(cpi, cb - c0);
         cx<T> v[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int e = base + u * kWG + t;
-            if (e < total) v[u] = A[sw.src[e % n] + (size_t)(ca + e / n) * lda];
+            const int e = u * kWG + t;
+            if (e < tot) v[u] = A[sw.src[e % n] + (size_t)(c0 + e / n) * lda];
         }
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int e = base + u * kWG + t;
-            if (e < total) A[sw.row[e % n] + (size_t)(ca + e / n) * lda] = v[u];
+            const int e = u * kWG + t;
+            if (e < tot) A[sw.row[e % n] + (size_t)(c0 + e / n) * lda] = v[u];
         }
         __syncthreads();
     }

@@ -292,8 +292,8 @@ struct SolveShared {
 // chain (one LDS wait per kChain steps), and the lane's update is a select rather than a branch.
 // Unit lower: wi <- L^{-1} wi over nb pivots.
 constexpr int kChain = 4;   // (8 trips a code-generation error in this compiler release)
-template <typename T>
-__device__ __forceinline__ cx<T> wave_lower_solve(cx<T> wi, const SolveShared<T>& sh, int nb, int lane) {
+template <typename T, int R>
+__device__ __forceinline__ void wave_lower_solve(cx<T> (&wi)[R], const SolveShared<T>& sh, int nb, int lane) {
     for (int k0 = 0; k0 < nb - 1; k0 += kChain) {
         cx<T> dr[kChain];
 #pragma unroll
@@ -302,19 +302,21 @@ __device__ __forceinline__ cx<T> wave_lower_solve(cx<T> wi, const SolveShared<T>
         for (int j = 0; j < kChain; ++j) {
             const int k = k0 + j;
             if (k < nb - 1) {
-                const cx<T> wk = lane_cx(wi, k);
-                const cx<T> u = cfms(wi, dr[j], wk);
                 const bool upd = lane > k;
-                wi.re = upd ? u.re : wi.re;   // per component: a select of the values
-                wi.im = upd ? u.im : wi.im;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {   // independent chains interleaved
+                    const cx<T> wk = lane_cx(wi[r], k);
+                    const cx<T> u = cfms(wi[r], dr[j], wk);
+                    wi[r].re = upd ? u.re : wi[r].re;   // per component: a select of the values
+                    wi[r].im = upd ? u.im : wi[r].im;
+                }
             }
         }
     }
-    return wi;
 }
 // Upper: wi <- U^{-1} wi, sh.rd holding the reciprocals of U's diagonal.
-template <typename T>
-__device__ __forceinline__ cx<T> wave_upper_solve(cx<T> wi, const SolveShared<T>& sh, int nb, int lane) {
+template <typename T, int R>
+__device__ __forceinline__ void wave_upper_solve(cx<T> (&wi)[R], const SolveShared<T>& sh, int nb, int lane) {
     for (int k1 = nb - 1; k1 >= 0; k1 -= kChain) {
         cx<T> dr[kChain], rr[kChain];
 #pragma unroll
@@ -326,15 +328,55 @@ __device__ __forceinline__ cx<T> wave_upper_solve(cx<T> wi, const SolveShared<T>
         for (int j = 0; j < kChain; ++j) {
             const int k = k1 - j;
             if (k >= 0) {
-                const cx<T> xk = cmul(lane_cx(wi, k), rr[j]);
-                const cx<T> u = cfms(wi, dr[j], xk);
                 const bool piv = lane == k, upd = lane < k;
-                wi.re = piv ? xk.re : (upd ? u.re : wi.re);
-                wi.im = piv ? xk.im : (upd ? u.im : wi.im);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const cx<T> xk = cmul(lane_cx(wi[r], k), rr[j]);
+                    const cx<T> u = cfms(wi[r], dr[j], xk);
+                    wi[r].re = piv ? xk.re : (upd ? u.re : wi[r].re);
+                    wi[r].im = piv ? xk.im : (upd ? u.im : wi[r].im);
+                }
             }
         }
     }
-    return wi;
+}
+
+// The block's right-hand sides [l0, l0 + nr) of the front vector w (column stride m) through the
+// diagonal solve: wave v takes right-hand sides v, v + W, v + 2 W, ... (W waves), up to R of them
+// interleaved in one pass; the solved values go back to w (pivot rows < nb) and to sh.y.
+template <typename T, int NT, bool UPPER>
+__device__ __forceinline__ void wave_diag_solve(cx<T>* w, int64_t m, int kb, int nb, int l0, int nr,
+                                                SolveShared<T>& sh) {
+    constexpr int W = NT / 64, R = (kSR + W - 1) / W;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int cnt = nr > wave ? (nr - wave + W - 1) / W : 0;   // right-hand sides of this wave
+    if (cnt == 0) return;
+    if (cnt == 1) {
+        cx<T> wi[1];
+        cx<T>* wl = w + (size_t)(l0 + wave) * m;
+        wi[0] = lane < nb ? wl[kb + lane] : cx<T>{T(0), T(0)};
+        if (UPPER) wave_upper_solve<T, 1>(wi, sh, nb, lane);
+        else wave_lower_solve<T, 1>(wi, sh, nb, lane);
+        if (lane < nb) wl[kb + lane] = wi[0];
+        sh.y[lane][wave] = wi[0];
+        return;
+    }
+    cx<T> wi[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int lr = wave + r * W;
+        wi[r] = (r < cnt && lane < nb) ? w[kb + lane + (size_t)(l0 + lr) * m] : cx<T>{T(0), T(0)};
+    }
+    if (UPPER) wave_upper_solve<T, R>(wi, sh, nb, lane);
+    else wave_lower_solve<T, R>(wi, sh, nb, lane);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int lr = wave + r * W;
+        if (r < cnt) {
+            if (lane < nb) w[kb + lane + (size_t)(l0 + lr) * m] = wi[r];
+            sh.y[lane][lr] = wi[r];
+        }
+    }
 }
 
 // Column split of a panel product over few rows: with ne = rows x right-hand sides entries and
@@ -581,14 +623,8 @@ __device__ void front_fwd_body(int f, const SolveArgs<T>& a, SolveShared<T>& sh)
         for (int l0 = 0; l0 < nrhs; l0 += kSR) {
             const int nr = min(kSR, nrhs - l0);
             __syncthreads();
-            // diagonal block: unit lower triangular, one wave per right-hand side
-            for (int lr = wave; lr < nr; lr += NT / 64) {
-                cx<T>* wl = w + (size_t)(l0 + lr) * m;
-                cx<T> wi = lane < nb ? wl[kb + lane] : cx<T>{T(0), T(0)};
-                wi = wave_lower_solve<T>(wi, sh, nb, lane);
-                if (lane < nb) wl[kb + lane] = wi;
-                sh.y[lane][lr] = wi;
-            }
+            // diagonal block: unit lower triangular, right-hand sides spread over the waves
+            wave_diag_solve<T, NT, false>(w, m, kb, nb, l0, nr, sh);
             __syncthreads();
             // rows below the block: w[r] -= F[r, kb:kb+nb] y
             panel_fms<T, NT, (NT > 256 ? 16 : 32), MR>(w + (size_t)l0 * m, m, kb + nb, m - kb - nb, nr,
@@ -726,13 +762,7 @@ __device__ void front_bwd_body(int f, const SolveArgs<T>& a, SolveShared<T>& sh)
         for (int l0 = 0; l0 < nrhs; l0 += kSR) {
             const int nr = min(kSR, nrhs - l0);
             __syncthreads();
-            for (int lr = wave; lr < nr; lr += NT / 64) {
-                cx<T>* wl = w + (size_t)(l0 + lr) * m;
-                cx<T> wi = lane < nb ? wl[kb + lane] : cx<T>{T(0), T(0)};
-                wi = wave_upper_solve<T>(wi, sh, nb, lane);
-                if (lane < nb) wl[kb + lane] = wi;
-                sh.y[lane][lr] = wi;
-            }
+            wave_diag_solve<T, NT, true>(w, m, kb, nb, l0, nr, sh);
             __syncthreads();
             // rows above the block: w[r] -= F[r, kb:kb+nb] x_blk
             panel_fms<T, NT, 0, MR>(w + (size_t)l0 * m, m, 0, kb, nr, F + (size_t)kb * m, nb, sh);
@@ -765,16 +795,30 @@ __global__ void __launch_bounds__(NT) k_front_bwd(const int32_t* __restrict__ le
 template <typename T>
 __device__ void huge_diag_solve(const cx<T>* F, int m, int kb, int nb, const cx<T>* w, int l0, int nr, bool upper,
                                 cx<T>* xout, int64_t ldx, SolveShared<T>& sh) {
+    constexpr int W = kWG / 64, R = (kSR + W - 1) / W;   // right-hand sides interleaved per wave
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    for (int lr = wave; lr < nr; lr += kWG / 64) {
-        const cx<T>* wl = w + (size_t)(l0 + lr) * m;
-        cx<T> wi = lane < nb ? wl[kb + lane] : cx<T>{T(0), T(0)};
-        if (upper)
-            wi = wave_upper_solve<T>(wi, sh, nb, lane);
-        else
-            wi = wave_lower_solve<T>(wi, sh, nb, lane);
-        sh.y[lane][lr] = wi;
-        if (blockIdx.x == 0 && lane < nb) xout[kb + lane + (size_t)(l0 + lr) * ldx] = wi;
+    const int cnt = nr > wave ? (nr - wave + W - 1) / W : 0;
+    if (cnt == 0) return;
+    cx<T> wi[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        wi[r] = (r < cnt && lane < nb) ? w[kb + lane + (size_t)(l0 + wave + r * W) * m] : cx<T>{T(0), T(0)};
+    if (cnt == 1) {
+        cx<T> w1[1] = {wi[0]};
+        if (upper) wave_upper_solve<T, 1>(w1, sh, nb, lane);
+        else wave_lower_solve<T, 1>(w1, sh, nb, lane);
+        wi[0] = w1[0];
+    } else {
+        if (upper) wave_upper_solve<T, R>(wi, sh, nb, lane);
+        else wave_lower_solve<T, R>(wi, sh, nb, lane);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int lr = wave + r * W;
+        if (r < cnt) {
+            sh.y[lane][lr] = wi[r];
+            if (blockIdx.x == 0 && lane < nb) xout[kb + lane + (size_t)(l0 + lr) * ldx] = wi[r];
+        }
     }
 }
 
