@@ -170,7 +170,7 @@ __device__ void wg_apply_swaps(cx<T>* __restrict__ A, int lda, const int* ipiv, 
 // update to the rest of the panel and takes the next column's pivot candidates on the way.
 // Pivots with cabs1 <= tiny (or NaN) are replaced by tiny in their own direction and counted
 // in *nperturb.
-// LEAN = true keeps every loop register-light (one row or entry in flight per thread) for
+// LEAN = true keeps the long-column loop register-light (one row in flight per thread) for
 // callers whose occupancy matters more than memory-level parallelism (the reduced-model sweep).
 template <typename T, bool LEAN = false>
 __device__ __forceinline__ void wg_panel(cx<T>* __restrict__ A, int lda, int m, int p, int k0, int k1, int* __restrict__ ipiv, T tiny,
@@ -264,7 +264,7 @@ __device__ __forceinline__ void wg_panel(cx<T>* __restrict__ A, int lda, int m, 
             // of the rank-1 update is one thread's work so that all threads stay busy
             for (int i = k + 1 + t; i < rend; i += kWG) A[i + (size_t)k * lda] = cmul(A[i + (size_t)k * lda], r);
             __syncthreads();
-            batched_for<kWG, LEAN ? 1 : 4>(rows * nc,
+            batched_for<kWG, 4>(rows * nc,
                 [&](int e) {
                     const int i = k + 1 + e % rows, j = k + 1 + e / rows;
                     return cfms(A[i + (size_t)j * lda], A[i + (size_t)k * lda], A[k + (size_t)j * lda]);
@@ -350,7 +350,7 @@ __device__ void wg_panel_lds(cx<T>* __restrict__ A, int lda, int p, int k0, int 
 
 // One 64 x 64 tile (rows i0.., columns j0..) of the trailing update
 // A[k1:m, k1:m] -= A[k1:m, k0:k1] A[k0:k1, k1:m], with k1 - k0 <= kNB.
-template <typename T, bool LEAN = false>
+template <typename T>
 __device__ void wg_tile_update(cx<T>* __restrict__ A, int lda, int m, int k0, int k1, int i0, int j0, LuShared<T>& sh) {
     const int t = threadIdx.x;
     const int nbk = k1 - k0;
@@ -387,21 +387,6 @@ __device__ void wg_tile_update(cx<T>* __restrict__ A, int lda, int m, int k0, in
                 acc[a][b].im += av[a].re * bv[b].im + av[a].im * bv[b].re;
             }
     }
-    if constexpr (LEAN) {
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int i = i0 + tx + 16 * a, j = j0 + ty + 16 * b;
-                if (i < m && j < m) {
-                    cx<T>& x = A[i + (size_t)j * lda];
-                    x.re -= acc[a][b].re;
-                    x.im -= acc[a][b].im;
-                }
-            }
-        __syncthreads();
-        return;
-    }
     // all 16 entries of the thread are loaded before the first store (one memory latency)
     cx<T> cv[4][4];
 #pragma unroll
@@ -432,7 +417,7 @@ __device__ void wg_getrf(cx<T>* __restrict__ A, int lda, int m, int p, int* __re
         if (k1 >= m) break;
         const int tiles = (m - k1 + kTile - 1) / kTile;
         for (int tile = 0; tile < tiles * tiles; ++tile)
-            wg_tile_update<T, LEAN>(A, lda, m, k0, k1, k1 + (tile % tiles) * kTile, k1 + (tile / tiles) * kTile, sh);
+            wg_tile_update<T>(A, lda, m, k0, k1, k1 + (tile % tiles) * kTile, k1 + (tile / tiles) * kTile, sh);
     }
     __syncthreads();
 }

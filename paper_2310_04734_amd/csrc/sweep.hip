@@ -38,23 +38,29 @@ __device__ void wg_lu_solve(const cx<T>* __restrict__ A, int lda, int q, const i
         }
     }
     __syncthreads();
-    // column-oriented substitutions over independent (row, right-hand side) entries
+    // column-oriented substitutions over independent (row, right-hand side) entries; within a
+    // step row k of B is only read, so each thread's entries are loaded before any is stored
+    // (four at a time) instead of one memory round trip per entry
     for (int k = 0; k < q - 1; ++k) {
         const int rows = q - k - 1;
-        for (int e = t; e < rows * L; e += kWG) {
-            const int i = k + 1 + e % rows, l = e / rows;
-            B[i + (size_t)l * q] = cfms(B[i + (size_t)l * q], A[i + (size_t)k * lda], B[k + (size_t)l * q]);
-        }
+        batched_for<kWG, 4>(rows * L,
+            [&](int e) {
+                const int i = k + 1 + e % rows, l = e / rows;
+                return cfms(B[i + (size_t)l * q], A[i + (size_t)k * lda], B[k + (size_t)l * q]);
+            },
+            [&](int e, cx<T> v) { B[k + 1 + e % rows + (size_t)(e / rows) * q] = v; });
         __syncthreads();
     }
     for (int k = q - 1; k >= 0; --k) {
         const cx<T> d = crecip(A[k + (size_t)k * lda]);
         for (int l = t; l < L; l += kWG) B[k + (size_t)l * q] = cmul(B[k + (size_t)l * q], d);
         __syncthreads();
-        for (int e = t; e < k * L; e += kWG) {
-            const int i = e % k, l = e / k;
-            B[i + (size_t)l * q] = cfms(B[i + (size_t)l * q], A[i + (size_t)k * lda], B[k + (size_t)l * q]);
-        }
+        batched_for<kWG, 4>(k * L,
+            [&](int e) {
+                const int i = e % k, l = e / k;
+                return cfms(B[i + (size_t)l * q], A[i + (size_t)k * lda], B[k + (size_t)l * q]);
+            },
+            [&](int e, cx<T> v) { B[e % k + (size_t)(e / k) * q] = v; });
         __syncthreads();
     }
 }
