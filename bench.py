@@ -303,9 +303,19 @@ def main():
         if a.only and a.only != name:
             continue
         Y = torch.empty((len(w.omegas), sysg.L, sysg.n_o), dtype=torch.complex128, device=ctx.device)
+        # warm-up steps with every hot kernel timed (per-kernel breakdown, and they name the
+        # dominant kernel); the timed steps then carry events only around the kernels the
+        # roofline reports, so that the instrumentation stays out of the measured step
+        wprof = {}
+        if a.warmup > 0:
+            ctx.profile(True)
         for _ in range(a.warmup):
             step(prec, Y)
         torch.cuda.synchronize()
+        if a.warmup > 0:
+            wprof = ctx.profile_read()
+            ctx.profile(False)
+            ctx.profile_select([max(wprof, key=lambda k: wprof[k][1]), "front_gemm"])
         ctx.profile(True)
         builds = []
         t0 = time.perf_counter()
@@ -316,12 +326,13 @@ def main():
         wall = time.perf_counter() - t0
         prof = ctx.profile_read()
         ctx.profile(False)
+        ctx.profile_select(None)
         ts = time.perf_counter()
         for _ in range(a.steps):
             R.sweep(w.omegas, prec=prec, out=Y)
         torch.cuda.synchronize()
         sweep_rate = n_results * a.steps / (time.perf_counter() - ts)
-        runs[name] = dict(prec=prec, Y=Y, wall=wall, builds=builds, prof=prof, B=B, sweep_rate=sweep_rate,
+        runs[name] = dict(prec=prec, Y=Y, wall=wall, builds=builds, prof=prof, wprof=wprof, B=B, sweep_rate=sweep_rate,
                           sweep_info=R.last_info)
         print(f"[bench] {name}: {1e3 * wall / a.steps:.2f} ms/step, build {1e3 * np.median(builds):.2f} ms, "
               f"q={B.q}, shifts={[int(i) for i in B.trace['shift_idx']]}, "
@@ -355,7 +366,8 @@ def main():
     total = {k: v[1] for k, v in prof.items()}
     dom = max(total, key=total.get)
     n_fact = (len(h["B"].trace["shift_idx"]) + h["B"].info["fp64_refactorizations"]) * a.steps
-    n_solves = (prof.get("front_fwd", (0, 0))[0] // max(an["n_levels"], 1))
+    # one launch per tree level and direction per solve (either direction's kernel may be the timed one)
+    n_solves = ((prof.get("front_fwd") or prof.get("front_bwd") or (0, 0))[0] // max(an["n_levels"], 1))
     elt = 16 if h["prec"] == P.CR_FP64 else 8
     roof = _roofline(dom, prof[dom][0], prof[dom][1], an, n_fact, n_solves, elt)
     gemm = _roofline("front_gemm", prof["front_gemm"][0], prof["front_gemm"][1], an, n_fact, n_solves, elt) \
@@ -386,8 +398,9 @@ def main():
                          "sweep_only_results_per_s": r["sweep_rate"], "max_rel_err_vs_oracle": r.get("err"),
                          "fp64_refactorizations": r["B"].info["fp64_refactorizations"],
                          "sweep_fp64_fallbacks": r["sweep_info"].get("fp64_fallbacks"),
-                         "kernels_ms": {kk: round(v[1], 3) for kk, v in
-                                        sorted(r["prof"].items(), key=lambda kv: -kv[1][1])}}
+                         "kernels_ms_per_step": {kk: round(v[1] / max(a.warmup, 1), 3) for kk, v in
+                                                 sorted((r["wprof"] or r["prof"]).items(), key=lambda kv: -kv[1][1])},
+                         "kernels_timed_in_measured_steps": sorted(r["prof"])}
                      for k, r in runs.items()},
         "roofline": roof,
         "frontal_gemm": gemm,

@@ -85,6 +85,11 @@ const char* cr_create_error(void);
    total_ms[i] summed event durations; *n receives the number of distinct names. */
 cr_status cr_profile_enable(cr_ctx ctx, int32_t on);
 cr_status cr_profile_read(cr_ctx ctx, int32_t max, char* names, int32_t* counts, double* total_ms, int32_t* n);
+/* Restricts the timing to the kernels named in names (comma-separated, e.g. "front_bwd,front_gemm";
+   NULL or "" times every hot kernel again), so that a timed run carries events only around the
+   launches it reports. Takes effect for launches after the call; the records are kept. Host
+   string, copied. */
+cr_status cr_profile_select(cr_ctx ctx, const char* names);
 
 /* ---------------------------------------------------------------- assembly (Section 2) --- */
 

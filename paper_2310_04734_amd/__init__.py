@@ -164,6 +164,7 @@ _sig("cr_sweep_plan_tuning", I32, P, C.POINTER(cr_tune), P, I32, C.POINTER(I32))
 _sig("cr_sweep_plan_destroy", None, P)
 _sig("cr_profile_enable", I32, P, I32)
 _sig("cr_profile_read", I32, P, I32, P, P, P, C.POINTER(I32))
+_sig("cr_profile_select", I32, P, C.c_char_p)
 
 
 def _ptr(a):
@@ -197,6 +198,11 @@ class Context:
     def profile(self, on: bool):
         """Start (clearing earlier records) or stop event timing of the library's kernels."""
         self.check(lib.cr_profile_enable(self.h, int(on)))
+
+    def profile_select(self, names=None):
+        """Time only the named kernels (an iterable of names; None: all of them again)."""
+        arg = None if not names else ",".join(names).encode()
+        self.check(lib.cr_profile_select(self.h, arg))
 
     def profile_read(self):
         """{kernel name: (launches, total ms)} over the launches since profile(True)."""

@@ -795,6 +795,24 @@ extern "C" cr_status cr_profile_enable(cr_ctx ctx, int32_t on) {
     });
 }
 
+extern "C" cr_status cr_profile_select(cr_ctx ctx, const char* names) {
+    if (!ctx) return CR_E_INVALID;
+    return cr_guard(ctx, [&] {
+        ctx->prof.only.clear();
+        if (!names) return;
+        std::string cur;
+        for (const char* c = names;; ++c) {
+            if (*c == ',' || *c == 0) {
+                if (!cur.empty()) ctx->prof.only.push_back(cur);
+                cur.clear();
+                if (*c == 0) break;
+            } else if (*c != ' ') {
+                cur.push_back(*c);
+            }
+        }
+    });
+}
+
 extern "C" cr_status cr_profile_read(cr_ctx ctx, int32_t max, char* names, int32_t* counts, double* total_ms, int32_t* n) {
     if (!ctx) return CR_E_INVALID;
     return cr_guard(ctx, [&] {

@@ -152,6 +152,13 @@ struct SweepEngine;
 // Event-bracketed kernel timing (off unless enabled through cr_profile_enable).
 struct Profiler {
     bool on = false;
+    std::vector<std::string> only;   // kernel names to time (empty: all)
+    bool wants(const char* name) const {
+        if (only.empty()) return true;
+        for (const auto& o : only)
+            if (o == name) return true;
+        return false;
+    }
     struct Rec {
         const char* name;
         hipEvent_t a, b;
@@ -196,7 +203,7 @@ struct ProfScope {
     const char* name;
     hipEvent_t a = nullptr;
     ProfScope(cr_ctx_s* c, const char* n, hipStream_t st) : ctx(c), s(st), name(n) {
-        if (ctx && ctx->prof.on) {
+        if (ctx && ctx->prof.on && ctx->prof.wants(name)) {
             a = ctx->prof.take();
             if (a) (void)hipEventRecord(a, s);
         }

@@ -140,3 +140,24 @@ def test_fuselage_variant_basis(P, ctx, fuselage_variant):
         Yo = rom.sweep(r, om)
         err = rom.relative_error(Y, Yo)
         assert np.median(err) <= 1e-8 and err.max() <= 1e-6, (prec, err.max())
+
+
+def test_profile_select_times_only_named_kernels(P, ctx, plate):
+    """cr_profile_select: events only around the named kernels; None restores all of them."""
+    _flush("profile select")
+    w, _ = plate
+    g = P.assemble(ctx, w.mesh, w.loads, w.receivers)
+    g.analyse()
+    ctx.profile_select(["front_bwd", "front_gemm"])
+    ctx.profile(True)
+    fac = g.factor(2 * np.pi * 150.0, P.CR_FP64)
+    fac.solve(torch.ones((g.n, 1), dtype=torch.complex128, device=ctx.device))
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    ctx.profile_select(None)
+    assert set(prof) <= {"front_bwd", "front_gemm"} and prof["front_bwd"][0] > 0
+    ctx.profile(True)
+    fac.solve(torch.ones((g.n, 1), dtype=torch.complex128, device=ctx.device))
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    assert "front_fwd" in prof and "front_bwd" in prof
