@@ -32,6 +32,28 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
+MEASURED = {}   # achievable peaks from the library's probes (copy kernel, MFMA loop), filled by main
+
+
+def _measure_peaks(ctx, P):
+    """Achievable peaks on this GPU: a 256 MiB streaming copy and back-to-back MFMA loops."""
+    MEASURED["hbm_gbs"] = ctx.probe_copy(256 << 20, 10)
+    MEASURED["fp64_mfma_tflops"] = ctx.probe_mfma(P.CR_FP64)
+    MEASURED["fp32_mfma_tflops"] = ctx.probe_mfma(P.CR_MIXED)
+    print(f"[bench] achievable peaks: copy {MEASURED['hbm_gbs']:.0f} GB/s, MFMA FP64 "
+          f"{MEASURED['fp64_mfma_tflops']:.1f} TFLOP/s, MFMA FP32 {MEASURED['fp32_mfma_tflops']:.1f} TFLOP/s",
+          file=sys.stderr, flush=True)
+
+
+def _with_measured(r):
+    """Adds the fraction of the achievable (probe-measured) peak next to the published one."""
+    key = {"GB/s": "hbm_gbs"}.get(r.get("unit"))
+    if r.get("bound") == "mfma":
+        key = "fp64_mfma_tflops" if r.get("peak") == PEAK_FP64_TFLOPS else "fp32_mfma_tflops"
+    pm = MEASURED.get(key) if key else None
+    r["peak_measured"] = pm
+    r["frac_measured"] = (r["achieved"] / pm) if (pm and r.get("achieved") is not None) else None
+    return r
 
 
 def _args():
@@ -86,20 +108,20 @@ def _roofline(name, launches, ms, an, n_fact, n_solves, elt):
         # each direction reads its triangle of every front once per solve: half the factor
         byts = 0.5 * an["factor_entries"] * elt * n_solves
         ach = byts / (ms * 1e-3) / 1e9
-        return {"kernel": name, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+        return _with_measured({"kernel": name, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": ach / PEAK_HBM_GBS, "traffic": _measured_traffic(name, elt),
                 "work_per_launch": f"{0.5 * an['factor_entries'] * elt / an['n_levels']:.4g} B "
                                    f"(factor triangle / tree levels)",
-                "launches": launches, "avg_launch_us": 1e3 * ms / launches}
+                "launches": launches, "avg_launch_us": 1e3 * ms / launches})
     if name == "front_gemm":
         # trailing GEMMs of the large fronts on the matrix cores: exact flops from the analysis
         flops = an["gemm_flops"] * n_fact
         peak = PEAK_FP32_TFLOPS if elt == 8 else PEAK_FP64_TFLOPS
         ach = flops / (ms * 1e-3) / 1e12
-        return {"kernel": name, "bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+        return _with_measured({"kernel": name, "bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
                 "frac": ach / peak, "traffic": None, "launches": launches, "avg_launch_us": 1e3 * ms / launches,
                 "work_per_launch": f"{an['gemm_flops'] * n_fact / launches:.4g} flop (8 (m - K1)^2 (K1 - K0) "
-                                   f"per 128-column block of every large front)"}
+                                   f"per 128-column block of every large front)"})
     if name in ("front_factor", "front_panel", "front_colstrip", "front_rowstrip"):
         flops = an["factor_flops"] * n_fact
         peak = PEAK_FP32_TFLOPS if elt == 8 else PEAK_FP64_TFLOPS
@@ -284,6 +306,7 @@ def main():
     w = W.plate_cavity_workload()
     rp = w.rom
     ctx = P.Context(0)
+    _measure_peaks(ctx, P)
     sysg = P.assemble(ctx, w.mesh, w.loads, w.receivers)
     an = sysg.analyse()
     n_results = len(w.omegas) * sysg.L
@@ -352,7 +375,13 @@ def main():
         for r in runs.values():
             r["err"] = float(rom.relative_error(r["Y"].cpu().numpy(), Yo).max())
         threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+        model = ""
+        try:
+            model = next((ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo") if ln.startswith("model name")), "")
+        except OSError:
+            pass
         cpu = {"value": n_results / tcpu, "unit": "FRF results/s", "cores": int(threads), "kind": "oracle",
+               "host": {"cpu_model": model, "nproc": os.cpu_count()},
                "sample": f"the full step once (assembly + greedy with {len(go['shift_idx'])} expansion points "
                          f"+ 1000-frequency sweep) in {tcpu:.2f} s; SuperLU single-threaded, "
                          f"BLAS with {threads} threads"}

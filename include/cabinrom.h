@@ -91,6 +91,15 @@ cr_status cr_profile_read(cr_ctx ctx, int32_t max, char* names, int32_t* counts,
    string, copied. */
 cr_status cr_profile_select(cr_ctx ctx, const char* names);
 
+/* Achievable-peak probes for the rooflines (measurement support, not part of the method).
+   cr_probe_copy: a streaming device-to-device copy of `bytes` (a multiple of 16) through a plain
+   kernel, reps times after one warm-up; *gbs = bytes read + written per second. cr_probe_mfma:
+   back-to-back 16x16x4 MFMA instructions (complex-free, FP64 for CR_FP64, FP32 for CR_MIXED) on 8
+   workgroups per compute unit, reps launches after one warm-up; *tflops = flops per second.
+   Both allocate their own device buffers and synchronise the context stream. */
+cr_status cr_probe_copy(cr_ctx ctx, int64_t bytes, int32_t reps, double* gbs);
+cr_status cr_probe_mfma(cr_ctx ctx, cr_precision prec, int32_t reps, double* tflops);
+
 /* ---------------------------------------------------------------- assembly (Section 2) --- */
 
 enum { CR_FLUID = 0, CR_SOLID = 1 };

@@ -165,6 +165,8 @@ _sig("cr_sweep_plan_destroy", None, P)
 _sig("cr_profile_enable", I32, P, I32)
 _sig("cr_profile_read", I32, P, I32, P, P, P, C.POINTER(I32))
 _sig("cr_profile_select", I32, P, C.c_char_p)
+_sig("cr_probe_copy", I32, P, C.c_int64, I32, C.POINTER(C.c_double))
+_sig("cr_probe_mfma", I32, P, I32, I32, C.POINTER(C.c_double))
 
 
 def _ptr(a):
@@ -203,6 +205,18 @@ class Context:
         """Time only the named kernels (an iterable of names; None: all of them again)."""
         arg = None if not names else ",".join(names).encode()
         self.check(lib.cr_profile_select(self.h, arg))
+
+    def probe_copy(self, nbytes=256 << 20, reps=10):
+        """Achievable HBM rate of a streaming copy (GB/s, bytes read + written)."""
+        v = C.c_double()
+        self.check(lib.cr_probe_copy(self.h, int(nbytes), int(reps), C.byref(v)))
+        return v.value
+
+    def probe_mfma(self, prec, reps=5):
+        """Achievable matrix-core rate (TFLOP/s): FP64 MFMA for CR_FP64, FP32 MFMA for CR_MIXED."""
+        v = C.c_double()
+        self.check(lib.cr_probe_mfma(self.h, int(prec), int(reps), C.byref(v)))
+        return v.value
 
     def profile_read(self):
         """{kernel name: (launches, total ms)} over the launches since profile(True)."""
