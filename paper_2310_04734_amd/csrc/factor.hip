@@ -690,19 +690,45 @@ __device__ void front_bwd_body(int f, const SolveArgs<T>& a, SolveShared<T>& sh)
             // few pivot rows: the contribution columns are split over G thread groups
             const int S = NT / G, g = t / S, e = t % S;
             cx<T> part = {T(0), T(0)};
-            for (int s0 = 0; s0 < c; s0 += kSB) {
-                const int ns = min(kSB, c - s0);
+            if (c * nr <= kSB * (kSB + 1)) {
+                // x_cb staged once, in the diagonal-block buffer (unused until the diagonal
+                // solves); group g then runs through its contiguous share of the columns with
+                // no barrier in between
+                cx<T>* xs = &sh.d[0][0];
                 __syncthreads();
-                for (int q = t; q < kSB * kSR; q += NT) {
-                    const int sidx = q % kSB, lr = q / kSB;
-                    sh.y[sidx][lr] = (sidx < ns && lr < nr) ? w[p + s0 + sidx + (size_t)(l0 + lr) * m] : cx<T>{T(0), T(0)};
-                }
+                for (int q = t; q < c * nr; q += NT) xs[q] = w[p + q % c + (size_t)(l0 + q / c) * m];
                 __syncthreads();
                 if (e < p * nr) {
-                    const cx<T> d = group_panel_partial<T, (NT > 256 ? 16 : 32)>(F + e % p + (size_t)(p + s0) * m, m, ns,
-                                                                                 g, G, sh.y, e / p);
-                    part.re += d.re;
-                    part.im += d.im;
+                    constexpr int BATCH = NT > 256 ? 8 : 16;
+                    const int per = (c + G - 1) / G, ka = g * per, cnt = min(per, c - ka);
+                    const cx<T>* Fr = F + e % p + (size_t)(p + ka) * m;
+                    const cx<T>* xl = xs + (size_t)(e / p) * c + ka;
+                    for (int h = 0; h < cnt; h += BATCH) {
+                        cx<T> fv[BATCH];
+#pragma unroll
+                        for (int k = 0; k < BATCH; ++k)
+                            if (h + k < cnt) fv[k] = Fr[(size_t)(h + k) * m];
+#pragma unroll
+                        for (int k = 0; k < BATCH; ++k)
+                            if (h + k < cnt) part = cfms(part, fv[k], xl[h + k]);
+                    }
+                }
+            } else {
+                for (int s0 = 0; s0 < c; s0 += kSB) {
+                    const int ns = min(kSB, c - s0);
+                    __syncthreads();
+                    for (int q = t; q < kSB * kSR; q += NT) {
+                        const int sidx = q % kSB, lr = q / kSB;
+                        sh.y[sidx][lr] =
+                            (sidx < ns && lr < nr) ? w[p + s0 + sidx + (size_t)(l0 + lr) * m] : cx<T>{T(0), T(0)};
+                    }
+                    __syncthreads();
+                    if (e < p * nr) {
+                        const cx<T> d = group_panel_partial<T, (NT > 256 ? 16 : 32)>(F + e % p + (size_t)(p + s0) * m, m,
+                                                                                     ns, g, G, sh.y, e / p);
+                        part.re += d.re;
+                        part.im += d.im;
+                    }
                 }
             }
             sh.red[t] = part;
