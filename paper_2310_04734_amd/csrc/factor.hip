@@ -616,10 +616,13 @@ __device__ void front_fwd_body(int f, const SolveArgs<T>& a, SolveShared<T>& sh)
     if (a.huge[f]) return;
     for (int kb = 0; kb < p; kb += kSB) {
         const int nb = min(kSB, p - kb);
-        for (int e = t; e < kSB * kSB; e += NT) {
-            const int i = e % kSB, k = e / kSB;
-            sh.d[i][k] = (i < nb && k < nb) ? F[kb + i + (size_t)(kb + k) * m] : cx<T>{T(0), T(0)};
-        }
+        // the diagonal block to LDS with all of a thread's loads in flight at once
+        batched_for<NT, kSB * kSB / NT>(kSB * kSB,
+            [&](int e) {
+                const int i = e % kSB, k = e / kSB;
+                return (i < nb && k < nb) ? F[kb + i + (size_t)(kb + k) * m] : cx<T>{T(0), T(0)};
+            },
+            [&](int e, cx<T> v) { sh.d[e % kSB][e / kSB] = v; });
         for (int l0 = 0; l0 < nrhs; l0 += kSR) {
             const int nr = min(kSR, nrhs - l0);
             __syncthreads();
@@ -779,10 +782,12 @@ __device__ void front_bwd_body(int f, const SolveArgs<T>& a, SolveShared<T>& sh)
     __syncthreads();
     for (int kb = ((p - 1) / kSB) * kSB; kb >= 0; kb -= kSB) {
         const int nb = min(kSB, p - kb);
-        for (int e = t; e < kSB * kSB; e += NT) {
-            const int i = e % kSB, k = e / kSB;
-            sh.d[i][k] = (i < nb && k < nb) ? F[kb + i + (size_t)(kb + k) * m] : cx<T>{T(1), T(0)};
-        }
+        batched_for<NT, kSB * kSB / NT>(kSB * kSB,
+            [&](int e) {
+                const int i = e % kSB, k = e / kSB;
+                return (i < nb && k < nb) ? F[kb + i + (size_t)(kb + k) * m] : cx<T>{T(1), T(0)};
+            },
+            [&](int e, cx<T> v) { sh.d[e % kSB][e / kSB] = v; });
         // the divisions leave the sequential chain: all reciprocals of the block's diagonal at once
         if (t < kSB) sh.rd[t] = t < nb ? crecip(F[kb + t + (size_t)(kb + t) * m]) : cx<T>{T(1), T(0)};
         for (int l0 = 0; l0 < nrhs; l0 += kSR) {
@@ -811,109 +816,38 @@ __global__ void __launch_bounds__(NT) k_front_bwd(const int32_t* __restrict__ le
     front_bwd_body<T, NT, MR>(level_fronts[blockIdx.x], a, sh);
 }
 
-// ---- the largest fronts: triangular solves by 64-pivot blocks with the rows spread over
-// workgroups (one launch per block). Every workgroup solves the block's diagonal system itself
-// from the unmodified work values (no workgroup writes them in that launch); workgroup 0 stores
-// the solved values to x; each workgroup then updates its own 64 rows of the work vector.
+// ---- the largest fronts: triangular solves by super-blocks of kHugeSB pivots. Per super-block
+// two launches: k_huge_diag, one workgroup per front, solves the super-block's four 64-pivot
+// diagonal blocks in order (each as in the per-level solves: diagonal block in LDS, right-hand
+// sides spread over the waves, then the rest of the super-block updated with the block's panel)
+// and stores the solved values to w and x; then k_huge_rows spreads the rows outside the
+// super-block over workgroups of 64 rows, each subtracting F[rows, super-block] times the solved
+// values (MFMA tiles with several right-hand sides). The backward direction first subtracts
+// U12 x_cb from the pivot rows (k_huge_rows over the contribution columns).
+constexpr int kHugeSB = 4 * kSB;
 
-// diagonal block of pivots [kb, kb + nb) into sh.d (lower = unit L, upper = U), the block's
-// solved values into sh.y (kSR right-hand sides starting at l0) and, for blockIdx.x == 0, x
+// w[r0 + i] -= F[r0 + i, c0:c0+nc] w[c0:c0+nc] for i < rows <= 64 (all right-hand sides); the
+// solved values are staged 64 columns at a time through sh.y
 template <typename T>
-__device__ void huge_diag_solve(const cx<T>* F, int m, int kb, int nb, const cx<T>* w, int l0, int nr, bool upper,
-                                cx<T>* xout, int64_t ldx, SolveShared<T>& sh) {
-    constexpr int W = kWG / 64, R = (kSR + W - 1) / W;   // right-hand sides interleaved per wave
+__device__ void huge_rows_update(const cx<T>* __restrict__ F, cx<T>* __restrict__ w, int m, int nrhs, int r0, int rows,
+                                 int c0, int nc, SolveShared<T>& sh) {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int cnt = nr > wave ? (nr - wave + W - 1) / W : 0;
-    if (cnt == 0) return;
-    cx<T> wi[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-        wi[r] = (r < cnt && lane < nb) ? w[kb + lane + (size_t)(l0 + wave + r * W) * m] : cx<T>{T(0), T(0)};
-    if (cnt == 1) {
-        cx<T> w1[1] = {wi[0]};
-        if (upper) wave_upper_solve<T, 1>(w1, sh, nb, lane);
-        else wave_lower_solve<T, 1>(w1, sh, nb, lane);
-        wi[0] = w1[0];
-    } else {
-        if (upper) wave_upper_solve<T, R>(wi, sh, nb, lane);
-        else wave_lower_solve<T, R>(wi, sh, nb, lane);
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int lr = wave + r * W;
-        if (r < cnt) {
-            sh.y[lane][lr] = wi[r];
-            if (blockIdx.x == 0 && lane < nb) xout[kb + lane + (size_t)(l0 + lr) * ldx] = wi[r];
-        }
-    }
-}
-
-template <typename T>
-__global__ void __launch_bounds__(kWG) k_huge_fwd(const int32_t* __restrict__ huge_list, int kb, SolveArgs<T> a) {
-    __shared__ SolveShared<T> sh;
-    const int f = huge_list[blockIdx.y];
-    const int m = a.fsize[f], p = a.npiv[f];
-    if (kb >= p) return;
-    const int nb = min(kSB, p - kb), r0 = kb + nb + kSB * (int)blockIdx.x;
-    if (blockIdx.x > 0 && r0 >= m) return;
-    const cx<T>* F = a.arena + a.front_off[f];
-    cx<T>* w = a.work + a.idx_off[f] * a.nrhs;
-    const int t = threadIdx.x;
-    for (int e = t; e < kSB * kSB; e += kWG) {
-        const int i = e % kSB, k = e / kSB;
-        sh.d[i][k] = (i < nb && k < nb) ? F[kb + i + (size_t)(kb + k) * m] : cx<T>{T(0), T(0)};
-    }
-    for (int l0 = 0; l0 < a.nrhs; l0 += kSR) {
-        const int nr = min(kSR, a.nrhs - l0);
-        __syncthreads();
-        huge_diag_solve<T>(F, m, kb, nb, w, l0, nr, false, a.x + a.first[f], a.ldx, sh);
-        __syncthreads();
-        // rows [r0, r0 + 64): w[r] -= F[r, kb:kb+nb] y
-        const int rows = min(kSB, m - r0);
-        if (nr >= kMfmaRhs) {
-            mfma_rows_update<T, kWG>(w + (size_t)l0 * m, m, r0, rows, nr, F + (size_t)kb * m, m, nb, sh.y);
-            continue;
-        }
-        for (int e = t; e < rows * nr; e += kWG) {
-            const int r = r0 + e % rows, lr = e / rows;
-            cx<T> acc = w[r + (size_t)(l0 + lr) * m];
-            const cx<T>* Fr = F + r + (size_t)kb * m;
-#pragma unroll 16
-            for (int k = 0; k < nb; ++k) acc = cfms(acc, Fr[(size_t)k * m], sh.y[k][lr]);
-            w[r + (size_t)(l0 + lr) * m] = acc;
-        }
-    }
-}
-
-// y_piv -= U12 x_cb for 64 pivot rows per workgroup (all contribution columns)
-template <typename T>
-__global__ void __launch_bounds__(kWG) k_huge_bwd_cb(const int32_t* __restrict__ huge_list, SolveArgs<T> a) {
-    __shared__ SolveShared<T> sh;
-    const int f = huge_list[blockIdx.y];
-    const int m = a.fsize[f], p = a.npiv[f], c = m - p;
-    const int r0 = kSB * (int)blockIdx.x;
-    if (r0 >= p) return;
-    const int rows = min(kSB, p - r0);
-    const cx<T>* F = a.arena + a.front_off[f];
-    cx<T>* w = a.work + a.idx_off[f] * a.nrhs;
-    const int t = threadIdx.x;
-    const int lane = t & 63, wave = t >> 6;
-    for (int l0 = 0; l0 < a.nrhs; l0 += kSR) {
-        const int nr = min(kSR, a.nrhs - l0);
+    for (int l0 = 0; l0 < nrhs; l0 += kSR) {
+        const int nr = min(kSR, nrhs - l0);
         if (nr >= kMfmaRhs) {
             // wave w: rows [r0 + 16 w, +16) on the matrix cores, accumulated over all columns
             const int tr0 = r0 + 16 * wave, trows = min(16, rows - 16 * wave), i = lane & 15;
             typename MfmaAcc<T>::type dre = {0, 0, 0, 0}, dim = {0, 0, 0, 0};
-            for (int s0 = 0; s0 < c; s0 += kSB) {
-                const int ns = min(kSB, c - s0);
+            for (int s0 = 0; s0 < nc; s0 += kSB) {
+                const int ns = min(kSB, nc - s0);
                 __syncthreads();
                 for (int e = t; e < kSB * kSR; e += kWG) {
                     const int si = e % kSB, lr = e / kSB;
-                    sh.y[si][lr] = (si < ns && lr < nr) ? w[p + s0 + si + (size_t)(l0 + lr) * m] : cx<T>{T(0), T(0)};
+                    sh.y[si][lr] = (si < ns && lr < nr) ? w[c0 + s0 + si + (size_t)(l0 + lr) * m] : cx<T>{T(0), T(0)};
                 }
                 __syncthreads();
                 if (trows > 0)
-                    mfma_panel_accum<T>(dre, dim, F + tr0 + i + (size_t)(p + s0) * m, m, i < trows, ns, sh.y, nr);
+                    mfma_panel_accum<T>(dre, dim, F + tr0 + i + (size_t)(c0 + s0) * m, m, i < trows, ns, sh.y, nr);
             }
             if (trows > 0) mfma_tile_sub<T>(w + (size_t)l0 * m, m, tr0, trows, nr, dre, dim);
             __syncthreads();
@@ -925,19 +859,19 @@ __global__ void __launch_bounds__(kWG) k_huge_bwd_cb(const int32_t* __restrict__
             const int e = g * kWG + t;
             acc[g] = e < rows * nr ? w[r0 + e % rows + (size_t)(l0 + e / rows) * m] : cx<T>{T(0), T(0)};
         }
-        for (int s0 = 0; s0 < c; s0 += kSB) {
-            const int ns = min(kSB, c - s0);
+        for (int s0 = 0; s0 < nc; s0 += kSB) {
+            const int ns = min(kSB, nc - s0);
             __syncthreads();
             for (int e = t; e < kSB * kSR; e += kWG) {
                 const int si = e % kSB, lr = e / kSB;
-                sh.y[si][lr] = (si < ns && lr < nr) ? w[p + s0 + si + (size_t)(l0 + lr) * m] : cx<T>{T(0), T(0)};
+                sh.y[si][lr] = (si < ns && lr < nr) ? w[c0 + s0 + si + (size_t)(l0 + lr) * m] : cx<T>{T(0), T(0)};
             }
             __syncthreads();
             for (int g = 0; g < 4; ++g) {
                 const int e = g * kWG + t;
                 if (e >= rows * nr) break;
                 const int r = r0 + e % rows, lr = e / rows;
-                const cx<T>* Fr = F + r + (size_t)(p + s0) * m;
+                const cx<T>* Fr = F + r + (size_t)(c0 + s0) * m;
                 cx<T> v = acc[g];
 #pragma unroll 16
                 for (int k = 0; k < ns; ++k) v = cfms(v, Fr[(size_t)k * m], sh.y[k][lr]);
@@ -952,42 +886,71 @@ __global__ void __launch_bounds__(kWG) k_huge_bwd_cb(const int32_t* __restrict__
     }
 }
 
+// mode 0 (forward): rows [K1, m) receive the super-block [K0, K1); mode 1 (backward): rows
+// [0, K0) receive it; mode 2 (backward, first): rows [0, p) receive the contribution columns
+// [p, m) (U12 x_cb). Workgroup x takes 64 rows.
 template <typename T>
-__global__ void __launch_bounds__(kWG) k_huge_bwd(const int32_t* __restrict__ huge_list, int kb, SolveArgs<T> a) {
+__global__ void __launch_bounds__(kWG) k_huge_rows(const int32_t* __restrict__ huge_list, int mode, int K0,
+                                                   SolveArgs<T> a) {
     __shared__ SolveShared<T> sh;
     const int f = huge_list[blockIdx.y];
     const int m = a.fsize[f], p = a.npiv[f];
-    if (kb >= p) return;
-    const int nb = min(kSB, p - kb), r0 = kSB * (int)blockIdx.x;
-    if (blockIdx.x > 0 && r0 >= kb) return;
+    int rb, re, c0, nc;
+    if (mode == 2) {
+        rb = 0, re = p, c0 = p, nc = m - p;
+    } else {
+        if (K0 >= p) return;
+        const int K1 = min(K0 + kHugeSB, p);
+        c0 = K0, nc = K1 - K0;
+        rb = mode == 0 ? K1 : 0;
+        re = mode == 0 ? m : K0;
+    }
+    const int r0 = rb + kSB * (int)blockIdx.x;
+    if (r0 >= re || nc <= 0) return;
+    huge_rows_update<T>(a.arena + a.front_off[f], a.work + a.idx_off[f] * a.nrhs, m, a.nrhs, r0, min(kSB, re - r0), c0,
+                        nc, sh);
+}
+
+// the super-block [K0, K1) of one front (grid: one workgroup per huge front)
+template <typename T, bool UPPER>
+__global__ void __launch_bounds__(kWG) k_huge_diag(const int32_t* __restrict__ huge_list, int K0, SolveArgs<T> a) {
+    __shared__ SolveShared<T> sh;
+    const int f = huge_list[blockIdx.x];
+    const int m = a.fsize[f], p = a.npiv[f], f0 = a.first[f];
+    if (K0 >= p) return;
+    const int K1 = min(K0 + kHugeSB, p), t = threadIdx.x;
     const cx<T>* F = a.arena + a.front_off[f];
     cx<T>* w = a.work + a.idx_off[f] * a.nrhs;
-    const int t = threadIdx.x;
-    for (int e = t; e < kSB * kSB; e += kWG) {
-        const int i = e % kSB, k = e / kSB;
-        sh.d[i][k] = (i < nb && k < nb) ? F[kb + i + (size_t)(kb + k) * m] : cx<T>{T(1), T(0)};
-    }
-    if (t < kSB) sh.rd[t] = t < nb ? crecip(F[kb + t + (size_t)(kb + t) * m]) : cx<T>{T(1), T(0)};
-    for (int l0 = 0; l0 < a.nrhs; l0 += kSR) {
-        const int nr = min(kSR, a.nrhs - l0);
-        __syncthreads();
-        huge_diag_solve<T>(F, m, kb, nb, w, l0, nr, true, a.x + a.first[f], a.ldx, sh);
-        __syncthreads();
-        // rows [r0, min(r0 + 64, kb)): w[r] -= F[r, kb:kb+nb] x_blk
-        const int rows = max(0, min(kSB, kb - r0));
-        if (nr >= kMfmaRhs) {
-            mfma_rows_update<T, kWG>(w + (size_t)l0 * m, m, r0, rows, nr, F + (size_t)kb * m, m, nb, sh.y);
-            continue;
+    const int nrhs = a.nrhs;
+    for (int l0 = 0; l0 < nrhs; l0 += kSR) {
+        const int nr = min(kSR, nrhs - l0);
+        const int kfirst = UPPER ? K0 + ((K1 - 1 - K0) / kSB) * kSB : K0;
+        for (int kb = kfirst; UPPER ? kb >= K0 : kb < K1; kb += UPPER ? -kSB : kSB) {
+            const int nb = min(kSB, K1 - kb);
+            __syncthreads();
+            batched_for<kWG, kSB * kSB / kWG>(kSB * kSB,
+                [&](int e) {
+                    const int i = e % kSB, k = e / kSB;
+                    return (i < nb && k < nb) ? F[kb + i + (size_t)(kb + k) * m]
+                                              : (UPPER ? cx<T>{T(1), T(0)} : cx<T>{T(0), T(0)});
+                },
+                [&](int e, cx<T> v) { sh.d[e % kSB][e / kSB] = v; });
+            if (UPPER && t < kSB) sh.rd[t] = t < nb ? crecip(F[kb + t + (size_t)(kb + t) * m]) : cx<T>{T(1), T(0)};
+            __syncthreads();
+            wave_diag_solve<T, kWG, UPPER>(w, m, kb, nb, l0, nr, sh);
+            __syncthreads();
+            // the rest of the super-block with the block's panel
+            if (UPPER)
+                panel_fms<T, kWG, 0, true>(w + (size_t)l0 * m, m, K0, kb - K0, nr, F + (size_t)kb * m, nb, sh);
+            else
+                panel_fms<T, kWG, 32, true>(w + (size_t)l0 * m, m, kb + nb, K1 - kb - nb, nr, F + (size_t)kb * m, nb,
+                                            sh);
         }
-        for (int e = t; e < rows * nr; e += kWG) {
-            const int r = r0 + e % rows, lr = e / rows;
-            cx<T> acc = w[r + (size_t)(l0 + lr) * m];
-            const cx<T>* Fr = F + r + (size_t)kb * m;
-#pragma unroll 16
-            for (int k = 0; k < nb; ++k) acc = cfms(acc, Fr[(size_t)k * m], sh.y[k][lr]);
-            w[r + (size_t)(l0 + lr) * m] = acc;
-        }
     }
+    __syncthreads();
+    const int nk = K1 - K0;
+    batched_for<kWG, 4>(nk * nrhs, [&](int e) { return w[K0 + e % nk + (size_t)(e / nk) * m]; },
+                        [&](int e, cx<T> v) { a.x[f0 + K0 + e % nk + (size_t)(e / nk) * a.ldx] = v; });
 }
 
 // gather (with precision change) B (old numbering, n x nrhs FP64) -> xp (new numbering, T)
@@ -1182,14 +1145,15 @@ void run_solve(const Factor& f, int nrhs, cx<T>* xp, cx<T>* work, hipStream_t s,
             }
             const int nh = S.huge_off[l + 1] - S.huge_off[l];
             const int32_t* hl = D.huge_list.p + S.huge_off[l];
-            for (int kb = 0; kb < S.huge_piv[l]; kb += kSB) {
+            for (int K0 = 0; K0 < S.huge_piv[l]; K0 += kHugeSB) {
                 unsigned gx = 1;
                 for (int q = S.huge_off[l]; q < S.huge_off[l + 1]; ++q) {
                     const int hf = S.huge_list[q], m = S.fsize[hf], p = S.npiv[hf];
-                    if (kb < p) gx = std::max(gx, (unsigned)((m - std::min(kb + kSB, p) + kSB - 1) / kSB));
+                    if (K0 < p) gx = std::max(gx, (unsigned)((m - std::min(K0 + kHugeSB, p) + kSB - 1) / kSB));
                 }
                 ProfScope ps(sys->ctx, "front_fwd_huge", s);
-                hipLaunchKernelGGL(k_huge_fwd<T>, dim3(gx, nh), dim3(kWG), 0, s, hl, kb, a);
+                hipLaunchKernelGGL((k_huge_diag<T, false>), dim3(nh), dim3(kWG), 0, s, hl, K0, a);
+                hipLaunchKernelGGL(k_huge_rows<T>, dim3(gx, nh), dim3(kWG), 0, s, hl, 0, K0, a);
             }
         }
         for (int l = S.nlevel - 1; l >= 0; --l) {
@@ -1206,11 +1170,13 @@ void run_solve(const Factor& f, int nrhs, cx<T>* xp, cx<T>* work, hipStream_t s,
             const int32_t* hl = D.huge_list.p + S.huge_off[l];
             {
                 ProfScope ps(sys->ctx, "front_bwd_huge", s);
-                hipLaunchKernelGGL(k_huge_bwd_cb<T>, dim3((S.huge_piv[l] + kSB - 1) / kSB, nh), dim3(kWG), 0, s, hl, a);
+                hipLaunchKernelGGL(k_huge_rows<T>, dim3((S.huge_piv[l] + kSB - 1) / kSB, nh), dim3(kWG), 0, s, hl, 2, 0, a);
             }
-            for (int kb = ((S.huge_piv[l] - 1) / kSB) * kSB; kb >= 0; kb -= kSB) {
+            for (int K0 = ((S.huge_piv[l] - 1) / kHugeSB) * kHugeSB; K0 >= 0; K0 -= kHugeSB) {
                 ProfScope ps(sys->ctx, "front_bwd_huge", s);
-                hipLaunchKernelGGL(k_huge_bwd<T>, dim3(std::max(1, (kb + kSB - 1) / kSB), nh), dim3(kWG), 0, s, hl, kb, a);
+                hipLaunchKernelGGL((k_huge_diag<T, true>), dim3(nh), dim3(kWG), 0, s, hl, K0, a);
+                if (K0 > 0)
+                    hipLaunchKernelGGL(k_huge_rows<T>, dim3((K0 + kSB - 1) / kSB, nh), dim3(kWG), 0, s, hl, 1, K0, a);
             }
         }
     }
