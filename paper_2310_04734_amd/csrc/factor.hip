@@ -825,6 +825,7 @@ __global__ void __launch_bounds__(NT) k_front_bwd(const int32_t* __restrict__ le
 // values (MFMA tiles with several right-hand sides). The backward direction first subtracts
 // U12 x_cb from the pivot rows (k_huge_rows over the contribution columns).
 constexpr int kHugeSB = 4 * kSB;
+constexpr int kHugeDiagWG = 512;   // threads of k_huge_diag: two waves per SIMD, two right-hand sides per wave
 
 // w[r0 + i] -= F[r0 + i, c0:c0+nc] w[c0:c0+nc] for i < rows <= 64 (all right-hand sides); the
 // solved values are staged 64 columns at a time through sh.y
@@ -913,7 +914,8 @@ __global__ void __launch_bounds__(kWG) k_huge_rows(const int32_t* __restrict__ h
 
 // the super-block [K0, K1) of one front (grid: one workgroup per huge front)
 template <typename T, bool UPPER>
-__global__ void __launch_bounds__(kWG) k_huge_diag(const int32_t* __restrict__ huge_list, int K0, SolveArgs<T> a) {
+__global__ void __launch_bounds__(kHugeDiagWG) k_huge_diag(const int32_t* __restrict__ huge_list, int K0, SolveArgs<T> a) {
+    constexpr int NT = kHugeDiagWG;
     __shared__ SolveShared<T> sh;
     const int f = huge_list[blockIdx.x];
     const int m = a.fsize[f], p = a.npiv[f], f0 = a.first[f];
@@ -928,7 +930,7 @@ __global__ void __launch_bounds__(kWG) k_huge_diag(const int32_t* __restrict__ h
         for (int kb = kfirst; UPPER ? kb >= K0 : kb < K1; kb += UPPER ? -kSB : kSB) {
             const int nb = min(kSB, K1 - kb);
             __syncthreads();
-            batched_for<kWG, kSB * kSB / kWG>(kSB * kSB,
+            batched_for<NT, kSB * kSB / NT>(kSB * kSB,
                 [&](int e) {
                     const int i = e % kSB, k = e / kSB;
                     return (i < nb && k < nb) ? F[kb + i + (size_t)(kb + k) * m]
@@ -937,19 +939,19 @@ __global__ void __launch_bounds__(kWG) k_huge_diag(const int32_t* __restrict__ h
                 [&](int e, cx<T> v) { sh.d[e % kSB][e / kSB] = v; });
             if (UPPER && t < kSB) sh.rd[t] = t < nb ? crecip(F[kb + t + (size_t)(kb + t) * m]) : cx<T>{T(1), T(0)};
             __syncthreads();
-            wave_diag_solve<T, kWG, UPPER>(w, m, kb, nb, l0, nr, sh);
+            wave_diag_solve<T, NT, UPPER>(w, m, kb, nb, l0, nr, sh);
             __syncthreads();
             // the rest of the super-block with the block's panel
             if (UPPER)
-                panel_fms<T, kWG, 0, true>(w + (size_t)l0 * m, m, K0, kb - K0, nr, F + (size_t)kb * m, nb, sh);
+                panel_fms<T, NT, 0, true>(w + (size_t)l0 * m, m, K0, kb - K0, nr, F + (size_t)kb * m, nb, sh);
             else
-                panel_fms<T, kWG, 32, true>(w + (size_t)l0 * m, m, kb + nb, K1 - kb - nb, nr, F + (size_t)kb * m, nb,
-                                            sh);
+                panel_fms<T, NT, 16, true>(w + (size_t)l0 * m, m, kb + nb, K1 - kb - nb, nr, F + (size_t)kb * m, nb,
+                                           sh);
         }
     }
     __syncthreads();
     const int nk = K1 - K0;
-    batched_for<kWG, 4>(nk * nrhs, [&](int e) { return w[K0 + e % nk + (size_t)(e / nk) * m]; },
+    batched_for<NT, 4>(nk * nrhs, [&](int e) { return w[K0 + e % nk + (size_t)(e / nk) * m]; },
                         [&](int e, cx<T> v) { a.x[f0 + K0 + e % nk + (size_t)(e / nk) * a.ldx] = v; });
 }
 
@@ -1152,7 +1154,7 @@ void run_solve(const Factor& f, int nrhs, cx<T>* xp, cx<T>* work, hipStream_t s,
                     if (K0 < p) gx = std::max(gx, (unsigned)((m - std::min(K0 + kHugeSB, p) + kSB - 1) / kSB));
                 }
                 ProfScope ps(sys->ctx, "front_fwd_huge", s);
-                hipLaunchKernelGGL((k_huge_diag<T, false>), dim3(nh), dim3(kWG), 0, s, hl, K0, a);
+                hipLaunchKernelGGL((k_huge_diag<T, false>), dim3(nh), dim3(kHugeDiagWG), 0, s, hl, K0, a);
                 hipLaunchKernelGGL(k_huge_rows<T>, dim3(gx, nh), dim3(kWG), 0, s, hl, 0, K0, a);
             }
         }
@@ -1174,7 +1176,7 @@ void run_solve(const Factor& f, int nrhs, cx<T>* xp, cx<T>* work, hipStream_t s,
             }
             for (int K0 = ((S.huge_piv[l] - 1) / kHugeSB) * kHugeSB; K0 >= 0; K0 -= kHugeSB) {
                 ProfScope ps(sys->ctx, "front_bwd_huge", s);
-                hipLaunchKernelGGL((k_huge_diag<T, true>), dim3(nh), dim3(kWG), 0, s, hl, K0, a);
+                hipLaunchKernelGGL((k_huge_diag<T, true>), dim3(nh), dim3(kHugeDiagWG), 0, s, hl, K0, a);
                 if (K0 > 0)
                     hipLaunchKernelGGL(k_huge_rows<T>, dim3((K0 + kSB - 1) / kSB, nh), dim3(kWG), 0, s, hl, 1, K0, a);
             }
