@@ -831,8 +831,10 @@ __global__ void __launch_bounds__(256) k_resid_partial(int64_t n, int q, int L, 
     }
 }
 
-// Large q x L: one candidate per workgroup column of the grid, one row per thread, X_c staged
-// through LDS 32 rows at a time, up to 16 load columns per pass.
+// Large q x L: one candidate per workgroup (grid x), 256 rows per workgroup (grid y), one row per
+// thread, X_c staged through LDS 32 rows at a time, up to 16 load columns per pass. Candidates
+// vary fastest over the grid, so the workgroups resident together share their rows of KV and
+// MV and re-read them from L2 rather than from HBM once per candidate.
 __global__ void __launch_bounds__(256) k_resid_partial_big(int64_t n, int q, int L, int ncand, const zd* __restrict__ KV,
                                                            const zd* __restrict__ MV, int64_t ldv, const zd* __restrict__ F,
                                                            const zd* __restrict__ X, const zd* __restrict__ scal,
@@ -840,10 +842,10 @@ __global__ void __launch_bounds__(256) k_resid_partial_big(int64_t n, int q, int
     constexpr int kKc = 32, kLc = 16;
     __shared__ zd xs[kKc][kLc];
     __shared__ double red[4];
-    const int c = blockIdx.y;
+    const int c = blockIdx.x;
     const zd* Xc = X + (size_t)c * q * L;
     const double w2c = w2[c];
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.y * 256 + threadIdx.x;
     const bool act = i < n;
     double acc2 = 0;
     for (int l0 = 0; l0 < L; l0 += kLc) {
@@ -885,7 +887,7 @@ __global__ void __launch_bounds__(256) k_resid_partial_big(int64_t n, int q, int
     for (int off = 32; off > 0; off >>= 1) acc2 += __shfl_xor(acc2, off);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x / 64] = acc2;
     __syncthreads();
-    if (threadIdx.x == 0) partial[(size_t)blockIdx.x * ncand + c] = ((red[0] + red[1]) + red[2]) + red[3];
+    if (threadIdx.x == 0) partial[(size_t)blockIdx.y * ncand + c] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
 __global__ void k_resid_reduce(int nchunk, int ncand, const double* __restrict__ partial, double* __restrict__ out) {
@@ -909,7 +911,8 @@ void candidate_residuals(int64_t n, int q, int L, int ncand, const zd* KV, const
         hipLaunchKernelGGL(k_resid_partial, dim3(nchunk, (ncand + kCandChunk - 1) / kCandChunk), dim3(256), shmem, s, n,
                            q, L, ncand, KV, MV, ldv, F, X, scal, w2, partial.p);
     } else {
-        hipLaunchKernelGGL(k_resid_partial_big, dim3(nchunk, ncand), dim3(256), 0, s, n, q, L, ncand, KV, MV, ldv, F, X,
+        CR_REQUIRE(nchunk <= 65535, CR_E_INVALID, "candidate residuals: more than 65535 x 256 rows");
+        hipLaunchKernelGGL(k_resid_partial_big, dim3(ncand, nchunk), dim3(256), 0, s, n, q, L, ncand, KV, MV, ldv, F, X,
                            scal, w2, partial.p);
     }
     hipLaunchKernelGGL(k_resid_reduce, dim3((ncand + 255) / 256), dim3(256), 0, s, nchunk, ncand, partial.p, res2);
