@@ -869,14 +869,26 @@ __global__ void __launch_bounds__(256) k_resid_partial_big(int64_t n, int q, int
             }
             __syncthreads();
             if (act) {
-                for (int kk = 0; kk < nk; ++kk) {
-                    const zd kv = KV[i + (int64_t)(k0 + kk) * ldv], mv = MV[i + (int64_t)(k0 + kk) * ldv];
-                    const double ar = kv.re - w2c * mv.re, ai = kv.im - w2c * mv.im;
+                // kG rows of K~V and M~V loaded together (the rows past nk repeat row nk - 1 and
+                // meet zero columns of xs), so that their latency is paid once per kG
+                constexpr int kG = 4;
+                for (int g0 = 0; g0 < nk; g0 += kG) {
+                    zd kv[kG], mv[kG];
 #pragma unroll
-                    for (int l = 0; l < kLc; ++l) {
-                        const zd x = xs[kk][l];
-                        rr[l] -= ar * x.re - ai * x.im;
-                        ri[l] -= ar * x.im + ai * x.re;
+                    for (int g = 0; g < kG; ++g) {
+                        const int64_t col = k0 + min(g0 + g, nk - 1);
+                        kv[g] = KV[i + col * ldv];
+                        mv[g] = MV[i + col * ldv];
+                    }
+#pragma unroll
+                    for (int g = 0; g < kG; ++g) {
+                        const double ar = kv[g].re - w2c * mv[g].re, ai = kv[g].im - w2c * mv[g].im;
+#pragma unroll
+                        for (int l = 0; l < kLc; ++l) {
+                            const zd x = xs[g0 + g][l];
+                            rr[l] -= ar * x.re - ai * x.im;
+                            ri[l] -= ar * x.im + ai * x.re;
+                        }
                     }
                 }
             }
