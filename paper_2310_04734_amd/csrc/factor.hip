@@ -614,15 +614,38 @@ __device__ void front_fwd_body(int f, const SolveArgs<T>& a, SolveShared<T>& sh)
                        [&](int e, cx<T> v) { w[e % p + (size_t)(e / p) * m] = v; });
     __syncthreads();
     if (a.huge[f]) return;
+    // Wide single-right-hand-side kernels hold the next diagonal block in registers (U entries
+    // a thread): its loads are issued before the current block's chain and panel, so that they
+    // share a memory round trip with the chain's own loads instead of starting one of their own.
+    constexpr int U = kSB * kSB / NT;
+    constexpr bool kAhead = NT >= 1024 && !MR;
+    cx<T> ahead[kAhead ? U : 1];
+    auto load_diag = [&](int kb, int nb, cx<T>* v) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = t + u * NT, i = e % kSB, k = e / kSB;
+            v[u] = (i < nb && k < nb) ? F[kb + i + (size_t)(kb + k) * m] : cx<T>{T(0), T(0)};
+        }
+    };
+    if constexpr (kAhead) load_diag(0, min(kSB, p), ahead);
     for (int kb = 0; kb < p; kb += kSB) {
         const int nb = min(kSB, p - kb);
-        // the diagonal block to LDS with all of a thread's loads in flight at once
-        batched_for<NT, kSB * kSB / NT>(kSB * kSB,
-            [&](int e) {
-                const int i = e % kSB, k = e / kSB;
-                return (i < nb && k < nb) ? F[kb + i + (size_t)(kb + k) * m] : cx<T>{T(0), T(0)};
-            },
-            [&](int e, cx<T> v) { sh.d[e % kSB][e / kSB] = v; });
+        if constexpr (kAhead) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = t + u * NT;
+                sh.d[e % kSB][e / kSB] = ahead[u];
+            }
+            if (kb + kSB < p) load_diag(kb + kSB, min(kSB, p - kb - kSB), ahead);
+        } else {
+            // the diagonal block to LDS with all of a thread's loads in flight at once
+            batched_for<NT, U>(kSB * kSB,
+                [&](int e) {
+                    const int i = e % kSB, k = e / kSB;
+                    return (i < nb && k < nb) ? F[kb + i + (size_t)(kb + k) * m] : cx<T>{T(0), T(0)};
+                },
+                [&](int e, cx<T> v) { sh.d[e % kSB][e / kSB] = v; });
+        }
         for (int l0 = 0; l0 < nrhs; l0 += kSR) {
             const int nr = min(kSR, nrhs - l0);
             __syncthreads();
