@@ -117,23 +117,37 @@ __device__ void wg_apply_swaps(cx<T>* __restrict__ A, int lda, const int* ipiv, 
                                SwapShared& sw) {
     const int t = threadIdx.x;
     __syncthreads();   // an earlier call's readers of sw are done
-    if (t == 0) {
-        int n = 0;
-        for (int k = k0; k < k1; ++k) {
-            const int r = ipiv[k];
-            if (r == k) continue;
-            int a = -1, b = -1;
-            for (int q = 0; q < n; ++q) {
-                if (sw.row[q] == k) a = q;
-                if (sw.row[q] == r) b = q;
-            }
-            if (a < 0) { sw.row[n] = k; sw.src[n] = k; a = n++; }
-            if (b < 0) { sw.row[n] = r; sw.src[n] = r; b = n++; }
-            const int x = sw.src[a];
-            sw.src[a] = sw.src[b];
-            sw.src[b] = x;
+    if (t < 64) {
+        // the first wave composes them in registers: lane j < 16 stands for row k0 + j, lane
+        // 16 + j for row ipiv[k0 + j] (one load for all of them); val = the row whose value is
+        // at the lane's row so far. A row held by several lanes is tracked in the lowest one.
+        const int nk = k1 - k0;
+        int row = -1;
+        if (t < nk) row = k0 + t;
+        else if (t >= kNB && t - kNB < nk) row = ipiv[k0 + t - kNB];
+        int val = row;
+        for (int k = 0; k < nk; ++k) {
+            const int rk = k0 + k, pk = __builtin_amdgcn_readlane(row, kNB + k);
+            if (pk == rk) continue;
+            const int la = __ffsll((unsigned long long)__ballot(row == rk)) - 1;
+            const int lb = __ffsll((unsigned long long)__ballot(row == pk)) - 1;
+            const int va = __builtin_amdgcn_readlane(val, la), vb = __builtin_amdgcn_readlane(val, lb);
+            if (t == la) val = vb;
+            if (t == lb) val = va;
         }
-        sw.n = n;
+        bool dup = false;
+        for (int q = 0; q < 2 * kNB; ++q) {
+            const int other = __builtin_amdgcn_readlane(row, q);
+            dup = dup || (q < t && other == row);
+        }
+        const bool keep = row >= 0 && !dup && val != row;
+        const unsigned long long kb = (unsigned long long)__ballot(keep);
+        const int slot = __builtin_amdgcn_mbcnt_hi((unsigned)(kb >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)kb, 0u));
+        if (keep) {
+            sw.row[slot] = row;
+            sw.src[slot] = val;
+        }
+        if (t == 0) sw.n = __popcll(kb);
     }
     __syncthreads();
     const int n = sw.n;
@@ -304,10 +318,9 @@ __device__ void wg_panel_lds(cx<T>* __restrict__ A, int lda, int p, int k0, int 
                              int* nperturb, LuShared<T>& sh, cx<T> (*P)[kNB + 1], int sw0) {
     const int t = threadIdx.x;
     const int rows = p - k0, nb = k1 - k0;
-    for (int e = t; e < rows * nb; e += kWG) {
-        const int i = e % rows, c = e / rows;
-        P[i][c] = A[k0 + i + (size_t)(k0 + c) * lda];
-    }
+    // eight loads in flight per thread (a plain strided loop waits for each load in turn)
+    batched_for<kWG, 8>(rows * nb, [&](int e) { return A[k0 + e % rows + (size_t)(k0 + e / rows) * lda]; },
+                        [&](int e, cx<T> v) { P[e % rows][e / rows] = v; });
     __syncthreads();
     for (int k = 0; k < nb; ++k) {
         T best = T(-1);
@@ -350,23 +363,24 @@ __device__ void wg_panel_lds(cx<T>* __restrict__ A, int lda, int p, int k0, int 
 
 // One 64 x 64 tile (rows i0.., columns j0..) of the trailing update
 // A[k1:m, k1:m] -= A[k1:m, k0:k1] A[k0:k1, k1:m], with k1 - k0 <= kNB.
-template <typename T>
+template <typename T, int U = kTile * kNB / kWG>
 __device__ void wg_tile_update(cx<T>* __restrict__ A, int lda, int m, int k0, int k1, int i0, int j0, LuShared<T>& sh) {
     const int t = threadIdx.x;
     const int nbk = k1 - k0;
     const int tx = t & 15, ty = t >> 4;   // 16 x 16 threads, 4 x 4 each
-    for (int e = t; e < kTile * kNB; e += kWG) {
-        int r = e % kTile, c = e / kTile;
-        cx<T> v = {T(0), T(0)};
-        if (i0 + r < m && c < nbk) v = A[i0 + r + (size_t)(k0 + c) * lda];
-        sh.a[r][c] = v;
-    }
-    for (int e = t; e < kTile * kNB; e += kWG) {
-        int r = e % kNB, c = e / kNB;
-        cx<T> v = {T(0), T(0)};
-        if (j0 + c < m && r < nbk) v = A[k0 + r + (size_t)(j0 + c) * lda];
-        sh.b[r][c] = v;
-    }
+    // both tiles staged with U loads in flight per thread (all of them by default)
+    batched_for<kWG, U>(kTile * kNB,
+        [&](int e) {
+            const int r = e % kTile, c = e / kTile;
+            return (i0 + r < m && c < nbk) ? A[i0 + r + (size_t)(k0 + c) * lda] : cx<T>{T(0), T(0)};
+        },
+        [&](int e, cx<T> v) { sh.a[e % kTile][e / kTile] = v; });
+    batched_for<kWG, U>(kTile * kNB,
+        [&](int e) {
+            const int r = e % kNB, c = e / kNB;
+            return (j0 + c < m && r < nbk) ? A[k0 + r + (size_t)(j0 + c) * lda] : cx<T>{T(0), T(0)};
+        },
+        [&](int e, cx<T> v) { sh.b[e % kNB][e / kNB] = v; });
     __syncthreads();
     cx<T> acc[4][4];
 #pragma unroll
@@ -417,7 +431,8 @@ __device__ void wg_getrf(cx<T>* __restrict__ A, int lda, int m, int p, int* __re
         if (k1 >= m) break;
         const int tiles = (m - k1 + kTile - 1) / kTile;
         for (int tile = 0; tile < tiles * tiles; ++tile)
-            wg_tile_update<T>(A, lda, m, k0, k1, k1 + (tile % tiles) * kTile, k1 + (tile / tiles) * kTile, sh);
+            wg_tile_update<T, LEAN ? 1 : kTile * kNB / kWG>(A, lda, m, k0, k1, k1 + (tile % tiles) * kTile,
+                                                              k1 + (tile / tiles) * kTile, sh);
     }
     __syncthreads();
 }

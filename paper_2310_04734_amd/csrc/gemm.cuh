@@ -191,7 +191,7 @@ __device__ void wg_strip_update(cx<T>* __restrict__ A, int lda, int r0, int nr, 
             if (e < nr * nc) {
                 const int i = e % nr, j = e / nr;
                 cx<T> a = acc[g];
-#pragma unroll
+#pragma unroll 4
                 for (int k = 0; k < kNB; ++k) {
                     a.re += sh.l[i][k].re * sh.u[k][j].re - sh.l[i][k].im * sh.u[k][j].im;
                     a.im += sh.l[i][k].re * sh.u[k][j].im + sh.l[i][k].im * sh.u[k][j].re;
