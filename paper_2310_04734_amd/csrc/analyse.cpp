@@ -302,13 +302,16 @@ std::unique_ptr<Symbolic> analyse_pattern(int64_t n, const std::vector<int64_t>&
         S.big_off[l + 1] = (int32_t)S.big_list.size();
         S.huge_off[l + 1] = (int32_t)S.huge_list.size();
         S.nsteps[l] = steps;
-        // levels whose one-workgroup solves carry large triangles get 1024-thread workgroups
+        // levels whose one-workgroup solves carry large triangles get 1024-thread workgroups:
+        // bit 0 for solves with several right-hand sides (m p >= 32768; below that the MFMA
+        // kernels' register spills at 1024 threads cost more than the extra waves gain), bit 1
+        // for single right-hand sides (m p >= 4096)
         double work = 0;
         for (int q = S.level_off[l]; q < S.level_off[l + 1]; ++q) {
             const int f = S.level_fronts[q];
             if (!S.huge[f]) work = std::max(work, (double)S.fsize[f] * S.npiv[f]);
         }
-        S.wide_solve.push_back(work >= 32768.0 ? 1 : 0);
+        S.wide_solve.push_back((work >= 32768.0 ? 1 : 0) | (work >= 4096.0 ? 2 : 0));
     }
     S.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return sym;

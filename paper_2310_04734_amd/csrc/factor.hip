@@ -1165,7 +1165,7 @@ void run_solve(const Factor& f, int nrhs, cx<T>* xp, cx<T>* work, hipStream_t s,
                 ProfScope ps(sys->ctx, "front_fwd", s);
                 const int32_t* lf = D.level_fronts.p + S.level_off[l];
                 const bool mr = nrhs >= kMfmaRhs;
-                if (S.wide_solve[l]) launch_level<T, kWideSolve>(true, mr, nf, s, lf, a);
+                if (S.wide_solve[l] & (mr ? 1 : 2)) launch_level<T, kWideSolve>(true, mr, nf, s, lf, a);
                 else launch_level<T, kWG>(true, mr, nf, s, lf, a);
             }
             const int nh = S.huge_off[l + 1] - S.huge_off[l];
@@ -1187,7 +1187,7 @@ void run_solve(const Factor& f, int nrhs, cx<T>* xp, cx<T>* work, hipStream_t s,
                 ProfScope ps(sys->ctx, "front_bwd", s);
                 const int32_t* lf = D.level_fronts.p + S.level_off[l];
                 const bool mr = nrhs >= kMfmaRhs;
-                if (S.wide_solve[l]) launch_level<T, kWideSolve>(false, mr, nf, s, lf, a);
+                if (S.wide_solve[l] & (mr ? 1 : 2)) launch_level<T, kWideSolve>(false, mr, nf, s, lf, a);
                 else launch_level<T, kWG>(false, mr, nf, s, lf, a);
             }
             const int nh = S.huge_off[l + 1] - S.huge_off[l];

@@ -114,7 +114,7 @@ struct Symbolic {
     std::vector<int32_t> huge;                 // per front: 1 = multi-workgroup solve
     std::vector<int32_t> huge_off, huge_list;  // per level
     std::vector<int32_t> huge_piv;             // per level: max pivots of its huge fronts
-    std::vector<int32_t> wide_solve;           // per level: 1 = solve with 1024-thread workgroups
+    std::vector<int32_t> wide_solve;           // per level: 1024-thread solve workgroups (bit 0: multi-RHS, bit 1: one RHS)
     int64_t factor_entries = 0;
     double factor_flops = 0;
     double gemm_flops = 0;         // trailing-GEMM part of factor_flops (large fronts)
