@@ -86,10 +86,16 @@ def test_sweep_edge_cases(P, ctx):
     assert R.sweep(np.zeros(0), prec=1).shape[0] == 0
 
 
-@pytest.mark.parametrize("name", ["box", "plate_cavity_small", "plate_cavity"])
+def _fuselage_small():
+    """A short coarse fuselage segment with three random-phase skin-pressure loads."""
+    return W.fuselage_workload(n_core=4, n_ring=2, h_z=0.25, n_loads=3, n_freq=16, length=1.0, frame_z=(0.5,))
+
+
+@pytest.mark.parametrize("name", ["box", "plate_cavity_small", "plate_cavity", "fuselage_small_skin_load"])
 def test_assembly_parity(P, ctx, name):
     _flush(f"assembly parity {name}")
-    w = {"box": W.box, "plate_cavity_small": W.small_plate_cavity, "plate_cavity": W.plate_cavity_workload}[name]()
+    w = {"box": W.box, "plate_cavity_small": W.small_plate_cavity, "plate_cavity": W.plate_cavity_workload,
+         "fuselage_small_skin_load": _fuselage_small}[name]()
     s = assembly.assemble(w.mesh, w.loads, w.receivers)
     g = P.assemble(ctx, w.mesh, w.loads, w.receivers)
     e = g.export()

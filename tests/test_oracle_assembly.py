@@ -180,3 +180,112 @@ def test_dof_counts_plate_cavity():
     w = W.plate_cavity_workload()
     dm = assembly.DofMap(w.mesh)
     assert dm.n_u == 2070 and dm.n_p == 5525 and dm.n == 7595
+
+
+# ------------------------------------------------------------------ skin-pressure load
+# f_u = -int N_s^T p n_out dGamma with n_out pointing away from the structure. Because the
+# element is isoparametric, sum_a N_a X_a = X on every face, so weighted sums of the nodal
+# forces are exact surface integrals that can be written out without the oracle:
+#   sum_a f_a            = -int p n_out dGamma
+#   sum_a (f_a . X_a)    = -int p (n_out . X) dGamma
+
+
+def _plate_patch(lx=0.3, ly=0.2, t=0.002, nx=3, ny=2):
+    coords = grid_nodes(np.linspace(0, lx, nx + 1), np.linspace(0, ly, ny + 1), np.array([0.0, t]))
+    nid = lambda i, j, k: i + (nx + 1) * (j + (ny + 1) * k)
+    elems = grid_elems(nx, ny, 1, nid)
+    top = np.array([[nid(i, j, 1), nid(i + 1, j, 1), nid(i + 1, j + 1, 1), nid(i, j + 1, 1)]
+                    for j in range(ny) for i in range(nx)], np.int64)   # right-hand normal +z
+    mat = Material(kind=SOLID, rho=2700.0, eta=0.02, E=70e9, nu=0.3)
+    mesh = Mesh(coords=coords, elems=elems, elem_mat=np.zeros(len(elems), np.int32), materials=[mat],
+                clamped=np.zeros(0, np.int64), iface=np.zeros((0, 4), np.int64))
+    return mesh, top
+
+
+def _nodal_forces(s, mesh, l=0):
+    dm = s["dof"]
+    f = np.zeros((mesh.n_nodes, 3), complex)
+    ok = dm.u[:, 0] >= 0
+    f[ok] = s["F"][dm.u[ok], l]
+    return f
+
+
+def test_skin_pressure_flat_patch_total_force_and_moment():
+    """Uniform p on a flat top face (normal +z, away from the plate): total force -p A e_z.
+    Linear p = a + b x + c y: sum f_z = -int p dA and sum x_a f_z,a = -int x p dA in closed form."""
+    from workloads.meshes import LOAD_SKIN_PRESSURE
+    lx, ly = 0.3, 0.2
+    mesh, top = _plate_patch(lx, ly)
+    x, y = mesh.coords[:, 0], mesh.coords[:, 1]
+    a, b, c = 2.0 - 1.0j, 3.0 + 0.5j, -1.5 + 2.0j
+    loads = [Load(kind=LOAD_SKIN_PRESSURE, faces=top, amp=np.full(mesh.n_nodes, 1.0 + 0j)),
+             Load(kind=LOAD_SKIN_PRESSURE, faces=top, amp=a + b * x + c * y)]
+    s = assembly.assemble(mesh, loads, np.zeros(0, np.int64))
+    assert np.array_equal(s["flags"], [0, 0])
+    A = lx * ly
+    f0 = _nodal_forces(s, mesh, 0)
+    assert np.allclose(f0.sum(axis=0), [0.0, 0.0, -A], rtol=0, atol=1e-15)
+    # only the loaded face's nodes carry force
+    loaded = np.unique(top)
+    assert np.all(f0[np.setdiff1d(np.arange(mesh.n_nodes), loaded)] == 0)
+    f1 = _nodal_forces(s, mesh, 1)
+    int_p = a * A + b * lx ** 2 / 2 * ly + c * ly ** 2 / 2 * lx
+    int_xp = a * lx ** 2 / 2 * ly + b * lx ** 3 / 3 * ly + c * (lx ** 2 / 2) * (ly ** 2 / 2)
+    assert np.isclose(f1[:, 2].sum(), -int_p, rtol=1e-13)
+    assert np.isclose((x * f1[:, 2]).sum(), -int_xp, rtol=1e-13)
+    assert np.allclose(f1[:, :2], 0, atol=1e-15)
+
+
+def test_skin_pressure_closed_cylinder_net_force_and_virial():
+    """Uniform unit pressure on the fuselage skin (faces as the workload generator orients them):
+    the net force vanishes, and sum_a f_a . X_a = -sum_faces A_f (n_f . X_f), with n_f the plane
+    normal of each (planar) face taken pointing AWAY FROM THE AXIS (computed here from the face
+    corners, not from the generator's orientation). A face list oriented into the structure, or a
+    factor of two in the face integrals, fails this."""
+    from workloads.fuselage import fuselage
+    from workloads.meshes import LOAD_SKIN_PRESSURE
+    air = Material(kind=FLUID, rho=1.21, eta=0.01, c=343.0)
+    alu = Material(kind=SOLID, rho=2700.0, eta=0.02, E=70e9, nu=0.3)
+    mesh = fuselage(length=1.0, frame_z=(0.5,), n_core=4, n_ring=2, h_z=0.25, air=air, metal=alu)
+    mesh.clamped = np.zeros(0, np.int64)          # every skin node free, so no force is dropped
+    faces = mesh.meta["skin_faces"]
+    s = assembly.assemble(mesh, [Load(kind=LOAD_SKIN_PRESSURE, faces=faces, amp=np.ones(mesh.n_nodes, complex))],
+                          np.zeros(0, np.int64))
+    f = _nodal_forces(s, mesh)
+    X = mesh.coords
+    expect, area = 0.0, 0.0
+    for q in faces:
+        c = X[q]
+        d1, d2 = c[2] - c[0], c[3] - c[1]
+        nv = np.cross(d1, d2)
+        Af = 0.5 * np.linalg.norm(nv)                 # planar quad: half the diagonals' cross product
+        n = nv / np.linalg.norm(nv)
+        mid = c.mean(axis=0)
+        if np.dot(n[:2], mid[:2]) < 0:
+            n = -n
+        assert abs(np.dot(c - c[0], n)).max() < 1e-12   # the face is planar
+        expect += -Af * np.dot(n, mid)
+        area += Af
+    assert np.abs(f.sum(axis=0)).max() <= 1e-12 * area
+    assert np.isclose(np.einsum("ad,ad->", f, X), expect, rtol=1e-12)
+    assert expect < 0
+
+
+def test_skin_pressure_power_is_positive():
+    """A skin pressure on a damped coupled model injects positive time-averaged power:
+    Re(f^H v) > 0 with v = i w u (e^{+i w t}); checked on a small fuselage segment."""
+    from workloads.fuselage import fuselage
+    from workloads.meshes import LOAD_SKIN_PRESSURE
+    air = Material(kind=FLUID, rho=1.21, eta=0.01, c=343.0)
+    alu = Material(kind=SOLID, rho=2700.0, eta=0.02, E=70e9, nu=0.3)
+    mesh = fuselage(length=1.0, frame_z=(0.5,), n_core=3, n_ring=1, h_z=0.25, air=air, metal=alu)
+    faces = mesh.meta["skin_faces"]
+    rng = W.SplitMix64(4242)
+    amp = np.exp(2j * np.pi * rng.uniforms(mesh.n_nodes))
+    s = assembly.assemble(mesh, [Load(kind=LOAD_SKIN_PRESSURE, faces=faces, amp=amp)], np.zeros(0, np.int64))
+    n_u = s["n_u"]
+    for f_hz in (23.0, 97.0, 211.0, 289.0):
+        om = 2 * np.pi * f_hz
+        x = solve.full_solve(s["K"], s["M"], s["F"], s["flags"], om)[:, 0]
+        power = np.vdot(s["F"][:n_u, 0], 1j * om * x[:n_u]).real
+        assert power > 0

@@ -76,23 +76,56 @@ def test_orthonormal_basis(small_rom):
 
 
 def test_moment_matching(small_rom):
-    """C_R (A_Rj^{-1} M_R)^i A_Rj^{-1} F_R = C^T (A_j^{-1} M)^i A_j^{-1} F for i < k_j."""
+    """Zeroth moment (interpolation) at every expansion point of the converged 7-point model."""
     _, s, _, shifts, rb, r = small_rom
     K, M, F = s["K"].toarray(), s["M"].toarray(), s["F"]
     recv = s["recv"]
     for om in shifts:
-        A = K - om ** 2 * M
-        AR = r["KR"] - om ** 2 * r["MR"]
-        x = np.linalg.solve(A, F)
-        xr = np.linalg.solve(AR, r["FR"])
-        for i in range(5):
-            yf, yr = x[recv], r["CR"] @ xr
-            # the zeroth moment is interpolation; higher moments of the unscaled full-order
-            # recurrence lose accuracy as (A_j^{-1} M)^i aligns with the dominant modes
-            tol = 1e-10 if i == 0 else 1e-4
-            assert np.abs(yf - yr).max() <= tol * np.abs(yf).max()
-            x = np.linalg.solve(A, M @ x)
-            xr = np.linalg.solve(AR, r["MR"] @ xr)
+        yf = np.linalg.solve(K - om ** 2 * M, F)[recv]
+        yr = r["CR"] @ np.linalg.solve(r["KR"] - om ** 2 * r["MR"], r["FR"])
+        assert np.abs(yf - yr).max() <= 1e-10 * np.abs(yf).max()
+
+
+@pytest.mark.parametrize("shifts_hz,blocks", [((30.0, 200.0, 370.0), 4), ((60.0, 180.0, 300.0), 3)])
+def test_higher_moments_match_in_backward_error(shifts_hz, blocks):
+    """Moment matching of Eq. (10)-(11) for every moment i < k_j, in the scaled system.
+
+    The ROM's moments x_R,0 = A_Rj^{-1} F_R, x_R,i+1 = A_Rj^{-1} M_R x_R,i, lifted by V, satisfy the
+    full-order recurrence A_j x_0 = F, A_j x_i+1 = M x_i exactly (the Krylov blocks lie in span V
+    and the model is a Galerkin projection), so their normwise backward errors against the full
+    matrices are at rounding level. The check is in backward-error form because the forward
+    error of high moments carries kappa(A_j) ~ 1e6. Off the expansion points the same quantity
+    is the model's own residual (>= 1e-9 here), which shows that the check discriminates.
+    (When a block nearly deflates, i.e. a norm ratio close to 1e-10, the continuation vector
+    of the next block is accurate to eps / ratio only and later moments match to that level;
+    these two models are far from converged so no block comes close to deflating.)"""
+    w = W.small_plate_cavity()
+    s = assembly.assemble(w.mesh, w.loads, w.receivers)
+    ss = krylov.jacobi_scaled(s)
+    K, M, F = ss["K"], ss["M"], ss["F"]
+    shifts = 2 * np.pi * np.array(shifts_hz)
+    rb = krylov.build_basis(ss, shifts, blocks)
+    assert rb.deflated == 0 and rb.q == len(shifts) * blocks
+    V, r = rb.basis, krylov.project(ss, rb.basis)
+
+    def berr(A, x, b):
+        nA = abs(A).sum(axis=1).max()
+        return np.abs(A @ x - b).max() / (nA * np.abs(x).max() + np.abs(b).max())
+
+    for om in shifts:
+        A, AR = K - om ** 2 * M, r["KR"] - om ** 2 * r["MR"]
+        xr, b = np.linalg.solve(AR, r["FR"]), F
+        for i in range(blocks):
+            x = V @ xr
+            assert berr(A, x, b) <= 1e-13, (om, i)
+            # the same moment at the receivers, forward error bounded by kappa(A_j) eps
+            yf = np.linalg.solve(A.toarray(), b)[ss["recv"]] * ss["scale"][ss["recv"]][:, None]
+            assert np.abs(r["CR"] @ xr - yf).max() <= 1e-9 * np.abs(yf).max(), (om, i)
+            b, xr = M @ x, np.linalg.solve(AR, r["MR"] @ xr)
+    om = 2 * np.pi * 123.0
+    A = K - om ** 2 * M
+    x = V @ np.linalg.solve(r["KR"] - om ** 2 * r["MR"], r["FR"])
+    assert berr(A, x, F) >= 1e-9
 
 
 def test_interpolation_and_galerkin(small_rom):
