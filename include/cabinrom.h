@@ -266,9 +266,10 @@ void cr_basis_destroy(cr_basis b);
    V^T f read as V^H f), C_R = C^T V (rows of the unscaled basis at the receivers). FP64. */
 cr_status cr_project(cr_sys sys, cr_basis b, cr_rom* out);
 
-/* A reduced model from host FP64 column-major arrays: K_R, M_R (q x q), D_R (q x q or NULL for
-   D_R = 0; Rayleigh damping alpha M_R + beta K_R can be passed here), F_R (q x L),
-   C_R (n_o x q), flags[L]. */
+/* A reduced model of the form of Eq. (11) (Section 3.3; D_R = V^H D V of the reduced system, or
+   the Rayleigh form alpha M_R + beta K_R given after Eq. (11)) from host FP64 column-major arrays:
+   K_R, M_R (q x q), D_R (q x q or NULL for D_R = 0), F_R (q x L), C_R (n_o x q), flags[L]
+   (load column l is F_R[:, l] (i w)^flags[l]). 1 <= q <= 4096, L >= 1. Arrays are copied. */
 cr_status cr_rom_import(cr_ctx ctx, int32_t q, int32_t L, int32_t n_o, const cr_z* KR,
                         const cr_z* DR, const cr_z* MR, const cr_z* FR, const cr_z* CR,
                         const int32_t* flags, cr_rom* out);
@@ -284,26 +285,38 @@ typedef struct {
     int32_t not_converged;     /* frequencies whose refinement missed 1e-14                  */
     int32_t fp64_fallbacks;    /* CR_MIXED frequencies redone with a complex-FP64 LU because
                                   refinement of the complex-FP32 LU stalled                  */
+    int32_t n_perturbed;       /* pivots of the reduced LU that were zero, non-finite or below
+                                  eps^2 max|A_R| (numerically singular) and were perturbed;
+                                  such a frequency is always refined in FP64                 */
     double seconds;
 } cr_sweep_info;
 
-/* Reduced sweep: for each w, A_R = K_R + i w D_R - w^2 M_R formed in FP64, dense LU with
-   partial pivoting (complex FP32 under CR_MIXED, complex FP64 under CR_FP64), solve for the L
-   load columns F_R (i w)^flags, FP64 refinement under CR_MIXED, then Y = C_R X_R.
-   Y_dev: nfreq x L x n_o complex128, receiver index fastest ([w][l][o]). */
+/* Reduced sweep, the online phase of the MOR (Section 3.3, reduced system of Eq. (11), with
+   y = C^T x of Eq. (8)): for each w, A_R = K_R + i w D_R - w^2 M_R formed in FP64, dense LU with
+   partial pivoting over every row (complex FP32 under CR_MIXED, complex FP64 under CR_FP64),
+   solve for the L load columns F_R (i w)^flags, then Y = C_R X_R. CR_MIXED refines every
+   frequency in FP64 with FP64 K_R, M_R, D_R until each load column's normwise backward error
+   ||r_l||_inf / (||A_R||_inf ||x_l||_inf + ||b_l||_inf) <= 1e-14 (or its last correction is below
+   1e-14 ||x_l||), and redoes a frequency with a complex-FP64 LU when refinement stalls. CR_FP64
+   solves once, and refines only a frequency whose LU had to perturb a pivot.
+   Y_dev: nfreq x L x n_o complex128, receiver index fastest ([w][l][o]).
+   Errors: CR_E_NOT_CONVERGED when a refined frequency misses the tolerance (Y and info are
+   still written); CR_E_UNSUPPORTED for q > 4096 or L > 64. */
 cr_status cr_sweep(cr_rom r, int32_t nfreq, const double* omegas, cr_precision prec, cr_z* Y_dev,
                    cr_sweep_info* info);
 
-/* Launch tuning of the batched sweep: variant (0 = automatic choice, 1 = LDS-resident reduced
-   matrix for orders that fit nb KiB of LDS, 2 = global-memory workspace only), resident
-   workgroups per compute unit (0 = automatic), nb, and refine (1 = also refine CR_FP64 sweeps
-   with FP64 residuals, e.g. to serve as a reference). */
+/* Launch shape of the batched sweep: variant (0 = default, 1 = reduced matrix LDS-resident for
+   orders whose q^2 entries fit nb KiB of LDS, 2 = global-memory workspace only), resident
+   workgroups per compute unit (0 = 2), nb (KiB, <= 150, variant 1 only), and refine (1 = also refine
+   CR_FP64 sweeps with FP64 residuals, e.g. to serve as a reference). */
 typedef struct { int32_t variant, grid_per_cu, nb, refine; } cr_tune;
 
-/* Batched sweep of nrom reduced models of uneven order in one persistent launch. omegas:
-   nrom x nfreq (row-major, host); Y_dev: host array of nrom device pointers, each
-   nfreq x L_m x n_o_m. Work items (model, w) are taken longest-first (q^3 descending). tune may
-   be NULL (autotuned per order bucket, cached for the process). */
+/* Batched sweep (the paper's online phase, Section 3.3, run for many reduced models at once):
+   nrom reduced models of uneven order in one persistent launch. omegas: nrom x nfreq
+   (row-major, host); Y_dev: host array of nrom device pointers, each nfreq x L_m x n_o_m. Work
+   items (model, w) are taken longest-first (q^3 descending). Per item exactly as cr_sweep.
+   tune may be NULL (2 workgroups per compute unit, global-memory workspace); the autotuned
+   launch shape and graph replay are cr_sweep_plan_create's. Errors as cr_sweep. */
 cr_status cr_sweep_batched(cr_ctx ctx, int32_t nrom, const cr_rom* roms, int32_t nfreq,
                            const double* omegas, cr_precision prec, cr_z* const* Y_dev,
                            const cr_tune* tune, cr_sweep_info* info);

@@ -107,7 +107,11 @@ class cr_greedy_trace(C.Structure):
 
 class cr_sweep_info(C.Structure):
     _fields_ = [("max_ir_iterations", C.c_int32), ("not_converged", C.c_int32), ("fp64_fallbacks", C.c_int32),
-                ("seconds", C.c_double)]
+                ("n_perturbed", C.c_int32), ("seconds", C.c_double)]
+
+
+def _sweep_info(info):
+    return {k: getattr(info, k) for k, _ in cr_sweep_info._fields_}
 
 
 class cr_tune(C.Structure):
@@ -438,9 +442,9 @@ class Rom:
         Y = out if out is not None else torch.empty((len(om), self.L, self.n_o), dtype=torch.complex128,
                                                     device=self.ctx.device)
         info = cr_sweep_info()
-        self.ctx.check(lib.cr_sweep(self.h, len(om), _ptr(om), prec, _dev_ptr(Y), C.byref(info)))
-        self.last_info = dict(max_ir_iterations=info.max_ir_iterations, not_converged=info.not_converged,
-                              fp64_fallbacks=info.fp64_fallbacks, seconds=info.seconds)
+        st = lib.cr_sweep(self.h, len(om), _ptr(om), prec, _dev_ptr(Y), C.byref(info))
+        self.last_info = _sweep_info(info)
+        self.ctx.check(st)
         return Y
 
     def __del__(self):
@@ -541,9 +545,10 @@ class SweepPlan:
 
     def execute(self):
         info = cr_sweep_info()
-        self.ctx.check(lib.cr_sweep_plan_execute(self.h, C.byref(info)))
-        return dict(max_ir_iterations=info.max_ir_iterations, not_converged=info.not_converged,
-                    fp64_fallbacks=info.fp64_fallbacks, seconds=info.seconds)
+        st = lib.cr_sweep_plan_execute(self.h, C.byref(info))
+        self.last_info = _sweep_info(info)
+        self.ctx.check(st)
+        return self.last_info
 
     def tuning(self):
         ch = cr_tune()
@@ -558,8 +563,9 @@ class SweepPlan:
             self.h = None
 
 
-def sweep_batched(ctx: Context, roms, omegas, prec=CR_MIXED, outs=None, grid_per_cu=0):
-    """omegas: (nrom, nfreq) host array; returns a list of Y tensors (nfreq x L x n_o)."""
+def sweep_batched(ctx: Context, roms, omegas, prec=CR_MIXED, outs=None, tune=None):
+    """omegas: (nrom, nfreq) host array; returns a list of Y tensors (nfreq x L x n_o) and the
+    sweep info. tune: None or dict(variant, grid_per_cu, nb, refine)."""
     torch = ctx.torch
     om = np.ascontiguousarray(omegas, np.float64)
     nrom, nfreq = om.shape
@@ -567,8 +573,12 @@ def sweep_batched(ctx: Context, roms, omegas, prec=CR_MIXED, outs=None, grid_per
         outs = [torch.empty((nfreq, r.L, r.n_o), dtype=torch.complex128, device=ctx.device) for r in roms]
     hs = (P * nrom)(*[r.h for r in roms])
     ys = (P * nrom)(*[Y.data_ptr() for Y in outs])
-    tune = cr_tune(0, int(grid_per_cu), 0, 0)
+    t = None
+    if tune is not None:
+        t = cr_tune(int(tune.get("variant", 0)), int(tune.get("grid_per_cu", 0)), int(tune.get("nb", 0)),
+                    int(tune.get("refine", 0)))
     info = cr_sweep_info()
-    ctx.check(lib.cr_sweep_batched(ctx.h, nrom, hs, nfreq, _ptr(om), prec, ys, C.byref(tune), C.byref(info)))
-    return outs, dict(max_ir_iterations=info.max_ir_iterations, not_converged=info.not_converged,
-                      fp64_fallbacks=info.fp64_fallbacks, seconds=info.seconds)
+    st = lib.cr_sweep_batched(ctx.h, nrom, hs, nfreq, _ptr(om), prec, ys, C.byref(t) if t is not None else None,
+                              C.byref(info))
+    ctx.check(st)
+    return outs, _sweep_info(info)

@@ -14,8 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcabinrom.so")
-SOURCES = ["api.cpp", "assemble.cpp", "analyse.cpp", "factor.hip", "linalg.hip", "sweep.hip", "greedy.cpp", "probe.hip",
-           "mlp.hip"]
+SOURCES = ["api.cpp", "assemble.cpp", "analyse.cpp", "factor.hip", "linalg.hip", "sweep.hip", "probe.hip", "mlp.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",
          "-packed-fp32-ops", "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unused-result",
@@ -33,7 +32,10 @@ def _compile(src: str) -> str:
 
 def build(jobs: int | None = None, verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    missing = [s for s in SOURCES if not os.path.exists(os.path.join(CSRC, s))]
+    if missing:
+        raise FileNotFoundError(f"library sources missing: {missing}")
+    srcs = SOURCES
     jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 4)))
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(_compile, srcs))

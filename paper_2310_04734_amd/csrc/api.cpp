@@ -269,6 +269,15 @@ std::unique_ptr<cr_rom_s> rom_from_basis(cr_basis B) {
     return r;
 }
 
+void fill_sweep_info(cr_sweep_info* info, int mi, int nc, int fb, int np, double secs) {
+    if (!info) return;
+    info->max_ir_iterations = mi;
+    info->not_converged = nc;
+    info->fp64_fallbacks = fb;
+    info->n_perturbed = np;
+    info->seconds = secs;
+}
+
 RomDesc desc_of(const cr_rom_s* r, const double* omegas_dev, zd* out, int out_x) {
     RomDesc d;
     d.KR = r->KR.p;
@@ -737,12 +746,9 @@ cr_status cr_sweep(cr_rom r, int32_t nfreq, const double* omegas, cr_precision p
         for (int i = 0; i < nfreq; ++i) items[i] = make_int2(0, i);
         int mi = 0, nc = 0, np = 0, fb = 0;
         E.run(roms, items, prec, prec == CR_MIXED, s, &mi, &nc, &np, 0, &fb);
-        if (info) {
-            info->max_ir_iterations = mi;
-            info->not_converged = nc;
-            info->fp64_fallbacks = fb;
-            info->seconds = now() - t0;
-        }
+        fill_sweep_info(info, mi, nc, fb, np, now() - t0);
+        CR_REQUIRE(nc == 0, CR_E_NOT_CONVERGED,
+                   "cr_sweep: refinement did not reach its tolerance at " + std::to_string(nc) + " frequencies");
     });
 }
 
@@ -753,10 +759,14 @@ cr_status cr_sweep_batched(cr_ctx ctx, int32_t nrom, const cr_rom* roms, int32_t
         CR_REQUIRE(nrom >= 0 && nfreq >= 0 && (nrom == 0 || (roms && Y_dev)) && (nfreq == 0 || omegas), CR_E_INVALID,
                    "cr_sweep_batched: bad arguments");
         CR_REQUIRE(prec == CR_FP64 || prec == CR_MIXED, CR_E_INVALID, "cr_sweep_batched: bad precision");
+        CR_REQUIRE(!tune || (tune->variant >= 0 && tune->variant <= 2 && tune->grid_per_cu >= 0 && tune->nb >= 0 &&
+                             tune->nb <= 150),
+                   CR_E_INVALID, "cr_sweep_batched: bad tuning");
         const double t0 = now();
         hipStream_t s = ctx->stream;
         SweepEngine& E = engine(ctx);
         const size_t nw = (size_t)nrom * nfreq;
+        for (size_t i = 0; i < nw; ++i) CR_REQUIRE(std::isfinite(omegas[i]), CR_E_INVALID, "cr_sweep_batched: non-finite frequency");
         E.d_omega.reserve(std::max<size_t>(nw, 1));
         if (nw) CR_HIP(hipMemcpyAsync(E.d_omega.p, omegas, nw * sizeof(double), hipMemcpyHostToDevice, s));
         std::vector<RomDesc> ds(nrom);
@@ -773,14 +783,15 @@ cr_status cr_sweep_batched(cr_ctx ctx, int32_t nrom, const cr_rom* roms, int32_t
         for (int m : order)
             for (int i = 0; i < nfreq; ++i) items.push_back(make_int2(m, i));
         int mi = 0, nc = 0, np = 0, fb = 0;
-        const int grid = tune && tune->grid_per_cu > 0 ? tune->grid_per_cu * ctx->num_cu : 0;
-        E.run(ds, items, prec, prec == CR_MIXED, s, &mi, &nc, &np, grid, &fb);
-        if (info) {
-            info->max_ir_iterations = mi;
-            info->not_converged = nc;
-            info->fp64_fallbacks = fb;
-            info->seconds = now() - t0;
-        }
+        const bool refine = prec == CR_MIXED || (tune && tune->refine);
+        const int gpc = tune && tune->grid_per_cu > 0 ? tune->grid_per_cu : 2;
+        const int lds = tune && tune->variant == 1 ? tune->nb * 1024 : 0;
+        E.prepare(ds, items, s);
+        E.launch(prec, refine, gpc, lds, s);
+        E.read_stats(s, &mi, &nc, &np, &fb);
+        fill_sweep_info(info, mi, nc, fb, np, now() - t0);
+        CR_REQUIRE(nc == 0, CR_E_NOT_CONVERGED,
+                   "cr_sweep_batched: refinement did not reach its tolerance at " + std::to_string(nc) + " items");
     });
 }
 
@@ -931,12 +942,9 @@ extern "C" cr_status cr_sweep_plan_execute(cr_sweep_plan plan, cr_sweep_info* in
         }
         int mi = 0, nc = 0, np = 0, fb = 0;
         plan->eng->read_stats(s, &mi, &nc, &np, &fb);
-        if (info) {
-            info->max_ir_iterations = mi;
-            info->not_converged = nc;
-            info->fp64_fallbacks = fb;
-            info->seconds = now() - t0;
-        }
+        fill_sweep_info(info, mi, nc, fb, np, now() - t0);
+        CR_REQUIRE(nc == 0, CR_E_NOT_CONVERGED,
+                   "cr_sweep_plan_execute: refinement did not reach its tolerance at " + std::to_string(nc) + " items");
     });
 }
 

@@ -83,13 +83,47 @@ __device__ __forceinline__ T wg_max(T v, T* red) {
     return fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
 }
 
+// Per load column l of the q x L column-major arrays (ld q): the largest entry magnitude of each of
+// three arrays, into out[0][l], out[1][l], out[2][l] (LDS, L <= kMaxLoads). One wave per column
+// (columns dealt round-robin to the four waves), lanes strided over the rows, then a shuffle
+// reduction; ends with a barrier.
+constexpr int kMaxLoads = 64;
+template <typename TA, typename TB, typename TC>
+__device__ void col_max3(const TA* __restrict__ a, const TB* __restrict__ b, const TC* __restrict__ c, int q, int L,
+                         double (*out)[kMaxLoads]) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int l = wave; l < L; l += kWG / 64) {
+        double ma = 0, mb = 0, mc = 0;
+        for (int i = lane; i < q; i += 64) {
+            const size_t e = i + (size_t)l * q;
+            ma = fmax(ma, hypot((double)a[e].re, (double)a[e].im));
+            mb = fmax(mb, hypot((double)b[e].re, (double)b[e].im));
+            mc = fmax(mc, hypot((double)c[e].re, (double)c[e].im));
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            ma = fmax(ma, __shfl_xor(ma, off));
+            mb = fmax(mb, __shfl_xor(mb, off));
+            mc = fmax(mc, __shfl_xor(mc, off));
+        }
+        if (lane == 0) { out[0][l] = ma; out[1][l] = mb; out[2][l] = mc; }
+    }
+    __syncthreads();
+}
+
 // Factor and solve one reduced system in precision T: A_R(w) rounded to T, LU with partial
-// pivoting, X = A_R^{-1} B with FP64 refinement (refine) or a single solve. Returns whether the
-// normwise backward error reached tol (always true without refinement).
+// pivoting over every row, X = A_R^{-1} B with FP64 refinement (refine) or a single solve.
+// Only a pivot that is zero, non-finite or below eps_T^2 max|A_R| (numerically singular) is
+// perturbed, and a perturbed factor is always refined in FP64 so that its solution is either
+// certified or reported. Refinement stops per load column: column l has converged when its
+// normwise backward error ||r_l|| / (||A_R|| ||x_l|| + ||b_l||) <= tol or when the last
+// correction is below tol ||x_l|| (infinity norms); the item converges when every column has.
+// It stops unconverged after max_iter corrections or when the largest backward error of the
+// unconverged columns fails to halve. Returns whether the item converged.
 template <typename T>
 __device__ bool solve_item(const RomDesc& rd, double w, cx<T>* __restrict__ A, int* __restrict__ ipiv, zd* __restrict__ X,
                            zd* __restrict__ R, const zd* __restrict__ Bv, cx<T>* __restrict__ D, bool refine, int max_iter,
-                           double tol, LuShared<T>& sh, double* red, int* s_perturb, int* its_out) {
+                           double tol, LuShared<T>& sh, double* red, int* s_perturb, int* its_out,
+                           double (*cm)[kMaxLoads], double* s_bn) {
     const int t = threadIdx.x;
     const int q = rd.q, L = rd.L;
     const double w2 = w * w;
@@ -108,10 +142,12 @@ __device__ bool solve_item(const RomDesc& rd, double w, cx<T>* __restrict__ A, i
     }
     if (t == 0) *s_perturb = 0;
     __syncthreads();
-    const T tiny = sizeof(T) == 4 ? T(3e-4 * amax) : T(1e-8 * amax);
+    constexpr double eps = sizeof(T) == 4 ? 5.96e-8 : 1.11e-16;
+    const T tiny = amax > 0 ? T(amax * eps * eps) : T(sizeof(T) == 4 ? 1e-37 : 1e-307);
     wg_getrf<T, true>(A, q, q, q, ipiv, tiny, s_perturb, sh);
+    refine = refine || *s_perturb > 0;
     int its = 0;
-    double prev = 1e300;
+    double prev = 1e300, an = 0;
     bool conv = false;
     for (;;) {
         for (int e = t; e < q * L; e += kWG) D[e] = {T(R[e].re), T(R[e].im)};
@@ -120,12 +156,11 @@ __device__ bool solve_item(const RomDesc& rd, double w, cx<T>* __restrict__ A, i
         for (int e = t; e < q * L; e += kWG) { X[e].re += (double)D[e].re; X[e].im += (double)D[e].im; }
         __syncthreads();
         if (!refine) { conv = true; break; }
-        // R = B - A_R X in FP64; backward error max ||r||_inf / (||A||_inf ||x||_inf + ||b||_inf),
-        // pooled over the load columns. One thread per row reads K_R, M_R (and D_R) once per
+        // R = B - A_R X in FP64. One thread per row reads K_R, M_R (and D_R) once per
         // refinement step for up to kLc load columns; X comes through LDS kJc rows at a time.
         constexpr int kLc = 16, kJc = 32;
         __shared__ zd xs[kJc][kLc];
-        double anorm_part = 0, rmax = 0, xmax = 0, bmax = 0;
+        double anorm_part = 0;
         for (int l0 = 0; l0 < L; l0 += kLc) {
             const int nl = min(kLc, L - l0);
             for (int i0 = 0; i0 < q; i0 += kWG) {
@@ -151,7 +186,7 @@ __device__ bool solve_item(const RomDesc& rd, double w, cx<T>* __restrict__ A, i
                             const zd k = rd.KR[o], m = rd.MR[o];
                             double ar = k.re - w2 * m.re, ai = k.im - w2 * m.im;
                             if (rd.DR) { const zd d = rd.DR[o]; ar -= w * d.im; ai += w * d.re; }
-                            if (l0 == 0) rowsum += hypot(ar, ai);
+                            if (its == 0 && l0 == 0) rowsum += hypot(ar, ai);
 #pragma unroll
                             for (int c = 0; c < kLc; ++c) {
                                 const zd x = xs[jj][c];
@@ -164,26 +199,27 @@ __device__ bool solve_item(const RomDesc& rd, double w, cx<T>* __restrict__ A, i
                 if (act) {
                     anorm_part = fmax(anorm_part, rowsum);
 #pragma unroll
-                    for (int c = 0; c < kLc; ++c) {
-                        if (c < nl) {
-                            const size_t e = i + (size_t)(l0 + c) * q;
-                            R[e] = {rr[c], ri[c]};
-                            rmax = fmax(rmax, hypot(rr[c], ri[c]));
-                            xmax = fmax(xmax, hypot(X[e].re, X[e].im));
-                            bmax = fmax(bmax, hypot(Bv[e].re, Bv[e].im));
-                        }
-                    }
+                    for (int c = 0; c < kLc; ++c)
+                        if (c < nl) R[i + (size_t)(l0 + c) * q] = {rr[c], ri[c]};
                 }
             }
         }
-        const double an = wg_max(anorm_part, red);
-        const double rn = wg_max(rmax, red);
-        const double xn = wg_max(xmax, red);
-        const double bn = wg_max(bmax, red);
-        const double be = rn / (an * xn + bn);
-        if (be <= tol) { conv = true; break; }
-        if (its >= max_iter || !(be < 0.5 * prev)) break;
-        prev = be;
+        if (its == 0) an = wg_max(anorm_part, red);
+        __syncthreads();
+        // per column: cm[0] = ||r_l||, cm[1] = ||x_l||, cm[2] = ||d_l|| (last correction)
+        col_max3(R, X, D, q, L, cm);
+        bool all = true;
+        double worst = 0;
+        for (int l = 0; l < L; ++l) {
+            const double be = cm[0][l] / (an * cm[1][l] + s_bn[l]);
+            const bool ok = be <= tol || cm[2][l] <= tol * cm[1][l];
+            all = all && ok;
+            if (!ok) worst = fmax(worst, be);
+        }
+        __syncthreads();
+        if (all) { conv = true; break; }
+        if (its >= max_iter || !(worst < 0.5 * prev)) break;
+        prev = worst;
         ++its;
     }
     *its_out = its;
@@ -203,6 +239,8 @@ __global__ void __launch_bounds__(kWG) k_sweep(const RomDesc* __restrict__ roms,
     __shared__ double red[8];
     __shared__ int s_item;
     __shared__ int s_perturb;
+    __shared__ double s_cm[3][kMaxLoads];   // per-column norms of the refinement
+    __shared__ double s_bn[kMaxLoads];      // ||b_l||_inf of the current item
     const int t = threadIdx.x;
     zd* Aslot = wsA + (size_t)blockIdx.x * slot_a;   // slot_a complex128 entries (fits either precision)
     int* ipiv = wsP + (size_t)blockIdx.x * 4096;
@@ -227,17 +265,24 @@ __global__ void __launch_bounds__(kWG) k_sweep(const RomDesc* __restrict__ roms,
             Bv[e] = rd.flags[l] ? zd{-w * f.im, w * f.re} : f;
         }
         __syncthreads();
-        int its = 0, fell_back = 0;
+        col_max3(Bv, Bv, Bv, q, L, s_cm);
+        for (int l = t; l < L; l += kWG) s_bn[l] = s_cm[0][l];
+        __syncthreads();
+        int its = 0, fell_back = 0, nperturbed = 0;
         cx<T>* Awork = q <= q_lds ? reinterpret_cast<cx<T>*>(dyn_lds) : reinterpret_cast<cx<T>*>(Aslot);
         bool conv = solve_item<T>(rd, w, Awork, ipiv, X, R, Bv, reinterpret_cast<cx<T>*>(Dslot),
-                                  refine != 0, max_iter, tol, reinterpret_cast<LuShared<T>&>(sh), red, &s_perturb, &its);
+                                  refine != 0, max_iter, tol, reinterpret_cast<LuShared<T>&>(sh), red, &s_perturb, &its,
+                                  s_cm, s_bn);
+        nperturbed = s_perturb;
         if (!conv && sizeof(T) == 4) {
             // complex-FP32 LU too inaccurate for refinement to converge (kappa(A_R) u_32 >~ 1):
             // redo this frequency with a complex-FP64 LU
             fell_back = 1;
             int its2 = 0;
             conv = solve_item<double>(rd, w, reinterpret_cast<cx<double>*>(Aslot), ipiv, X, R, Bv,
-                                      reinterpret_cast<cx<double>*>(Dslot), true, max_iter, tol, sh, red, &s_perturb, &its2);
+                                      reinterpret_cast<cx<double>*>(Dslot), true, max_iter, tol, sh, red, &s_perturb, &its2,
+                                      s_cm, s_bn);
+            nperturbed += s_perturb;
             its += its2;
         }
         if (rd.out_x) {
@@ -269,7 +314,7 @@ __global__ void __launch_bounds__(kWG) k_sweep(const RomDesc* __restrict__ roms,
         if (t == 0) {
             atomicMax(stats + 0, its);
             if (!conv) atomicAdd(stats + 1, 1);
-            if (s_perturb) atomicAdd(stats + 2, s_perturb);
+            if (nperturbed) atomicAdd(stats + 2, nperturbed);
             if (fell_back) atomicAdd(stats + 3, 1);
         }
         __syncthreads();
@@ -294,6 +339,7 @@ void SweepEngine::prepare(const std::vector<RomDesc>& roms, const std::vector<in
         Lmax = std::max(Lmax, r.L);
     }
     CR_REQUIRE(qmax <= 4096, CR_E_UNSUPPORTED, "reduced order above 4096");
+    CR_REQUIRE(Lmax <= 64, CR_E_UNSUPPORTED, "more than 64 load columns in a reduced model");
     nitems = (int)items.size();
     d_roms.reserve(roms.size());
     d_items.reserve(items.size());

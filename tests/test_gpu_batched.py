@@ -87,3 +87,49 @@ def test_plan_graph_replay(P, ctx, variant_roms, tune):
         torch.cuda.synchronize()
     for k, (w, r) in enumerate(variant_roms):
         assert _rel(plan.outs[k].cpu().numpy(), rom.sweep(r, w.omegas)).max() <= 1e-6
+
+
+@pytest.fixture(scope="module")
+def large_variant_roms():
+    """Oracle ROMs of four seeded plate-cavity / box variants with 16 loads and orders above 256
+    (the reduced LU's long-column panel path), truncated to their q."""
+    out = []
+    for w, q in W.batched_variants(n_rom=4, q_range=(257, 400), n_freq=41, n_loads=16, plate_cells=(12, 8, 6)):
+        s = assembly.assemble(w.mesh, w.loads, w.receivers)
+        ss = krylov.jacobi_scaled(s)
+        rb = krylov.build_basis(ss, 2 * np.pi * w.rom["shifts_hz"], w.rom["blocks"])
+        assert rb.q >= q
+        out.append((w, krylov.project(ss, rb.basis[:, :q])))
+    return out
+
+
+def test_batched_large_orders_16_loads(P, ctx, large_variant_roms):
+    """q in (256, 400] with 16 loads of very different response size per model: every result
+    within 1e-6 of the oracle's LAPACK sweep in both precisions, refinement converged per load."""
+    _flush("batched large orders, 16 loads")
+    roms = [P.Rom.from_arrays(ctx, r["KR"], r["MR"], r["FR"], r["CR"], r["flags"]) for _, r in large_variant_roms]
+    assert min(r.q for r in roms) > 256 and all(r.L == 16 for r in roms)
+    oms = np.stack([w.omegas for w, _ in large_variant_roms])
+    refs = [rom.sweep(r, w.omegas) for w, r in large_variant_roms]
+    for prec in (0, 1):
+        Ys, info = P.sweep_batched(ctx, roms, oms, prec=prec)
+        for k in range(len(roms)):
+            e = _rel(Ys[k].cpu().numpy(), refs[k])
+            assert e.max() <= 1e-6, (k, prec, e.max())
+        assert info["not_converged"] == 0 and info["n_perturbed"] == 0
+
+
+def test_batched_loads_of_different_size(P, ctx, variant_roms):
+    """Load columns scaled over twelve orders of magnitude: refinement must converge each column
+    on its own (a backward error pooled over the columns would stop on the largest ones)."""
+    _flush("batched loads of different size")
+    out, refs, roms = [], [], []
+    for w, r in variant_roms[:3]:
+        sc = 10.0 ** (-np.arange(r["FR"].shape[1]) * 4.0)
+        rr = dict(r, FR=r["FR"] * sc[None, :])
+        roms.append(P.Rom.from_arrays(ctx, rr["KR"], rr["MR"], rr["FR"], rr["CR"], rr["flags"]))
+        refs.append(rom.sweep(rr, w.omegas))
+    oms = np.stack([w.omegas for w, _ in variant_roms[:3]])
+    Ys, info = P.sweep_batched(ctx, roms, oms, prec=1)
+    for k in range(len(roms)):
+        assert _rel(Ys[k].cpu().numpy(), refs[k]).max() <= 1e-6, k
