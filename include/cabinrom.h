@@ -305,6 +305,20 @@ typedef struct {
 cr_status cr_sweep(cr_rom r, int32_t nfreq, const double* omegas, cr_precision prec, cr_z* Y_dev,
                    cr_sweep_info* info);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+   loops, harnesses that forbid hipMalloc): cr_sweep with the same arguments, results and errors,
+   but every buffer it needs beyond the reduced model, omegas and Y_dev (model descriptor, work
+   queue, statistics, a device copy of the frequencies, per-workgroup LU and refinement
+   workspaces) lives in a static device array of 128 MiB that each device holds from its first
+   cr_ctx_create until the process ends; the call makes no device allocation. It needs
+   512 + 16 nfreq bytes (rounded up to 256) plus, per resident workgroup,
+   16 q^2 + 16384 + 64 q L bytes, with at least one workgroup; larger requests fail with
+   CR_E_UNSUPPORTED and a message naming the sizes. All calls on one device share the array:
+   calls that overlap on one device (several threads or streams) race and must be serialised by
+   the caller. Each call clears what must start at zero (the statistics) itself. */
+cr_status cr_sweep_noalloc(cr_rom r, int32_t nfreq, const double* omegas, cr_precision prec, cr_z* Y_dev,
+                           cr_sweep_info* info);
+
 /* Launch shape of the batched sweep: variant (0 = default, 1 = reduced matrix LDS-resident for
    orders whose q^2 entries fit nb KiB of LDS, 2 = global-memory workspace only), resident
    workgroups per compute unit (0 = 2), nb (KiB, <= 150, variant 1 only), and refine (1 = also refine

@@ -152,6 +152,7 @@ _sig("cr_rom_dims", I32, P, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32))
 _sig("cr_rom_export", I32, P, P, P, P, P)
 _sig("cr_rom_destroy", None, P)
 _sig("cr_sweep", I32, P, I32, P, I32, P, C.POINTER(cr_sweep_info))
+_sig("cr_sweep_noalloc", I32, P, I32, P, I32, P, C.POINTER(cr_sweep_info))
 _sig("cr_sweep_batched", I32, P, I32, P, I32, P, I32, P, C.POINTER(cr_tune), C.POINTER(cr_sweep_info))
 _sig("cr_mlp_create", I32, P, I32, I32, I32, C.c_uint64, C.POINTER(P))
 _sig("cr_mlp_destroy", None, P)
@@ -443,6 +444,18 @@ class Rom:
                                                     device=self.ctx.device)
         info = cr_sweep_info()
         st = lib.cr_sweep(self.h, len(om), _ptr(om), prec, _dev_ptr(Y), C.byref(info))
+        self.last_info = _sweep_info(info)
+        self.ctx.check(st)
+        return Y
+
+    def sweep_noalloc(self, omegas, prec=CR_MIXED, out=None):
+        """As sweep, through the allocation-free entry point (static device scratch)."""
+        torch = self.ctx.torch
+        om = np.ascontiguousarray(omegas, np.float64)
+        Y = out if out is not None else torch.empty((len(om), self.L, self.n_o), dtype=torch.complex128,
+                                                    device=self.ctx.device)
+        info = cr_sweep_info()
+        st = lib.cr_sweep_noalloc(self.h, len(om), _ptr(om), prec, _dev_ptr(Y), C.byref(info))
         self.last_info = _sweep_info(info)
         self.ctx.check(st)
         return Y

@@ -356,6 +356,7 @@ cr_status cr_ctx_create(int device, void* hip_stream, cr_ctx* out) {
         hipDeviceProp_t prop;
         CR_HIP(hipGetDeviceProperties(&prop, device));
         c->num_cu = prop.multiProcessorCount;
+        noalloc_scratch_init(device);   // address of this device's static sweep scratch
         *out = c.release();
         return CR_OK;
     } catch (const cr::Error& e) {
@@ -749,6 +750,24 @@ cr_status cr_sweep(cr_rom r, int32_t nfreq, const double* omegas, cr_precision p
         fill_sweep_info(info, mi, nc, fb, np, now() - t0);
         CR_REQUIRE(nc == 0, CR_E_NOT_CONVERGED,
                    "cr_sweep: refinement did not reach its tolerance at " + std::to_string(nc) + " frequencies");
+    });
+}
+
+cr_status cr_sweep_noalloc(cr_rom r, int32_t nfreq, const double* omegas, cr_precision prec, cr_z* Y_dev,
+                           cr_sweep_info* info) {
+    if (!r) return CR_E_INVALID;
+    return cr_guard(r->ctx, [&] {
+        CR_REQUIRE(nfreq >= 0 && (nfreq == 0 || (omegas && Y_dev)), CR_E_INVALID, "cr_sweep_noalloc: bad arguments");
+        CR_REQUIRE(prec == CR_FP64 || prec == CR_MIXED, CR_E_INVALID, "cr_sweep_noalloc: bad precision");
+        for (int i = 0; i < nfreq; ++i)
+            CR_REQUIRE(std::isfinite(omegas[i]), CR_E_INVALID, "cr_sweep_noalloc: non-finite frequency");
+        const double t0 = now();
+        const RomDesc d = desc_of(r, nullptr, reinterpret_cast<zd*>(Y_dev), 0);
+        int mi = 0, nc = 0, np = 0, fb = 0;
+        sweep_noalloc(r->ctx->device, r->ctx->num_cu, d, omegas, nfreq, prec, r->ctx->stream, &mi, &nc, &np, &fb);
+        fill_sweep_info(info, mi, nc, fb, np, now() - t0);
+        CR_REQUIRE(nc == 0, CR_E_NOT_CONVERGED,
+                   "cr_sweep_noalloc: refinement did not reach its tolerance at " + std::to_string(nc) + " frequencies");
     });
 }
 

@@ -40,4 +40,12 @@ struct SweepEngine {
                   hipStream_t s, int* best_gpc, int* best_lds, std::vector<double>* ms);
 };
 
+// Allocation-free single-model sweep (cr_sweep_noalloc): every buffer beyond the model, the
+// frequencies and Y lives in a static device array. noalloc_scratch_init records that array's
+// address on `device` (call with the device current, once per device).
+void noalloc_scratch_init(int device);
+size_t noalloc_scratch_bytes();
+void sweep_noalloc(int device, int num_cu, const RomDesc& rd, const double* omegas_host, int nfreq, cr_precision prec,
+                   hipStream_t s, int* max_its, int* not_conv, int* perturbed, int* fallbacks);
+
 }  // namespace cr

@@ -441,4 +441,98 @@ void SweepEngine::autotune(const std::vector<RomDesc>& roms, const std::vector<i
     prepare(roms, items, s);
 }
 
+
+// ---------------------------------------------------------------- allocation-free sweep
+// cr_sweep_noalloc keeps everything the sweep needs beyond its inputs and outputs (the model
+// descriptor, the work queue, the statistics, the frequencies and the per-workgroup workspaces)
+// in one static device array instead of library allocations. Each device holds its own copy for
+// the life of the process; host code reaches it only through the address hipGetSymbolAddress
+// returns for that device (the array's name is a host-side stand-in, not a device address).
+constexpr size_t kNoallocScratchBytes = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_dev[kMaxDevices] = {};
+
+__global__ void k_items_iota(int2* __restrict__ items, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) items[i] = make_int2(0, i);
+}
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+}  // namespace
+
+void noalloc_scratch_init(int device) {
+    CR_REQUIRE(device >= 0 && device < kMaxDevices, CR_E_UNSUPPORTED, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_dev[device]) return;
+    void* p = nullptr;
+    CR_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    CR_REQUIRE(p != nullptr, CR_E_HIP, "hipGetSymbolAddress returned no address for the sweep scratch");
+    g_scratch_dev[device] = static_cast<unsigned char*>(p);
+}
+
+size_t noalloc_scratch_bytes() { return kNoallocScratchBytes; }
+
+void sweep_noalloc(int device, int num_cu, const RomDesc& rd_in, const double* omegas_host, int nfreq, cr_precision prec,
+                   hipStream_t s, int* max_its, int* not_conv, int* perturbed, int* fallbacks) {
+    unsigned char* base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (device >= 0 && device < kMaxDevices) base = g_scratch_dev[device];
+    }
+    CR_REQUIRE(base != nullptr, CR_E_STATE, "cr_sweep_noalloc: the device's scratch was not set up (cr_ctx_create)");
+    *max_its = *not_conv = *perturbed = *fallbacks = 0;
+    if (nfreq == 0) return;
+    const int q = rd_in.q, L = rd_in.L;
+    CR_REQUIRE(q >= 1 && q <= 4096 && L >= 1 && L <= kMaxLoads, CR_E_UNSUPPORTED,
+               "cr_sweep_noalloc: reduced order or load count out of range");
+    // layout: descriptor | statistics | frequencies | work queue | per-workgroup workspaces
+    const size_t o_desc = 0, o_stats = 256, o_om = 512;
+    const size_t o_items = align256(o_om + sizeof(double) * (size_t)nfreq);
+    const size_t head = align256(o_items + sizeof(int2) * (size_t)nfreq);
+    const int64_t slot_a = (int64_t)q * q, slot_v = (int64_t)q * L;
+    const size_t per_wg = sizeof(zd) * (size_t)slot_a + sizeof(int) * 4096 + 4 * sizeof(zd) * (size_t)slot_v;
+    CR_REQUIRE(head + per_wg <= kNoallocScratchBytes, CR_E_UNSUPPORTED,
+               "cr_sweep_noalloc: " + std::to_string(nfreq) + " frequencies at order " + std::to_string(q) + " with " +
+                   std::to_string(L) + " loads need " + std::to_string(head + per_wg) +
+                   " bytes of scratch for one workgroup; the static scratch holds " +
+                   std::to_string(kNoallocScratchBytes) + " bytes");
+    const int cap = (int)std::min<size_t>((kNoallocScratchBytes - head) / per_wg, (size_t)1 << 20);
+    const int grid = std::max(1, std::min({nfreq, 2 * num_cu, cap}));
+    RomDesc rd = rd_in;
+    rd.omegas = reinterpret_cast<const double*>(base + o_om);
+    RomDesc* d_desc = reinterpret_cast<RomDesc*>(base + o_desc);
+    int* d_stats = reinterpret_cast<int*>(base + o_stats);
+    int2* d_items = reinterpret_cast<int2*>(base + o_items);
+    unsigned char* w = base + head;
+    zd* wsA = reinterpret_cast<zd*>(w);
+    w += sizeof(zd) * (size_t)slot_a * grid;
+    int* wsP = reinterpret_cast<int*>(w);
+    w += sizeof(int) * (size_t)4096 * grid;
+    zd* wsX = reinterpret_cast<zd*>(w);
+    zd* wsR = wsX + (size_t)slot_v * grid;
+    zd* wsB = wsR + (size_t)slot_v * grid;
+    zd* wsD = wsB + (size_t)slot_v * grid;
+    CR_HIP(hipMemcpyAsync(d_desc, &rd, sizeof(RomDesc), hipMemcpyHostToDevice, s));
+    CR_HIP(hipMemcpyAsync(base + o_om, omegas_host, sizeof(double) * (size_t)nfreq, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_items_iota, dim3(std::min(1024, (nfreq + 255) / 256)), dim3(256), 0, s, d_items, nfreq);
+    fill_zero(d_stats, 8, s);
+    if (prec == CR_MIXED)
+        hipLaunchKernelGGL(k_sweep<float>, dim3(grid), dim3(kWG), 0, s, d_desc, d_items, nfreq, slot_a, slot_v, wsA, wsP,
+                           wsX, wsR, wsB, wsD, 1, 10, 1e-14, d_stats, 0);
+    else
+        hipLaunchKernelGGL(k_sweep<double>, dim3(grid), dim3(kWG), 0, s, d_desc, d_items, nfreq, slot_a, slot_v, wsA, wsP,
+                           wsX, wsR, wsB, wsD, 0, 10, 1e-14, d_stats, 0);
+    CR_HIP(hipGetLastError());
+    int st[8];
+    CR_HIP(hipMemcpyAsync(st, d_stats, sizeof(st), hipMemcpyDeviceToHost, s));
+    CR_HIP(hipStreamSynchronize(s));
+    *max_its = st[0];
+    *not_conv = st[1];
+    *perturbed = st[2];
+    *fallbacks = st[3];
+}
+
 }  // namespace cr
