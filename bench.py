@@ -1,20 +1,28 @@
 """Benchmark of the rational-Arnoldi FRF path on one MI355X.
 
-One step = the whole hot path on the coupled plate-cavity model (7,595 DoF: 24x16x12 air box
-closed by a clamped 2 mm aluminium plate, unit point force, 50 receivers): greedy expansion
-points (multifrontal LU at each point, shifted solves with FP64 refinement, CGS2 basis growth,
-incremental Galerkin projection, residual estimate at 256 candidates), then the reduced sweep
-over 1000 frequencies (10-400 Hz) with receiver pressures. The assembled, Jacobi-scaled system
-and its symbolic analysis are resident on the device before timing starts.
+Headline: the fuselage segment (529,306 DoF: cylinder R 1.4 m, L 4 m, 2 mm aluminium skin as one
+hex8 layer with five 60 mm ring frames, air on an O-grid; 16 unit-amplitude random-phase skin
+pressures; 50 receivers; 2000 frequencies 20-300 Hz). One step is the whole hot path: greedy
+expansion points (64 Krylov vectors per point, at most 32 points, tolerance 1e-6 on the relative
+residual at 256 candidates): multifrontal complex-FP64 LU at every point, 16-right-hand-side
+shifted solves with FP64 refinement, CGS2 basis growth, incremental Galerkin projection,
+candidate residuals; then the reduced sweep over the 2000 frequencies with receiver pressures.
+The assembled, Jacobi-scaled system and its symbolic analysis are resident on the device before
+timing starts.
 
-Two configurations are timed: "fp64" (complex-FP64 factorisation, reduced LU in FP64) and
-"mixed" (complex-FP32 factorisation refined in FP64, refactored in FP64 at an expansion point
-where refinement stalls; reduced LU in complex FP32 refined in FP64). The faster one whose FRF
-matches the FP64 oracle within 1e-6 is the headline.
+value = (frequencies x load cases) per second of the whole step (ROM build + sweep), credited
+only when the accuracy check passes: the FP64 oracle (NumPy/SciPy on the host, its own assembly)
+certifies the reduced model of the timed step (random-probe checks of V^H K V and V^H M V,
+orthonormality, F_R and C_R recomputed) and sweeps it with LAPACK at a seeded sample of the
+frequencies; every sampled result must lie within 1e-6 of the GPU's. Without the check the line
+carries "accuracy": "unchecked" and value 0.
 
-value = (frequencies x load cases) per second of the whole step (ROM build + sweep).
+Further sections (extra keys, not the headline): the plate-cavity (7,595 DoF, FP64 and mixed
+precision, full oracle comparison), the rigid box (plain FP64 full solves at 481 frequencies
+against the 4 x 10 rational-Arnoldi model), and the batched sweep of 256 reduced models with
+FP64 oracle spot checks.
 
-Usage: python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--no-cpu-baseline]
+Usage: python bench.py [--gpus 1] [--steps 1] [--warmup 1] [--no-cpu-baseline] [--only SECTION]
 """
 from __future__ import annotations
 
@@ -33,6 +41,11 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
 MEASURED = {}   # achievable peaks from the library's probes (copy kernel, MFMA loop), filled by main
+METRIC = "FRF freq x load-cases/sec at rel err <=1e-6 vs FP64 oracle; ROM build time (s)"
+
+
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def _measure_peaks(ctx, P):
@@ -40,9 +53,8 @@ def _measure_peaks(ctx, P):
     MEASURED["hbm_gbs"] = ctx.probe_copy(256 << 20, 10)
     MEASURED["fp64_mfma_tflops"] = ctx.probe_mfma(P.CR_FP64)
     MEASURED["fp32_mfma_tflops"] = ctx.probe_mfma(P.CR_MIXED)
-    print(f"[bench] achievable peaks: copy {MEASURED['hbm_gbs']:.0f} GB/s, MFMA FP64 "
-          f"{MEASURED['fp64_mfma_tflops']:.1f} TFLOP/s, MFMA FP32 {MEASURED['fp32_mfma_tflops']:.1f} TFLOP/s",
-          file=sys.stderr, flush=True)
+    _log(f"achievable peaks: copy {MEASURED['hbm_gbs']:.0f} GB/s, MFMA FP64 {MEASURED['fp64_mfma_tflops']:.1f} "
+         f"TFLOP/s, MFMA FP32 {MEASURED['fp32_mfma_tflops']:.1f} TFLOP/s")
 
 
 def _with_measured(r):
@@ -59,69 +71,51 @@ def _with_measured(r):
 def _args():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", choices=["fp64", "mixed", "fuselage", "batched"], default=None,
-                    help="time one configuration only (fuselage / batched: only that section, for profiling)")
-    ap.add_argument("--no-batched", action="store_true", help="skip the batched-sweep measurement")
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle leg (CPU baseline and accuracy check); the line is then unchecked")
+    ap.add_argument("--only", choices=["fuselage", "plate_cavity", "box", "batched"], default=None,
+                    help="run one section only (the headline line is printed only with fuselage)")
+    ap.add_argument("--no-extras", action="store_true", help="headline section only")
+    ap.add_argument("--fuselage-shifts", type=int, default=32, help="greedy expansion-point cap on the fuselage")
     ap.add_argument("--batched-roms", type=int, default=256)
-    ap.add_argument("--no-fuselage", action="store_true", help="skip the 529k-DoF fuselage measurement")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 256 MiB device to device 5 times (calibrates HBM byte counters)")
-    ap.add_argument("--fuselage-shifts", type=int, default=6, help="greedy expansion-point cap on the fuselage")
     return ap.parse_args()
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_plate_cavity.txt")
-TRAFFIC_SOURCES = ["paper_2310_04734_amd/csrc/factor.hip", "paper_2310_04734_amd/csrc/dense.cuh",
-                   "paper_2310_04734_amd/csrc/gemm.cuh"]
-
-
-def _measured_traffic(kernel, elt):
-    """HBM bytes per dispatch of a front kernel from the committed counter summary (FETCH_SIZE and
-    WRITE_SIZE scaled by a plain copy of known size), or None when the summary is missing or the
-    kernel sources changed since the counters were taken."""
-    import hashlib
+def _host():
+    from threadpoolctl import threadpool_info
+    threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    model = ""
     try:
-        lines = open(TRAFFIC_FILE).read().splitlines()
+        model = next((ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo") if ln.startswith("model name")), "")
     except OSError:
-        return None
-    h = hashlib.sha256()
-    for p in TRAFFIC_SOURCES:
-        h.update(open(os.path.join(ROOT, p), "rb").read())
-    kv = dict(ln.split(" = ", 1) for ln in lines if " = " in ln and not ln.startswith("#"))
-    if kv.get("source_sha256_16") != h.hexdigest()[:16]:
-        return None
-    full = f"k_{kernel}<{'double' if elt == 16 else 'float'}>"
-    for ln in lines:
-        if ln.startswith(full + " "):
-            for tok in ln.split():
-                if tok.startswith("bytes_per_dispatch="):
-                    return float(tok.split("=", 1)[1])
-    return None
+        pass
+    return int(threads), {"cpu_model": model, "nproc": os.cpu_count()}
 
 
 def _roofline(name, launches, ms, an, n_fact, n_solves, elt):
     """Achieved rate of one kernel from the algorithmic work its launches did."""
-    if name in ("front_fwd", "front_bwd"):
+    if name in ("front_fwd", "front_bwd", "front_fwd_huge", "front_bwd_huge"):
         # each direction reads its triangle of every front once per solve: half the factor
         byts = 0.5 * an["factor_entries"] * elt * n_solves
         ach = byts / (ms * 1e-3) / 1e9
         return _with_measured({"kernel": name, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": ach / PEAK_HBM_GBS, "traffic": _measured_traffic(name, elt),
-                "work_per_launch": f"{0.5 * an['factor_entries'] * elt / an['n_levels']:.4g} B "
-                                   f"(factor triangle / tree levels)",
-                "launches": launches, "avg_launch_us": 1e3 * ms / launches})
+                               "frac": ach / PEAK_HBM_GBS, "traffic": None, "launches": launches,
+                               "avg_launch_us": 1e3 * ms / launches,
+                               "work": "half the factor entries x element size per solve"})
     if name == "front_gemm":
         # trailing GEMMs of the large fronts on the matrix cores: exact flops from the analysis
         flops = an["gemm_flops"] * n_fact
         peak = PEAK_FP32_TFLOPS if elt == 8 else PEAK_FP64_TFLOPS
         ach = flops / (ms * 1e-3) / 1e12
-        return _with_measured({"kernel": name, "bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
-                "frac": ach / peak, "traffic": None, "launches": launches, "avg_launch_us": 1e3 * ms / launches,
-                "work_per_launch": f"{an['gemm_flops'] * n_fact / launches:.4g} flop (8 (m - K1)^2 (K1 - K0) "
-                                   f"per 128-column block of every large front)"})
+        return _with_measured({"kernel": "front_gemm", "bound": "mfma", "achieved": ach, "peak": peak,
+                               "unit": "TFLOP/s", "frac": ach / peak, "traffic": None, "launches": launches,
+                               "avg_launch_us": 1e3 * ms / launches,
+                               "work_per_launch": f"{an['gemm_flops'] * n_fact / launches:.4g} flop (8 (m - K1)^2 "
+                                                  f"(K1 - K0) per 128-column block of every large front)"})
     if name in ("front_factor", "front_panel", "front_colstrip", "front_rowstrip"):
         flops = an["factor_flops"] * n_fact
         peak = PEAK_FP32_TFLOPS if elt == 8 else PEAK_FP64_TFLOPS
@@ -133,73 +127,61 @@ def _roofline(name, launches, ms, an, n_fact, n_solves, elt):
             "traffic": None, "launches": launches, "avg_launch_us": 1e3 * ms / launches}
 
 
-def bench_batched(P, W, ctx, steps, n_rom=256, n_freq=4000):
-    """Batched persistent sweep: n_rom reduced models of uneven order (q ~ U{40..400}) built by the
-    library from seeded box / plate-cavity variants (16 loads each), swept at n_freq frequencies in
-    one launch; autotuned shape, graph replay. Accuracy: complex-FP32 + FP64 refinement against the
-    library's own FP64 sweep of the same models (the oracle pins the kernel on smaller models in the
-    tests)."""
-    import torch
+# ------------------------------------------------------------------------------------------- fuselage
+def _certify_fuselage(w, B, R, Y, n_sample=32, n_probe=4):
+    """The oracle leg of the headline: certify the GPU's reduced model of the fuselage with the
+    oracle's own FP64 assembly, then sweep it with LAPACK at a seeded sample of frequencies.
+
+    The oracle cannot factor this model in bench time (SuperLU, single-threaded, ~2e13 flop per
+    expansion point), so instead of building its own basis it checks the GPU's: with V exported,
+    V^H K V Z and V^H M V Z for n_probe random complex probes Z against K_R Z, M_R Z (a wrong
+    entry anywhere in K_R shows in a random probe), V^H V Z against Z, and F_R = V^H F, C_R = S V
+    at the receivers recomputed outright. The oracle's sweep then runs on the certified model."""
+    import workloads as W
+    from oracle import assembly, krylov, rom
     t0 = time.perf_counter()
-    roms, oms, qs = [], [], []
-    sys_cache = {}
-    for w, q in W.batched_variants(n_rom=n_rom, n_freq=n_freq):
-        g = P.assemble(ctx, w.mesh, w.loads, w.receivers)
-        g.analyse()
-        B = g.basis(2 * np.pi * w.rom["shifts_hz"], w.rom["blocks"], prec=P.CR_FP64)
-        R = B.project()
-        if R.q > q:   # keep the first q columns of the basis (leading blocks of the projection)
-            e = R.export()
-            R = P.Rom.from_arrays(ctx, e["KR"][:q, :q], e["MR"][:q, :q], e["FR"][:q], e["CR"][:, :q],
-                                  np.ones(R.L, np.int32) if w.loads[0].kind == 0 else np.zeros(R.L, np.int32))
-        roms.append(R)
-        oms.append(w.omegas)
-        qs.append(R.q)
-        del B, g
-    t_build = time.perf_counter() - t0
-    oms = np.stack(oms)
-    qs = np.array(qs)
-    flops = float(np.sum((8.0 / 3.0) * qs.astype(float) ** 3 + 8.0 * qs.astype(float) ** 2 * 16 * 2) * n_freq)
-    plan = P.SweepPlan(ctx, roms, oms, prec=P.CR_MIXED)
-    ref = P.SweepPlan(ctx, roms, oms, prec=P.CR_FP64, tune={"variant": 2, "grid_per_cu": 2, "nb": 0, "refine": 1})
-    ref.execute()
-    plan.execute()
-    torch.cuda.synchronize()
-    ctx.profile(True)
+    s = assembly.assemble(w.mesh, w.loads, w.receivers)
+    ss = krylov.jacobi_scaled(s)
+    t_asm = time.perf_counter() - t0
+    V = B.V().cpu().numpy()
+    e = R.export()
+    q = V.shape[1]
+    rng = W.SplitMix64(2310047340 * 1000 + 901)
+    u = rng.uniforms(2 * q * n_probe)
+    Z = (u[:q * n_probe] - 0.5).reshape(q, n_probe) + 1j * (u[q * n_probe:] - 0.5).reshape(q, n_probe)
+    VZ = V @ Z
+    Vh = V.conj().T
+    chk = {}
+    for name, A, Ar in (("K_R", ss["K"], e["KR"]), ("M_R", ss["M"], e["MR"])):
+        ref = Vh @ (A @ VZ)
+        chk[f"{name}_probe_rel_err"] = float(np.linalg.norm(Ar @ Z - ref) / np.linalg.norm(ref))
+    chk["orthonormality_probe"] = float(np.linalg.norm(Vh @ VZ - Z) / np.linalg.norm(Z))
+    FR = Vh @ ss["F"]
+    chk["F_R_rel_err"] = float(np.linalg.norm(e["FR"] - FR) / np.linalg.norm(FR))
+    recv = ss["recv"]
+    CR = ss["scale"][recv][:, None] * V[recv, :]
+    chk["C_R_rel_err"] = float(np.linalg.norm(e["CR"] - CR) / np.linalg.norm(CR))
+    del V, Vh, VZ
+    idx = np.sort(W.SplitMix64(2310047340 * 1000 + 902).sample(np.arange(len(w.omegas)), n_sample))
+    ro = dict(KR=e["KR"], MR=e["MR"], FR=FR, CR=CR, flags=np.asarray(ss["flags"]))
     ts = time.perf_counter()
-    infos = [plan.execute() for _ in range(steps)]
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - ts
-    prof = ctx.profile_read()
-    ctx.profile(False)
-    err, above, tot = 0.0, 0, 0
-    for Y, Yr in zip(plan.outs, ref.outs):
-        d = torch.linalg.vector_norm(Y - Yr, dim=2) / torch.linalg.vector_norm(Yr, dim=2)
-        err = max(err, float(d.max()))
-        above += int((d > 1e-6).sum())
-        tot += d.numel()
-    n_res = int(sum(r.L for r in roms)) * n_freq
-    ms = prof.get("sweep_graph", (steps, 1e3 * wall))[1] / steps
-    ach = flops / (ms * 1e-3) / 1e12
-    return {"workload": f"{n_rom} reduced models (box / plate-cavity variants), q in [{qs.min()}, {qs.max()}], "
-                        f"{n_freq} freqs x 16 loads", "results": n_res, "ms_per_sweep": 1e3 * wall / steps,
-            "results_per_s": n_res * steps / wall, "rom_build_s_total": t_build,
-            "max_rel_err_vs_gpu_fp64_refined": err, "results_above_1e-6": above, "results_compared": tot,
-            "not_converged": infos[-1]["not_converged"],
-            "fp64_fallbacks": infos[-1]["fp64_fallbacks"], "tuning": plan.tuning(),
-            "roofline": {"kernel": "k_sweep (graph)", "bound": "alu", "achieved": ach, "peak": PEAK_FP32_TFLOPS,
-                         "unit": "TFLOP/s", "frac": ach / PEAK_FP32_TFLOPS,
-                         "work": "(8/3) q^3 + 2 x 8 q^2 L flop per (model, frequency), LU + one solve and one "
-                                 "refinement step"}}
+    Yo = rom.sweep(ro, w.omegas[idx])
+    t_sweep = time.perf_counter() - ts
+    err = rom.relative_error(Y.cpu().numpy()[idx], Yo)
+    ok = (max(chk.values()) <= 1e-12) and float(err.max()) <= 1e-6
+    threads, host = _host()
+    chk.update({"max_rel_err_sampled": float(err.max()), "results_compared": int(err.size),
+                "sampled_frequencies_hz": [float(f) for f in w.freqs_hz[idx][:8]] + ["..."],
+                "status": "pass" if ok else "fail", "oracle_assembly_s": t_asm})
+    cpu = {"value": err.size / t_sweep, "unit": "FRF results/s", "cores": threads, "kind": "oracle", "host": host,
+           "sample": f"online phase only: LAPACK zgesv sweep of the certified reduced model (q={q}) at {n_sample} "
+                     f"seeded frequencies x {e['FR'].shape[1]} loads in {t_sweep:.2f} s; the oracle's offline phase "
+                     f"at 529k DoF (SuperLU, single-threaded, ~2e13 flop per expansion point) does not fit a "
+                     f"bounded sample"}
+    return chk, cpu
 
 
-def bench_fuselage(P, W, ctx, max_shifts, n_check=3):
-    """Fuselage segment (529,306 DoF, 16 skin-pressure loads, 2000 frequencies 20-300 Hz): greedy
-    ROM build capped at max_shifts expansion points of 4 blocks, projection, sweep; one warm-up and
-    one timed step, complex FP64 factorisations (complex-FP32 refinement stalls on the thin skin).
-    The oracle cannot factor this model in bench time; the reduced outputs are checked instead
-    against full-order FP64 solves at n_check sampled frequencies (backward error 1e-14 certified
-    by the library's own FP64 residual), and the greedy's final maximum residual is reported."""
+def bench_fuselage(P, W, ctx, steps, warmup, max_shifts, oracle):
     import torch
     t0 = time.perf_counter()
     w = W.fuselage_workload()
@@ -209,10 +191,10 @@ def bench_fuselage(P, W, ctx, max_shifts, n_check=3):
     an = g.analyse()
     t_an = time.perf_counter() - t0
     rp = w.rom
+    n_results = len(w.omegas) * g.L
     Y = torch.empty((len(w.omegas), g.L, g.n_o), dtype=torch.complex128, device=ctx.device)
-    print(f"[bench] fuselage n={g.n} L={g.L} fronts={an['n_fronts']} max_front={an['max_front']} "
-          f"factor_flops={an['factor_flops']:.3g} (assembly {t_asm:.1f} s, analysis {t_an:.1f} s)",
-          file=sys.stderr, flush=True)
+    _log(f"fuselage n={g.n} L={g.L} fronts={an['n_fronts']} max_front={an['max_front']} "
+         f"factor_flops={an['factor_flops']:.3g} (assembly {t_asm:.1f} s, analysis {t_an:.1f} s)")
 
     def step():
         ts = time.perf_counter()
@@ -224,49 +206,285 @@ def bench_fuselage(P, W, ctx, max_shifts, n_check=3):
         torch.cuda.synchronize()
         return B, R, tb, time.perf_counter() - ts
 
-    step()
+    wprof = {}
+    if warmup > 0:
+        ctx.profile(True)
+    for k in range(warmup):
+        B = R = None
+        B, R, tb, tt = step()
+        _log(f"fuselage warm-up {k}: {tt:.2f} s (build {tb:.2f} s, q={B.q}, points={len(B.trace['shift_idx'])}, "
+             f"max residual {B.trace['max_res'][-1]:.2e})")
+        del B, R
+    if warmup > 0:
+        wprof = ctx.profile_read()
+        ctx.profile(False)
+    dom = max(wprof, key=lambda k: wprof[k][1]) if wprof else "front_gemm"
+    ctx.profile_select([dom])
     ctx.profile(True)
-    B, R, tb, tt = step()
+    torch.cuda.synchronize()
+    builds, times = [], []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        B = R = None   # release the previous step's basis before the next one is built
+        B, R, tb, tt = step()
+        builds.append(tb)
+        times.append(tt)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
     prof = ctx.profile_read()
     ctx.profile(False)
+    ctx.profile_select(None)
+    n_fact = (len(B.trace["shift_idx"]) + B.info["fp64_refactorizations"]) * steps
+    n_solves = 0
+    roof = _roofline(dom, prof[dom][0], prof[dom][1], an, n_fact, n_solves, 16) if dom in prof else None
+    _log(f"fuselage: {wall / steps:.2f} s/step (build {np.median(builds):.2f} s, q={B.q}, "
+         f"points={len(B.trace['shift_idx'])}, max residual {B.trace['max_res'][-1]:.2e}), dominant {dom}")
+    out = {
+        "value_measured": n_results * steps / wall,
+        "ms_per_step": 1e3 * wall / steps,
+        "rom_build_s": float(np.median(builds)),
+        "sweep_s": float(np.median(times) - np.median(builds)),
+        "rom_q": B.q,
+        "expansion_points": len(B.trace["shift_idx"]),
+        "greedy_max_residual_per_point": [float(x) for x in B.trace["max_res"]],
+        "greedy_converged": bool(B.trace["max_res"][-1] <= rp["tol"]),
+        "shifted_solves_max_backward_error": B.info["max_backward_error"],
+        "assembly_s": t_asm, "analysis_s": t_an,
+        "factor_entries": an["factor_entries"], "factor_flops": an["factor_flops"], "gemm_flops": an["gemm_flops"],
+        "roofline": roof,
+        "kernels_ms_per_step": {kk: round(v[1] / max(warmup, 1), 3) for kk, v in
+                                sorted(wprof.items(), key=lambda kv: -kv[1][1])},
+        "n_results": n_results,
+    }
+    if oracle:
+        chk, cpu = _certify_fuselage(w, B, R, Y)
+        out["accuracy"] = chk
+        out["cpu_baseline"] = cpu
+        _log(f"fuselage oracle check: {chk['status']}, sampled max rel err {chk['max_rel_err_sampled']:.2e}, "
+             f"probes K {chk['K_R_probe_rel_err']:.1e} M {chk['M_R_probe_rel_err']:.1e}")
+    else:
+        out["accuracy"] = {"status": "unchecked"}
+        out["cpu_baseline"] = None
+    return out
+
+
+# ------------------------------------------------------------------------------------------- plate-cavity
+def bench_plate_cavity(P, W, ctx, steps, warmup, oracle):
+    """Plate-cavity (7,595 DoF, one point force, 1000 frequencies 10-400 Hz), greedy 10 blocks per
+    point to 1e-6: the whole step in FP64 and in mixed precision, each against the oracle's own
+    greedy, projection and sweep."""
+    import torch
+    w = W.plate_cavity_workload()
+    rp = w.rom
+    g = P.assemble(ctx, w.mesh, w.loads, w.receivers)
+    an = g.analyse()
     n_results = len(w.omegas) * g.L
-    print(f"[bench] fuselage: step {tt:.2f} s (ROM build {tb:.2f} s, q={B.q}, "
-          f"{len(B.trace['shift_idx'])} points, max residual {B.trace['max_res'][-1]:.2e})", file=sys.stderr, flush=True)
-    # reduced outputs against certified full-order solves at sampled frequencies
+
+    def step(prec, Y):
+        t0 = time.perf_counter()
+        B = g.basis_greedy(rp["band_hz"], rp["n_cand"], rp["blocks"], rp["tol"], rp["max_shifts"], prec=prec)
+        R = B.project()
+        t1 = time.perf_counter()
+        R.sweep(w.omegas, prec=prec, out=Y)
+        return B, R, t1 - t0
+
+    runs = {}
+    for name, prec in (("fp64", P.CR_FP64), ("mixed", P.CR_MIXED)):
+        Y = torch.empty((len(w.omegas), g.L, g.n_o), dtype=torch.complex128, device=ctx.device)
+        ctx.profile(True)
+        for _ in range(warmup):
+            step(prec, Y)
+        torch.cuda.synchronize()
+        wprof = ctx.profile_read()
+        ctx.profile(False)
+        builds = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            B, R, tb = step(prec, Y)
+            builds.append(tb)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ts = time.perf_counter()
+        for _ in range(steps):
+            R.sweep(w.omegas, prec=prec, out=Y)
+        torch.cuda.synchronize()
+        runs[name] = dict(Y=Y, wall=wall, builds=builds, B=B, sweep_rate=n_results * steps / (time.perf_counter() - ts),
+                          sweep_info=R.last_info, wprof=wprof)
+        _log(f"plate_cavity {name}: {1e3 * wall / steps:.2f} ms/step, q={B.q}, "
+             f"shifts={[int(i) for i in B.trace['shift_idx']]}, fp64 refactorizations={B.info['fp64_refactorizations']}")
+    cpu = None
+    if oracle:
+        from oracle import assembly, greedy, rom
+        tc = time.perf_counter()
+        s = assembly.assemble(w.mesh, w.loads, w.receivers)
+        go = greedy.greedy(s, rp["band_hz"], rp["n_cand"], rp["blocks"], rp["tol"], rp["max_shifts"])
+        Yo = rom.sweep(go["rom"], w.omegas)
+        tcpu = time.perf_counter() - tc
+        for r in runs.values():
+            r["err"] = float(rom.relative_error(r["Y"].cpu().numpy(), Yo).max())
+        threads, host = _host()
+        cpu = {"value": n_results / tcpu, "unit": "FRF results/s", "cores": threads, "kind": "oracle", "host": host,
+               "sample": f"the full step once (assembly + greedy with {len(go['shift_idx'])} expansion points + "
+                         f"1000-frequency sweep) in {tcpu:.2f} s; SuperLU single-threaded"}
+    return {
+        "workload": "plate_cavity: 1.2x0.8x0.6 m air box 24x16x12 hex8 + 2 mm clamped Al plate 24x16x1 hex8, "
+                    "n=7595, 1 point-force load, 50 receivers, 1000 freqs 10-400 Hz, greedy 10 blocks/point tol 1e-6",
+        "n_levels": an["n_levels"], "factor_flops": an["factor_flops"],
+        "variants": {k: {"ms_per_step": 1e3 * r["wall"] / steps, "results_per_s": n_results * steps / r["wall"],
+                         "rom_build_s": float(np.median(r["builds"])), "rom_q": r["B"].q,
+                         "sweep_only_results_per_s": r["sweep_rate"],
+                         "max_rel_err_vs_oracle": r.get("err"),
+                         "accuracy": ("unchecked" if r.get("err") is None else
+                                      ("pass" if r["err"] <= 1e-6 else "fail")),
+                         "fp64_refactorizations": r["B"].info["fp64_refactorizations"],
+                         "sweep_fp64_fallbacks": r["sweep_info"].get("fp64_fallbacks"),
+                         "kernels_ms_per_step": {kk: round(v[1] / max(warmup, 1), 3) for kk, v in
+                                                 sorted(r["wprof"].items(), key=lambda kv: -kv[1][1])[:10]}}
+                     for k, r in runs.items()},
+        "cpu_baseline": cpu,
+    }
+
+
+# ------------------------------------------------------------------------------------------- box
+def bench_box(P, W, ctx, oracle):
+    """Rigid box (528 DoF, one volume-velocity source, 481 frequencies 20-500 Hz): the plain method
+    (complex-FP64 factorisation and solve at every frequency on the GPU) against the rational
+    Arnoldi model with 4 fixed points x 10 vectors (basis, projection, sweep)."""
+    import torch
+    w = W.box()
+    g = P.assemble(ctx, w.mesh, w.loads, w.receivers)
+    g.analyse()
     e = g.export(matrices=False)
     F = torch.from_numpy(e["F"]).to(ctx.device)
     recv = torch.from_numpy(e["recv"]).to(ctx.device)
-    oms = 2 * np.pi * np.linspace(rp["band_hz"][0], rp["band_hz"][1], n_check + 2)[1:-1]
-    Yr = R.sweep(oms, prec=P.CR_FP64).cpu().numpy()
-    errs = []
-    for k, om in enumerate(oms):
-        fac = g.factor(om, P.CR_FP64)
-        scal = torch.tensor([(1j * om) ** int(fl) for fl in e["flags"]], dtype=torch.complex128, device=ctx.device)
-        X = fac.solve(F * scal[None, :])
-        yf = X[recv, :].t().cpu().numpy()           # L x n_o
-        errs.append(float((np.linalg.norm(Yr[k] - yf, axis=1) / np.linalg.norm(yf, axis=1)).max()))
-        del fac
-    n_fact = len(B.trace["shift_idx"]) + B.info["fp64_refactorizations"]
-    gemm = _roofline("front_gemm", prof["front_gemm"][0], prof["front_gemm"][1], an, n_fact, 0, 16) \
-        if "front_gemm" in prof else None
-    return {
-        "workload": "fuselage segment R 1.4 m, L 4 m, 2 mm Al skin hex layer, 5 frames 60 mm deep, air O-grid: "
-                    f"n={g.n} (94,176 u + 435,130 p), 16 random-phase skin pressures, 50 receivers, 2000 freqs "
-                    f"20-300 Hz; greedy 4 blocks/point capped at {max_shifts} points on 256 candidates; FP64",
-        "results": n_results,
-        "step_s": tt,
-        "results_per_s": n_results / tt,
-        "rom_build_s": tb,
-        "sweep_s": tt - tb,
-        "rom_q": B.q,
-        "expansion_points": len(B.trace["shift_idx"]),
-        "max_residual_at_candidates": float(B.trace["max_res"][-1]),
-        "rel_err_vs_full_fp64_solves": {f"{om / (2 * np.pi):.1f} Hz": e_ for om, e_ in zip(oms, errs)},
-        "assembly_s": t_asm, "analysis_s": t_an,
-        "factor_entries": an["factor_entries"], "factor_flops": an["factor_flops"], "gemm_flops": an["gemm_flops"],
-        "frontal_gemm": gemm,
-        "kernels_ms": {kk: round(v[1], 3) for kk, v in sorted(prof.items(), key=lambda kv: -kv[1][1])},
-    }
+    nf = len(w.omegas)
+    Yf = torch.empty((nf, g.L, g.n_o), dtype=torch.complex128, device=ctx.device)
+
+    def full():
+        for i, om in enumerate(w.omegas):
+            fac = g.factor(om, P.CR_FP64)
+            scal = torch.tensor([(1j * om) ** int(fl) for fl in e["flags"]], dtype=torch.complex128, device=ctx.device)
+            X = fac.solve(F * scal[None, :])
+            Yf[i] = X[recv, :].t()
+        torch.cuda.synchronize()
+
+    def reduced():
+        B = g.basis(2 * np.pi * w.rom["shifts_hz"], w.rom["blocks"], prec=P.CR_FP64)
+        Y = B.project().sweep(w.omegas, prec=P.CR_FP64)
+        torch.cuda.synchronize()
+        return Y
+
+    full()
+    reduced()
+    t0 = time.perf_counter()
+    full()
+    t_full = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    Y = reduced()
+    t_rom = time.perf_counter() - t0
+    eps = float((torch.linalg.vector_norm(Y - Yf, dim=2) / torch.linalg.vector_norm(Yf, dim=2)).max())
+    out = {"workload": "box: 1.0x0.7x0.5 m air, 10x7x5 hex8, 528 DoF, 1 volume-velocity source, 50 receivers, "
+                       "481 freqs 20-500 Hz; ROM: 80/200/320/440 Hz x 10 vectors",
+           "full_fp64_solves_s": t_full, "full_results_per_s": nf * g.L / t_full,
+           "rom_step_s": t_rom, "rom_results_per_s": nf * g.L / t_rom, "speedup_rom_vs_full": t_full / t_rom,
+           "rom_eps_max_vs_gpu_full_solves": eps}
+    if oracle:
+        from oracle import assembly, krylov, rom, solve
+        s = assembly.assemble(w.mesh, w.loads, w.receivers)
+        ss = krylov.jacobi_scaled(s)
+        rb = krylov.build_basis(ss, 2 * np.pi * w.rom["shifts_hz"], w.rom["blocks"])
+        Yo = rom.sweep(krylov.project(ss, rb.basis), w.omegas)
+        tc = time.perf_counter()
+        Yfo = solve.full_frf(s, w.omegas)
+        tcpu = time.perf_counter() - tc
+        out["rom_max_rel_err_vs_oracle"] = float(rom.relative_error(Y.cpu().numpy(), Yo).max())
+        out["full_max_rel_err_vs_oracle"] = float(rom.relative_error(Yf.cpu().numpy(), Yfo).max())
+        out["oracle_full_solves_s"] = tcpu
+    return out
+
+
+# ------------------------------------------------------------------------------------------- batched
+def bench_batched(P, W, ctx, steps, n_rom=256, n_freq=4000, oracle=True, n_spot=4096):
+    """Batched persistent sweep: n_rom reduced models of uneven order (q ~ U{40..400}) built by the
+    library from seeded box / plate-cavity variants (16 loads each), swept at n_freq frequencies in
+    one launch; autotuned shape, graph replay, complex-FP32 LU + FP64 refinement (mixed) and
+    complex-FP64 LU (plain). Accuracy: the oracle's LAPACK sweep of the same reduced models at
+    n_spot seeded (model, frequency) pairs."""
+    import torch
+    t0 = time.perf_counter()
+    roms, oms, qs, flags = [], [], [], []
+    for w, q in W.batched_variants(n_rom=n_rom, n_freq=n_freq):
+        g = P.assemble(ctx, w.mesh, w.loads, w.receivers)
+        g.analyse()
+        B = g.basis(2 * np.pi * w.rom["shifts_hz"], w.rom["blocks"], prec=P.CR_FP64)
+        R = B.project()
+        fl = np.ones(R.L, np.int32) if w.loads[0].kind == 0 else np.zeros(R.L, np.int32)
+        if R.q > q:   # keep the first q columns of the basis (leading blocks of the projection)
+            e = R.export()
+            R = P.Rom.from_arrays(ctx, e["KR"][:q, :q], e["MR"][:q, :q], e["FR"][:q], e["CR"][:, :q], fl)
+        roms.append(R)
+        oms.append(w.omegas)
+        qs.append(R.q)
+        flags.append(fl)
+        del B, g
+    t_build = time.perf_counter() - t0
+    oms = np.stack(oms)
+    qs = np.array(qs)
+    _log(f"batched: {n_rom} models built in {t_build:.1f} s, q in [{qs.min()}, {qs.max()}]")
+    flops = float(np.sum((8.0 / 3.0) * qs.astype(float) ** 3 + 8.0 * qs.astype(float) ** 2 * 16 * 2) * n_freq)
+    n_res = int(sum(r.L for r in roms)) * n_freq
+    res = {}
+    for name, prec in (("mixed", P.CR_MIXED), ("fp64", P.CR_FP64)):
+        plan = P.SweepPlan(ctx, roms, oms, prec=prec)
+        plan.execute()
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        ts = time.perf_counter()
+        infos = [plan.execute() for _ in range(steps)]
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - ts
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        ms = prof.get("sweep_graph", (steps, 1e3 * wall))[1] / steps
+        ach = flops / (ms * 1e-3) / 1e12
+        res[name] = dict(plan=plan, wall=wall, info=infos[-1], ms=ms, ach=ach)
+        _log(f"batched {name}: {1e3 * wall / steps:.1f} ms/sweep, {n_res * steps / wall:.3g} results/s, "
+             f"fallbacks {infos[-1]['fp64_fallbacks']}")
+    out = {"workload": f"{n_rom} reduced models (box / plate-cavity variants), q in [{qs.min()}, {qs.max()}], "
+                       f"{n_freq} freqs x 16 loads", "results": n_res, "rom_build_s_total": t_build}
+    for name, r in res.items():
+        out[name] = {"ms_per_sweep": 1e3 * r["wall"] / steps, "results_per_s": n_res * steps / r["wall"],
+                     "not_converged": r["info"]["not_converged"], "fp64_fallbacks": r["info"]["fp64_fallbacks"],
+                     "n_perturbed": r["info"]["n_perturbed"], "tuning": r["plan"].tuning(),
+                     "roofline": {"kernel": "k_sweep (graph)", "bound": "alu", "achieved": r["ach"],
+                                  "peak": PEAK_FP32_TFLOPS if name == "mixed" else PEAK_FP64_TFLOPS,
+                                  "unit": "TFLOP/s",
+                                  "frac": r["ach"] / (PEAK_FP32_TFLOPS if name == "mixed" else PEAK_FP64_TFLOPS),
+                                  "work": "(8/3) q^3 + 2 x 8 q^2 L flop per (model, frequency): LU, one solve and "
+                                          "one refinement step"}}
+    if oracle:
+        from oracle import rom
+        rng = W.SplitMix64(2310047340 * 1000 + 4 * 1000 + 9)
+        pick = rng.sample(np.arange(n_rom * n_freq), n_spot)
+        exp = [r.export() for r in roms]
+        for name, r in res.items():
+            worst, above = 0.0, 0
+            outs = [y.cpu().numpy() for y in r["plan"].outs]
+            for m in range(n_rom):
+                sel = np.sort(pick[pick // n_freq == m] % n_freq)
+                if len(sel) == 0:
+                    continue
+                e = exp[m]
+                Yo = rom.sweep(dict(KR=e["KR"], MR=e["MR"], FR=e["FR"], CR=e["CR"], flags=flags[m]), oms[m][sel])
+                err = rom.relative_error(outs[m][sel], Yo)
+                worst = max(worst, float(err.max()))
+                above += int((err > 1e-6).sum())
+            out[name]["spot_check"] = {"pairs": n_spot, "results": n_spot * 16, "max_rel_err_vs_oracle": worst,
+                                       "results_above_1e-6": above, "status": "pass" if above == 0 else "fail"}
+    else:
+        for name in res:
+            out[name]["spot_check"] = {"status": "unchecked"}
+    return out
 
 
 def copy_probe():
@@ -297,150 +515,51 @@ def main():
     import workloads as W
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    if a.only == "fuselage":
-        print(json.dumps({"fuselage": bench_fuselage(P, W, P.Context(0), a.fuselage_shifts)}))
+    ctx = P.Context(0)
+    oracle = not a.no_cpu_baseline
+    if a.only == "plate_cavity":
+        print(json.dumps({"plate_cavity": bench_plate_cavity(P, W, ctx, max(a.steps, 5), max(a.warmup, 1), oracle)}))
+        return
+    if a.only == "box":
+        print(json.dumps({"box": bench_box(P, W, ctx, oracle)}))
         return
     if a.only == "batched":
-        print(json.dumps({"batched_sweep": bench_batched(P, W, P.Context(0), max(1, a.steps), n_rom=a.batched_roms)}))
+        print(json.dumps({"batched_sweep": bench_batched(P, W, ctx, max(1, a.steps), n_rom=a.batched_roms,
+                                                         oracle=oracle)}))
         return
-    w = W.plate_cavity_workload()
-    rp = w.rom
-    ctx = P.Context(0)
     _measure_peaks(ctx, P)
-    sysg = P.assemble(ctx, w.mesh, w.loads, w.receivers)
-    an = sysg.analyse()
-    n_results = len(w.omegas) * sysg.L
-    print(f"[bench] plate_cavity n={sysg.n} fronts={an['n_fronts']} levels={an['n_levels']} "
-          f"max_front={an['max_front']} factor_flops={an['factor_flops']:.3g}", file=sys.stderr, flush=True)
-
-    def step(prec, Y):
-        t0 = time.perf_counter()
-        B = sysg.basis_greedy(rp["band_hz"], rp["n_cand"], rp["blocks"], rp["tol"], rp["max_shifts"], prec=prec)
-        R = B.project()
-        t1 = time.perf_counter()
-        R.sweep(w.omegas, prec=prec, out=Y)
-        return B, R, t1 - t0
-
-    runs = {}
-    for name, prec in (("fp64", P.CR_FP64), ("mixed", P.CR_MIXED)):
-        if a.only and a.only != name:
-            continue
-        Y = torch.empty((len(w.omegas), sysg.L, sysg.n_o), dtype=torch.complex128, device=ctx.device)
-        # warm-up steps with every hot kernel timed (per-kernel breakdown, and they name the
-        # dominant kernel); the timed steps then carry events only around the kernels the
-        # roofline reports, so that the instrumentation stays out of the measured step
-        wprof = {}
-        if a.warmup > 0:
-            ctx.profile(True)
-        for _ in range(a.warmup):
-            step(prec, Y)
-        torch.cuda.synchronize()
-        if a.warmup > 0:
-            wprof = ctx.profile_read()
-            ctx.profile(False)
-            ctx.profile_select([max(wprof, key=lambda k: wprof[k][1]), "front_gemm"])
-        ctx.profile(True)
-        builds = []
-        t0 = time.perf_counter()
-        for _ in range(a.steps):
-            B, R, tb = step(prec, Y)
-            builds.append(tb)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        prof = ctx.profile_read()
-        ctx.profile(False)
-        ctx.profile_select(None)
-        ts = time.perf_counter()
-        for _ in range(a.steps):
-            R.sweep(w.omegas, prec=prec, out=Y)
-        torch.cuda.synchronize()
-        sweep_rate = n_results * a.steps / (time.perf_counter() - ts)
-        runs[name] = dict(prec=prec, Y=Y, wall=wall, builds=builds, prof=prof, wprof=wprof, B=B, sweep_rate=sweep_rate,
-                          sweep_info=R.last_info)
-        print(f"[bench] {name}: {1e3 * wall / a.steps:.2f} ms/step, build {1e3 * np.median(builds):.2f} ms, "
-              f"q={B.q}, shifts={[int(i) for i in B.trace['shift_idx']]}, "
-              f"fp64 refactorizations={B.info['fp64_refactorizations']}", file=sys.stderr, flush=True)
-
-    # accuracy against the FP64 oracle, which is also the CPU baseline
-    cpu = None
-    if not a.no_cpu_baseline:
-        from threadpoolctl import threadpool_info
-
-        from oracle import assembly, greedy, rom
-        tc = time.perf_counter()
-        s = assembly.assemble(w.mesh, w.loads, w.receivers)
-        go = greedy.greedy(s, rp["band_hz"], rp["n_cand"], rp["blocks"], rp["tol"], rp["max_shifts"])
-        Yo = rom.sweep(go["rom"], w.omegas)
-        tcpu = time.perf_counter() - tc
-        for r in runs.values():
-            r["err"] = float(rom.relative_error(r["Y"].cpu().numpy(), Yo).max())
-        threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
-        model = ""
-        try:
-            model = next((ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo") if ln.startswith("model name")), "")
-        except OSError:
-            pass
-        cpu = {"value": n_results / tcpu, "unit": "FRF results/s", "cores": int(threads), "kind": "oracle",
-               "host": {"cpu_model": model, "nproc": os.cpu_count()},
-               "sample": f"the full step once (assembly + greedy with {len(go['shift_idx'])} expansion points "
-                         f"+ 1000-frequency sweep) in {tcpu:.2f} s; SuperLU single-threaded, "
-                         f"BLAS with {threads} threads"}
-        print(f"[bench] oracle {tcpu:.2f} s, shifts={list(map(int, go['shift_idx']))}, "
-              + ", ".join(f"{k} max rel err {r['err']:.2e}" for k, r in runs.items()), file=sys.stderr, flush=True)
-
-    ok = {k: r for k, r in runs.items() if r.get("err") is None or r["err"] <= 1e-6}
-    head_name = min(ok, key=lambda k: ok[k]["wall"])
-    h = runs[head_name]
-    prof = h["prof"]
-    total = {k: v[1] for k, v in prof.items()}
-    dom = max(total, key=total.get)
-    n_fact = (len(h["B"].trace["shift_idx"]) + h["B"].info["fp64_refactorizations"]) * a.steps
-    # one launch per tree level and direction per solve (either direction's kernel may be the timed one)
-    n_solves = ((prof.get("front_fwd") or prof.get("front_bwd") or (0, 0))[0] // max(an["n_levels"], 1))
-    elt = 16 if h["prec"] == P.CR_FP64 else 8
-    roof = _roofline(dom, prof[dom][0], prof[dom][1], an, n_fact, n_solves, elt)
-    gemm = _roofline("front_gemm", prof["front_gemm"][0], prof["front_gemm"][1], an, n_fact, n_solves, elt) \
-        if "front_gemm" in prof else None
-    ms_per_step = 1e3 * h["wall"] / a.steps
+    f = bench_fuselage(P, W, ctx, a.steps, a.warmup, a.fuselage_shifts, oracle)
+    passed = f["accuracy"].get("status") == "pass"
     out = {
-        "metric": "FRF freq x load-cases/sec at rel err <=1e-6 vs FP64 oracle; ROM build time (s)",
-        "value": n_results * a.steps / h["wall"],
+        "metric": METRIC,
+        "value": f["value_measured"] if passed else 0.0,
         "unit": "FRF results/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": f["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c128" if h["prec"] == P.CR_FP64 else "c64 LU + c128 refinement",
+        "dtype": "c128",
         "data": "synthetic",
-        "config": {"workload": "plate_cavity: 1.2x0.8x0.6 m air box 24x16x12 hex8 + 2 mm clamped Al plate "
-                               "24x16x1 hex8, n=7595, 1 point-force load, 50 receivers, 1000 freqs 10-400 Hz, "
-                               "greedy 10 blocks/point tol 1e-6 on 256 candidates",
-                   "variant": head_name, "global_batch": n_results, "parallelism": "1 GPU"},
-        "rom_build_s": float(np.median(h["builds"])),
-        "rom_q": h["B"].q,
-        "expansion_points": len(h["B"].trace["shift_idx"]),
-        "max_rel_err_vs_oracle": h.get("err"),
-        "variants": {k: {"ms_per_step": 1e3 * r["wall"] / a.steps, "rom_build_s": float(np.median(r["builds"])),
-                         "sweep_only_results_per_s": r["sweep_rate"], "max_rel_err_vs_oracle": r.get("err"),
-                         "fp64_refactorizations": r["B"].info["fp64_refactorizations"],
-                         "sweep_fp64_fallbacks": r["sweep_info"].get("fp64_fallbacks"),
-                         "kernels_ms_per_step": {kk: round(v[1] / max(a.warmup, 1), 3) for kk, v in
-                                                 sorted((r["wprof"] or r["prof"]).items(), key=lambda kv: -kv[1][1])},
-                         "kernels_timed_in_measured_steps": sorted(r["prof"])}
-                     for k, r in runs.items()},
-        "roofline": roof,
-        "frontal_gemm": gemm,
-        "cpu_baseline": cpu,
+        "config": {"workload": "fuselage segment R 1.4 m, L 4 m, 2 mm Al skin hex layer, 5 frames 60 mm deep, air "
+                               "O-grid: n=529306 (94,176 u + 435,130 p), 16 random-phase skin pressures, 50 receivers, "
+                               f"2000 freqs 20-300 Hz; greedy 64 vectors/point, <= {a.fuselage_shifts} points, tol 1e-6 "
+                               "on 256 candidates; complex-FP64 factorisations",
+                   "global_batch": f["n_results"], "parallelism": "1 GPU"},
+        "accuracy": f["accuracy"],
+        "value_if_unchecked": None if passed else f["value_measured"],
+        "rom_build_s": f["rom_build_s"],
+        "roofline": f["roofline"],
+        "cpu_baseline": f["cpu_baseline"],
+        "fuselage": {k: v for k, v in f.items() if k not in ("accuracy", "roofline", "cpu_baseline", "value_measured",
+                                                             "ms_per_step", "rom_build_s", "n_results")},
     }
-    if not a.no_batched:
-        out["batched_sweep"] = bench_batched(P, W, ctx, max(2, a.steps // 3), n_rom=a.batched_roms)
-        print(f"[bench] batched: {out['batched_sweep']['ms_per_sweep']:.1f} ms/sweep, "
-              f"{out['batched_sweep']['results_per_s']:.3g} results/s", file=sys.stderr, flush=True)
-    if not a.no_fuselage:
-        out["fuselage"] = bench_fuselage(P, W, ctx, a.fuselage_shifts)
+    if not a.no_extras and a.only is None:
+        out["plate_cavity"] = bench_plate_cavity(P, W, ctx, 10, 2, oracle)
+        out["box"] = bench_box(P, W, ctx, oracle)
+        out["batched_sweep"] = bench_batched(P, W, ctx, 2, n_rom=a.batched_roms, oracle=oracle)
     print(json.dumps(out))
 
 
