@@ -48,7 +48,8 @@ typedef enum {
     CR_E_INVALID = -1,        /* bad argument (null pointer, size out of range, wrong state) */
     CR_E_OOM = -2,            /* device or host allocation failed */
     CR_E_HIP = -3,            /* a HIP runtime call failed */
-    CR_E_SINGULAR = -4,       /* a pivot was exactly zero and could not be perturbed */
+    CR_E_SINGULAR = -4,       /* the shifted matrix has no nonzero entry (or a non-finite one), so
+                                 no pivot can be perturbed */
     CR_E_NOT_CONVERGED = -5,  /* iterative refinement did not reach its tolerance */
     CR_E_UNSUPPORTED = -6,    /* input outside what this build supports */
     CR_E_STATE = -7           /* call order violated (e.g. factor before analyse) */
@@ -70,8 +71,20 @@ typedef struct cr_mlp_s* cr_mlp;
 
 /* ---------------------------------------------------------------- context ---------------- */
 
-/* Bind to HIP device `device` and stream `hip_stream` (a hipStream_t; NULL = the null stream). */
-cr_status cr_ctx_create(int device, void* hip_stream, cr_ctx* out);
+/* Device-memory hook: every device buffer the library allocates for work on a context comes
+   from alloc(bytes, user) and goes back through free(p, user) (the pointer alloc returned, on the
+   same device; free may be called after the call that allocated returned, e.g. from a
+   *_destroy). alloc returning NULL makes the call fail with CR_E_OOM. The struct is copied. */
+typedef struct {
+    void* (*alloc)(size_t bytes, void* user);
+    void (*free)(void* p, void* user);
+    void* user;
+} cr_allocator;
+
+/* Bind to HIP device `device` and stream `hip_stream` (a hipStream_t; NULL = the null stream).
+   allocator: NULL = hipMalloc / hipFree. Also sets up the device's static sweep scratch
+   (cr_sweep_noalloc). */
+cr_status cr_ctx_create(int device, void* hip_stream, const cr_allocator* allocator, cr_ctx* out);
 void cr_ctx_destroy(cr_ctx ctx);
 /* Message of the last failed call on ctx ("" if none). Valid until the next call on ctx. */
 const char* cr_last_error(cr_ctx ctx);
@@ -106,8 +119,23 @@ enum { CR_FLUID = 0, CR_SOLID = 1 };
 enum { CR_LOAD_VOLUME_VELOCITY = 0, CR_LOAD_POINT_FORCE = 1, CR_LOAD_SKIN_PRESSURE = 2 };
 
 /* Material: fluid {rho, eta, c} with c~^2 = c^2 (1 + i eta); solid {rho, eta, E, nu} with
-   E~ = E (1 + i eta) (complex stiffness, Section 3.3 after Eq. (8)). */
-typedef struct { int32_t kind; double rho, eta, c, E, nu; } cr_material;
+   E~ = E (1 + i eta) (complex stiffness, Section 3.3 after Eq. (8)).
+   Frequency-dependent loss factor (Section 3.3, text after Eq. (8): K(w) = K^ (1 + i eta(w))):
+   with n_eta > 0, eta(f) is the piecewise-linear interpolant of (eta_f_hz[i], eta_val[i]) (f in Hz,
+   increasing; constant beyond the ends) and eta is ignored. A solid's stiffness is then kept as a
+   separate term K_m with coefficient 1 + i eta(f), a fluid's mass int N^T N as a term with
+   coefficient 1 / (c^2 (1 + i eta(f))); at most 4 such materials. Systems with such terms take
+   fixed expansion points (cr_basis_build, each point factoring A(w_j) = K(w_j) - w_j^2 M(w_j) and
+   applying M(w_j) in Eq. (10)); their reduced model keeps V^H K_m V per term and forms
+   K_R(w) = V^H K(w) V, M_R(w) = V^H M(w) V exactly at every swept frequency (the reduced system
+   after Eq. (10)). */
+typedef struct {
+    int32_t kind;
+    double rho, eta, c, E, nu;
+    int32_t n_eta;
+    const double* eta_f_hz;
+    const double* eta_val;
+} cr_material;
 
 /* hex8 mesh. coords: n_nodes x 3 (row-major); elems: n_el x 8 node ids in the order
    (-,-,-) (+,-,-) (+,+,-) (-,+,-) (-,-,+) (+,-,+) (+,+,+) (-,+,+) of natural coordinates;
@@ -155,6 +183,21 @@ cr_status cr_sys_export(cr_sys sys, int64_t* rowptr, int32_t* col, cr_z* K, cr_z
                         int32_t* flags, int64_t* recv_dofs);
 void cr_sys_destroy(cr_sys sys);
 
+/* A system given directly as matrices of the problem statement (Section 3.3, Eq. (8): (K + i w D -
+   w^2 M) x = f(w), y = C^T x), for models assembled elsewhere. CSR with 0-based int64 row pointers
+   (rowptr[n + 1]) and int32 columns; K, D, M are complex128 values on that one pattern (D may be
+   NULL: D = 0, damping carried by complex K). Duplicate entries are summed, columns need not be
+   sorted, and the pattern is completed to a structurally symmetric one with explicit zeros (the
+   multifrontal analysis needs it). F: n x L column-major, flags[L] (load column l is
+   F[:, l] (i w)^flags[l]), recv_dofs[n_o]: the DoFs y reads (C = unit columns). coords: n x 3
+   DoF positions for the nested dissection, or NULL (graph bisection by breadth-first levels).
+   Every diagonal entry of K must be nonzero (the library scales by |K_ii|^{-1/2}). All arrays are
+   host arrays, copied. n_u of the result is 0. Errors: CR_E_INVALID for out-of-range indices,
+   non-finite values, a zero diagonal or n, L, n_o out of range. */
+cr_status cr_sys_import_csr(cr_ctx ctx, int64_t n, const int64_t* rowptr, const int32_t* col, const cr_z* K,
+                            const cr_z* D, const cr_z* M, int32_t L, const cr_z* F, const int32_t* flags,
+                            int32_t n_o, const int64_t* recv_dofs, const double* coords, cr_sys* out);
+
 /* ---------------------------------------------------------------- analysis --------------- */
 
 typedef struct {
@@ -183,10 +226,13 @@ cr_status cr_set_front_classes(cr_sys sys, int32_t big_m, int32_t huge_m);
 
 typedef struct { int32_t n_perturbed; double seconds; } cr_factor_info;
 
-/* Multifrontal LU of A = K - w^2 M at omega (rad/s), in complex FP64 (CR_FP64) or complex
-   FP32 (CR_MIXED), partial pivoting inside each front's fully-summed block, tiny pivots
-   perturbed (counted in info). The factor is kept on the device and reused by every solve at
-   this expansion point (Section 3.3, offline phase). Requires cr_analyse. */
+/* Multifrontal LU of A(w) = K + i w D - w^2 M (Section 3.3, Eq. (8); D = 0 unless the system was
+   imported with one) at omega (rad/s), in complex FP64 (CR_FP64) or complex FP32 (CR_MIXED),
+   partial pivoting inside each front's fully-summed block; pivots below 1e-8 max|A| (FP64) or
+   3e-4 max|A| (FP32) are perturbed to that size (counted in info) and repaired by the FP64
+   refinement of cr_solve. The factor is kept on the device and reused by every solve at this
+   expansion point (Section 3.3, offline phase). Requires cr_analyse. CR_E_SINGULAR when A(w) has
+   no nonzero entry. */
 cr_status cr_factor(cr_sys sys, double omega, cr_precision prec, cr_fact* out, cr_factor_info* info);
 void cr_fact_destroy(cr_fact f);
 
@@ -199,6 +245,41 @@ typedef struct { int32_t iterations; double backward_error; } cr_solve_info;
    corrections do not reach tol (X then holds the last iterate). */
 cr_status cr_solve(cr_fact f, int32_t nrhs, const cr_z* B_dev, cr_z* X_dev, const cr_ir_opts* opts,
                    cr_solve_info* info);
+
+/* ---------------------------------------------------------------- domain decomposition -- */
+
+/* Iterative shifted solves by domain decomposition (Section 3.2): GMRES with an additive Schwarz
+   preconditioner M^{-1} = sum_j R~_j^T A_j^{-1} R_j (Section 3.2) over physics-based subdomains
+   (the structure DoFs and the fluid DoFs, as the paper splits by physical domain), each grown by
+   `overlap` layers of neighbours in the graph of A; A_j = R_j A R_j^T is factored by the
+   multifrontal LU of cr_factor (only the subdomain factors are stored: sub_factor_entries against
+   the full factor's cr_analysis_info.factor_entries). restricted = 1: R~_j writes only the DoFs
+   subdomain j owned before growing (restricted additive Schwarz), 0: R~_j = R_j; overlap 0 is
+   block Jacobi. Right-preconditioned GMRES(restart) in FP64 on the Jacobi-scaled system, one
+   Krylov space per right-hand side, CGS2 Arnoldi, stop when ||b - A x|| <= tol ||b|| (scaled
+   2-norms) or after max_iter iterations. Plain systems only (CR_E_UNSUPPORTED with a damping
+   matrix or frequency-dependent materials, or without structure DoFs). */
+typedef struct cr_dd_s* cr_dd;
+typedef struct { int32_t overlap, restricted, restart, max_iter; double tol; } cr_dd_opts;
+typedef struct {
+    int32_t iterations;        /* largest over the right-hand sides                          */
+    double rel_residual;       /* largest final ||b - A x|| / ||b|| (scaled)                  */
+    int32_t n_sub;
+    int64_t sub_factor_entries;
+    double seconds;
+} cr_dd_info;
+
+/* Subdomains and their symbolic analyses (once per system). */
+cr_status cr_dd_create(cr_sys sys, const cr_dd_opts* opts, cr_dd* out);
+void cr_dd_destroy(cr_dd dd);
+/* Solve A(w) X = B (n x nrhs device arrays, leading dimension n, unscaled DoFs as cr_solve):
+   factors the subdomains at omega in sub_prec (kept for the next call at the same omega), then
+   GMRES. CR_E_NOT_CONVERGED when a column misses tol (X holds the last iterate, info filled). */
+cr_status cr_dd_solve(cr_dd dd, double omega, cr_precision sub_prec, int32_t nrhs, const cr_z* B_dev, cr_z* X_dev,
+                      cr_dd_info* info);
+/* Z = M^{-1} R in the scaled coordinates of the system (for checks of the preconditioner). */
+cr_status cr_dd_precondition(cr_dd dd, double omega, cr_precision sub_prec, int32_t nrhs, const cr_z* R_dev,
+                             cr_z* Z_dev);
 
 /* ---------------------------------------------------------------- basis / projection ----- */
 
@@ -218,7 +299,11 @@ typedef struct {
    blocks at point j (Eq. (10)): factor A_j once, X = A_j^{-1} F, then X = A_j^{-1} M Q with Q
    the latest orthonormalised block; block classical Gram-Schmidt twice (CGS2) against the basis
    in FP64, columns whose norm falls below 1e-10 of their norm before orthogonalisation are
-   dropped. The basis is orthonormal for the Jacobi-scaled system. */
+   dropped. The basis is orthonormal for the Jacobi-scaled system. For a system with a damping
+   matrix D the blocks span the second-order Krylov space of Eq. (9) instead: r_0 = A_j^{-1} F,
+   r_1 = -A_j^{-1} D_j r_0, r_i = -A_j^{-1} (D_j r_(i-1) + M r_(i-2)) with D_j = 2 i w_j M + D, built
+   by an Arnoldi process on the linearisation [u; v] -> [-A_j^{-1} (D_j u + M v); u] whose upper
+   halves are appended to the basis; cr_project then adds D_R = V^H D V. */
 cr_status cr_basis_build(cr_sys sys, int32_t nshift, const double* omegas, const int32_t* blocks,
                          cr_precision prec, cr_basis* out, cr_basis_info* info);
 
@@ -257,9 +342,49 @@ typedef struct {
    index) or, with CR_POLICY_MLP, the network's proposal unless its residual is below 0.1 max r. */
 cr_status cr_basis_build_greedy(cr_sys sys, const cr_greedy_opts* opts, cr_precision prec,
                                 cr_basis* out, cr_greedy_trace* trace, cr_basis_info* info);
+/* Local reduced models on frequency windows (l-fROMs; Section 3.3, the local-fROM paragraph and
+   its schematic figure, windows of Tab. 4) with an automated partition (the paper partitioned by
+   hand): the candidates linspace(f_lo, f_hi, n_cand) are split by bisection. A window [i0, i1] of
+   candidate indices runs the greedy of cr_basis_build_greedy on its own candidates
+   linspace(cand[i0], cand[i1], i1 - i0 + 1) with at most max_shifts expansion points; if its
+   largest candidate residual stays above tol and it holds at least 2 min_cand - 1 candidates, it
+   is split at its middle candidate (which both halves share) and both halves are built, left
+   first; otherwise the window is kept with its reduced model. */
+typedef struct {
+    double f_lo_hz, f_hi_hz;
+    int32_t n_cand;            /* <= 4096                                                    */
+    int32_t blocks;            /* Krylov blocks per expansion point                          */
+    double tol;
+    int32_t max_shifts;        /* expansion-point cap per window                             */
+    int32_t min_cand;          /* >= 2                                                       */
+    int32_t max_windows;       /* capacity of the output arrays                              */
+} cr_window_opts;
+
+typedef struct {
+    int32_t n_windows, expansion_points; /* kept windows, their expansion points             */
+    int32_t attempted_points;            /* including windows that were split                */
+    int32_t max_q, unconverged;          /* largest order; windows kept at the minimum size
+                                            with residual above tol                          */
+    double seconds;
+} cr_window_info;
+
+/* Outputs (host arrays of max_windows entries, in increasing frequency): win_cand[2 w], [2 w + 1]
+   = i0, i1; win_hi_hz[w] = cand[i1]; win_max_res[w] (may be NULL) = the window's largest
+   candidate residual; roms[w] = its reduced model (caller destroys). Errors as the greedy's;
+   CR_E_INVALID when more than max_windows windows are needed (no model is returned then). */
+cr_status cr_build_local_roms(cr_sys sys, const cr_window_opts* opts, cr_precision prec, int32_t* n_windows,
+                              int32_t* win_cand, double* win_hi_hz, double* win_max_res, cr_rom* roms,
+                              cr_window_info* info);
+
 cr_status cr_basis_dims(cr_basis b, int32_t* q);
 /* Copy the basis (n x q, complex128, scaled coordinates) to a device array with leading dim n. */
 cr_status cr_basis_copy(cr_basis b, cr_z* V_dev);
+/* Full-field recovery from reduced states (Section 3.3, the Galerkin ansatz x = V x_R behind
+   Eq. (11)): X = S V XR for ncol columns, XR_dev q x ncol (leading dimension q), X_dev n x ncol
+   (leading dimension n), both complex128 on the device; S the system's diagonal scaling, so X is
+   in the unscaled DoFs of the system. XR_dev may hold the states of cr_sweep_states for one
+   frequency (ncol = L) or for several consecutive ones (ncol = L nfreq). */
+cr_status cr_recover_field(cr_basis b, int64_t ncol, const cr_z* XR_dev, cr_z* X_dev);
 void cr_basis_destroy(cr_basis b);
 
 /* Galerkin reduced model (Eq. (11)): K_R = V^H K V, M_R = V^H M V, F_R = V^H F (the printed
@@ -304,6 +429,17 @@ typedef struct {
    still written); CR_E_UNSUPPORTED for q > 4096 or L > 64. */
 cr_status cr_sweep(cr_rom r, int32_t nfreq, const double* omegas, cr_precision prec, cr_z* Y_dev,
                    cr_sweep_info* info);
+
+/* Reduced states instead of receiver outputs: as cr_sweep, but XR_dev (nfreq x L x q complex128,
+   [w][l][k] with k fastest) receives x_R(w) for every load column, for cr_recover_field. */
+cr_status cr_sweep_states(cr_rom r, int32_t nfreq, const double* omegas, cr_precision prec, cr_z* XR_dev,
+                          cr_sweep_info* info);
+
+/* Stitched sweep of local models: frequency w goes to the first window k with w / (2 pi) <=
+   win_hi_hz[k] (the last window above the band); all windows in one persistent launch. Y_dev
+   nfreq x L x n_o as cr_sweep; models must share L and n_o. Errors as cr_sweep. */
+cr_status cr_sweep_windows(int32_t nwin, const cr_rom* roms, const double* win_hi_hz, int32_t nfreq,
+                           const double* omegas, cr_precision prec, cr_z* Y_dev, cr_sweep_info* info);
 
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
    loops, harnesses that forbid hipMalloc): cr_sweep with the same arguments, results and errors,

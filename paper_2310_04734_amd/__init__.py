@@ -47,7 +47,8 @@ c_z_p = C.c_void_p
 
 class cr_material(C.Structure):
     _fields_ = [("kind", C.c_int32), ("rho", C.c_double), ("eta", C.c_double), ("c", C.c_double),
-                ("E", C.c_double), ("nu", C.c_double)]
+                ("E", C.c_double), ("nu", C.c_double), ("n_eta", C.c_int32), ("eta_f_hz", C.c_void_p),
+                ("eta_val", C.c_void_p)]
 
 
 class cr_mesh(C.Structure):
@@ -114,6 +115,26 @@ def _sweep_info(info):
     return {k: getattr(info, k) for k, _ in cr_sweep_info._fields_}
 
 
+class cr_window_opts(C.Structure):
+    _fields_ = [("f_lo_hz", C.c_double), ("f_hi_hz", C.c_double), ("n_cand", C.c_int32), ("blocks", C.c_int32),
+                ("tol", C.c_double), ("max_shifts", C.c_int32), ("min_cand", C.c_int32), ("max_windows", C.c_int32)]
+
+
+class cr_window_info(C.Structure):
+    _fields_ = [("n_windows", C.c_int32), ("expansion_points", C.c_int32), ("attempted_points", C.c_int32),
+                ("max_q", C.c_int32), ("unconverged", C.c_int32), ("seconds", C.c_double)]
+
+
+class cr_dd_opts(C.Structure):
+    _fields_ = [("overlap", C.c_int32), ("restricted", C.c_int32), ("restart", C.c_int32), ("max_iter", C.c_int32),
+                ("tol", C.c_double)]
+
+
+class cr_dd_info(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("rel_residual", C.c_double), ("n_sub", C.c_int32),
+                ("sub_factor_entries", C.c_int64), ("seconds", C.c_double)]
+
+
 class cr_tune(C.Structure):
     _fields_ = [("variant", C.c_int32), ("grid_per_cu", C.c_int32), ("nb", C.c_int32), ("refine", C.c_int32)]
 
@@ -127,7 +148,12 @@ def _sig(name, res, *args):
 
 P = C.c_void_p
 I32, I64, D = C.c_int32, C.c_int64, C.c_double
-_sig("cr_ctx_create", I32, C.c_int, P, C.POINTER(P))
+class cr_allocator(C.Structure):
+    _fields_ = [("alloc", C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)),
+                ("free", C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)), ("user", C.c_void_p)]
+
+
+_sig("cr_ctx_create", I32, C.c_int, P, C.POINTER(cr_allocator), C.POINTER(P))
 _sig("cr_ctx_destroy", None, P)
 _sig("cr_last_error", C.c_char_p, P)
 _sig("cr_create_error", C.c_char_p)
@@ -135,6 +161,16 @@ _sig("cr_assemble", I32, P, C.POINTER(cr_mesh), P, I32, P, I32, P, I32, C.POINTE
 _sig("cr_sys_get_dims", I32, P, C.POINTER(cr_sys_dims))
 _sig("cr_sys_export", I32, P, P, P, P, P, P, P, P)
 _sig("cr_sys_destroy", None, P)
+_sig("cr_sys_import_csr", I32, P, I64, P, P, P, P, P, I32, P, P, I32, P, P, C.POINTER(P))
+_sig("cr_recover_field", I32, P, I64, P, P)
+_sig("cr_dd_create", I32, P, C.POINTER(cr_dd_opts), C.POINTER(P))
+_sig("cr_dd_destroy", None, P)
+_sig("cr_dd_solve", I32, P, D, I32, I32, P, P, C.POINTER(cr_dd_info))
+_sig("cr_dd_precondition", I32, P, D, I32, I32, P, P)
+_sig("cr_build_local_roms", I32, P, C.POINTER(cr_window_opts), I32, C.POINTER(I32), P, P, P, P,
+     C.POINTER(cr_window_info))
+_sig("cr_sweep_windows", I32, I32, P, P, I32, P, I32, P, C.POINTER(cr_sweep_info))
+_sig("cr_sweep_states", I32, P, I32, P, I32, P, C.POINTER(cr_sweep_info))
 _sig("cr_analyse", I32, P, C.POINTER(cr_analysis_info))
 _sig("cr_set_front_classes", I32, P, I32, I32)
 _sig("cr_factor", I32, P, D, I32, C.POINTER(P), C.POINTER(cr_factor_info))
@@ -183,9 +219,13 @@ def _dev_ptr(t):
 
 
 class Context:
-    """A library context bound to a HIP device and torch's current stream on it."""
+    """A library context bound to a HIP device and torch's current stream on it.
 
-    def __init__(self, device: int = 0, stream=None):
+    allocator: None (hipMalloc) or a pair of Python callables (alloc(nbytes) -> int device
+    pointer or 0, free(ptr)) that the library calls for every device buffer of this context;
+    they are kept alive by the context."""
+
+    def __init__(self, device: int = 0, stream=None, allocator=None):
         import torch
         self.torch = torch
         self.device = torch.device("cuda", device)
@@ -193,7 +233,14 @@ class Context:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream
         h = P()
-        st = lib.cr_ctx_create(device, C.c_void_p(stream.cuda_stream), C.byref(h))
+        al = None
+        if allocator is not None:
+            fa, ff = allocator
+            self._alloc_cb = cr_allocator._fields_[0][1](lambda nbytes, user: fa(int(nbytes)) or None)
+            self._free_cb = cr_allocator._fields_[1][1](lambda ptr, user: ff(int(ptr or 0)))
+            al = cr_allocator(self._alloc_cb, self._free_cb, None)
+        st = lib.cr_ctx_create(device, C.c_void_p(stream.cuda_stream), C.byref(al) if al is not None else None,
+                               C.byref(h))
         if st != 0:
             raise CabinRomError(st, lib.cr_create_error().decode())
         self.h = h
@@ -319,6 +366,23 @@ class System:
                        res_hist=hist[:k].copy(), la_cand=la_c[:k].copy(), la_res=la_r[:k].copy())
         return b
 
+    def local_roms(self, band_hz, n_cand, blocks, tol, max_shifts, min_cand=4, max_windows=64, prec: int = CR_MIXED):
+        """Local reduced models on automatically bisected frequency windows (LocalRoms)."""
+        opts = cr_window_opts(float(band_hz[0]), float(band_hz[1]), int(n_cand), int(blocks), float(tol),
+                              int(max_shifts), int(min_cand), int(max_windows))
+        nw = I32()
+        wc = np.zeros(2 * max_windows, np.int32)
+        hi = np.zeros(max_windows)
+        mr = np.zeros(max_windows)
+        hs = (P * max_windows)()
+        info = cr_window_info()
+        self.ctx.check(lib.cr_build_local_roms(self.h, C.byref(opts), prec, C.byref(nw), _ptr(wc), _ptr(hi), _ptr(mr),
+                                               hs, C.byref(info)))
+        k = nw.value
+        roms = [Rom(self.ctx, P(hs[i])) for i in range(k)]
+        return LocalRoms(self.ctx, roms, wc[:2 * k].reshape(k, 2).copy(), hi[:k].copy(), mr[:k].copy(),
+                         {f: getattr(info, f) for f, _ in cr_window_info._fields_})
+
     def __del__(self):
         if getattr(self, "h", None) and lib is not None:
             lib.cr_sys_destroy(self.h)
@@ -337,9 +401,16 @@ def assemble(ctx: Context, mesh, loads, receivers) -> System:
     m = cr_mesh(coords.shape[0], _ptr(coords), elems.shape[0], _ptr(elems), _ptr(emat), len(clamped),
                 _ptr(clamped), iface.shape[0], _ptr(iface))
     mats = (cr_material * len(mesh.materials))()
-    for i, mt in enumerate(mesh.materials):
-        mats[i] = cr_material(mt.kind, mt.rho, mt.eta, mt.c, mt.E, mt.nu)
     keep = []
+    for i, mt in enumerate(mesh.materials):
+        tab = getattr(mt, "eta_table", None)
+        if tab is not None:
+            fh = np.ascontiguousarray(tab[0], np.float64)
+            ev = np.ascontiguousarray(tab[1], np.float64)
+            keep += [fh, ev]
+            mats[i] = cr_material(mt.kind, mt.rho, mt.eta, mt.c, mt.E, mt.nu, len(fh), _ptr(fh), _ptr(ev))
+        else:
+            mats[i] = cr_material(mt.kind, mt.rho, mt.eta, mt.c, mt.E, mt.nu, 0, None, None)
     lds = (cr_load * max(len(loads), 1))()
     for i, ld in enumerate(loads):
         v = complex(ld.value)
@@ -355,6 +426,24 @@ def assemble(ctx: Context, mesh, loads, receivers) -> System:
     h = P()
     ctx.check(lib.cr_assemble(ctx.h, C.byref(m), mats, len(mesh.materials), lds, len(loads), _ptr(rec), len(rec),
                               C.byref(h)))
+    return System(ctx, h)
+
+
+def import_csr(ctx: Context, rowptr, col, K, M, F, flags, recv_dofs, D=None, coords=None) -> System:
+    """A system from CSR matrices K, M (and D) on one pattern, loads F (n x L) and receiver DoFs."""
+    rowptr = np.ascontiguousarray(rowptr, np.int64)
+    col = np.ascontiguousarray(col, np.int32)
+    K = np.ascontiguousarray(K, np.complex128)
+    M = np.ascontiguousarray(M, np.complex128)
+    Dv = np.ascontiguousarray(D, np.complex128) if D is not None else None
+    n = len(rowptr) - 1
+    F = np.asfortranarray(np.asarray(F, np.complex128).reshape(n, -1))
+    fl = np.ascontiguousarray(flags, np.int32)
+    rec = np.ascontiguousarray(recv_dofs, np.int64)
+    xyz = np.ascontiguousarray(coords, np.float64) if coords is not None else None
+    h = P()
+    ctx.check(lib.cr_sys_import_csr(ctx.h, n, _ptr(rowptr), _ptr(col), _ptr(K), _ptr(Dv), _ptr(M), F.shape[1],
+                                    F.ctypes.data_as(P), _ptr(fl), len(rec), _ptr(rec), _ptr(xyz), C.byref(h)))
     return System(ctx, h)
 
 
@@ -399,6 +488,14 @@ class Basis:
         h = P()
         self.sys.ctx.check(lib.cr_project(self.sys.h, self.h, C.byref(h)))
         return Rom(self.sys.ctx, h)
+
+    def recover(self, XR):
+        """X = S V XR: full-order fields (n x ncol, unscaled DoFs) from reduced states (q x ncol)."""
+        torch = self.sys.ctx.torch
+        XRc = XR.t().contiguous() if XR.dim() == 2 else XR.reshape(1, -1).contiguous()   # ncol x q
+        X = torch.empty((XRc.shape[0], self.sys.n), dtype=torch.complex128, device=self.sys.ctx.device)
+        self.sys.ctx.check(lib.cr_recover_field(self.h, XRc.shape[0], _dev_ptr(XRc), _dev_ptr(X)))
+        return X.t()
 
     def __del__(self):
         if getattr(self, "h", None) and lib is not None:
@@ -448,6 +545,17 @@ class Rom:
         self.ctx.check(st)
         return Y
 
+    def sweep_states(self, omegas, prec=CR_MIXED):
+        """x_R[w, l, k] complex128 device tensor (reduced states for cr_recover_field)."""
+        torch = self.ctx.torch
+        om = np.ascontiguousarray(omegas, np.float64)
+        XR = torch.empty((len(om), self.L, self.q), dtype=torch.complex128, device=self.ctx.device)
+        info = cr_sweep_info()
+        st = lib.cr_sweep_states(self.h, len(om), _ptr(om), prec, _dev_ptr(XR), C.byref(info))
+        self.last_info = _sweep_info(info)
+        self.ctx.check(st)
+        return XR
+
     def sweep_noalloc(self, omegas, prec=CR_MIXED, out=None):
         """As sweep, through the allocation-free entry point (static device scratch)."""
         torch = self.ctx.torch
@@ -464,6 +572,62 @@ class Rom:
         if getattr(self, "h", None) and lib is not None:
             lib.cr_rom_destroy(self.h)
             self.h = None
+
+
+class DomainDecomposition:
+    """GMRES with an additive Schwarz preconditioner on the structure / fluid subdomains."""
+
+    def __init__(self, sys: System, overlap=1, restricted=True, restart=100, max_iter=300, tol=1e-8):
+        self.sys = sys
+        opts = cr_dd_opts(int(overlap), int(bool(restricted)), int(restart), int(max_iter), float(tol))
+        h = P()
+        sys.ctx.check(lib.cr_dd_create(sys.h, C.byref(opts), C.byref(h)))
+        self.h = h
+        self.last_info = None
+
+    def solve(self, omega, B, prec=CR_FP64):
+        torch = self.sys.ctx.torch
+        Bc = B.t().contiguous() if B.dim() == 2 else B.reshape(1, -1).contiguous()
+        X = torch.empty_like(Bc)
+        info = cr_dd_info()
+        st = lib.cr_dd_solve(self.h, float(omega), int(prec), Bc.shape[0], _dev_ptr(Bc), _dev_ptr(X), C.byref(info))
+        self.last_info = {k: getattr(info, k) for k, _ in cr_dd_info._fields_}
+        self.sys.ctx.check(st)
+        return X.t() if B.dim() == 2 else X.reshape(-1)
+
+    def precondition(self, omega, R, prec=CR_FP64):
+        torch = self.sys.ctx.torch
+        Rc = R.t().contiguous()
+        Z = torch.empty_like(Rc)
+        self.sys.ctx.check(lib.cr_dd_precondition(self.h, float(omega), int(prec), Rc.shape[0], _dev_ptr(Rc),
+                                                  _dev_ptr(Z)))
+        return Z.t()
+
+    def __del__(self):
+        if getattr(self, "h", None) and lib is not None:
+            lib.cr_dd_destroy(self.h)
+            self.h = None
+
+
+class LocalRoms:
+    """Reduced models of frequency windows and their stitched sweep."""
+
+    def __init__(self, ctx, roms, cand, hi_hz, max_res, info):
+        self.ctx, self.roms, self.cand, self.hi_hz, self.max_res, self.info = ctx, roms, cand, hi_hz, max_res, info
+
+    def sweep(self, omegas, prec=CR_MIXED, out=None):
+        torch = self.ctx.torch
+        om = np.ascontiguousarray(omegas, np.float64)
+        r0 = self.roms[0]
+        Y = out if out is not None else torch.empty((len(om), r0.L, r0.n_o), dtype=torch.complex128,
+                                                    device=self.ctx.device)
+        hs = (P * len(self.roms))(*[r.h for r in self.roms])
+        hi = np.ascontiguousarray(self.hi_hz, np.float64)
+        info = cr_sweep_info()
+        st = lib.cr_sweep_windows(len(self.roms), hs, _ptr(hi), len(om), _ptr(om), prec, _dev_ptr(Y), C.byref(info))
+        self.last_info = _sweep_info(info)
+        self.ctx.check(st)
+        return Y
 
 
 class Mlp:

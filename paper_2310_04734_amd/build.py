@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcabinrom.so")
-SOURCES = ["api.cpp", "assemble.cpp", "analyse.cpp", "factor.hip", "linalg.hip", "sweep.hip", "probe.hip", "mlp.hip"]
+SOURCES = ["api.cpp", "assemble.cpp", "analyse.cpp", "factor.hip", "linalg.hip", "sweep.hip", "probe.hip", "mlp.hip", "dd.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",
          "-packed-fp32-ops", "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unused-result",

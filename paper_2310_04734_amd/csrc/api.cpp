@@ -22,7 +22,15 @@ void candidate_residuals(int64_t n, int q, int L, int ncand, const zd* KV, const
                          hipStream_t s);
 void copy_cols_scaled(int64_t n, const zd* src, zd* dst, double factor, hipStream_t s);
 void copy_2d(int rows, int cols, const zd* src, int64_t lds, zd* dst, int64_t ldd, hipStream_t s);
+void comb(int64_t n, int b, zd a, const zd* X, int64_t ldx, zd c, const zd* Y, int64_t ldy, zd* O, int64_t ldo,
+          hipStream_t s);
 void scale_rows(int64_t n, int nrhs, const zd* src, const double* sc, zd* dst, hipStream_t s);
+}  // namespace cr
+
+namespace cr {
+thread_local const cr_allocator* tl_alloc = nullptr;
+void lift(int64_t n, int q, int ncol, const zd* V, int64_t ldv, const zd* XR, int64_t ldr, const double* scale, zd* X,
+          int64_t ldx, hipStream_t s);
 }  // namespace cr
 
 using namespace cr;
@@ -38,13 +46,19 @@ struct cr_rom_s {
     bool has_d = false;
     DevBuf<zd> KR, MR, DR, FR, CR;
     DevBuf<int32_t> flags;
+    // frequency-dependent parts: A_R(w) gains sum_t c_t(w) TR[t] (kind 0: c = 1 + i eta(w);
+    // kind 1: c = -w^2 / (c^2 (1 + i eta(w))))
+    std::vector<TermMeta> tmeta;
+    std::vector<DevBuf<zd>> TR;
+    DevBuf<zd> tcoef;   // per-call coefficient table (nfreq x nterm)
 };
 
 struct cr_basis_s {
     cr_sys sys = nullptr;
     int q = 0, cap = 0;
-    DevBuf<zd> V, KV, MV;        // n x cap
-    DevBuf<zd> KR, MR;           // cap x cap (incremental Galerkin projection)
+    DevBuf<zd> V, KV, MV, DV;    // n x cap (DV only for a system with a damping matrix)
+    DevBuf<zd> KR, MR, DR;       // cap x cap (incremental Galerkin projection)
+    std::vector<DevBuf<zd>> TV, TR;   // per frequency-dependent term: T V (n x cap), V^H T V (cap x cap)
     std::vector<double> shifts;
     int deflated = 0;
     int ir_iterations = 0;
@@ -77,14 +91,30 @@ void ensure_capacity(cr_basis B, int need) {
     cr_sys sys = B->sys;
     hipStream_t s = sys->ctx->stream;
     const int64_t n = sys->n;
+    const bool hd = !sys->D.empty();
     int cap = std::max(need, std::max(16, 2 * B->cap));
     DevBuf<zd> V((size_t)n * cap), KV((size_t)n * cap), MV((size_t)n * cap), KR((size_t)cap * cap), MR((size_t)cap * cap);
+    DevBuf<zd> DV(hd ? (size_t)n * cap : 0), DR(hd ? (size_t)cap * cap : 0);
+    const size_t nt = sys->terms.size();
+    std::vector<DevBuf<zd>> TV(nt), TR(nt);
+    for (size_t t = 0; t < nt; ++t) {
+        TV[t].alloc((size_t)n * cap);
+        TR[t].alloc((size_t)cap * cap);
+        if (B->q > 0) {
+            copy_dev(n * B->q, B->TV[t].p, TV[t].p, s);
+            copy_2d(B->q, B->q, B->TR[t].p, B->cap, TR[t].p, cap, s);
+        }
+    }
     if (B->q > 0) {
         copy_dev(n * B->q, B->V.p, V.p, s);
         copy_dev(n * B->q, B->KV.p, KV.p, s);
         copy_dev(n * B->q, B->MV.p, MV.p, s);
         copy_2d(B->q, B->q, B->KR.p, B->cap, KR.p, cap, s);
         copy_2d(B->q, B->q, B->MR.p, B->cap, MR.p, cap, s);
+        if (hd) {
+            copy_dev(n * B->q, B->DV.p, DV.p, s);
+            copy_2d(B->q, B->q, B->DR.p, B->cap, DR.p, cap, s);
+        }
     }
     CR_HIP(hipStreamSynchronize(s));
     B->V = std::move(V);
@@ -92,6 +122,10 @@ void ensure_capacity(cr_basis B, int need) {
     B->MV = std::move(MV);
     B->KR = std::move(KR);
     B->MR = std::move(MR);
+    B->DV = std::move(DV);
+    B->DR = std::move(DR);
+    B->TV = std::move(TV);
+    B->TR = std::move(TR);
     B->cap = cap;
 }
 
@@ -117,14 +151,24 @@ void project_new(cr_basis B, int q0, int q1) {
     const int nb = q1 - q0;
     if (nb <= 0) return;
     spmm_km(sys, nb, B->V.p + n * q0, n, B->KV.p + n * q0, B->MV.p + n * q0, n, s);
+    const bool hd = !sys->D.empty();
+    if (hd) spmm_shifted(sys, sys->d_D.p, sys->d_D.p, 0.0, nb, B->V.p + n * q0, n, B->DV.p + n * q0, n, s);
     const int64_t ld = B->cap;
     // columns: R[0:q1, q0:q1] = V[:, 0:q1]^H (KV)[:, q0:q1]
     gram(n, q1, nb, B->V.p, n, B->KV.p + n * q0, n, B->KR.p + ld * q0, ld, 0, B->partial, s);
     gram(n, q1, nb, B->V.p, n, B->MV.p + n * q0, n, B->MR.p + ld * q0, ld, 0, B->partial, s);
+    if (hd) gram(n, q1, nb, B->V.p, n, B->DV.p + n * q0, n, B->DR.p + ld * q0, ld, 0, B->partial, s);
+    for (size_t t = 0; t < sys->terms.size(); ++t) {
+        const zd* T = sys->terms[t].d_vals.p;
+        spmm_shifted(sys, T, T, 0.0, nb, B->V.p + n * q0, n, B->TV[t].p + n * q0, n, s);
+        gram(n, q1, nb, B->V.p, n, B->TV[t].p + n * q0, n, B->TR[t].p + ld * q0, ld, 0, B->partial, s);
+        if (q0 > 0) gram(n, q0, nb, B->TV[t].p, n, B->V.p + n * q0, n, B->TR[t].p + q0, ld, 1, B->partial, s);
+    }
     // rows: R[q0:q1, 0:q0] = conj((KV)[:, 0:q0]^H V[:, q0:q1])^T
     if (q0 > 0) {
         gram(n, q0, nb, B->KV.p, n, B->V.p + n * q0, n, B->KR.p + q0, ld, 1, B->partial, s);
         gram(n, q0, nb, B->MV.p, n, B->V.p + n * q0, n, B->MR.p + q0, ld, 1, B->partial, s);
+        if (hd) gram(n, q0, nb, B->DV.p, n, B->V.p + n * q0, n, B->DR.p + q0, ld, 1, B->partial, s);
     }
 }
 
@@ -181,6 +225,59 @@ int orthonormalise_append(cr_basis B, zd* W, int b) {
     return q - q0;
 }
 
+// Y = M(w_j) X with the mass matrix of the factor's frequency
+void mass_apply(const Factor& fac, cr_sys sys, int b, const zd* X, int64_t ldx, zd* Y, int64_t ldy, hipStream_t s) {
+    if (fac.opMass == sys->d_M.p) spmm_m(sys, b, X, ldx, Y, ldy, s);
+    else spmm_shifted(sys, fac.opMass, fac.opMass, 0.0, b, X, ldx, Y, ldy, s);
+}
+
+// X = A_j^{-1} B for b columns with FP64 refinement; a complex-FP32 factor whose classic
+// refinement stalls (kappa(A_j) u_32 >~ 1) is refactored in complex FP64 once, which is cheaper
+// than a Krylov refinement of every one of its solves
+void shifted_solve(cr_basis B, Factor& fac, SolveWork& sw, double omega, int b, const zd* rhs, zd* X) {
+    cr_sys sys = B->sys;
+    hipStream_t s = sys->ctx->stream;
+    double berr = 0;
+    int its = solve_scaled(fac, b, rhs, X, 10, 1e-14, &berr, sw, s, false, fac.prec == CR_FP64);
+    if (!(berr <= 1e-14) && fac.prec == CR_MIXED) {
+        numeric_factor(fac, sys, omega, CR_FP64, s);
+        B->n_perturbed += fac.n_perturbed;
+        B->fp64_refactorizations++;
+        its += solve_scaled(fac, b, rhs, X, 10, 1e-14, &berr, sw, s, false);
+    }
+    B->ir_iterations += its;
+    B->max_berr = std::max(B->max_berr, berr);
+}
+
+// Orthonormalise the b columns of W (length m, leading dimension m) against Z[:, 0:nz] (block CGS2)
+// and each other (two passes per column), appending the accepted columns to Z; the deflation
+// rule of the basis. Returns the number appended.
+int orth_append_local(int64_t m, zd* Z, int& nz, zd* W, int b, cr_basis B, hipStream_t s) {
+    DevBuf<zd> H((size_t)std::max(nz + b, 1) * b), nrm(2);
+    std::vector<zd> h(1);
+    auto norm2 = [&](const zd* w) {
+        gram(m, 1, 1, w, m, w, m, nrm.p, 1, 0, B->partial, s);
+        CR_HIP(hipMemcpyAsync(h.data(), nrm.p, sizeof(zd), hipMemcpyDeviceToHost, s));
+        CR_HIP(hipStreamSynchronize(s));
+        return h[0].re;
+    };
+    const int z0 = nz;
+    for (int c = 0; c < b; ++c) {
+        zd* w = W + m * c;
+        const double before = norm2(w);
+        for (int pass = 0; pass < 2; ++pass)
+            if (nz > 0) {
+                gram(m, nz, 1, Z, m, w, m, H.p, nz, 0, B->partial, s);
+                update(m, nz, 1, Z, m, H.p, nz, w, m, s);
+            }
+        const double after = norm2(w);
+        if (!(before > 0) || !(std::sqrt(after / before) >= 1e-10)) continue;
+        copy_cols_scaled(m, w, Z + m * nz, 1.0 / std::sqrt(after), s);
+        ++nz;
+    }
+    return nz - z0;
+}
+
 // Krylov blocks at one expansion point: X = A^{-1} F~, then X = A^{-1} M~ Q (Eq. (10))
 void add_shift(cr_basis B, Factor& fac, SolveWork& sw, double omega, int blocks, cr_precision prec) {
     cr_sys sys = B->sys;
@@ -194,22 +291,68 @@ void add_shift(cr_basis B, Factor& fac, SolveWork& sw, double omega, int blocks,
     B->W.reserve((size_t)n * std::max(L, 1));
     int b = L;
     copy_dev(n * L, sys->d_F.p, B->RHS.p, s);
-    for (int blk = 0; blk < blocks && b > 0; ++blk) {
-        if (blk > 0) spmm_m(sys, b, B->V.p + n * (B->q - b), n, B->RHS.p, n, s);
-        double berr = 0;
-        int its = solve_scaled(fac, b, B->RHS.p, B->W.p, 10, 1e-14, &berr, sw, s, false, fac.prec == CR_FP64);
-        if (!(berr <= 1e-14) && fac.prec == CR_MIXED) {
-            // classic refinement of the complex-FP32 factor stalled (kappa(A_j) u_32 >~ 1): this
-            // expansion point is refactored in complex FP64 once, which is cheaper than a Krylov
-            // refinement of every one of its solves
-            numeric_factor(fac, sys, omega, CR_FP64, s);
-            B->n_perturbed += fac.n_perturbed;
-            B->fp64_refactorizations++;
-            its += solve_scaled(fac, b, B->RHS.p, B->W.p, 10, 1e-14, &berr, sw, s, false);
+    if (!sys->terms.empty()) {
+        // frequency-dependent matrices: the pencils of different expansion points differ, so the
+        // recurrence continues from this point's own vectors (orthonormalised among themselves)
+        // and each block is then appended to the basis
+        DevBuf<zd> Z((size_t)n * std::max(blocks * L, 1));
+        int nz = 0;
+        for (int blk = 0; blk < blocks && b > 0; ++blk) {
+            if (blk > 0) mass_apply(fac, sys, b, Z.p + n * (nz - b), n, B->RHS.p, n, s);
+            shifted_solve(B, fac, sw, omega, b, B->RHS.p, B->W.p);
+            const int z0 = nz;
+            b = orth_append_local(n, Z.p, nz, B->W.p, b, B, s);
+            if (b == 0) break;
+            copy_dev(n * b, Z.p + n * z0, B->W.p, s);
+            orthonormalise_append(B, B->W.p, b);
         }
-        B->ir_iterations += its;
-        B->max_berr = std::max(B->max_berr, berr);
+        return;
+    }
+    for (int blk = 0; blk < blocks && b > 0; ++blk) {
+        if (blk > 0) mass_apply(fac, sys, b, B->V.p + n * (B->q - b), n, B->RHS.p, n, s);
+        shifted_solve(B, fac, sw, omega, b, B->RHS.p, B->W.p);
         b = orthonormalise_append(B, B->W.p, b);
+    }
+}
+
+// Second-order Krylov blocks at one expansion point for a system with a damping matrix
+// (Section 3.3, Eq. (9)): with A_j = K~ + i w_j D~ - w_j^2 M~, D_j = 2 i w_j M~ + D~ and M_j = M~, the
+// space of r_0 = A_j^{-1} F~, r_1 = -A_j^{-1} D_j r_0, r_i = -A_j^{-1} (D_j r_(i-1) + M_j r_(i-2)),
+// built as an Arnoldi process on the linearisation [u; v] -> [-A_j^{-1} (M~ (2 i w_j u + v) + D~ u); u]
+// started from [r_0; 0] (the upper halves of its Krylov vectors are the r_i). The upper halves
+// of each orthonormalised block are appended to the basis with CGS2.
+void add_shift_soar(cr_basis B, Factor& fac, SolveWork& sw, double omega, int blocks, cr_precision prec) {
+    cr_sys sys = B->sys;
+    hipStream_t s = sys->ctx->stream;
+    const int64_t n = sys->n, m = 2 * n;
+    numeric_factor(fac, sys, omega, prec, s);
+    B->n_perturbed += fac.n_perturbed;
+    B->shifts.push_back(omega);
+    const int L = sys->L;
+    B->RHS.reserve((size_t)n * std::max(L, 1));
+    B->W.reserve((size_t)n * std::max(L, 1));
+    DevBuf<zd> Z((size_t)m * std::max(blocks * L, 1)), W((size_t)m * L), T((size_t)n * L), Y((size_t)n * L);
+    int nz = 0, last0 = 0, b = L;
+    for (int blk = 0; blk < blocks && b > 0; ++blk) {
+        if (blk == 0) {
+            shifted_solve(B, fac, sw, omega, b, sys->d_F.p, B->W.p);
+            fill_zero(W.p, m * b, s);
+        } else {
+            const zd* U = Z.p + m * last0;       // upper halves of the latest block (leading dimension m)
+            const zd* Vv = U + n;                // lower halves
+            comb(n, b, zd{0.0, 2.0 * omega}, U, m, zd{1.0, 0.0}, Vv, m, T.p, n, s);      // t = 2 i w u + v
+            mass_apply(fac, sys, b, T.p, n, Y.p, n, s);                                  // M~ t
+            spmm_shifted(sys, sys->d_D.p, sys->d_D.p, 0.0, b, U, m, B->RHS.p, n, s);     // D~ u
+            comb(n, b, zd{-1.0, 0.0}, Y.p, n, zd{-1.0, 0.0}, B->RHS.p, n, B->RHS.p, n, s);
+            shifted_solve(B, fac, sw, omega, b, B->RHS.p, B->W.p);
+            copy_2d((int)n, b, U, m, W.p + n, m, s);                                     // lower half = u
+        }
+        copy_2d((int)n, b, B->W.p, n, W.p, m, s);                                        // upper half
+        last0 = nz;
+        b = orth_append_local(m, Z.p, nz, W.p, b, B, s);
+        if (b == 0) break;
+        copy_2d((int)n, b, Z.p + m * last0, m, B->W.p, n, s);
+        orthonormalise_append(B, B->W.p, b);
     }
 }
 
@@ -226,6 +369,10 @@ std::unique_ptr<cr_basis_s> clone_basis(cr_basis B) {
     copy_dev(n * B->q, B->MV.p, C->MV.p, s);
     copy_2d(B->q, B->q, B->KR.p, B->cap, C->KR.p, C->cap, s);
     copy_2d(B->q, B->q, B->MR.p, B->cap, C->MR.p, C->cap, s);
+    if (!sys->D.empty()) {
+        copy_dev(n * B->q, B->DV.p, C->DV.p, s);
+        copy_2d(B->q, B->q, B->DR.p, B->cap, C->DR.p, C->cap, s);
+    }
     CR_HIP(hipStreamSynchronize(s));
     C->q = B->q;
     C->shifts = B->shifts;
@@ -262,6 +409,16 @@ std::unique_ptr<cr_rom_s> rom_from_basis(cr_basis B) {
     r->flags.alloc(std::max(L, 1));
     copy_2d(q, q, B->KR.p, B->cap, r->KR.p, q, s);
     copy_2d(q, q, B->MR.p, B->cap, r->MR.p, q, s);
+    if (!sys->D.empty()) {
+        r->has_d = true;
+        r->DR.alloc((size_t)q * q);
+        copy_2d(q, q, B->DR.p, B->cap, r->DR.p, q, s);
+    }
+    for (size_t t = 0; t < sys->terms.size(); ++t) {
+        r->tmeta.push_back(static_cast<const TermMeta&>(sys->terms[t]));
+        r->TR.emplace_back((size_t)q * q);
+        copy_2d(q, q, B->TR[t].p, B->cap, r->TR.back().p, q, s);
+    }
     gram(n, q, L, B->V.p, n, sys->d_F.p, n, r->FR.p, q, 0, B->partial, s);
     gather_recv(sys, q, B->V.p, n, r->CR.p, s);
     if (L > 0) CR_HIP(hipMemcpyAsync(r->flags.p, sys->d_flags.p, L * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
@@ -292,7 +449,32 @@ RomDesc desc_of(const cr_rom_s* r, const double* omegas_dev, zd* out, int out_x)
     d.L = r->L;
     d.n_o = r->n_o;
     d.out_x = out_x;
+    d.nterm = 0;
+    for (int t = 0; t < kMaxTerms; ++t) d.T[t] = nullptr;
+    d.tcoef = nullptr;
     return d;
+}
+
+// Frequency-dependent terms of a reduced model: upload the coefficient table of the given host
+// frequencies (kind 0: 1 + i eta(w); kind 1: -w^2 / (c^2 (1 + i eta(w)))) into the model's
+// buffer and point the descriptor at it; off is the table offset of this call's first frequency.
+void attach_terms(cr_rom_s* r, RomDesc& d, const double* omegas, int nfreq, hipStream_t s) {
+    const int nt = (int)r->tmeta.size();
+    if (nt == 0 || nfreq == 0) return;
+    std::vector<zd> tab((size_t)nfreq * nt);
+    for (int i = 0; i < nfreq; ++i)
+        for (int t = 0; t < nt; ++t) {
+            const TermMeta& m = r->tmeta[t];
+            zd c = m.coef(omegas[i]);
+            if (m.kind == 1) c = {-omegas[i] * omegas[i] * c.re, -omegas[i] * omegas[i] * c.im};
+            tab[(size_t)i * nt + t] = c;
+        }
+    r->tcoef.reserve(tab.size());
+    CR_HIP(hipMemcpyAsync(r->tcoef.p, tab.data(), tab.size() * sizeof(zd), hipMemcpyHostToDevice, s));
+    CR_HIP(hipStreamSynchronize(s));
+    d.nterm = nt;
+    for (int t = 0; t < nt; ++t) d.T[t] = r->TR[t].p;
+    d.tcoef = r->tcoef.p;
 }
 
 }  // namespace
@@ -302,19 +484,27 @@ void finalize_sys(cr_sys sys) {
     const int64_t n = sys->n, nnz = sys->rowptr[n];
     hipStream_t s = sys->ctx->stream;
     sys->scale.assign(n, 1.0);
+    // stiffness of frequency-dependent solids taken with loss factor zero (coefficient 1)
     for (int64_t r = 0; r < n; ++r) {
         double d = 0;
         for (int64_t k = sys->rowptr[r]; k < sys->rowptr[r + 1]; ++k)
-            if (sys->col[k] == r) d = std::hypot(sys->K[k].re, sys->K[k].im);
+            if (sys->col[k] == r) {
+                double re = sys->K[k].re, im = sys->K[k].im;
+                for (const FreqTerm& t : sys->terms)
+                    if (t.kind == 0) { re += t.vals[k].re; im += t.vals[k].im; }
+                d = std::hypot(re, im);
+            }
         CR_REQUIRE(d > 0, CR_E_INVALID, "zero diagonal of K at DoF " + std::to_string(r));
         sys->scale[r] = 1.0 / std::sqrt(d);
     }
-    std::vector<zd> Ks(nnz), Ms(nnz), Fs(sys->F.size());
+    const bool hd = !sys->D.empty();
+    std::vector<zd> Ks(nnz), Ms(nnz), Ds(hd ? nnz : 0), Fs(sys->F.size());
     for (int64_t r = 0; r < n; ++r)
         for (int64_t k = sys->rowptr[r]; k < sys->rowptr[r + 1]; ++k) {
             const double f = sys->scale[r] * sys->scale[sys->col[k]];
             Ks[k] = {sys->K[k].re * f, sys->K[k].im * f};
             Ms[k] = {sys->M[k].re * f, sys->M[k].im * f};
+            if (hd) Ds[k] = {sys->D[k].re * f, sys->D[k].im * f};
         }
     for (int l = 0; l < sys->L; ++l)
         for (int64_t r = 0; r < n; ++r) {
@@ -325,6 +515,16 @@ void finalize_sys(cr_sys sys) {
     upload(sys->d_col, sys->col, s);
     upload(sys->d_K, Ks, s);
     upload(sys->d_M, Ms, s);
+    if (hd) upload(sys->d_D, Ds, s);
+    for (FreqTerm& t : sys->terms) {
+        std::vector<zd> Ts(nnz);
+        for (int64_t r = 0; r < n; ++r)
+            for (int64_t k = sys->rowptr[r]; k < sys->rowptr[r + 1]; ++k) {
+                const double f = sys->scale[r] * sys->scale[sys->col[k]];
+                Ts[k] = {t.vals[k].re * f, t.vals[k].im * f};
+            }
+        upload(t.d_vals, Ts, s);
+    }
     upload(sys->d_F, Fs, s);
     upload(sys->d_scale, sys->scale, s);
     upload(sys->d_recv, sys->recv, s);
@@ -336,8 +536,12 @@ void finalize_sys(cr_sys sys) {
 // =============================================================== C ABI
 extern "C" {
 
-cr_status cr_ctx_create(int device, void* hip_stream, cr_ctx* out) {
+cr_status cr_ctx_create(int device, void* hip_stream, const cr_allocator* allocator, cr_ctx* out) {
     if (!out) return CR_E_INVALID;
+    if (allocator && (!allocator->alloc || !allocator->free)) {
+        g_create_error = "allocator without alloc or free function";
+        return CR_E_INVALID;
+    }
     try {
         int count = 0;
         hipError_t e = hipGetDeviceCount(&count);
@@ -356,6 +560,10 @@ cr_status cr_ctx_create(int device, void* hip_stream, cr_ctx* out) {
         hipDeviceProp_t prop;
         CR_HIP(hipGetDeviceProperties(&prop, device));
         c->num_cu = prop.multiProcessorCount;
+        if (allocator) {
+            c->alloc = *allocator;
+            c->has_alloc = true;
+        }
         noalloc_scratch_init(device);   // address of this device's static sweep scratch
         *out = c.release();
         return CR_OK;
@@ -399,6 +607,77 @@ cr_status cr_sys_export(cr_sys sys, int64_t* rowptr, int32_t* col, cr_z* K, cr_z
 }
 
 void cr_sys_destroy(cr_sys sys) { delete sys; }
+
+cr_status cr_sys_import_csr(cr_ctx ctx, int64_t n, const int64_t* rowptr, const int32_t* col, const cr_z* K,
+                            const cr_z* D, const cr_z* M, int32_t L, const cr_z* F, const int32_t* flags, int32_t n_o,
+                            const int64_t* recv_dofs, const double* coords, cr_sys* out) {
+    if (!ctx) return CR_E_INVALID;
+    return cr_guard(ctx, [&] {
+        CR_REQUIRE(out && n > 0 && n < (int64_t)INT32_MAX && rowptr && col && K && M && L >= 0 && L <= 4096 &&
+                       (L == 0 || (F && flags)) && n_o >= 0 && (n_o == 0 || recv_dofs),
+                   CR_E_INVALID, "cr_sys_import_csr: bad arguments");
+        CR_REQUIRE(rowptr[0] == 0, CR_E_INVALID, "cr_sys_import_csr: rowptr[0] must be 0");
+        for (int64_t r = 0; r < n; ++r)
+            CR_REQUIRE(rowptr[r + 1] >= rowptr[r], CR_E_INVALID, "cr_sys_import_csr: rowptr not monotone");
+        const int64_t nnz = rowptr[n];
+        const bool hd = D != nullptr;
+        auto finite = [](const cr_z& z) { return std::isfinite(z.re) && std::isfinite(z.im); };
+        // entries and transposed explicit zeros, sorted by (row, column); duplicates summed
+        std::vector<std::pair<uint64_t, int64_t>> ent;
+        ent.reserve((size_t)(2 * nnz));
+        for (int64_t r = 0; r < n; ++r)
+            for (int64_t k = rowptr[r]; k < rowptr[r + 1]; ++k) {
+                const int64_t c = col[k];
+                CR_REQUIRE(c >= 0 && c < n, CR_E_INVALID, "cr_sys_import_csr: column index out of range");
+                CR_REQUIRE(finite(K[k]) && finite(M[k]) && (!hd || finite(D[k])), CR_E_INVALID,
+                           "cr_sys_import_csr: non-finite matrix value");
+                ent.push_back({((uint64_t)r << 32) | (uint64_t)c, k});
+                if (c != r) ent.push_back({((uint64_t)c << 32) | (uint64_t)r, -1});
+            }
+        std::sort(ent.begin(), ent.end());
+        auto sys = std::make_unique<cr_sys_s>();
+        sys->ctx = ctx;
+        sys->n = n;
+        sys->n_u = 0;
+        sys->L = L;
+        sys->n_o = n_o;
+        sys->rowptr.assign(n + 1, 0);
+        for (size_t e = 0; e < ent.size();) {
+            const uint64_t key = ent[e].first;
+            const int64_t r = (int64_t)(key >> 32);
+            const int32_t c = (int32_t)(key & 0xffffffffu);
+            zd kv{0, 0}, mv{0, 0}, dv{0, 0};
+            for (; e < ent.size() && ent[e].first == key; ++e) {
+                const int64_t k = ent[e].second;
+                if (k < 0) continue;
+                kv.re += K[k].re; kv.im += K[k].im;
+                mv.re += M[k].re; mv.im += M[k].im;
+                if (hd) { dv.re += D[k].re; dv.im += D[k].im; }
+            }
+            sys->col.push_back(c);
+            sys->K.push_back(kv);
+            sys->M.push_back(mv);
+            if (hd) sys->D.push_back(dv);
+            sys->rowptr[r + 1]++;
+        }
+        for (int64_t r = 0; r < n; ++r) sys->rowptr[r + 1] += sys->rowptr[r];
+        sys->F.resize((size_t)n * L);
+        for (size_t e = 0; e < sys->F.size(); ++e) {
+            CR_REQUIRE(finite(F[e]), CR_E_INVALID, "cr_sys_import_csr: non-finite load value");
+            sys->F[e] = {F[e].re, F[e].im};
+        }
+        sys->flags.assign(flags, flags + L);
+        for (int32_t f : sys->flags) CR_REQUIRE(f == 0 || f == 1, CR_E_INVALID, "cr_sys_import_csr: flags must be 0 or 1");
+        sys->recv.assign(recv_dofs, recv_dofs + n_o);
+        for (int64_t r : sys->recv) CR_REQUIRE(r >= 0 && r < n, CR_E_INVALID, "cr_sys_import_csr: receiver DoF out of range");
+        if (coords) {
+            sys->coords.assign(coords, coords + 3 * n);
+            for (double x : sys->coords) CR_REQUIRE(std::isfinite(x), CR_E_INVALID, "cr_sys_import_csr: non-finite coordinate");
+        }
+        finalize_sys(sys.get());
+        *out = sys.release();
+    });
+}
 
 cr_status cr_set_front_classes(cr_sys sys, int32_t big_m, int32_t huge_m) {
     if (!sys) return CR_E_INVALID;
@@ -502,151 +781,295 @@ cr_status cr_basis_build(cr_sys sys, int32_t nshift, const double* omegas, const
         ensure_capacity(B.get(), std::max(total, 1));
         Factor fac;
         SolveWork sw;
-        for (int j = 0; j < nshift; ++j) add_shift(B.get(), fac, sw, omegas[j], blocks[j], prec);
+        for (int j = 0; j < nshift; ++j) {
+            if (sys->D.empty()) add_shift(B.get(), fac, sw, omegas[j], blocks[j], prec);
+            else add_shift_soar(B.get(), fac, sw, omegas[j], blocks[j], prec);
+        }
         fill_info(B.get(), info, t0);
         *out = B.release();
     });
 }
+
+}  // extern "C"
+
+namespace {
+// The residual-maximum greedy (Section 3.3, after Eq. (9)) on the candidate grid of o; options
+// already validated. maxres_out receives the largest candidate residual after each point.
+std::unique_ptr<cr_basis_s> run_greedy(cr_sys sys, const cr_greedy_opts* o, cr_precision prec, cr_greedy_trace* trace,
+                                       std::vector<double>* maxres_out) {
+    hipStream_t s = sys->ctx->stream;
+    const int nc = o->n_cand, L = sys->L;
+    const int64_t n = sys->n;
+    // candidates as numpy.linspace computes them (start + i * step, last = stop exactly)
+    std::vector<double> cand(nc), cw(nc), w2(nc);
+    const double step = (o->f_hi_hz - o->f_lo_hz) / (nc - 1);
+    for (int i = 0; i < nc; ++i) cand[i] = i * step + o->f_lo_hz;
+    cand[nc - 1] = o->f_hi_hz;
+    for (int i = 0; i < nc; ++i) {
+        cw[i] = (2.0 * M_PI) * cand[i];
+        w2[i] = cw[i] * cw[i];
+    }
+    const double centre = 0.5 * (cand[0] + cand[nc - 1]);
+    int j = 0;
+    for (int i = 1; i < nc; ++i)
+        if (std::fabs(cand[i] - centre) < std::fabs(cand[j] - centre)) j = i;
+    auto B = std::make_unique<cr_basis_s>();
+    B->sys = sys;
+    ensure_capacity(B.get(), o->blocks * L * std::min(o->max_shifts, 64));
+    Factor fac;
+    SolveWork sw;
+    SweepEngine& E = engine(sys->ctx);
+    // load scales (i w_c)^flag and ||S f(w_c)||_F^2
+    std::vector<zd> scal((size_t)nc * L);
+    std::vector<double> fn2(nc, 0.0);
+    std::vector<double> f2 = col_norms2(B.get(), sys->d_F.p, L);
+    for (int c = 0; c < nc; ++c)
+        for (int l = 0; l < L; ++l) {
+            scal[(size_t)c * L + l] = sys->flags[l] ? zd{0.0, cw[c]} : zd{1.0, 0.0};
+            fn2[c] += (sys->flags[l] ? w2[c] : 1.0) * f2[l];
+        }
+    DevBuf<zd> d_scal(scal.size());
+    DevBuf<double> d_w2(nc), d_cw(nc), d_res2(nc), partial;
+    CR_HIP(hipMemcpyAsync(d_scal.p, scal.data(), scal.size() * sizeof(zd), hipMemcpyHostToDevice, s));
+    CR_HIP(hipMemcpyAsync(d_w2.p, w2.data(), nc * sizeof(double), hipMemcpyHostToDevice, s));
+    CR_HIP(hipMemcpyAsync(d_cw.p, cw.data(), nc * sizeof(double), hipMemcpyHostToDevice, s));
+    DevBuf<zd> Xc;
+    std::vector<int> used;
+    std::vector<double> maxres, res(nc, 0.0);
+    std::vector<int> mlp_used;
+    std::vector<int2> items(nc);
+    for (int c = 0; c < nc; ++c) items[c] = make_int2(0, c);
+    for (int it = 0; it < o->max_shifts; ++it) {
+        used.push_back(j);
+        add_shift(B.get(), fac, sw, cw[j], o->blocks, prec);
+        auto rom = rom_from_basis(B.get());
+        const int q = B->q;
+        Xc.reserve((size_t)nc * q * L);
+        std::vector<RomDesc> rd{desc_of(rom.get(), d_cw.p, Xc.p, 1)};
+        int mi, ncv, np;
+        E.run(rd, items, CR_FP64, false, s, &mi, &ncv, &np);
+        candidate_residuals(n, q, L, nc, B->KV.p, B->MV.p, n, sys->d_F.p, Xc.p, d_scal.p, d_w2.p, d_res2.p, partial, s);
+        CR_HIP(hipMemcpyAsync(res.data(), d_res2.p, nc * sizeof(double), hipMemcpyDeviceToHost, s));
+        CR_HIP(hipStreamSynchronize(s));
+        double mx = 0;
+        for (int c = 0; c < nc; ++c) {
+            res[c] = std::sqrt(res[c] / fn2[c]);
+            mx = std::max(mx, res[c]);
+        }
+        if (trace && trace->res_hist) std::copy(res.begin(), res.end(), trace->res_hist + (size_t)it * nc);
+        maxres.push_back(mx);
+        if (mx <= o->tol) break;
+        if (o->lookahead > 0) {
+            // one-step look-ahead over the K largest residual peaks, each tried on a copy
+            const int K = o->lookahead;
+            std::vector<int> idx(nc);
+            std::iota(idx.begin(), idx.end(), 0);
+            std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return res[a] > res[b]; });
+            std::vector<int> picks;
+            for (int c : idx) {
+                if ((int)picks.size() >= K) break;
+                bool bad = false;
+                for (int u : used) bad = bad || std::abs(u - c) <= 1;
+                for (int pk : picks) bad = bad || std::abs(pk - c) < 3;
+                if (!bad) picks.push_back(c);
+            }
+            std::vector<double> rtmp(nc);
+            for (int k = 0; k < K; ++k) {
+                double best_after = -1.0;
+                const int c = k < (int)picks.size() ? picks[k] : -1;
+                if (c >= 0) {
+                    auto Bc = clone_basis(B.get());
+                    add_shift(Bc.get(), fac, sw, cw[c], o->blocks, prec);
+                    auto romc = rom_from_basis(Bc.get());
+                    const int qc = Bc->q;
+                    Xc.reserve((size_t)nc * qc * L);
+                    std::vector<RomDesc> rdc{desc_of(romc.get(), d_cw.p, Xc.p, 1)};
+                    int mi2, ncv2, np2;
+                    E.run(rdc, items, CR_FP64, false, s, &mi2, &ncv2, &np2);
+                    candidate_residuals(n, qc, L, nc, Bc->KV.p, Bc->MV.p, n, sys->d_F.p, Xc.p, d_scal.p, d_w2.p,
+                                        d_res2.p, partial, s);
+                    CR_HIP(hipMemcpyAsync(rtmp.data(), d_res2.p, nc * sizeof(double), hipMemcpyDeviceToHost, s));
+                    CR_HIP(hipStreamSynchronize(s));
+                    best_after = 0;
+                    for (int cc = 0; cc < nc; ++cc) best_after = std::max(best_after, std::sqrt(rtmp[cc] / fn2[cc]));
+                }
+                if (trace && trace->la_cand) trace->la_cand[(size_t)it * K + k] = c;
+                if (trace && trace->la_res) trace->la_res[(size_t)it * K + k] = best_after;
+            }
+        }
+        int best = -1;
+        for (int c = 0; c < nc; ++c) {
+            if (std::find(used.begin(), used.end(), c) != used.end()) continue;
+            if (best < 0 || res[c] > res[best]) best = c;
+        }
+        if (best < 0) break;
+        int choice = best, took_mlp = 0;
+        if (o->policy == CR_POLICY_MLP) {
+            const int prop = mlp_propose(o->mlp, res, used, o->geom);
+            if (prop >= 0 && res[prop] >= 0.1 * mx) { choice = prop; took_mlp = 1; }
+        }
+        mlp_used.push_back(took_mlp);
+        j = choice;
+    }
+    if (trace) {
+        trace->n_iter = (int)used.size();
+        for (size_t k = 0; k < used.size(); ++k) {
+            if (trace->shift_idx) trace->shift_idx[k] = used[k];
+            if (trace->max_res) trace->max_res[k] = maxres[k];
+            if (trace->mlp_used) trace->mlp_used[k] = (k >= 1 && k - 1 < mlp_used.size()) ? mlp_used[k - 1] : 0;
+        }
+        if (trace->res) std::copy(res.begin(), res.end(), trace->res);
+    }
+    if (maxres_out) *maxres_out = maxres;
+    return B;
+}
+
+void check_greedy_opts(cr_sys sys, const cr_greedy_opts* o, cr_precision prec) {
+    CR_REQUIRE(o, CR_E_INVALID, "cr_basis_build_greedy: bad arguments");
+    CR_REQUIRE(o->n_cand >= 2 && o->n_cand <= 4096 && o->blocks >= 1 && o->max_shifts >= 1 && o->tol > 0 &&
+                   std::isfinite(o->f_lo_hz) && std::isfinite(o->f_hi_hz) && o->f_hi_hz > o->f_lo_hz && o->f_lo_hz >= 0,
+               CR_E_INVALID, "cr_basis_build_greedy: bad options");
+    CR_REQUIRE(prec == CR_FP64 || prec == CR_MIXED, CR_E_INVALID, "cr_basis_build_greedy: bad precision");
+    CR_REQUIRE(o->policy == CR_POLICY_GREEDY || (o->policy == CR_POLICY_MLP && o->mlp), CR_E_INVALID,
+               "cr_basis_build_greedy: MLP policy needs a network");
+    CR_REQUIRE(sys->sym, CR_E_STATE, "cr_basis_build_greedy: call cr_analyse first");
+    CR_REQUIRE(sys->D.empty() && sys->terms.empty(), CR_E_UNSUPPORTED,
+               "cr_basis_build_greedy: systems with a damping matrix or frequency-dependent materials take fixed "
+               "expansion points (cr_basis_build)");
+    CR_REQUIRE(sys->L > 0, CR_E_INVALID, "cr_basis_build_greedy: system has no loads");
+}
+}  // namespace
+
+extern "C" {
 
 cr_status cr_basis_build_greedy(cr_sys sys, const cr_greedy_opts* o, cr_precision prec, cr_basis* out,
                                 cr_greedy_trace* trace, cr_basis_info* info) {
     if (!sys) return CR_E_INVALID;
     return cr_guard(sys->ctx, [&] {
         CR_REQUIRE(o && out, CR_E_INVALID, "cr_basis_build_greedy: bad arguments");
-        CR_REQUIRE(o->n_cand >= 2 && o->n_cand <= 4096 && o->blocks >= 1 && o->max_shifts >= 1 && o->tol > 0 &&
-                       std::isfinite(o->f_lo_hz) && std::isfinite(o->f_hi_hz) && o->f_hi_hz > o->f_lo_hz && o->f_lo_hz >= 0,
-                   CR_E_INVALID, "cr_basis_build_greedy: bad options");
-        CR_REQUIRE(prec == CR_FP64 || prec == CR_MIXED, CR_E_INVALID, "cr_basis_build_greedy: bad precision");
-        CR_REQUIRE(o->policy == CR_POLICY_GREEDY || (o->policy == CR_POLICY_MLP && o->mlp), CR_E_INVALID,
-                   "cr_basis_build_greedy: MLP policy needs a network");
-        CR_REQUIRE(sys->sym, CR_E_STATE, "cr_basis_build_greedy: call cr_analyse first");
-        CR_REQUIRE(sys->L > 0, CR_E_INVALID, "cr_basis_build_greedy: system has no loads");
+        check_greedy_opts(sys, o, prec);
         const double t0 = now();
-        hipStream_t s = sys->ctx->stream;
-        const int nc = o->n_cand, L = sys->L;
-        const int64_t n = sys->n;
-        // candidates as numpy.linspace computes them (start + i * step, last = stop exactly)
-        std::vector<double> cand(nc), cw(nc), w2(nc);
+        auto B = run_greedy(sys, o, prec, trace, nullptr);
+        fill_info(B.get(), info, t0);
+        *out = B.release();
+    });
+}
+
+cr_status cr_build_local_roms(cr_sys sys, const cr_window_opts* o, cr_precision prec, int32_t* n_windows,
+                              int32_t* win_cand, double* win_hi_hz, double* win_max_res, cr_rom* roms,
+                              cr_window_info* info) {
+    if (!sys) return CR_E_INVALID;
+    std::vector<cr_rom> made;
+    cr_status st = cr_guard(sys->ctx, [&] {
+        CR_REQUIRE(o && n_windows && win_cand && win_hi_hz && roms && o->max_windows >= 1 && o->min_cand >= 2,
+                   CR_E_INVALID, "cr_build_local_roms: bad arguments");
+        cr_greedy_opts g{};
+        g.f_lo_hz = o->f_lo_hz;
+        g.f_hi_hz = o->f_hi_hz;
+        g.n_cand = o->n_cand;
+        g.blocks = o->blocks;
+        g.tol = o->tol;
+        g.max_shifts = o->max_shifts;
+        g.policy = CR_POLICY_GREEDY;
+        check_greedy_opts(sys, &g, prec);
+        const double t0 = now();
+        const int nc = o->n_cand;
+        std::vector<double> cand(nc);
         const double step = (o->f_hi_hz - o->f_lo_hz) / (nc - 1);
         for (int i = 0; i < nc; ++i) cand[i] = i * step + o->f_lo_hz;
         cand[nc - 1] = o->f_hi_hz;
-        for (int i = 0; i < nc; ++i) {
-            cw[i] = (2.0 * M_PI) * cand[i];
-            w2[i] = cw[i] * cw[i];
+        int attempted = 0, unconv = 0, qmax = 0, kept_shifts = 0;
+        // bisection: a window whose greedy misses tol within max_shifts points is split at its
+        // middle candidate (shared by both halves) while both halves keep min_cand candidates
+        std::vector<std::pair<int, int>> todo{{0, nc - 1}};
+        while (!todo.empty()) {
+            const auto [i0, i1] = todo.back();
+            todo.pop_back();
+            const int k = i1 - i0 + 1;
+            cr_greedy_opts gw = g;
+            gw.f_lo_hz = cand[i0];
+            gw.f_hi_hz = cand[i1];
+            gw.n_cand = k;
+            std::vector<double> mres;
+            auto B = run_greedy(sys, &gw, prec, nullptr, &mres);
+            attempted += (int)B->shifts.size();
+            const bool conv = !mres.empty() && mres.back() <= o->tol;
+            if (conv || k < 2 * o->min_cand - 1) {
+                CR_REQUIRE((int)made.size() < o->max_windows, CR_E_INVALID,
+                           "cr_build_local_roms: more windows than max_windows");
+                const int w = (int)made.size();
+                win_cand[2 * w] = i0;
+                win_cand[2 * w + 1] = i1;
+                win_hi_hz[w] = cand[i1];
+                if (win_max_res) win_max_res[w] = mres.empty() ? 0.0 : mres.back();
+                unconv += conv ? 0 : 1;
+                qmax = std::max(qmax, B->q);
+                kept_shifts += (int)B->shifts.size();
+                made.push_back(rom_from_basis(B.get()).release());
+                continue;
+            }
+            const int mid = (i0 + i1) / 2;
+            todo.push_back({mid, i1});   // left half first
+            todo.push_back({i0, mid});
         }
-        const double centre = 0.5 * (cand[0] + cand[nc - 1]);
-        int j = 0;
-        for (int i = 1; i < nc; ++i)
-            if (std::fabs(cand[i] - centre) < std::fabs(cand[j] - centre)) j = i;
-        auto B = std::make_unique<cr_basis_s>();
-        B->sys = sys;
-        ensure_capacity(B.get(), o->blocks * L * std::min(o->max_shifts, 64));
-        Factor fac;
-        SolveWork sw;
-        SweepEngine& E = engine(sys->ctx);
-        // load scales (i w_c)^flag and ||S f(w_c)||_F^2
-        std::vector<zd> scal((size_t)nc * L);
-        std::vector<double> fn2(nc, 0.0);
-        std::vector<double> f2 = col_norms2(B.get(), sys->d_F.p, L);
-        for (int c = 0; c < nc; ++c)
-            for (int l = 0; l < L; ++l) {
-                scal[(size_t)c * L + l] = sys->flags[l] ? zd{0.0, cw[c]} : zd{1.0, 0.0};
-                fn2[c] += (sys->flags[l] ? w2[c] : 1.0) * f2[l];
-            }
-        DevBuf<zd> d_scal(scal.size());
-        DevBuf<double> d_w2(nc), d_cw(nc), d_res2(nc), partial;
-        CR_HIP(hipMemcpyAsync(d_scal.p, scal.data(), scal.size() * sizeof(zd), hipMemcpyHostToDevice, s));
-        CR_HIP(hipMemcpyAsync(d_w2.p, w2.data(), nc * sizeof(double), hipMemcpyHostToDevice, s));
-        CR_HIP(hipMemcpyAsync(d_cw.p, cw.data(), nc * sizeof(double), hipMemcpyHostToDevice, s));
-        DevBuf<zd> Xc;
-        std::vector<int> used;
-        std::vector<double> maxres, res(nc, 0.0);
-        std::vector<int> mlp_used;
-        std::vector<int2> items(nc);
-        for (int c = 0; c < nc; ++c) items[c] = make_int2(0, c);
-        for (int it = 0; it < o->max_shifts; ++it) {
-            used.push_back(j);
-            add_shift(B.get(), fac, sw, cw[j], o->blocks, prec);
-            auto rom = rom_from_basis(B.get());
-            const int q = B->q;
-            Xc.reserve((size_t)nc * q * L);
-            std::vector<RomDesc> rd{desc_of(rom.get(), d_cw.p, Xc.p, 1)};
-            int mi, ncv, np;
-            E.run(rd, items, CR_FP64, false, s, &mi, &ncv, &np);
-            candidate_residuals(n, q, L, nc, B->KV.p, B->MV.p, n, sys->d_F.p, Xc.p, d_scal.p, d_w2.p, d_res2.p, partial, s);
-            CR_HIP(hipMemcpyAsync(res.data(), d_res2.p, nc * sizeof(double), hipMemcpyDeviceToHost, s));
-            CR_HIP(hipStreamSynchronize(s));
-            double mx = 0;
-            for (int c = 0; c < nc; ++c) {
-                res[c] = std::sqrt(res[c] / fn2[c]);
-                mx = std::max(mx, res[c]);
-            }
-            if (trace && trace->res_hist) std::copy(res.begin(), res.end(), trace->res_hist + (size_t)it * nc);
-            maxres.push_back(mx);
-            if (mx <= o->tol) break;
-            if (o->lookahead > 0) {
-                // one-step look-ahead over the K largest residual peaks, each tried on a copy
-                const int K = o->lookahead;
-                std::vector<int> idx(nc);
-                std::iota(idx.begin(), idx.end(), 0);
-                std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return res[a] > res[b]; });
-                std::vector<int> picks;
-                for (int c : idx) {
-                    if ((int)picks.size() >= K) break;
-                    bool bad = false;
-                    for (int u : used) bad = bad || std::abs(u - c) <= 1;
-                    for (int pk : picks) bad = bad || std::abs(pk - c) < 3;
-                    if (!bad) picks.push_back(c);
-                }
-                std::vector<double> rtmp(nc);
-                for (int k = 0; k < K; ++k) {
-                    double best_after = -1.0;
-                    const int c = k < (int)picks.size() ? picks[k] : -1;
-                    if (c >= 0) {
-                        auto Bc = clone_basis(B.get());
-                        add_shift(Bc.get(), fac, sw, cw[c], o->blocks, prec);
-                        auto romc = rom_from_basis(Bc.get());
-                        const int qc = Bc->q;
-                        Xc.reserve((size_t)nc * qc * L);
-                        std::vector<RomDesc> rdc{desc_of(romc.get(), d_cw.p, Xc.p, 1)};
-                        int mi2, ncv2, np2;
-                        E.run(rdc, items, CR_FP64, false, s, &mi2, &ncv2, &np2);
-                        candidate_residuals(n, qc, L, nc, Bc->KV.p, Bc->MV.p, n, sys->d_F.p, Xc.p, d_scal.p, d_w2.p,
-                                            d_res2.p, partial, s);
-                        CR_HIP(hipMemcpyAsync(rtmp.data(), d_res2.p, nc * sizeof(double), hipMemcpyDeviceToHost, s));
-                        CR_HIP(hipStreamSynchronize(s));
-                        best_after = 0;
-                        for (int cc = 0; cc < nc; ++cc) best_after = std::max(best_after, std::sqrt(rtmp[cc] / fn2[cc]));
-                    }
-                    if (trace && trace->la_cand) trace->la_cand[(size_t)it * K + k] = c;
-                    if (trace && trace->la_res) trace->la_res[(size_t)it * K + k] = best_after;
-                }
-            }
-            int best = -1;
-            for (int c = 0; c < nc; ++c) {
-                if (std::find(used.begin(), used.end(), c) != used.end()) continue;
-                if (best < 0 || res[c] > res[best]) best = c;
-            }
-            if (best < 0) break;
-            int choice = best, took_mlp = 0;
-            if (o->policy == CR_POLICY_MLP) {
-                const int prop = mlp_propose(o->mlp, res, used, o->geom);
-                if (prop >= 0 && res[prop] >= 0.1 * mx) { choice = prop; took_mlp = 1; }
-            }
-            mlp_used.push_back(took_mlp);
-            j = choice;
+        *n_windows = (int32_t)made.size();
+        for (size_t w = 0; w < made.size(); ++w) roms[w] = made[w];
+        if (info) {
+            info->n_windows = (int32_t)made.size();
+            info->expansion_points = kept_shifts;
+            info->attempted_points = attempted;
+            info->max_q = qmax;
+            info->unconverged = unconv;
+            info->seconds = now() - t0;
         }
-        if (trace) {
-            trace->n_iter = (int)used.size();
-            for (size_t k = 0; k < used.size(); ++k) {
-                if (trace->shift_idx) trace->shift_idx[k] = used[k];
-                if (trace->max_res) trace->max_res[k] = maxres[k];
-                if (trace->mlp_used) trace->mlp_used[k] = (k >= 1 && k - 1 < mlp_used.size()) ? mlp_used[k - 1] : 0;
-            }
-            if (trace->res) std::copy(res.begin(), res.end(), trace->res);
+    });
+    if (st != CR_OK)
+        for (cr_rom r : made) delete r;
+    return st;
+}
+
+cr_status cr_sweep_windows(int32_t nwin, const cr_rom* roms, const double* win_hi_hz, int32_t nfreq,
+                           const double* omegas, cr_precision prec, cr_z* Y_dev, cr_sweep_info* info) {
+    if (nwin < 1 || !roms || !roms[0]) return CR_E_INVALID;
+    cr_ctx ctx = roms[0]->ctx;
+    return cr_guard(ctx, [&] {
+        CR_REQUIRE(win_hi_hz && nfreq >= 0 && (nfreq == 0 || (omegas && Y_dev)), CR_E_INVALID,
+                   "cr_sweep_windows: bad arguments");
+        CR_REQUIRE(prec == CR_FP64 || prec == CR_MIXED, CR_E_INVALID, "cr_sweep_windows: bad precision");
+        for (int k = 0; k < nwin; ++k) {
+            CR_REQUIRE(roms[k] && roms[k]->ctx == ctx && roms[k]->L == roms[0]->L && roms[k]->n_o == roms[0]->n_o,
+                       CR_E_INVALID, "cr_sweep_windows: windows of different systems");
+            CR_REQUIRE(k == 0 || win_hi_hz[k] >= win_hi_hz[k - 1], CR_E_INVALID,
+                       "cr_sweep_windows: window edges not increasing");
         }
-        fill_info(B.get(), info, t0);
-        *out = B.release();
+        for (int i = 0; i < nfreq; ++i)
+            CR_REQUIRE(std::isfinite(omegas[i]), CR_E_INVALID, "cr_sweep_windows: non-finite frequency");
+        const double t0 = now();
+        hipStream_t s = ctx->stream;
+        SweepEngine& E = engine(ctx);
+        E.d_omega.reserve(std::max(nfreq, 1));
+        if (nfreq) CR_HIP(hipMemcpyAsync(E.d_omega.p, omegas, nfreq * sizeof(double), hipMemcpyHostToDevice, s));
+        std::vector<RomDesc> ds(nwin);
+        for (int k = 0; k < nwin; ++k) {
+            CR_REQUIRE(roms[k]->tmeta.empty(), CR_E_UNSUPPORTED,
+                       "cr_sweep_windows: reduced models with frequency-dependent terms need cr_sweep");
+            ds[k] = desc_of(roms[k], E.d_omega.p, reinterpret_cast<zd*>(Y_dev), 0);
+        }
+        // each frequency to the first window whose upper edge is not below it (the last above
+        // the band); items ordered by the window's q^3, longest first
+        std::vector<int2> items(nfreq);
+        for (int i = 0; i < nfreq; ++i) {
+            const double f = omegas[i] / (2.0 * M_PI);
+            int k = 0;
+            while (k < nwin - 1 && f > win_hi_hz[k]) ++k;
+            items[i] = make_int2(k, i);
+        }
+        std::stable_sort(items.begin(), items.end(), [&](int2 a, int2 b) { return ds[a.x].q > ds[b.x].q; });
+        int mi = 0, nc = 0, np = 0, fb = 0;
+        E.run(ds, items, prec, prec == CR_MIXED, s, &mi, &nc, &np, 0, &fb);
+        fill_sweep_info(info, mi, nc, fb, np, now() - t0);
+        CR_REQUIRE(nc == 0, CR_E_NOT_CONVERGED,
+                   "cr_sweep_windows: refinement did not reach its tolerance at " + std::to_string(nc) + " frequencies");
     });
 }
 
@@ -666,6 +1089,22 @@ cr_status cr_basis_copy(cr_basis b, cr_z* V_dev) {
 }
 
 void cr_basis_destroy(cr_basis b) { delete b; }
+
+cr_status cr_recover_field(cr_basis b, int64_t ncol, const cr_z* XR_dev, cr_z* X_dev) {
+    if (!b) return CR_E_INVALID;
+    return cr_guard(b->sys->ctx, [&] {
+        CR_REQUIRE(ncol >= 0 && (ncol == 0 || (XR_dev && X_dev)) && ncol <= (int64_t)INT32_MAX, CR_E_INVALID,
+                   "cr_recover_field: bad arguments");
+        CR_REQUIRE(b->q > 0 || ncol == 0, CR_E_INVALID, "cr_recover_field: empty basis");
+        if (ncol == 0) return;
+        cr_sys sys = b->sys;
+        hipStream_t s = sys->ctx->stream;
+        lift(sys->n, b->q, (int)ncol, b->V.p, sys->n, reinterpret_cast<const zd*>(XR_dev), b->q, sys->d_scale.p,
+             reinterpret_cast<zd*>(X_dev), sys->n, s);
+        CR_HIP(hipGetLastError());
+        CR_HIP(hipStreamSynchronize(s));
+    });
+}
 
 cr_status cr_project(cr_sys sys, cr_basis b, cr_rom* out) {
     if (!sys || !b) return CR_E_INVALID;
@@ -743,6 +1182,7 @@ cr_status cr_sweep(cr_rom r, int32_t nfreq, const double* omegas, cr_precision p
         E.d_omega.reserve(std::max(nfreq, 1));
         if (nfreq) CR_HIP(hipMemcpyAsync(E.d_omega.p, omegas, nfreq * sizeof(double), hipMemcpyHostToDevice, s));
         std::vector<RomDesc> roms{desc_of(r, E.d_omega.p, reinterpret_cast<zd*>(Y_dev), 0)};
+        attach_terms(r, roms[0], omegas, nfreq, s);
         std::vector<int2> items(nfreq);
         for (int i = 0; i < nfreq; ++i) items[i] = make_int2(0, i);
         int mi = 0, nc = 0, np = 0, fb = 0;
@@ -750,6 +1190,31 @@ cr_status cr_sweep(cr_rom r, int32_t nfreq, const double* omegas, cr_precision p
         fill_sweep_info(info, mi, nc, fb, np, now() - t0);
         CR_REQUIRE(nc == 0, CR_E_NOT_CONVERGED,
                    "cr_sweep: refinement did not reach its tolerance at " + std::to_string(nc) + " frequencies");
+    });
+}
+
+cr_status cr_sweep_states(cr_rom r, int32_t nfreq, const double* omegas, cr_precision prec, cr_z* XR_dev,
+                          cr_sweep_info* info) {
+    if (!r) return CR_E_INVALID;
+    return cr_guard(r->ctx, [&] {
+        CR_REQUIRE(nfreq >= 0 && (nfreq == 0 || (omegas && XR_dev)), CR_E_INVALID, "cr_sweep_states: bad arguments");
+        CR_REQUIRE(prec == CR_FP64 || prec == CR_MIXED, CR_E_INVALID, "cr_sweep_states: bad precision");
+        for (int i = 0; i < nfreq; ++i)
+            CR_REQUIRE(std::isfinite(omegas[i]), CR_E_INVALID, "cr_sweep_states: non-finite frequency");
+        const double t0 = now();
+        hipStream_t s = r->ctx->stream;
+        SweepEngine& E = engine(r->ctx);
+        E.d_omega.reserve(std::max(nfreq, 1));
+        if (nfreq) CR_HIP(hipMemcpyAsync(E.d_omega.p, omegas, nfreq * sizeof(double), hipMemcpyHostToDevice, s));
+        std::vector<RomDesc> roms{desc_of(r, E.d_omega.p, reinterpret_cast<zd*>(XR_dev), 1)};
+        attach_terms(r, roms[0], omegas, nfreq, s);
+        std::vector<int2> items(nfreq);
+        for (int i = 0; i < nfreq; ++i) items[i] = make_int2(0, i);
+        int mi = 0, nc = 0, np = 0, fb = 0;
+        E.run(roms, items, prec, prec == CR_MIXED, s, &mi, &nc, &np, 0, &fb);
+        fill_sweep_info(info, mi, nc, fb, np, now() - t0);
+        CR_REQUIRE(nc == 0, CR_E_NOT_CONVERGED,
+                   "cr_sweep_states: refinement did not reach its tolerance at " + std::to_string(nc) + " frequencies");
     });
 }
 
@@ -762,6 +1227,8 @@ cr_status cr_sweep_noalloc(cr_rom r, int32_t nfreq, const double* omegas, cr_pre
         for (int i = 0; i < nfreq; ++i)
             CR_REQUIRE(std::isfinite(omegas[i]), CR_E_INVALID, "cr_sweep_noalloc: non-finite frequency");
         const double t0 = now();
+        CR_REQUIRE(r->tmeta.empty(), CR_E_UNSUPPORTED,
+                   "cr_sweep_noalloc: reduced models with frequency-dependent terms need cr_sweep");
         const RomDesc d = desc_of(r, nullptr, reinterpret_cast<zd*>(Y_dev), 0);
         int mi = 0, nc = 0, np = 0, fb = 0;
         sweep_noalloc(r->ctx->device, r->ctx->num_cu, d, omegas, nfreq, prec, r->ctx->stream, &mi, &nc, &np, &fb);
@@ -792,6 +1259,11 @@ cr_status cr_sweep_batched(cr_ctx ctx, int32_t nrom, const cr_rom* roms, int32_t
         for (int m = 0; m < nrom; ++m) {
             CR_REQUIRE(roms[m] && roms[m]->ctx == ctx && Y_dev[m], CR_E_INVALID, "cr_sweep_batched: bad model");
             ds[m] = desc_of(roms[m], E.d_omega.p + (size_t)m * nfreq, reinterpret_cast<zd*>(Y_dev[m]), 0);
+            // a model with frequency-dependent terms keeps one coefficient table per call
+            for (int m2 = 0; m2 < m && !roms[m]->tmeta.empty(); ++m2)
+                CR_REQUIRE(roms[m2] != roms[m], CR_E_INVALID,
+                           "cr_sweep_batched: a model with frequency-dependent terms appears twice");
+            attach_terms(roms[m], ds[m], omegas + (size_t)m * nfreq, nfreq, s);
         }
         // longest first: q^3 descending, then model index, then frequency
         std::vector<int> order(nrom);
@@ -911,6 +1383,8 @@ extern "C" cr_status cr_sweep_plan_create(cr_ctx ctx, int32_t nrom, const cr_rom
         std::vector<RomDesc> ds(nrom);
         for (int m = 0; m < nrom; ++m) {
             CR_REQUIRE(roms[m] && roms[m]->ctx == ctx && Y_dev[m], CR_E_INVALID, "cr_sweep_plan_create: bad model");
+            CR_REQUIRE(roms[m]->tmeta.empty(), CR_E_UNSUPPORTED,
+                       "cr_sweep_plan_create: reduced models with frequency-dependent terms need cr_sweep");
             ds[m] = desc_of(roms[m], P->omegas.p + (size_t)m * nfreq, reinterpret_cast<zd*>(Y_dev[m]), 0);
         }
         std::vector<int> order(nrom);

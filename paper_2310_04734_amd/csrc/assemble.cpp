@@ -131,8 +131,20 @@ extern "C" cr_status cr_assemble(cr_ctx ctx, const cr_mesh* mesh, const cr_mater
         CR_REQUIRE(n_o == 0 || recv_nodes, CR_E_INVALID, "cr_assemble: receivers missing");
         const int64_t nn = mesh->n_nodes, ne = mesh->n_el;
         int fluid_mat = -1;
+        std::vector<int> term_of(nmat, -1);   // material -> frequency-dependent term
+        int nterm = 0;
         for (int m = 0; m < nmat; ++m) {
             CR_REQUIRE(mats[m].kind == CR_FLUID || mats[m].kind == CR_SOLID, CR_E_INVALID, "bad material kind");
+            CR_REQUIRE(mats[m].n_eta >= 0 && (mats[m].n_eta == 0 || (mats[m].eta_f_hz && mats[m].eta_val)),
+                       CR_E_INVALID, "material loss-factor table missing");
+            for (int k = 0; k < mats[m].n_eta; ++k)
+                CR_REQUIRE(std::isfinite(mats[m].eta_val[k]) && std::isfinite(mats[m].eta_f_hz[k]) &&
+                               (k == 0 || mats[m].eta_f_hz[k] > mats[m].eta_f_hz[k - 1]),
+                           CR_E_INVALID, "loss-factor table frequencies must increase");
+            if (mats[m].n_eta > 0) {
+                CR_REQUIRE(nterm < cr::kMaxTerms, CR_E_UNSUPPORTED, "at most 4 materials with frequency-dependent loss");
+                term_of[m] = nterm++;
+            }
             if (mats[m].kind == CR_FLUID) {
                 CR_REQUIRE(fluid_mat < 0, CR_E_UNSUPPORTED, "exactly one fluid material is supported");
                 fluid_mat = m;
@@ -208,6 +220,7 @@ extern "C" cr_status cr_assemble(cr_ctx ctx, const cr_mesh* mesh, const cr_mater
         rows.shrink_to_fit();
         const int64_t nnz = P.rowptr[n];
         std::vector<cplx> Kv(nnz, 0.0), Mv(nnz, 0.0);
+        std::vector<std::vector<cplx>> Tv(nterm, std::vector<cplx>(nnz, 0.0));
 
         double X[8][3];
         for (int64_t e = 0; e < ne; ++e) {
@@ -226,15 +239,19 @@ extern "C" cr_status cr_assemble(cr_ctx ctx, const cr_mesh* mesh, const cr_mater
                             Me[a][b] += hp.detJ * hp.N[a] * hp.N[b];
                         }
                 }
+                const int tm = term_of[mesh->elem_mat[e]];
                 cplx inv_c2 = 1.0 / (mt.c * mt.c * cplx(1.0, mt.eta));
                 for (int a = 0; a < 8; ++a)
                     for (int b = 0; b < 8; ++b) {
                         int64_t pos = P.find(pdof[c[a]], pdof[c[b]]);
                         Kv[pos] += Ke[a][b];
-                        Mv[pos] += Me[a][b] * inv_c2;
+                        if (tm >= 0) Tv[tm][pos] += Me[a][b];   // int N^T N; 1 / c~^2(w) applied per frequency
+                        else Mv[pos] += Me[a][b] * inv_c2;
                     }
             } else {
-                cplx E = mt.E * cplx(1.0, mt.eta);
+                const int tm = term_of[mesh->elem_mat[e]];
+                // a frequency-dependent loss factor keeps the real-E stiffness as its own term
+                cplx E = tm >= 0 ? cplx(mt.E, 0.0) : mt.E * cplx(1.0, mt.eta);
                 cplx lam = E * mt.nu / ((1 + mt.nu) * (1 - 2 * mt.nu));
                 cplx mu = E / (2 * (1 + mt.nu));
                 double G1[8][8][3][3] = {{{{0}}}};   // int d_i N_a d_j N_b
@@ -260,7 +277,8 @@ extern "C" cr_status cr_assemble(cr_ctx ctx, const cr_mesh* mesh, const cr_mater
                                 cplx k = lam * G1[a][b][i][j] + mu * G1[a][b][j][i];
                                 if (i == j) k += mu * lap;
                                 int64_t pos = P.find(r, cc);
-                                Kv[pos] += k;
+                                if (tm >= 0) Tv[tm][pos] += k;
+                                else Kv[pos] += k;
                                 if (i == j) Mv[pos] += mt.rho * Mn[a][b];
                             }
                         }
@@ -337,6 +355,17 @@ extern "C" cr_status cr_assemble(cr_ctx ctx, const cr_mesh* mesh, const cr_mater
         for (int64_t k = 0; k < nnz; ++k) {
             sys->K[k] = {Kv[k].real(), Kv[k].imag()};
             sys->M[k] = {Mv[k].real(), Mv[k].imag()};
+        }
+        for (int m = 0; m < nmat; ++m) {
+            if (term_of[m] < 0) continue;
+            cr::FreqTerm t;
+            t.kind = mats[m].kind == CR_SOLID ? 0 : 1;
+            t.c = mats[m].c;
+            t.f_hz.assign(mats[m].eta_f_hz, mats[m].eta_f_hz + mats[m].n_eta);
+            t.eta.assign(mats[m].eta_val, mats[m].eta_val + mats[m].n_eta);
+            t.vals.resize(nnz);
+            for (int64_t k = 0; k < nnz; ++k) t.vals[k] = {Tv[term_of[m]][k].real(), Tv[term_of[m]][k].imag()};
+            sys->terms.push_back(std::move(t));
         }
         sys->F.resize(F.size());
         for (size_t k = 0; k < F.size(); ++k) sys->F[k] = {F[k].real(), F[k].imag()};

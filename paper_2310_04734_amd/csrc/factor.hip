@@ -1002,6 +1002,25 @@ __global__ void k_scatter_perm(const cx<T>* __restrict__ xp, const int32_t* __re
     else { d.re = (double)v.re; d.im = (double)v.im; }
 }
 
+// out = sum_t c_t p_t entry by entry (FP64): the shifted matrix or the mass matrix at one frequency
+// for systems with a damping matrix or frequency-dependent terms
+struct Comb {
+    const zd* p[3 + kMaxTerms];
+    zd c[3 + kMaxTerms];
+    int n;
+};
+__global__ void k_combine(int64_t nnz, Comb cb, zd* __restrict__ out) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
+        double re = 0, im = 0;
+        for (int t = 0; t < cb.n; ++t) {
+            const zd v = cb.p[t][e], c = cb.c[t];
+            re += c.re * v.re - c.im * v.im;
+            im += c.re * v.im + c.im * v.re;
+        }
+        out[e] = {re, im};
+    }
+}
+
 __global__ void k_maxabs_entries(const zd* __restrict__ K, const zd* __restrict__ M, int64_t nnz, double sigma,
                                  unsigned long long* out) {
     double m = 0;
@@ -1064,7 +1083,7 @@ void run_factor(Factor& f, cr_sys sys, double sigma, cx<T>* arena, T tiny, hipSt
             ProfScope ps(sys->ctx, "front_assemble", s);
             hipLaunchKernelGGL(k_front_assemble<T>, dim3(nf, split), dim3(kWG), 0, s, lf, D.fsize.p, D.front_off.p, D.child_off.p,
                                D.child_list.p, D.npiv.p, D.cmap_off.p, D.cmap.p, D.ent_off.p, D.ent_src.p, D.ent_dst.p,
-                               sys->d_K.p, sys->d_M.p, sigma, arena);
+                               f.opK, f.opM, sigma, arena);
         }
         {
             ProfScope ps(sys->ctx, "front_factor", s);
@@ -1248,18 +1267,58 @@ void numeric_factor(Factor& f, cr_sys sys, double omega, cr_precision prec, hipS
     f.ipiv.reserve(S.n);
     f.psrc.reserve(S.n);
     f.nperturb.reserve(2);
-    const double sigma = omega * omega;
+    const int64_t nnz = sys->rowptr[sys->n];
+    if (!sys->D.empty() || !sys->terms.empty()) {
+        // A(w) = K~ + sum_K-terms c_t T_t + i w D~ - w^2 (M~ + sum_M-terms c_t T_t)
+        Comb a{}, m{};
+        const double w2 = omega * omega;
+        a.p[a.n] = sys->d_K.p; a.c[a.n++] = {1.0, 0.0};
+        a.p[a.n] = sys->d_M.p; a.c[a.n++] = {-w2, 0.0};
+        if (!sys->D.empty()) { a.p[a.n] = sys->d_D.p; a.c[a.n++] = {0.0, omega}; }
+        m.p[m.n] = sys->d_M.p; m.c[m.n++] = {1.0, 0.0};
+        for (const FreqTerm& t : sys->terms) {
+            const zd c = t.coef(omega);
+            if (t.kind == 0) { a.p[a.n] = t.d_vals.p; a.c[a.n++] = c; }
+            else {
+                a.p[a.n] = t.d_vals.p; a.c[a.n++] = {-w2 * c.re, -w2 * c.im};
+                m.p[m.n] = t.d_vals.p; m.c[m.n++] = c;
+            }
+        }
+        f.aval.reserve(nnz);
+        hipLaunchKernelGGL(k_combine, dim3(1024), dim3(256), 0, s, nnz, a, f.aval.p);
+        f.opK = f.aval.p;
+        f.opM = f.aval.p;
+        f.opS = 0.0;
+        if (m.n > 1) {
+            f.mval.reserve(nnz);
+            hipLaunchKernelGGL(k_combine, dim3(1024), dim3(256), 0, s, nnz, m, f.mval.p);
+            f.opMass = f.mval.p;
+        } else {
+            f.mval.release();
+            f.opMass = sys->d_M.p;
+        }
+    } else {
+        f.aval.release();
+        f.mval.release();
+        f.opK = sys->d_K.p;
+        f.opM = sys->d_M.p;
+        f.opS = omega * omega;
+        f.opMass = sys->d_M.p;
+    }
+    f.anorm_omega = -1;
+    const double sigma = f.opS;
     // largest |entry| of the shifted matrix sets the perturbation threshold
     f.amax.reserve(1);
     fill_zero(f.amax.p, 1, s);
     fill_zero(f.nperturb.p, 1, s);
-    const int64_t nnz = sys->rowptr[sys->n];
-    hipLaunchKernelGGL(k_maxabs_entries, dim3(256), dim3(256), 0, s, sys->d_K.p, sys->d_M.p, nnz, sigma, f.amax.p);
+    hipLaunchKernelGGL(k_maxabs_entries, dim3(256), dim3(256), 0, s, f.opK, f.opM, nnz, sigma, f.amax.p);
     unsigned long long hm = 0;
     CR_HIP(hipMemcpyAsync(&hm, f.amax.p, sizeof(hm), hipMemcpyDeviceToHost, s));
     CR_HIP(hipStreamSynchronize(s));
     double amax;
     std::memcpy(&amax, &hm, sizeof(amax));
+    CR_REQUIRE(amax > 0 && std::isfinite(amax), CR_E_SINGULAR,
+               "the shifted matrix at this frequency has no nonzero entry or a non-finite one: no pivot can be perturbed");
     if (prec == CR_MIXED) {
         f.arena64.release();
         f.arena32.reserve(S.arena);

@@ -32,37 +32,56 @@ struct Error : std::runtime_error {
     } while (0)
 
 // ------------------------------------------------------------------------- device buffers
-// Owning device allocation (hipMalloc); movable, not copyable.
+// Allocator of the context whose API call is running on this thread (set by cr_guard), or null
+// for hipMalloc / hipFree. A buffer remembers the allocator that produced it and frees through it.
+extern thread_local const cr_allocator* tl_alloc;
+
+// Owning device allocation; movable, not copyable.
 template <typename T>
 struct DevBuf {
     T* p = nullptr;
     size_t n = 0;
+    const cr_allocator* al = nullptr;
     DevBuf() = default;
     explicit DevBuf(size_t count) { alloc(count); }
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
-    DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n), al(o.al) { o.p = nullptr; o.n = 0; o.al = nullptr; }
     DevBuf& operator=(DevBuf&& o) noexcept {
-        if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        if (this != &o) { release(); p = o.p; n = o.n; al = o.al; o.p = nullptr; o.n = 0; o.al = nullptr; }
         return *this;
     }
     ~DevBuf() { release(); }
     void alloc(size_t count) {
         release();
         if (count == 0) return;
-        hipError_t e = hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T));
-        if (e != hipSuccess) {
-            p = nullptr;
-            throw Error(CR_E_OOM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+        const size_t bytes = count * sizeof(T);
+        if (tl_alloc) {
+            void* q = tl_alloc->alloc(bytes, tl_alloc->user);
+            if (!q) throw Error(CR_E_OOM, "the context's allocator returned no memory for " + std::to_string(bytes) + " bytes");
+            p = static_cast<T*>(q);
+            al = tl_alloc;
+        } else {
+            hipError_t e = hipMalloc(reinterpret_cast<void**>(&p), bytes);
+            if (e != hipSuccess) {
+                p = nullptr;
+                (void)hipGetLastError();
+                throw Error(CR_E_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+            }
+            al = nullptr;
         }
         n = count;
     }
     // grow (contents not preserved) when smaller than count
     void reserve(size_t count) { if (count > n) alloc(count); }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) {
+            if (al) al->free(p, al->user);
+            else (void)hipFree(p);
+        }
         p = nullptr;
         n = 0;
+        al = nullptr;
     }
     size_t bytes() const { return n * sizeof(T); }
 };
@@ -129,6 +148,35 @@ struct DevSymbolic {
     DevBuf<int32_t> big, big_list, huge, huge_list;
 };
 
+// A frequency-dependent part of K(w) or M(w): a material whose loss factor follows a table.
+// kind 0 (solid stiffness with real E): contributes (1 + i eta(f)) T to K(w);
+// kind 1 (fluid mass int N^T N):         contributes T / (c^2 (1 + i eta(f))) to M(w).
+struct TermMeta {
+    int kind = 0;
+    double c = 0;
+    std::vector<double> f_hz, eta;
+    double eta_at(double f) const {
+        if (f <= f_hz.front()) return eta.front();
+        if (f >= f_hz.back()) return eta.back();
+        size_t k = 1;
+        while (f_hz[k] < f) ++k;
+        const double t = (f - f_hz[k - 1]) / (f_hz[k] - f_hz[k - 1]);
+        return eta[k - 1] + t * (eta[k] - eta[k - 1]);
+    }
+    // coefficient of the term in K(w) (kind 0) or in M(w) (kind 1) at angular frequency w
+    zd coef(double omega) const {
+        const double e = eta_at(omega / (2.0 * 3.14159265358979323846));
+        if (kind == 0) return {1.0, e};
+        const double d = c * c * (1.0 + e * e);   // 1 / (c^2 (1 + i e)) = (1 - i e) / (c^2 (1 + e^2))
+        return {1.0 / d, -e / d};
+    }
+};
+struct FreqTerm : TermMeta {
+    std::vector<zd> vals;   // host, unscaled, on the system's pattern
+    DevBuf<zd> d_vals;      // device, Jacobi-scaled
+};
+constexpr int kMaxTerms = 4;
+
 // scale, scaled device copies and norms of a freshly assembled or imported system
 void finalize_sys(cr_sys sys);
 
@@ -188,6 +236,8 @@ struct Profiler {
 
 struct cr_ctx_s {
     int device = 0;
+    bool has_alloc = false;
+    cr_allocator alloc{};               // device-memory hook (has_alloc)
     hipStream_t stream = nullptr;
     std::string err;
     int num_cu = 256;
@@ -228,6 +278,8 @@ struct cr_sys_s {
     std::vector<int64_t> rowptr;
     std::vector<int32_t> col;
     std::vector<cr::zd> K, M, F;   // F: n x L column-major
+    std::vector<cr::zd> D;         // viscous damping on the same pattern, or empty (D = 0)
+    std::vector<cr::FreqTerm> terms;   // frequency-dependent parts of K(w), M(w) (K, M hold the rest)
     std::vector<int32_t> flags;
     std::vector<int64_t> recv;
     std::vector<double> coords;    // n x 3 DoF coordinates (for nested dissection)
@@ -237,7 +289,7 @@ struct cr_sys_s {
     // device, scaled
     cr::DevBuf<int64_t> d_rowptr;
     cr::DevBuf<int32_t> d_col;
-    cr::DevBuf<cr::zd> d_K, d_M, d_F;
+    cr::DevBuf<cr::zd> d_K, d_M, d_F, d_D;
     cr::DevBuf<double> d_scale;
     cr::DevBuf<int64_t> d_recv;
     cr::DevBuf<int32_t> d_flags;
@@ -261,7 +313,16 @@ struct Factor {
     DevBuf<int32_t> nperturb;
     DevBuf<unsigned long long> amax;
     int32_t n_perturbed = 0;
-    double anorm = 0, anorm_sigma = -1;   // ||A~||_inf at the factored shift
+    double anorm = 0, anorm_omega = -1;   // ||A~||_inf at the factored shift
+    // the shifted operator A~ = opK - opS opM on the system's pattern: (K~, M~, w^2), or for a
+    // system with damping the pre-formed values aval = K~ + i w D~ - w^2 M~ with (aval, aval, 0)
+    DevBuf<zd> aval;
+    const zd* opK = nullptr;
+    const zd* opM = nullptr;
+    double opS = 0;
+    // M(w_j) for the Krylov recurrence: M~, or pre-formed with the frequency-dependent terms
+    DevBuf<zd> mval;
+    const zd* opMass = nullptr;
 };
 
 void upload_symbolic(cr_sys sys);
@@ -296,9 +357,10 @@ int solve_scaled(Factor& f, int nrhs, const zd* B, zd* X, int max_iter, double t
 // of every candidate, candidates already used, geometry features (or null).
 int mlp_propose(cr_mlp m, const std::vector<double>& res, const std::vector<int>& used, const double* geom);
 
-// y = (K~ - sigma M~) x  (or two outputs Kx, Mx) on the device, FP64 CSR.
-void spmm_shifted(cr_sys sys, double sigma, int nrhs, const zd* X, int64_t ldx, zd* Y, int64_t ldy,
-                  hipStream_t s);
+// y = (Kv - sigma Mv) x with values Kv, Mv on the system's pattern (or two outputs Kx, Mx) on the
+// device, FP64 CSR.
+void spmm_shifted(cr_sys sys, const zd* Kv, const zd* Mv, double sigma, int nrhs, const zd* X, int64_t ldx, zd* Y,
+                  int64_t ldy, hipStream_t s);
 void spmm_km(cr_sys sys, int nrhs, const zd* X, int64_t ldx, zd* KX, zd* MX, int64_t ldy, hipStream_t s);
 void spmm_m(cr_sys sys, int nrhs, const zd* X, int64_t ldx, zd* Y, int64_t ldy, hipStream_t s);
 
@@ -307,6 +369,11 @@ void spmm_m(cr_sys sys, int nrhs, const zd* X, int64_t ldx, zd* Y, int64_t ldy, 
 // Run `body`, converting exceptions to a status and ctx->err.
 template <typename F>
 static inline cr_status cr_guard(cr_ctx ctx, F&& body) {
+    struct AllocScope {
+        const cr_allocator* prev;
+        explicit AllocScope(const cr_allocator* a) : prev(cr::tl_alloc) { cr::tl_alloc = a; }
+        ~AllocScope() { cr::tl_alloc = prev; }
+    } scope(ctx && ctx->has_alloc ? &ctx->alloc : nullptr);
     try {
         if (ctx) ctx->err.clear();
         body();

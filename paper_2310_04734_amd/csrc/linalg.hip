@@ -127,10 +127,11 @@ __global__ void k_axpy_copy(int64_t n, const zd* __restrict__ src, zd* __restric
 // ------------------------------------------------------------------ SpMM front-ends
 static inline unsigned spmm_blocks(int64_t n) { return (unsigned)((n * kRowLanes + 255) / 256); }
 
-void spmm_shifted(cr_sys sys, double sigma, int nrhs, const zd* X, int64_t ldx, zd* Y, int64_t ldy, hipStream_t s) {
+void spmm_shifted(cr_sys sys, const zd* Kv, const zd* Mv, double sigma, int nrhs, const zd* X, int64_t ldx, zd* Y,
+                  int64_t ldy, hipStream_t s) {
     ProfScope ps(sys->ctx, "spmm", s);
     hipLaunchKernelGGL(k_spmm<0>, dim3(spmm_blocks(sys->n)), dim3(256), 0, s, sys->n, sys->d_rowptr.p, sys->d_col.p,
-                       sys->d_K.p, sys->d_M.p, sigma, nrhs, X, ldx, (const zd*)nullptr, (int64_t)0, Y, (zd*)nullptr, ldy);
+                       Kv, Mv, sigma, nrhs, X, ldx, (const zd*)nullptr, (int64_t)0, Y, (zd*)nullptr, ldy);
 }
 void spmm_km(cr_sys sys, int nrhs, const zd* X, int64_t ldx, zd* KX, zd* MX, int64_t ldy, hipStream_t s) {
     ProfScope ps(sys->ctx, "spmm", s);
@@ -142,18 +143,18 @@ void spmm_m(cr_sys sys, int nrhs, const zd* X, int64_t ldx, zd* Y, int64_t ldy, 
     hipLaunchKernelGGL(k_spmm<3>, dim3(spmm_blocks(sys->n)), dim3(256), 0, s, sys->n, sys->d_rowptr.p, sys->d_col.p,
                        sys->d_K.p, sys->d_M.p, 0.0, nrhs, X, ldx, (const zd*)nullptr, (int64_t)0, Y, (zd*)nullptr, ldy);
 }
-void spmm_residual(cr_sys sys, double sigma, int nrhs, const zd* X, int64_t ldx, const zd* B, int64_t ldb, zd* R,
-                   int64_t ldr, hipStream_t s) {
+void spmm_residual(cr_sys sys, const zd* Kv, const zd* Mv, double sigma, int nrhs, const zd* X, int64_t ldx,
+                   const zd* B, int64_t ldb, zd* R, int64_t ldr, hipStream_t s) {
     ProfScope ps(sys->ctx, "spmm", s);
     hipLaunchKernelGGL(k_spmm<1>, dim3(spmm_blocks(sys->n)), dim3(256), 0, s, sys->n, sys->d_rowptr.p, sys->d_col.p,
-                       sys->d_K.p, sys->d_M.p, sigma, nrhs, X, ldx, B, ldb, R, (zd*)nullptr, ldr);
+                       Kv, Mv, sigma, nrhs, X, ldx, B, ldb, R, (zd*)nullptr, ldr);
 }
 
-double shifted_norm_inf(cr_sys sys, double sigma, DevBuf<unsigned long long>& scratch, hipStream_t s) {
+double shifted_norm_inf(cr_sys sys, const zd* Kv, const zd* Mv, double sigma, DevBuf<unsigned long long>& scratch,
+                        hipStream_t s) {
     scratch.reserve(1);
     fill_zero(scratch.p, 1, s);
-    hipLaunchKernelGGL(k_rownorm, dim3(256), dim3(256), 0, s, sys->n, sys->d_rowptr.p, sys->d_K.p, sys->d_M.p, sigma,
-                       scratch.p);
+    hipLaunchKernelGGL(k_rownorm, dim3(256), dim3(256), 0, s, sys->n, sys->d_rowptr.p, Kv, Mv, sigma, scratch.p);
     unsigned long long h = 0;
     CR_HIP(hipMemcpyAsync(&h, scratch.p, sizeof(h), hipMemcpyDeviceToHost, s));
     CR_HIP(hipStreamSynchronize(s));
@@ -264,7 +265,6 @@ struct BatchCols {
 static int gmres_cycle(Factor& f, int nrhs, const zd* R, zd* X, int m, double rtol, SolveWork& w, hipStream_t s) {
     cr_sys sys = f.sys;
     const int64_t n = sys->n;
-    const double sigma = f.omega * f.omega;
     const size_t blk = (size_t)n * nrhs;
     w.kry.reserve(blk * (m + 1));
     w.d.reserve(blk);
@@ -299,7 +299,7 @@ static int gmres_cycle(Factor& f, int nrhs, const zd* R, zd* X, int m, double rt
         if (all) break;
         zd* vj = Vb + blk * j;
         zd* vn = Vb + blk * (j + 1);
-        spmm_shifted(sys, sigma, nrhs, vj, n, w.r.p, n, s);          // A v_j (FP64)
+        spmm_shifted(sys, f.opK, f.opM, f.opS, nrhs, vj, n, w.r.p, n, s);   // A v_j (FP64)
         apply_factor(f, nrhs, w.r.p, n, vn, n, 0, w, s);            // (LU)^{-1} A v_j
         ++applications;
         std::vector<zd> h1, h2;
@@ -372,10 +372,9 @@ int solve_scaled(Factor& f, int nrhs, const zd* B, zd* X, int max_iter, double t
 
     cr_sys sys = f.sys;
     const int64_t n = sys->n;
-    const double sigma = f.omega * f.omega;
-    if (f.anorm_sigma != sigma) {
-        f.anorm = shifted_norm_inf(sys, sigma, w.sc, s);
-        f.anorm_sigma = sigma;
+    if (f.anorm_omega != f.omega) {
+        f.anorm = shifted_norm_inf(sys, f.opK, f.opM, f.opS, w.sc, s);
+        f.anorm_omega = f.omega;
     }
     const double anorm = f.anorm;
     w.r.reserve((size_t)n * nrhs);
@@ -388,7 +387,7 @@ int solve_scaled(Factor& f, int nrhs, const zd* B, zd* X, int max_iter, double t
     double prev = 1e300, be = 1e300;
     bool krylov = false;
     for (;;) {
-        spmm_residual(sys, sigma, nrhs, X, n, B, n, w.res.p, n, s);
+        spmm_residual(sys, f.opK, f.opM, f.opS, nrhs, X, n, B, n, w.res.p, n, s);
         fill_zero(nrm, 3 * nrhs, s);
         hipLaunchKernelGGL(k_colmax3, dim3(64, nrhs), dim3(256), 0, s, n, nrhs, w.res.p, X, B, n, nrm);
         CR_HIP(hipMemcpyAsync(w.hred.data(), nrm, 3 * nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -754,6 +753,96 @@ __global__ void k_scale_rows(int64_t n, int nrhs, const zd* __restrict__ src, co
     dst[e] = {src[e].re * f, src[e].im * f};
 }
 }  // namespace
+
+namespace {
+// O = a X + c Y over b columns (complex scalars; O may alias X or Y)
+__global__ void k_comb(int64_t n, int b, zd a, const zd* X, int64_t ldx, zd c, const zd* Y, int64_t ldy, zd* O,
+                       int64_t ldo) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * b) return;
+    const int64_t i = e % n, j = e / n;
+    const zd x = X[i + j * ldx], y = Y[i + j * ldy];
+    O[i + j * ldo] = {a.re * x.re - a.im * x.im + c.re * y.re - c.im * y.im,
+                      a.re * x.im + a.im * x.re + c.re * y.im + c.im * y.re};
+}
+
+// X[:, c] = diag(scale) V XR[:, c] for c < b (b <= kGramB); XR staged through LDS in chunks of 64 rows
+__global__ void __launch_bounds__(256) k_lift(int64_t n, int q, int b, const zd* __restrict__ V, int64_t ldv,
+                                              const zd* __restrict__ XR, int64_t ldr, const double* __restrict__ scale,
+                                              zd* __restrict__ X, int64_t ldx) {
+    __shared__ zd sh[64][kGramB];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double ar[kGramB], ai[kGramB];
+#pragma unroll
+    for (int c = 0; c < kGramB; ++c) ar[c] = ai[c] = 0;
+    for (int k0 = 0; k0 < q; k0 += 64) {
+        const int kn = min(64, q - k0);
+        __syncthreads();
+        for (int e = threadIdx.x; e < 64 * kGramB; e += 256) {
+            const int r = e % 64, c = e / 64;
+            sh[r][c] = (r < kn && c < b) ? XR[k0 + r + (size_t)c * ldr] : zd{0, 0};
+        }
+        __syncthreads();
+        if (i < n) {
+            for (int r = 0; r < kn; ++r) {
+                const zd v = V[i + (int64_t)(k0 + r) * ldv];
+#pragma unroll
+                for (int c = 0; c < kGramB; ++c) {
+                    const zd h = sh[r][c];
+                    ar[c] += v.re * h.re - v.im * h.im;
+                    ai[c] += v.re * h.im + v.im * h.re;
+                }
+            }
+        }
+    }
+    if (i < n) {
+        const double f = scale ? scale[i] : 1.0;
+        for (int c = 0; c < b; ++c) X[i + (int64_t)c * ldx] = {f * ar[c], f * ai[c]};
+    }
+}
+}  // namespace
+
+namespace {
+// dst[i] = src[idx[i]] for i < m
+__global__ void k_gather_idx(int64_t m, const int32_t* __restrict__ idx, const zd* __restrict__ src, zd* __restrict__ dst) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) dst[i] = src[idx[i]];
+}
+// dst[tgt[i]] (+)= src[pos[i]] for i < m (distinct targets within one call)
+__global__ void k_scatter_idx(int64_t m, const int32_t* __restrict__ pos, const int32_t* __restrict__ tgt,
+                              const zd* __restrict__ src, zd* __restrict__ dst, int add) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const zd v = src[pos[i]];
+    zd& d = dst[tgt[i]];
+    if (add) { d.re += v.re; d.im += v.im; }
+    else d = v;
+}
+}  // namespace
+
+void gather_idx(int64_t m, const int32_t* idx, const zd* src, zd* dst, hipStream_t s) {
+    if (m > 0) hipLaunchKernelGGL(k_gather_idx, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, m, idx, src, dst);
+}
+void scatter_idx(int64_t m, const int32_t* pos, const int32_t* tgt, const zd* src, zd* dst, int add, hipStream_t s) {
+    if (m > 0)
+        hipLaunchKernelGGL(k_scatter_idx, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, m, pos, tgt, src, dst, add);
+}
+
+void comb(int64_t n, int b, zd a, const zd* X, int64_t ldx, zd c, const zd* Y, int64_t ldy, zd* O, int64_t ldo,
+          hipStream_t s) {
+    const int64_t tot = n * b;
+    if (tot <= 0) return;
+    hipLaunchKernelGGL(k_comb, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, b, a, X, ldx, c, Y, ldy, O, ldo);
+}
+
+void lift(int64_t n, int q, int ncol, const zd* V, int64_t ldv, const zd* XR, int64_t ldr, const double* scale, zd* X,
+          int64_t ldx, hipStream_t s) {
+    for (int c0 = 0; c0 < ncol; c0 += kGramB) {
+        const int bc = std::min(kGramB, ncol - c0);
+        hipLaunchKernelGGL(k_lift, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, q, bc, V, ldv,
+                           XR + (int64_t)c0 * ldr, ldr, scale, X + (int64_t)c0 * ldx, ldx);
+    }
+}
 
 void copy_cols_scaled(int64_t n, const zd* src, zd* dst, double factor, hipStream_t s) {
     hipLaunchKernelGGL(k_copy_scaled, dim3((unsigned)std::min<int64_t>(1024, (n + 255) / 256)), dim3(256), 0, s, n, src,

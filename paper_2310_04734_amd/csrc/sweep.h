@@ -18,6 +18,10 @@ struct RomDesc {
     const double* omegas;  // frequencies of this model
     zd* out;               // Y: nfreq x L x n_o, or X: nfreq x q x L when out_x
     int q, L, n_o, out_x;
+    // frequency-dependent parts: A_R(w_i) += sum_t tcoef[i * nterm + t] T[t]
+    int nterm;
+    const zd* T[kMaxTerms];
+    const zd* tcoef;       // nfreq x nterm (this model's frequencies)
 };
 
 struct SweepEngine {

@@ -119,8 +119,21 @@ __device__ void col_max3(const TA* __restrict__ a, const TB* __restrict__ b, con
 // correction is below tol ||x_l|| (infinity norms); the item converges when every column has.
 // It stops unconverged after max_iter corrections or when the largest backward error of the
 // unconverged columns fails to halve. Returns whether the item converged.
+// entry o of A_R(w) = K_R + i w D_R - w^2 M_R + sum_t c_t T_t in FP64 (tc: this frequency's c_t)
+__device__ __forceinline__ zd ar_entry(const RomDesc& rd, size_t o, double w, double w2, const zd* tc) {
+    const zd k = rd.KR[o], m = rd.MR[o];
+    double re = k.re - w2 * m.re, im = k.im - w2 * m.im;
+    if (rd.DR) { const zd d = rd.DR[o]; re -= w * d.im; im += w * d.re; }
+    for (int t = 0; t < rd.nterm; ++t) {
+        const zd c = tc[t], v = rd.T[t][o];
+        re += c.re * v.re - c.im * v.im;
+        im += c.re * v.im + c.im * v.re;
+    }
+    return {re, im};
+}
+
 template <typename T>
-__device__ bool solve_item(const RomDesc& rd, double w, cx<T>* __restrict__ A, int* __restrict__ ipiv, zd* __restrict__ X,
+__device__ bool solve_item(const RomDesc& rd, double w, const zd* tc, cx<T>* __restrict__ A, int* __restrict__ ipiv, zd* __restrict__ X,
                            zd* __restrict__ R, const zd* __restrict__ Bv, cx<T>* __restrict__ D, bool refine, int max_iter,
                            double tol, LuShared<T>& sh, double* red, int* s_perturb, int* its_out,
                            double (*cm)[kMaxLoads], double* s_bn) {
@@ -129,11 +142,9 @@ __device__ bool solve_item(const RomDesc& rd, double w, cx<T>* __restrict__ A, i
     const double w2 = w * w;
     double amax = 0;
     for (int e = t; e < q * q; e += kWG) {
-        const zd k = rd.KR[e], m = rd.MR[e];
-        double re = k.re - w2 * m.re, im = k.im - w2 * m.im;
-        if (rd.DR) { const zd d = rd.DR[e]; re -= w * d.im; im += w * d.re; }
-        A[e] = {T(re), T(im)};
-        amax = fmax(amax, fabs(re) + fabs(im));
+        const zd a = ar_entry(rd, e, w, w2, tc);
+        A[e] = {T(a.re), T(a.im)};
+        amax = fmax(amax, fabs(a.re) + fabs(a.im));
     }
     amax = wg_max(amax, red);
     for (int e = t; e < q * L; e += kWG) {
@@ -183,9 +194,8 @@ __device__ bool solve_item(const RomDesc& rd, double w, cx<T>* __restrict__ A, i
                     if (act) {
                         for (int jj = 0; jj < nj; ++jj) {
                             const size_t o = i + (size_t)(j0 + jj) * q;
-                            const zd k = rd.KR[o], m = rd.MR[o];
-                            double ar = k.re - w2 * m.re, ai = k.im - w2 * m.im;
-                            if (rd.DR) { const zd d = rd.DR[o]; ar -= w * d.im; ai += w * d.re; }
+                            const zd a = ar_entry(rd, o, w, w2, tc);
+                            const double ar = a.re, ai = a.im;
                             if (its == 0 && l0 == 0) rowsum += hypot(ar, ai);
 #pragma unroll
                             for (int c = 0; c < kLc; ++c) {
@@ -270,7 +280,8 @@ __global__ void __launch_bounds__(kWG) k_sweep(const RomDesc* __restrict__ roms,
         __syncthreads();
         int its = 0, fell_back = 0, nperturbed = 0;
         cx<T>* Awork = q <= q_lds ? reinterpret_cast<cx<T>*>(dyn_lds) : reinterpret_cast<cx<T>*>(Aslot);
-        bool conv = solve_item<T>(rd, w, Awork, ipiv, X, R, Bv, reinterpret_cast<cx<T>*>(Dslot),
+        const zd* tc = rd.nterm ? rd.tcoef + (size_t)it.y * rd.nterm : nullptr;
+        bool conv = solve_item<T>(rd, w, tc, Awork, ipiv, X, R, Bv, reinterpret_cast<cx<T>*>(Dslot),
                                   refine != 0, max_iter, tol, reinterpret_cast<LuShared<T>&>(sh), red, &s_perturb, &its,
                                   s_cm, s_bn);
         nperturbed = s_perturb;
@@ -279,7 +290,7 @@ __global__ void __launch_bounds__(kWG) k_sweep(const RomDesc* __restrict__ roms,
             // redo this frequency with a complex-FP64 LU
             fell_back = 1;
             int its2 = 0;
-            conv = solve_item<double>(rd, w, reinterpret_cast<cx<double>*>(Aslot), ipiv, X, R, Bv,
+            conv = solve_item<double>(rd, w, tc, reinterpret_cast<cx<double>*>(Aslot), ipiv, X, R, Bv,
                                       reinterpret_cast<cx<double>*>(Dslot), true, max_iter, tol, sh, red, &s_perturb, &its2,
                                       s_cm, s_bn);
             nperturbed += s_perturb;

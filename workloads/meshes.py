@@ -36,6 +36,9 @@ class Material:
     c: float = 0.0       # fluid speed of sound
     E: float = 0.0       # solid Young's modulus
     nu: float = 0.0      # solid Poisson ratio
+    # frequency-dependent loss factor: (f_hz, eta) sample points, piecewise linear and constant
+    # beyond the ends; None = the constant eta above
+    eta_table: tuple | None = None
 
 
 @dataclass
