@@ -322,6 +322,9 @@ typedef struct {
                                   largest residual peaks (at least 3 candidates apart, not
                                   next to a used point) on a copy of the basis and record
                                   the max residual each would leave (training labels)      */
+    int32_t stall_stop;        /* 0, or S > 0: stop once S expansion points in a row added no
+                                  basis column (every new Krylov column fell under the
+                                  deflation ratio, so the reduced model cannot change)      */
 } cr_greedy_opts;
 
 typedef struct {

@@ -4,7 +4,10 @@ subdomains (the iterative alternative of Section 3.2 to one full LU per frequenc
 TEST INFRASTRUCTURE ONLY (see oracle/assembly.py).
 
 Subdomains follow the physical domains (Section 3.2: one subdomain per domain, here the structure
-DoFs and the fluid DoFs), each grown by `overlap` layers of neighbours in the graph of A. The
+DoFs and the fluid DoFs), each grown by `overlap` layers of neighbours in the graph of the
+assembled matrices: DoFs i and j are neighbours when (i, j) is an entry of K or M as assembled
+(the finite-element connectivity, explicit zeros included, e.g. the coupling entries of a face
+normal's zero components). The
 preconditioner is the additive Schwarz sum of Section 3.2,
 
     M^{-1} r = sum_j R_j^T A_j^{-1} R_j r,     A_j = R_j A R_j^T,
@@ -21,11 +24,28 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 
-def subdomains(A, n_u, overlap):
+def structure(*mats):
+    """0/1 matrix of the union of the stored entries of the given CSR matrices and their
+    transposes (explicit zeros count: the graph is the assembled connectivity). Pass the matrices
+    as assembled: a sparse product such as the Jacobi scaling drops stored zeros."""
+    n = mats[0].shape[0]
+    rows, cols = [], []
+    for A in mats:
+        A = A.tocsr()
+        r = np.repeat(np.arange(n), np.diff(A.indptr))
+        rows += [r, A.indices]
+        cols += [A.indices, r]
+    r, c = np.concatenate(rows), np.concatenate(cols)
+    G = sp.csr_matrix((np.ones(len(r)), (r, c)), shape=(n, n))
+    G.data[:] = 1.0
+    return G
+
+
+def subdomains(G, n_u, overlap):
     """[(idx_j, owned_j)]: grown index set (sorted) and the mask of its owned DoFs, per physical
-    domain (structure DoFs < n_u, fluid DoFs >= n_u; an empty domain is left out)."""
-    n = A.shape[0]
-    G = (abs(A) + abs(A).T).tocsr()
+    domain (structure DoFs < n_u, fluid DoFs >= n_u; an empty domain is left out); G is the
+    connectivity (structure(K, M))."""
+    n = G.shape[0]
     out = []
     for lo, hi in ((0, n_u), (n_u, n)):
         if hi <= lo:

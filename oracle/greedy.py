@@ -43,10 +43,12 @@ def first_candidate(cand_hz):
     return int(np.flatnonzero(d == d.min())[0])
 
 
-def greedy(sysd, band_hz, n_cand, blocks, tol, max_shifts):
+def greedy(sysd, band_hz, n_cand, blocks, tol, max_shifts, stall_stop=0):
     """Return dict(basis, rom, shift_idx, shifts_hz, maxres (per iteration), res (last)).
 
-    sysd is the assembled system; the loop runs on its Jacobi-scaled form."""
+    sysd is the assembled system; the loop runs on its Jacobi-scaled form. stall_stop > 0 also
+    stops once that many expansion points in a row added no basis column (all their Krylov
+    columns deflated, so the reduced model and its residuals cannot change any more)."""
     sysd = jacobi_scaled(sysd)
     cand_hz = np.linspace(band_hz[0], band_hz[1], n_cand)
     cand_w = 2 * np.pi * cand_hz
@@ -55,13 +57,18 @@ def greedy(sysd, band_hz, n_cand, blocks, tol, max_shifts):
     used, maxres = [], []
     j = first_candidate(cand_hz)
     res = None
+    stalled = 0
     for _ in range(max_shifts):
         used.append(j)
+        q_before = rb.q
         rb.add_shift(sysd["K"], sysd["M"], sysd["F"], cand_w[j], blocks)
+        stalled = stalled + 1 if rb.q == q_before else 0
         rom = project(sysd, rb.basis)
         res = candidate_residuals(sysd, rb.basis, rom, cand_w)
         maxres.append(float(res.max()))
         if res.max() <= tol:
+            break
+        if stall_stop > 0 and stalled >= stall_stop:
             break
         masked = res.copy()
         masked[used] = -np.inf

@@ -98,7 +98,7 @@ class cr_basis_info(C.Structure):
 class cr_greedy_opts(C.Structure):
     _fields_ = [("f_lo_hz", C.c_double), ("f_hi_hz", C.c_double), ("n_cand", C.c_int32), ("blocks", C.c_int32),
                 ("tol", C.c_double), ("max_shifts", C.c_int32), ("policy", C.c_int32), ("mlp", C.c_void_p),
-                ("geom", C.c_void_p), ("lookahead", C.c_int32)]
+                ("geom", C.c_void_p), ("lookahead", C.c_int32), ("stall_stop", C.c_int32)]
 
 
 class cr_greedy_trace(C.Structure):
@@ -344,10 +344,11 @@ class System:
         return Basis(self, h, info)
 
     def basis_greedy(self, band_hz, n_cand, blocks, tol, max_shifts, prec: int = CR_MIXED, policy=CR_POLICY_GREEDY,
-                     mlp=None, geom=None, lookahead=0):
+                     mlp=None, geom=None, lookahead=0, stall_stop=0):
         g = np.ascontiguousarray(geom if geom is not None else np.zeros(0), np.float64)
         opts = cr_greedy_opts(float(band_hz[0]), float(band_hz[1]), int(n_cand), int(blocks), float(tol),
-                              int(max_shifts), int(policy), mlp.h if mlp is not None else None, _ptr(g), int(lookahead))
+                              int(max_shifts), int(policy), mlp.h if mlp is not None else None, _ptr(g), int(lookahead),
+                              int(stall_stop))
         sidx = np.full(max_shifts, -1, np.int32)
         mres = np.zeros(max_shifts)
         res = np.zeros(n_cand)

@@ -839,9 +839,12 @@ std::unique_ptr<cr_basis_s> run_greedy(cr_sys sys, const cr_greedy_opts* o, cr_p
     std::vector<int> mlp_used;
     std::vector<int2> items(nc);
     for (int c = 0; c < nc; ++c) items[c] = make_int2(0, c);
+    int stalled = 0;
     for (int it = 0; it < o->max_shifts; ++it) {
         used.push_back(j);
+        const int q_before = B->q;
         add_shift(B.get(), fac, sw, cw[j], o->blocks, prec);
+        stalled = B->q == q_before ? stalled + 1 : 0;
         auto rom = rom_from_basis(B.get());
         const int q = B->q;
         Xc.reserve((size_t)nc * q * L);
@@ -859,6 +862,7 @@ std::unique_ptr<cr_basis_s> run_greedy(cr_sys sys, const cr_greedy_opts* o, cr_p
         if (trace && trace->res_hist) std::copy(res.begin(), res.end(), trace->res_hist + (size_t)it * nc);
         maxres.push_back(mx);
         if (mx <= o->tol) break;
+        if (o->stall_stop > 0 && stalled >= o->stall_stop) break;
         if (o->lookahead > 0) {
             // one-step look-ahead over the K largest residual peaks, each tried on a copy
             const int K = o->lookahead;
@@ -927,6 +931,7 @@ std::unique_ptr<cr_basis_s> run_greedy(cr_sys sys, const cr_greedy_opts* o, cr_p
 void check_greedy_opts(cr_sys sys, const cr_greedy_opts* o, cr_precision prec) {
     CR_REQUIRE(o, CR_E_INVALID, "cr_basis_build_greedy: bad arguments");
     CR_REQUIRE(o->n_cand >= 2 && o->n_cand <= 4096 && o->blocks >= 1 && o->max_shifts >= 1 && o->tol > 0 &&
+                   o->stall_stop >= 0 && o->lookahead >= 0 &&
                    std::isfinite(o->f_lo_hz) && std::isfinite(o->f_hi_hz) && o->f_hi_hz > o->f_lo_hz && o->f_lo_hz >= 0,
                CR_E_INVALID, "cr_basis_build_greedy: bad options");
     CR_REQUIRE(prec == CR_FP64 || prec == CR_MIXED, CR_E_INVALID, "cr_basis_build_greedy: bad precision");

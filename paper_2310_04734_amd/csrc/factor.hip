@@ -1298,13 +1298,20 @@ void numeric_factor(Factor& f, cr_sys sys, double omega, cr_precision prec, hipS
             f.opMass = sys->d_M.p;
         }
     } else {
-        f.aval.release();
+        // the shifted operator pre-formed for the refinement residual; the front assembly reads
+        // K~ and M~ directly
+        Comb a{};
+        a.p[a.n] = sys->d_K.p; a.c[a.n++] = {1.0, 0.0};
+        a.p[a.n] = sys->d_M.p; a.c[a.n++] = {-omega * omega, 0.0};
+        f.aval.reserve(nnz);
+        hipLaunchKernelGGL(k_combine, dim3(1024), dim3(256), 0, s, nnz, a, f.aval.p);
         f.mval.release();
         f.opK = sys->d_K.p;
         f.opM = sys->d_M.p;
         f.opS = omega * omega;
         f.opMass = sys->d_M.p;
     }
+    f.opA = f.aval.p;
     f.anorm_omega = -1;
     const double sigma = f.opS;
     // largest |entry| of the shifted matrix sets the perturbation threshold

@@ -317,6 +317,7 @@ struct Factor {
     // the shifted operator A~ = opK - opS opM on the system's pattern: (K~, M~, w^2), or for a
     // system with damping the pre-formed values aval = K~ + i w D~ - w^2 M~ with (aval, aval, 0)
     DevBuf<zd> aval;
+    const zd* opA = nullptr;   // A~ pre-formed (FP64): the refinement residual reads 20 B per entry
     const zd* opK = nullptr;
     const zd* opM = nullptr;
     double opS = 0;

@@ -21,10 +21,11 @@ namespace cr {
 namespace {
 
 constexpr int kRowLanes = 8;   // lanes per CSR row
-constexpr int kRhsChunk = 4;   // right-hand sides per pass over a row
 
 // MODE 0: Y = (K - s M) X     MODE 1: Y = B - (K - s M) X     MODE 2: Y = K X, Y2 = M X     MODE 3: Y = M X
-template <int MODE>
+// M may be null in modes 0 and 1 (K then holds the pre-formed operator). RC right-hand sides per
+// pass over a row: every matrix entry and column index is read once per RC columns of X.
+template <int MODE, int RC>
 __global__ void __launch_bounds__(256) k_spmm(int64_t n, const int64_t* __restrict__ rowptr,
                                               const int32_t* __restrict__ col, const zd* __restrict__ K,
                                               const zd* __restrict__ M, double s, int nrhs, const zd* __restrict__ X,
@@ -34,19 +35,26 @@ __global__ void __launch_bounds__(256) k_spmm(int64_t n, const int64_t* __restri
     const int lane = threadIdx.x % kRowLanes;
     const bool valid = row < n;
     const int64_t b = valid ? rowptr[row] : 0, e = valid ? rowptr[row + 1] : 0;
-    for (int l0 = 0; l0 < nrhs; l0 += kRhsChunk) {
-        double ar[kRhsChunk], ai[kRhsChunk], br[kRhsChunk], bi[kRhsChunk];
+    const bool single = (MODE == 0 || MODE == 1) && M == nullptr;
+    for (int l0 = 0; l0 < nrhs; l0 += RC) {
+        double ar[RC], ai[RC], br[MODE == 2 ? RC : 1], bi[MODE == 2 ? RC : 1];
 #pragma unroll
-        for (int c = 0; c < kRhsChunk; ++c) ar[c] = ai[c] = br[c] = bi[c] = 0;
+        for (int c = 0; c < RC; ++c) ar[c] = ai[c] = 0;
+#pragma unroll
+        for (int c = 0; c < (MODE == 2 ? RC : 1); ++c) br[c] = bi[c] = 0;
         for (int64_t k = b + lane; k < e; k += kRowLanes) {
             const int32_t j = col[k];
-            const zd kv = K[k], mv = M[k];
             double vr, vi;
-            if (MODE == 2) { vr = kv.re; vi = kv.im; }
-            else if (MODE == 3) { vr = mv.re; vi = mv.im; }
-            else { vr = kv.re - s * mv.re; vi = kv.im - s * mv.im; }
+            zd mv{0, 0};
+            if (MODE == 3) { mv = M[k]; vr = mv.re; vi = mv.im; }
+            else {
+                const zd kv = K[k];
+                if (MODE == 2) { mv = M[k]; vr = kv.re; vi = kv.im; }
+                else if (single) { vr = kv.re; vi = kv.im; }
+                else { mv = M[k]; vr = kv.re - s * mv.re; vi = kv.im - s * mv.im; }
+            }
 #pragma unroll
-            for (int c = 0; c < kRhsChunk; ++c) {
+            for (int c = 0; c < RC; ++c) {
                 if (l0 + c >= nrhs) break;
                 const zd x = X[j + (l0 + c) * ldx];
                 ar[c] += vr * x.re - vi * x.im;
@@ -58,7 +66,7 @@ __global__ void __launch_bounds__(256) k_spmm(int64_t n, const int64_t* __restri
             }
         }
 #pragma unroll
-        for (int c = 0; c < kRhsChunk; ++c) {
+        for (int c = 0; c < RC; ++c) {
             for (int off = kRowLanes / 2; off > 0; off >>= 1) {
                 ar[c] += __shfl_xor(ar[c], off, kRowLanes);
                 ai[c] += __shfl_xor(ai[c], off, kRowLanes);
@@ -70,7 +78,7 @@ __global__ void __launch_bounds__(256) k_spmm(int64_t n, const int64_t* __restri
         }
         if (valid && lane == 0) {
 #pragma unroll
-            for (int c = 0; c < kRhsChunk; ++c) {
+            for (int c = 0; c < RC; ++c) {
                 if (l0 + c >= nrhs) break;
                 const int64_t o = row + (l0 + c) * ldy;
                 if (MODE == 0 || MODE == 3) Y[o] = {ar[c], ai[c]};
@@ -110,7 +118,8 @@ __global__ void k_rownorm(int64_t n, const int64_t* __restrict__ rowptr, const z
     double m = 0;
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
         double acc = 0;
-        for (int64_t k = rowptr[r]; k < rowptr[r + 1]; ++k) acc += hypot(K[k].re - s * M[k].re, K[k].im - s * M[k].im);
+        for (int64_t k = rowptr[r]; k < rowptr[r + 1]; ++k)
+            acc += M ? hypot(K[k].re - s * M[k].re, K[k].im - s * M[k].im) : hypot(K[k].re, K[k].im);
         m = fmax(m, acc);
     }
     for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
@@ -127,27 +136,36 @@ __global__ void k_axpy_copy(int64_t n, const zd* __restrict__ src, zd* __restric
 // ------------------------------------------------------------------ SpMM front-ends
 static inline unsigned spmm_blocks(int64_t n) { return (unsigned)((n * kRowLanes + 255) / 256); }
 
+// one launch of k_spmm<MODE, RC> with RC the smallest chunk of {4, 8, 16} that covers nrhs
+template <int MODE>
+static void spmm_launch(cr_sys sys, const zd* Kv, const zd* Mv, double sigma, int nrhs, const zd* X, int64_t ldx,
+                        const zd* B, int64_t ldb, zd* Y, zd* Y2, int64_t ldy, hipStream_t s) {
+    ProfScope ps(sys->ctx, "spmm", s);
+    const dim3 grid(spmm_blocks(sys->n)), blk(256);
+    if (nrhs <= 4 || MODE == 2)
+        hipLaunchKernelGGL((k_spmm<MODE, 4>), grid, blk, 0, s, sys->n, sys->d_rowptr.p, sys->d_col.p, Kv, Mv, sigma, nrhs,
+                           X, ldx, B, ldb, Y, Y2, ldy);
+    else if (nrhs <= 8)
+        hipLaunchKernelGGL((k_spmm<MODE, 8>), grid, blk, 0, s, sys->n, sys->d_rowptr.p, sys->d_col.p, Kv, Mv, sigma, nrhs,
+                           X, ldx, B, ldb, Y, Y2, ldy);
+    else
+        hipLaunchKernelGGL((k_spmm<MODE, 16>), grid, blk, 0, s, sys->n, sys->d_rowptr.p, sys->d_col.p, Kv, Mv, sigma,
+                           nrhs, X, ldx, B, ldb, Y, Y2, ldy);
+}
+
 void spmm_shifted(cr_sys sys, const zd* Kv, const zd* Mv, double sigma, int nrhs, const zd* X, int64_t ldx, zd* Y,
                   int64_t ldy, hipStream_t s) {
-    ProfScope ps(sys->ctx, "spmm", s);
-    hipLaunchKernelGGL(k_spmm<0>, dim3(spmm_blocks(sys->n)), dim3(256), 0, s, sys->n, sys->d_rowptr.p, sys->d_col.p,
-                       Kv, Mv, sigma, nrhs, X, ldx, (const zd*)nullptr, (int64_t)0, Y, (zd*)nullptr, ldy);
+    spmm_launch<0>(sys, Kv, Mv, sigma, nrhs, X, ldx, nullptr, 0, Y, nullptr, ldy, s);
 }
 void spmm_km(cr_sys sys, int nrhs, const zd* X, int64_t ldx, zd* KX, zd* MX, int64_t ldy, hipStream_t s) {
-    ProfScope ps(sys->ctx, "spmm", s);
-    hipLaunchKernelGGL(k_spmm<2>, dim3(spmm_blocks(sys->n)), dim3(256), 0, s, sys->n, sys->d_rowptr.p, sys->d_col.p,
-                       sys->d_K.p, sys->d_M.p, 0.0, nrhs, X, ldx, (const zd*)nullptr, (int64_t)0, KX, MX, ldy);
+    spmm_launch<2>(sys, sys->d_K.p, sys->d_M.p, 0.0, nrhs, X, ldx, nullptr, 0, KX, MX, ldy, s);
 }
 void spmm_m(cr_sys sys, int nrhs, const zd* X, int64_t ldx, zd* Y, int64_t ldy, hipStream_t s) {
-    ProfScope ps(sys->ctx, "spmm", s);
-    hipLaunchKernelGGL(k_spmm<3>, dim3(spmm_blocks(sys->n)), dim3(256), 0, s, sys->n, sys->d_rowptr.p, sys->d_col.p,
-                       sys->d_K.p, sys->d_M.p, 0.0, nrhs, X, ldx, (const zd*)nullptr, (int64_t)0, Y, (zd*)nullptr, ldy);
+    spmm_launch<3>(sys, sys->d_K.p, sys->d_M.p, 0.0, nrhs, X, ldx, nullptr, 0, Y, nullptr, ldy, s);
 }
 void spmm_residual(cr_sys sys, const zd* Kv, const zd* Mv, double sigma, int nrhs, const zd* X, int64_t ldx,
                    const zd* B, int64_t ldb, zd* R, int64_t ldr, hipStream_t s) {
-    ProfScope ps(sys->ctx, "spmm", s);
-    hipLaunchKernelGGL(k_spmm<1>, dim3(spmm_blocks(sys->n)), dim3(256), 0, s, sys->n, sys->d_rowptr.p, sys->d_col.p,
-                       Kv, Mv, sigma, nrhs, X, ldx, B, ldb, R, (zd*)nullptr, ldr);
+    spmm_launch<1>(sys, Kv, Mv, sigma, nrhs, X, ldx, B, ldb, R, nullptr, ldr, s);
 }
 
 double shifted_norm_inf(cr_sys sys, const zd* Kv, const zd* Mv, double sigma, DevBuf<unsigned long long>& scratch,
@@ -299,7 +317,7 @@ static int gmres_cycle(Factor& f, int nrhs, const zd* R, zd* X, int m, double rt
         if (all) break;
         zd* vj = Vb + blk * j;
         zd* vn = Vb + blk * (j + 1);
-        spmm_shifted(sys, f.opK, f.opM, f.opS, nrhs, vj, n, w.r.p, n, s);   // A v_j (FP64)
+        spmm_shifted(sys, f.opA, nullptr, 0.0, nrhs, vj, n, w.r.p, n, s);   // A v_j (FP64)
         apply_factor(f, nrhs, w.r.p, n, vn, n, 0, w, s);            // (LU)^{-1} A v_j
         ++applications;
         std::vector<zd> h1, h2;
@@ -373,7 +391,7 @@ int solve_scaled(Factor& f, int nrhs, const zd* B, zd* X, int max_iter, double t
     cr_sys sys = f.sys;
     const int64_t n = sys->n;
     if (f.anorm_omega != f.omega) {
-        f.anorm = shifted_norm_inf(sys, f.opK, f.opM, f.opS, w.sc, s);
+        f.anorm = shifted_norm_inf(sys, f.opA, nullptr, 0.0, w.sc, s);
         f.anorm_omega = f.omega;
     }
     const double anorm = f.anorm;
@@ -387,7 +405,7 @@ int solve_scaled(Factor& f, int nrhs, const zd* B, zd* X, int max_iter, double t
     double prev = 1e300, be = 1e300;
     bool krylov = false;
     for (;;) {
-        spmm_residual(sys, f.opK, f.opM, f.opS, nrhs, X, n, B, n, w.res.p, n, s);
+        spmm_residual(sys, f.opA, nullptr, 0.0, nrhs, X, n, B, n, w.res.p, n, s);
         fill_zero(nrm, 3 * nrhs, s);
         hipLaunchKernelGGL(k_colmax3, dim3(64, nrhs), dim3(256), 0, s, n, nrhs, w.res.p, X, B, n, nrm);
         CR_HIP(hipMemcpyAsync(w.hred.data(), nrm, 3 * nrhs * sizeof(double), hipMemcpyDeviceToHost, s));

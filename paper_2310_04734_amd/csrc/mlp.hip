@@ -7,8 +7,9 @@
 //   loss = mean over the batch of -log softmax(logits masked to allowed classes)[label]
 //
 // Weights are held as FP32 master copies and used in BF16 (rounded to nearest even) by the
-// forward and backward products, which accumulate in FP32; Adam updates the FP32 masters and
-// re-rounds the BF16 copies. Activations and gradients stay FP32.
+// forward and backward products, which run on the matrix cores (BF16 MFMA, FP32 accumulation);
+// Adam updates the FP32 masters and re-rounds the BF16 copies. Activations and gradients stay
+// FP32 and enter the products as two BF16 parts (hi + lo), so they keep 16 significant bits.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -31,33 +32,59 @@ __device__ __forceinline__ float bf16_round(float x) {
     return __uint_as_float(u);
 }
 
-constexpr int kT = 16;   // GEMM tile
+constexpr int kT = 16;   // MFMA tile (16 x 16 outputs per wave, K = 16 per instruction)
 
-// C[m, n] (+)= sum_k A[m, k] B[k, n] with arbitrary strides; optional bias[n], relu, and
-// relu' mask from Z (C *= (Z > 0)). One 16 x 16 tile per workgroup of 256 threads.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short bf16_bits(float x) { return (short)(__float_as_uint(bf16_round(x)) >> 16); }
+__device__ __forceinline__ float bf16_value(short b) { return __uint_as_float(((unsigned)(unsigned short)b) << 16); }
+
+// C[m, n] (+)= sum_k A[m, k] B[k, n] with arbitrary strides on the matrix cores
+// (v_mfma_f32_16x16x16bf16_1k, FP32 accumulation); optional bias[n], relu, and relu' mask from Z
+// (C *= (Z > 0)). An FP32 operand is split into bf16 hi + lo parts (hi = bf16(x), lo = bf16(x - hi),
+// 16 significant bits together) and multiplied part by part: hi*hi + lo*hi (SPLIT_A) + hi*lo
+// (SPLIT_B); an operand that is already bf16-valued (the weights) is not split. Operand layout of
+// the instruction on gfx950: A[i][k] in lane i + 16 (k / 4), item k % 4; B[k][j] in lane
+// j + 16 (k / 4), item k % 4; output item r of lane l is D[4 (l / 16) + r][l % 16].
+// 256 threads = 4 waves, each one 16 x 16 tile of a 32 x 32 block.
+template <bool SPLIT_A, bool SPLIT_B>
 __global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, const float* __restrict__ A, int64_t sam, int64_t sak,
                                               const float* __restrict__ B, int64_t sbk, int64_t sbn, float* __restrict__ Cm,
                                               int64_t scm, int64_t scn, const float* __restrict__ bias, int relu,
                                               const float* __restrict__ Z, int64_t szm, int64_t szn, int accumulate) {
-    __shared__ float sa[kT][kT + 1], sb[kT][kT + 1];
-    const int tx = threadIdx.x % kT, ty = threadIdx.x / kT;
-    const int m = blockIdx.y * kT + ty, n = blockIdx.x * kT + tx;
-    float acc = 0.f;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int m0 = blockIdx.y * 32 + 16 * (w & 1), n0 = blockIdx.x * 32 + 16 * (w >> 1);
+    const int ia = m0 + (lane & 15), jb = n0 + (lane & 15), kq = 4 * (lane >> 4);
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
     for (int k0 = 0; k0 < K; k0 += kT) {
-        const int ka = k0 + tx, kb = k0 + ty;
-        sa[ty][tx] = (m < M && ka < K) ? A[m * sam + ka * sak] : 0.f;
-        sb[ty][tx] = (kb < K && n < N) ? B[kb * sbk + n * sbn] : 0.f;
-        __syncthreads();
+        bf16x4 ah, al, bh, bl;
 #pragma unroll
-        for (int k = 0; k < kT; ++k) acc = fmaf(sa[ty][k], sb[k][tx], acc);
-        __syncthreads();
+        for (int e = 0; e < 4; ++e) {
+            const int k = k0 + kq + e;
+            const float av = (ia < M && k < K) ? A[ia * sam + k * sak] : 0.f;
+            const float bv = (k < K && jb < N) ? B[k * sbk + jb * sbn] : 0.f;
+            ah[e] = bf16_bits(av);
+            bh[e] = bf16_bits(bv);
+            if (SPLIT_A) al[e] = bf16_bits(av - bf16_value(ah[e]));
+            if (SPLIT_B) bl[e] = bf16_bits(bv - bf16_value(bh[e]));
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc, 0, 0, 0);
+        if (SPLIT_A) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc, 0, 0, 0);
+        if (SPLIT_B) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc, 0, 0, 0);
     }
-    if (m < M && n < N) {
-        if (bias) acc += bias[n];
-        if (accumulate) acc += Cm[m * scm + n * scn];
-        if (relu) acc = fmaxf(acc, 0.f);
-        if (Z && !(Z[m * szm + n * szn] > 0.f)) acc = 0.f;
-        Cm[m * scm + n * scn] = acc;
+    const int n = n0 + (lane & 15);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int m = m0 + 4 * (lane >> 4) + r;
+        if (m < M && n < N) {
+            float v = acc[r];
+            if (bias) v += bias[n];
+            if (accumulate) v += Cm[m * scm + n * scn];
+            if (relu) v = fmaxf(v, 0.f);
+            if (Z && !(Z[m * szm + n * szn] > 0.f)) v = 0.f;
+            Cm[m * scm + n * scn] = v;
+        }
     }
 }
 
@@ -171,12 +198,27 @@ void reserve_batch(cr_mlp m, int batch) {
     m->cap = batch;
 }
 
-void gemm(hipStream_t s, int M, int N, int K, const float* A, int64_t sam, int64_t sak, const float* B, int64_t sbk,
-          int64_t sbn, float* Cm, int64_t scm, int64_t scn, const float* bias, int relu, const float* Z = nullptr,
-          int64_t szm = 0, int64_t szn = 0) {
-    dim3 grid((N + kT - 1) / kT, (M + kT - 1) / kT);
-    hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, M, N, K, A, sam, sak, B, sbk, sbn, Cm, scm, scn, bias, relu, Z, szm,
-                       szn, 0);
+// operand kinds: the weights are bf16-valued (used as they are), activations and gradients are
+// FP32 (split into bf16 hi + lo)
+enum { kF32 = 0, kBF16 = 1 };
+
+void gemm(hipStream_t s, int M, int N, int K, const float* A, int64_t sam, int64_t sak, int kind_a, const float* B,
+          int64_t sbk, int64_t sbn, int kind_b, float* Cm, int64_t scm, int64_t scn, const float* bias, int relu,
+          const float* Z = nullptr, int64_t szm = 0, int64_t szn = 0) {
+    dim3 grid((N + 31) / 32, (M + 31) / 32);
+    const bool sa = kind_a == kF32, sb = kind_b == kF32;
+    if (sa && sb)
+        hipLaunchKernelGGL((k_gemm<true, true>), grid, dim3(256), 0, s, M, N, K, A, sam, sak, B, sbk, sbn, Cm, scm, scn,
+                           bias, relu, Z, szm, szn, 0);
+    else if (sa)
+        hipLaunchKernelGGL((k_gemm<true, false>), grid, dim3(256), 0, s, M, N, K, A, sam, sak, B, sbk, sbn, Cm, scm, scn,
+                           bias, relu, Z, szm, szn, 0);
+    else if (sb)
+        hipLaunchKernelGGL((k_gemm<false, true>), grid, dim3(256), 0, s, M, N, K, A, sam, sak, B, sbk, sbn, Cm, scm, scn,
+                           bias, relu, Z, szm, szn, 0);
+    else
+        hipLaunchKernelGGL((k_gemm<false, false>), grid, dim3(256), 0, s, M, N, K, A, sam, sak, B, sbk, sbn, Cm, scm, scn,
+                           bias, relu, Z, szm, szn, 0);
 }
 
 // forward on X (batch x n_in): activations z_l (pre-relu), a_l, logits
@@ -196,12 +238,12 @@ void forward(cr_mlp m, int batch, const float* X) {
     const float* in = X;
     int nin = m->n_in;
     for (int l = 0; l < 3; ++l) {
-        gemm(s, batch, H, nin, in, nin, 1, Wb + m->off[2 * l], 1, nin, z[l], H, 1, w + m->off[2 * l + 1], 0);
-        gemm(s, batch, H, nin, in, nin, 1, Wb + m->off[2 * l], 1, nin, a[l], H, 1, w + m->off[2 * l + 1], 1);
+        gemm(s, batch, H, nin, in, nin, 1, kF32, Wb + m->off[2 * l], 1, nin, kBF16, z[l], H, 1, w + m->off[2 * l + 1], 0);
+        gemm(s, batch, H, nin, in, nin, 1, kF32, Wb + m->off[2 * l], 1, nin, kBF16, a[l], H, 1, w + m->off[2 * l + 1], 1);
         in = a[l];
         nin = H;
     }
-    gemm(s, batch, m->n_out, H, a[2], H, 1, Wb + m->off[6], 1, H, m->logits.p, m->n_out, 1, w + m->off[7], 0);
+    gemm(s, batch, m->n_out, H, a[2], H, 1, kF32, Wb + m->off[6], 1, H, kBF16, m->logits.p, m->n_out, 1, w + m->off[7], 0);
 }
 
 float backward(cr_mlp m, int batch, const float* X, const int32_t* labels, const float* mask) {
@@ -220,16 +262,16 @@ float backward(cr_mlp m, int batch, const float* X, const int32_t* labels, const
     // layer 4: dW4[o, i] = sum_b dlog[b, o] a3[b, i]; db4 = colsum(dlog); da3 = dlog W4 (masked by z3 > 0)
     float* d_cur = m->dact.p;
     float* d_nxt = m->dact.p + (size_t)batch * H;
-    gemm(s, no, H, batch, m->dlog.p, 1, no, a[2], H, 1, g + m->off[6], H, 1, nullptr, 0);
+    gemm(s, no, H, batch, m->dlog.p, 1, no, kF32, a[2], H, 1, kF32, g + m->off[6], H, 1, nullptr, 0);
     hipLaunchKernelGGL(k_colsum, dim3((no + 255) / 256), dim3(256), 0, s, batch, no, m->dlog.p, g + m->off[7]);
-    gemm(s, batch, H, no, m->dlog.p, no, 1, Wb + m->off[6], H, 1, d_cur, H, 1, nullptr, 0, z[2], H, 1);
+    gemm(s, batch, H, no, m->dlog.p, no, 1, kF32, Wb + m->off[6], H, 1, kBF16, d_cur, H, 1, nullptr, 0, z[2], H, 1);
     for (int l = 2; l >= 0; --l) {
         const float* in = l > 0 ? a[l - 1] : X;
         const int nin = l > 0 ? H : m->n_in;
-        gemm(s, H, nin, batch, d_cur, 1, H, in, nin, 1, g + m->off[2 * l], nin, 1, nullptr, 0);
+        gemm(s, H, nin, batch, d_cur, 1, H, kF32, in, nin, 1, kF32, g + m->off[2 * l], nin, 1, nullptr, 0);
         hipLaunchKernelGGL(k_colsum, dim3((H + 255) / 256), dim3(256), 0, s, batch, H, d_cur, g + m->off[2 * l + 1]);
         if (l > 0) {
-            gemm(s, batch, H, H, d_cur, H, 1, Wb + m->off[2 * l], H, 1, d_nxt, H, 1, nullptr, 0, z[l - 1], H, 1);
+            gemm(s, batch, H, H, d_cur, H, 1, kF32, Wb + m->off[2 * l], H, 1, kBF16, d_nxt, H, 1, nullptr, 0, z[l - 1], H, 1);
             std::swap(d_cur, d_nxt);
         }
     }

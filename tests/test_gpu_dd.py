@@ -33,14 +33,16 @@ def test_preconditioner_matches_oracle(P, ctx, overlap, restricted):
     ss = krylov.jacobi_scaled(s)
     om = 2 * np.pi * 140.0
     A = (ss["K"] - om ** 2 * ss["M"]).tocsr()
-    doms = dd.subdomains(A, s["n_u"], overlap)
+    doms = dd.subdomains(dd.structure(s["K"], s["M"]), s["n_u"], overlap)
     g = P.assemble(ctx, w.mesh, w.loads, w.receivers)
     D = P.DomainDecomposition(g, overlap=overlap, restricted=restricted)
     u = W.SplitMix64(11).uniforms(4 * A.shape[0])
     R = (u[:2 * A.shape[0]] + 1j * u[2 * A.shape[0]:]).reshape(A.shape[0], 2)
     Zo = dd.preconditioner(A, doms, restricted)(R)
     Z = D.precondition(om, torch.from_numpy(R).to(ctx.device)).cpu().numpy()
-    assert np.abs(Z - Zo).max() <= 1e-10 * np.abs(Zo).max()
+    # two backward-stable solves of each subdomain system differ by up to kappa(A_j) u
+    kappa = max(np.linalg.cond(A[idx][:, idx].toarray()) for idx, _ in doms)
+    assert np.abs(Z - Zo).max() <= 50 * kappa * 2.2e-16 * np.abs(Zo).max(), kappa
 
 
 @pytest.mark.parametrize("name", ["plate_cavity_small", "plate_cavity"])

@@ -223,3 +223,19 @@ def test_batched_sweep(P, ctx):
         for k in range(len(roms_o)):
             Yo = rom.sweep(roms_o[k], oms[k])
             assert _rel(Ys[k].cpu().numpy(), Yo).max() <= 1e-6, (k, prec)
+
+
+def test_greedy_stall_stop_box(P, ctx):
+    """The saturation stop of the greedy: the same points up to saturation and the same stop as the
+    oracle (past saturation every residual is at rounding level, so which candidate the maximum
+    picks there is not compared)."""
+    _flush("greedy stall stop")
+    w = W.box()
+    s = assembly.assemble(w.mesh, w.loads, w.receivers)
+    go = greedy.greedy(s, (20.0, 500.0), 64, 10, 1e-15, 30, stall_stop=2)
+    g = P.assemble(ctx, w.mesh, w.loads, w.receivers)
+    g.analyse()
+    B = g.basis_greedy((20.0, 500.0), 64, 10, 1e-15, 30, prec=P.CR_FP64, stall_stop=2)
+    k = len(go["shift_idx"])
+    assert len(B.trace["shift_idx"]) == k and B.q == go["basis"].q
+    assert list(B.trace["shift_idx"][:k - 2]) == list(go["shift_idx"][:k - 2])

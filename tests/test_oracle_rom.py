@@ -204,3 +204,18 @@ def test_greedy_properties():
     om = 2 * np.pi * cand[::7]
     err = rom.relative_error(rom.sweep(g["rom"], om), solve.full_frf(s, om))
     assert err.max() < 1e-4
+
+
+def test_greedy_stops_when_the_space_saturates():
+    """With an unreachable tolerance, stall_stop = 2 ends the greedy after two expansion points in
+    a row that add no column (their Krylov columns all deflate), with the residual unchanged
+    since the last point that added columns; without it the loop runs to the cap."""
+    w = W.box()
+    s = assembly.assemble(w.mesh, w.loads, w.receivers)
+    g = greedy.greedy(s, (20.0, 500.0), 64, 10, 1e-15, 30, stall_stop=2)
+    k = len(g["shift_idx"])
+    assert 3 <= k < 30
+    assert g["maxres"][-1] == g["maxres"][-2] == g["maxres"][-3]
+    g0 = greedy.greedy(s, (20.0, 500.0), 64, 10, 1e-15, 8)
+    assert len(g0["shift_idx"]) == 8 and g0["basis"].q == g["basis"].q
+    assert list(g0["shift_idx"][:k]) == list(g["shift_idx"])
