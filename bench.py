@@ -230,7 +230,7 @@ def bench_fuselage(P, W, ctx, steps, warmup, max_shifts, oracle):
     def step():
         ts = time.perf_counter()
         B = g.basis_greedy(rp["band_hz"], rp["n_cand"], rp["blocks"], rp["tol"], max_shifts, prec=P.CR_FP64,
-                           stall_stop=2)
+                           stall_stop=1)
         R = B.project()
         torch.cuda.synchronize()
         tb = time.perf_counter() - ts
@@ -578,7 +578,7 @@ def main():
         "config": {"workload": "fuselage segment R 1.4 m, L 4 m, 2 mm Al skin hex layer, 5 frames 60 mm deep, air "
                                "O-grid: n=529306 (94,176 u + 435,130 p), 16 random-phase skin pressures, 50 receivers, "
                                f"2000 freqs 20-300 Hz; greedy 64 vectors/point, <= {a.fuselage_shifts} points, tol 1e-6 "
-                               "on 256 candidates, stop after 2 points that add no column; complex-FP64 "
+                               "on 256 candidates, stop at the first point that adds no column; complex-FP64 "
                                "factorisations",
                    "global_batch": f["n_results"], "parallelism": "1 GPU"},
         "accuracy": f["accuracy"],

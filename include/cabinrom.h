@@ -424,8 +424,10 @@ typedef struct {
    partial pivoting over every row (complex FP32 under CR_MIXED, complex FP64 under CR_FP64),
    solve for the L load columns F_R (i w)^flags, then Y = C_R X_R. CR_MIXED refines every
    frequency in FP64 with FP64 K_R, M_R, D_R until each load column's normwise backward error
-   ||r_l||_inf / (||A_R||_inf ||x_l||_inf + ||b_l||_inf) <= 1e-14 (or its last correction is below
-   1e-14 ||x_l||), and redoes a frequency with a complex-FP64 LU when refinement stalls. CR_FP64
+   ||r_l||_inf / (||A_R||_inf ||x_l||_inf + ||b_l||_inf) <= 1e-14 and its last correction is below
+   1e-12 ||x_l||_inf (or that correction is below 1e-14 ||x_l||_inf): a backward error alone would
+   leave up to kappa(A_R) 1e-14 in X. A frequency whose refinement stalls or runs out of
+   corrections is redone with a complex-FP64 LU (counted in fp64_fallbacks). CR_FP64
    solves once, and refines only a frequency whose LU had to perturb a pivot.
    Y_dev: nfreq x L x n_o complex128, receiver index fastest ([w][l][o]).
    Errors: CR_E_NOT_CONVERGED when a refined frequency misses the tolerance (Y and info are

@@ -854,9 +854,9 @@ constexpr int kHugeDiagWG = 512;   // threads of k_huge_diag: two waves per SIMD
 // solved values are staged 64 columns at a time through sh.y
 template <typename T>
 __device__ void huge_rows_update(const cx<T>* __restrict__ F, cx<T>* __restrict__ w, int m, int nrhs, int r0, int rows,
-                                 int c0, int nc, SolveShared<T>& sh) {
+                                 int c0, int nc, SolveShared<T>& sh, int lbeg, int lend) {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    for (int l0 = 0; l0 < nrhs; l0 += kSR) {
+    for (int l0 = lbeg; l0 < min(lend, nrhs); l0 += kSR) {
         const int nr = min(kSR, nrhs - l0);
         if (nr >= kMfmaRhs) {
             // wave w: rows [r0 + 16 w, +16) on the matrix cores, accumulated over all columns
@@ -912,12 +912,25 @@ __device__ void huge_rows_update(const cx<T>* __restrict__ F, cx<T>* __restrict_
 
 // mode 0 (forward): rows [K1, m) receive the super-block [K0, K1); mode 1 (backward): rows
 // [0, K0) receive it; mode 2 (backward, first): rows [0, p) receive the contribution columns
-// [p, m) (U12 x_cb). Workgroup x takes 64 rows.
+// [p, m) (U12 x_cb). A workgroup takes 64 rows and kSR right-hand sides. The workgroups of one
+// row tile's right-hand-side chunks get block indices 8 apart: the dispatcher deals consecutive
+// indices round-robin to the 8 XCDs, so they run on one XCD and share its L2 copy of the rows.
+__device__ __forceinline__ void huge_tile_of(int bid, int nch, int* rowtile, int* chunk) {
+    const int rest = bid >> 3;
+    *chunk = rest % nch;
+    *rowtile = (rest / nch) * 8 + (bid & 7);
+}
+static unsigned huge_grid_x(unsigned rowtiles, int nrhs) {
+    const unsigned nch = (unsigned)((nrhs + kSR - 1) / kSR);
+    return ((rowtiles + 7) / 8) * 8 * nch;
+}
 template <typename T>
 __global__ void __launch_bounds__(kWG) k_huge_rows(const int32_t* __restrict__ huge_list, int mode, int K0,
                                                    SolveArgs<T> a) {
     __shared__ SolveShared<T> sh;
     const int f = huge_list[blockIdx.y];
+    int rowtile, chunk;
+    huge_tile_of((int)blockIdx.x, (a.nrhs + kSR - 1) / kSR, &rowtile, &chunk);
     const int m = a.fsize[f], p = a.npiv[f];
     int rb, re, c0, nc;
     if (mode == 2) {
@@ -929,13 +942,14 @@ __global__ void __launch_bounds__(kWG) k_huge_rows(const int32_t* __restrict__ h
         rb = mode == 0 ? K1 : 0;
         re = mode == 0 ? m : K0;
     }
-    const int r0 = rb + kSB * (int)blockIdx.x;
+    const int r0 = rb + kSB * rowtile;
     if (r0 >= re || nc <= 0) return;
     huge_rows_update<T>(a.arena + a.front_off[f], a.work + a.idx_off[f] * a.nrhs, m, a.nrhs, r0, min(kSB, re - r0), c0,
-                        nc, sh);
+                        nc, sh, chunk * kSR, (chunk + 1) * kSR);
 }
 
-// the super-block [K0, K1) of one front (grid: one workgroup per huge front)
+// the super-block [K0, K1) of one front (grid: one workgroup per huge front and chunk of kSR
+// right-hand sides; the chunks are independent)
 template <typename T, bool UPPER>
 __global__ void __launch_bounds__(kHugeDiagWG) k_huge_diag(const int32_t* __restrict__ huge_list, int K0, SolveArgs<T> a) {
     constexpr int NT = kHugeDiagWG;
@@ -947,7 +961,8 @@ __global__ void __launch_bounds__(kHugeDiagWG) k_huge_diag(const int32_t* __rest
     const cx<T>* F = a.arena + a.front_off[f];
     cx<T>* w = a.work + a.idx_off[f] * a.nrhs;
     const int nrhs = a.nrhs;
-    for (int l0 = 0; l0 < nrhs; l0 += kSR) {
+    const int lc = (int)blockIdx.y * kSR;
+    for (int l0 = lc; l0 < min(nrhs, lc + kSR); l0 += kSR) {
         const int nr = min(kSR, nrhs - l0);
         const int kfirst = UPPER ? K0 + ((K1 - 1 - K0) / kSB) * kSB : K0;
         for (int kb = kfirst; UPPER ? kb >= K0 : kb < K1; kb += UPPER ? -kSB : kSB) {
@@ -973,9 +988,9 @@ __global__ void __launch_bounds__(kHugeDiagWG) k_huge_diag(const int32_t* __rest
         }
     }
     __syncthreads();
-    const int nk = K1 - K0;
-    batched_for<NT, 4>(nk * nrhs, [&](int e) { return w[K0 + e % nk + (size_t)(e / nk) * m]; },
-                        [&](int e, cx<T> v) { a.x[f0 + K0 + e % nk + (size_t)(e / nk) * a.ldx] = v; });
+    const int nk = K1 - K0, nrc = min(kSR, nrhs - lc);
+    batched_for<NT, 4>(nk * nrc, [&](int e) { return w[K0 + e % nk + (size_t)(lc + e / nk) * m]; },
+                        [&](int e, cx<T> v) { a.x[f0 + K0 + e % nk + (size_t)(lc + e / nk) * a.ldx] = v; });
 }
 
 // gather (with precision change) B (old numbering, n x nrhs FP64) -> xp (new numbering, T)
@@ -1177,6 +1192,7 @@ void run_solve(const Factor& f, int nrhs, cx<T>* xp, cx<T>* work, hipStream_t s,
     a.ldx = (int64_t)S.n;
     a.nrhs = nrhs;
     a.work = const_cast<cx<T>*>(work);
+    const unsigned nch = (unsigned)((nrhs + kSR - 1) / kSR);
     {
         for (int l = 0; l < S.nlevel; ++l) {
             const int nf = S.level_off[l + 1] - S.level_off[l];
@@ -1196,8 +1212,8 @@ void run_solve(const Factor& f, int nrhs, cx<T>* xp, cx<T>* work, hipStream_t s,
                     if (K0 < p) gx = std::max(gx, (unsigned)((m - std::min(K0 + kHugeSB, p) + kSB - 1) / kSB));
                 }
                 ProfScope ps(sys->ctx, "front_fwd_huge", s);
-                hipLaunchKernelGGL((k_huge_diag<T, false>), dim3(nh), dim3(kHugeDiagWG), 0, s, hl, K0, a);
-                hipLaunchKernelGGL(k_huge_rows<T>, dim3(gx, nh), dim3(kWG), 0, s, hl, 0, K0, a);
+                hipLaunchKernelGGL((k_huge_diag<T, false>), dim3(nh, nch), dim3(kHugeDiagWG), 0, s, hl, K0, a);
+                hipLaunchKernelGGL(k_huge_rows<T>, dim3(huge_grid_x(gx, nrhs), nh), dim3(kWG), 0, s, hl, 0, K0, a);
             }
         }
         for (int l = S.nlevel - 1; l >= 0; --l) {
@@ -1214,13 +1230,15 @@ void run_solve(const Factor& f, int nrhs, cx<T>* xp, cx<T>* work, hipStream_t s,
             const int32_t* hl = D.huge_list.p + S.huge_off[l];
             {
                 ProfScope ps(sys->ctx, "front_bwd_huge", s);
-                hipLaunchKernelGGL(k_huge_rows<T>, dim3((S.huge_piv[l] + kSB - 1) / kSB, nh), dim3(kWG), 0, s, hl, 2, 0, a);
+                hipLaunchKernelGGL(k_huge_rows<T>, dim3(huge_grid_x((S.huge_piv[l] + kSB - 1) / kSB, nrhs), nh),
+                                   dim3(kWG), 0, s, hl, 2, 0, a);
             }
             for (int K0 = ((S.huge_piv[l] - 1) / kHugeSB) * kHugeSB; K0 >= 0; K0 -= kHugeSB) {
                 ProfScope ps(sys->ctx, "front_bwd_huge", s);
-                hipLaunchKernelGGL((k_huge_diag<T, true>), dim3(nh), dim3(kHugeDiagWG), 0, s, hl, K0, a);
+                hipLaunchKernelGGL((k_huge_diag<T, true>), dim3(nh, nch), dim3(kHugeDiagWG), 0, s, hl, K0, a);
                 if (K0 > 0)
-                    hipLaunchKernelGGL(k_huge_rows<T>, dim3((K0 + kSB - 1) / kSB, nh), dim3(kWG), 0, s, hl, 1, K0, a);
+                    hipLaunchKernelGGL(k_huge_rows<T>, dim3(huge_grid_x((K0 + kSB - 1) / kSB, nrhs), nh), dim3(kWG), 0,
+                                       s, hl, 1, K0, a);
             }
         }
     }

@@ -938,75 +938,120 @@ __global__ void __launch_bounds__(256) k_resid_partial(int64_t n, int q, int L, 
     }
 }
 
-// Large q x L: one candidate per workgroup (grid x), 256 rows per workgroup (grid y), one row per
-// thread, X_c staged through LDS 32 rows at a time, up to 16 load columns per pass. Candidates
-// vary fastest over the grid, so the workgroups resident together share their rows of KV and
-// MV and re-read them from L2 rather than from HBM once per candidate.
-__global__ void __launch_bounds__(256) k_resid_partial_big(int64_t n, int q, int L, int ncand, const zd* __restrict__ KV,
-                                                           const zd* __restrict__ MV, int64_t ldv, const zd* __restrict__ F,
-                                                           const zd* __restrict__ X, const zd* __restrict__ scal,
-                                                           const double* __restrict__ w2, double* __restrict__ partial) {
-    constexpr int kKc = 32, kLc = 16;
-    __shared__ zd xs[kKc][kLc];
-    __shared__ double red[4];
-    const int c = blockIdx.x;
-    const zd* Xc = X + (size_t)c * q * L;
-    const double w2c = w2[c];
-    const int64_t i = (int64_t)blockIdx.y * 256 + threadIdx.x;
-    const bool act = i < n;
-    double acc2 = 0;
-    for (int l0 = 0; l0 < L; l0 += kLc) {
-        const int nl = min(kLc, L - l0);
-        double rr[kLc], ri[kLc];
+// Large q x L on the matrix cores: a workgroup takes 64 rows (16 per wave) and kRG candidates;
+// for each candidate c the wave forms its A operand (K~V - w_c^2 M~V)[rows, k..k+4) from one load
+// of K~V and M~V (shared by the kRG candidates) and multiplies it with X_c[k..k+4, 16 loads] from
+// LDS, v_mfma_f64_16x16x4f64, each complex product as four real ones into real and imaginary
+// accumulators; the epilogue subtracts the product from s_c F and sums |.|^2.
+constexpr int kRG = 8;    // candidates per workgroup
+constexpr int kRK = 16;   // rows of X staged in LDS per chunk
+typedef double rf64x4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256) k_resid_mfma(int64_t n, int q, int L, int ncand, const zd* __restrict__ KV,
+                                                    const zd* __restrict__ MV, int64_t ldv, const zd* __restrict__ F,
+                                                    const zd* __restrict__ X, const zd* __restrict__ scal,
+                                                    const double* __restrict__ w2, double* __restrict__ partial) {
+    __shared__ zd sx[kRG][kRK][16];
+    __shared__ double red[4][kRG];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    // flat grid, candidate group fastest: the groups of one row chunk are dispatched together
+    const int ngroup = (ncand + kRG - 1) / kRG;
+    const int64_t chunk = blockIdx.x / ngroup;
+    const int c0 = (int)(blockIdx.x % ngroup) * kRG, nc = min(kRG, ncand - c0);
+    const int64_t rbase = chunk * 64 + 16 * wave;
+    const int64_t arow = rbase + li;   // the row this lane supplies to the A operand
+    const bool aok = arow < n;
+    double w2c[kRG], acc2[kRG];
 #pragma unroll
-        for (int l = 0; l < kLc; ++l) {
-            rr[l] = ri[l] = 0;
-            if (act && l < nl) {
-                const zd f = F[i + (int64_t)(l0 + l) * n], sc = scal[c * L + l0 + l];
-                rr[l] = f.re * sc.re - f.im * sc.im;
-                ri[l] = f.re * sc.im + f.im * sc.re;
-            }
-        }
-        for (int k0 = 0; k0 < q; k0 += kKc) {
-            const int nk = min(kKc, q - k0);
-            __syncthreads();
-            for (int e = threadIdx.x; e < kKc * kLc; e += 256) {
-                const int kk = e % kKc, l = e / kKc;
-                xs[kk][l] = (kk < nk && l < nl) ? Xc[k0 + kk + (size_t)(l0 + l) * q] : zd{0, 0};
-            }
-            __syncthreads();
-            if (act) {
-                // kG rows of K~V and M~V loaded together (the rows past nk repeat row nk - 1 and
-                // meet zero columns of xs), so that their latency is paid once per kG
-                constexpr int kG = 4;
-                for (int g0 = 0; g0 < nk; g0 += kG) {
-                    zd kv[kG], mv[kG];
-#pragma unroll
-                    for (int g = 0; g < kG; ++g) {
-                        const int64_t col = k0 + min(g0 + g, nk - 1);
-                        kv[g] = KV[i + col * ldv];
-                        mv[g] = MV[i + col * ldv];
-                    }
-#pragma unroll
-                    for (int g = 0; g < kG; ++g) {
-                        const double ar = kv[g].re - w2c * mv[g].re, ai = kv[g].im - w2c * mv[g].im;
-#pragma unroll
-                        for (int l = 0; l < kLc; ++l) {
-                            const zd x = xs[g0 + g][l];
-                            rr[l] -= ar * x.re - ai * x.im;
-                            ri[l] -= ar * x.im + ai * x.re;
-                        }
-                    }
-                }
-            }
-        }
-#pragma unroll
-        for (int l = 0; l < kLc; ++l) acc2 += rr[l] * rr[l] + ri[l] * ri[l];
+    for (int c = 0; c < kRG; ++c) {
+        w2c[c] = c < nc ? w2[c0 + c] : 0.0;
+        acc2[c] = 0.0;
     }
-    for (int off = 32; off > 0; off >>= 1) acc2 += __shfl_xor(acc2, off);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x / 64] = acc2;
+    for (int l0 = 0; l0 < L; l0 += 16) {
+        const int nl = min(16, L - l0);
+        rf64x4 are[kRG], aim[kRG];
+#pragma unroll
+        for (int c = 0; c < kRG; ++c) {
+            are[c] = rf64x4{0, 0, 0, 0};
+            aim[c] = rf64x4{0, 0, 0, 0};
+        }
+        // software pipeline: the next chunk's X entries and A-operand rows are loaded into
+        // registers while the current chunk is multiplied
+        constexpr int XPER = kRG * kRK * 16 / 256;
+        zd xr[XPER], kv[kRK / 4], mv[kRK / 4], kvn[kRK / 4], mvn[kRK / 4];
+        auto fetch = [&](int k0) {
+#pragma unroll
+            for (int u = 0; u < XPER; ++u) {
+                const int e = t + 256 * u;
+                const int l = e % 16, k = (e / 16) % kRK, c = e / (16 * kRK);
+                xr[u] = (c < nc && k0 + k < q && l < nl) ? X[((size_t)(c0 + c) * L + l0 + l) * q + k0 + k]
+                                                         : zd{0.0, 0.0};
+            }
+#pragma unroll
+            for (int s = 0; s < kRK / 4; ++s) {
+                const int k = k0 + 4 * s + lk;
+                const bool ok = aok && k < q;
+                kvn[s] = ok ? KV[arow + (int64_t)k * ldv] : zd{0.0, 0.0};
+                mvn[s] = ok ? MV[arow + (int64_t)k * ldv] : zd{0.0, 0.0};
+            }
+        };
+        fetch(0);
+        for (int k0 = 0; k0 < q; k0 += kRK) {
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < XPER; ++u) {
+                const int e = t + 256 * u;
+                sx[e / (16 * kRK)][(e / 16) % kRK][e % 16] = xr[u];
+            }
+#pragma unroll
+            for (int s = 0; s < kRK / 4; ++s) {
+                kv[s] = kvn[s];
+                mv[s] = mvn[s];
+            }
+            __syncthreads();
+            if (k0 + kRK < q) fetch(k0 + kRK);
+#pragma unroll 1
+            for (int s = 0; s < kRK / 4; ++s)
+#pragma unroll
+                for (int c = 0; c < kRG; ++c) {
+                    const zd b = sx[c][4 * s + lk][li];
+                    const double ar = kv[s].re - w2c[c] * mv[s].re, ai = kv[s].im - w2c[c] * mv[s].im;
+                    are[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, b.re, are[c], 0, 0, 0);
+                    are[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, b.im, are[c], 0, 0, 0);
+                    aim[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, b.im, aim[c], 0, 0, 0);
+                    aim[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, b.re, aim[c], 0, 0, 0);
+                }
+        }
+        // accumulator item r of lane l: row lk + 4 r of the wave's 16, load column li
+        zd fv[4];
+        bool rok[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t row = rbase + lk + 4 * r;
+            rok[r] = row < n && li < nl;
+            fv[r] = rok[r] ? F[row + (int64_t)(l0 + li) * n] : zd{0.0, 0.0};
+        }
+#pragma unroll
+        for (int c = 0; c < kRG; ++c) {
+            if (c >= nc) break;
+            const zd sc = li < nl ? scal[(c0 + c) * L + l0 + li] : zd{0.0, 0.0};
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const double rr = fv[r].re * sc.re - fv[r].im * sc.im - are[c][r];
+                const double ri = fv[r].re * sc.im + fv[r].im * sc.re - aim[c][r];
+                if (rok[r]) acc2[c] += rr * rr + ri * ri;
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < kRG; ++c) {
+        double v = acc2[c];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        if (lane == 0) red[wave][c] = v;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) partial[(size_t)blockIdx.y * ncand + c] = ((red[0] + red[1]) + red[2]) + red[3];
+    if (t < nc) partial[(size_t)chunk * ncand + c0 + t] = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
 }
 
 __global__ void k_resid_reduce(int nchunk, int ncand, const double* __restrict__ partial, double* __restrict__ out) {
@@ -1023,16 +1068,21 @@ __global__ void k_resid_reduce(int nchunk, int ncand, const double* __restrict__
 void candidate_residuals(int64_t n, int q, int L, int ncand, const zd* KV, const zd* MV, int64_t ldv, const zd* F,
                          const zd* X, const zd* scal, const double* w2, double* res2, DevBuf<double>& partial,
                          hipStream_t s) {
-    const int nchunk = (int)((n + 255) / 256);
-    partial.reserve((size_t)nchunk * ncand);
     const size_t shmem = (size_t)q * L * kCandChunk * sizeof(zd);
+    int nchunk;
     if (shmem <= 64 * 1024) {
+        nchunk = (int)((n + 255) / 256);
+        partial.reserve((size_t)nchunk * ncand);
         hipLaunchKernelGGL(k_resid_partial, dim3(nchunk, (ncand + kCandChunk - 1) / kCandChunk), dim3(256), shmem, s, n,
                            q, L, ncand, KV, MV, ldv, F, X, scal, w2, partial.p);
     } else {
-        CR_REQUIRE(nchunk <= 65535, CR_E_INVALID, "candidate residuals: more than 65535 x 256 rows");
-        hipLaunchKernelGGL(k_resid_partial_big, dim3(ncand, nchunk), dim3(256), 0, s, n, q, L, ncand, KV, MV, ldv, F, X,
-                           scal, w2, partial.p);
+        const int64_t nch = (n + 63) / 64, ngroup = (ncand + kRG - 1) / kRG;
+        CR_REQUIRE(nch * ngroup * 256 < ((int64_t)1 << 32), CR_E_UNSUPPORTED,
+                   "candidate residuals: rows x candidates beyond one launch");
+        nchunk = (int)nch;
+        partial.reserve((size_t)nchunk * ncand);
+        hipLaunchKernelGGL(k_resid_mfma, dim3((unsigned)(nch * ngroup)), dim3(256), 0, s, n, q, L, ncand, KV, MV, ldv, F,
+                           X, scal, w2, partial.p);
     }
     hipLaunchKernelGGL(k_resid_reduce, dim3((ncand + 255) / 256), dim3(256), 0, s, nchunk, ncand, partial.p, res2);
 }

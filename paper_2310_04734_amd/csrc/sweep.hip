@@ -116,9 +116,12 @@ __device__ void col_max3(const TA* __restrict__ a, const TB* __restrict__ b, con
 // perturbed, and a perturbed factor is always refined in FP64 so that its solution is either
 // certified or reported. Refinement stops per load column: column l has converged when its
 // normwise backward error ||r_l|| / (||A_R|| ||x_l|| + ||b_l||) <= tol or when the last
-// correction is below tol ||x_l|| (infinity norms); the item converges when every column has.
+// correction is below tol ||x_l|| (infinity norms); with a complex-FP32 factor the backward
+// error test also needs a last correction below 1e-12 ||x_l||. The item converges when every
+// column has.
 // It stops unconverged after max_iter corrections or when the largest backward error of the
 // unconverged columns fails to halve. Returns whether the item converged.
+constexpr double kDxF32 = 1e-12;
 // entry o of A_R(w) = K_R + i w D_R - w^2 M_R + sum_t c_t T_t in FP64 (tc: this frequency's c_t)
 __device__ __forceinline__ zd ar_entry(const RomDesc& rd, size_t o, double w, double w2, const zd* tc) {
     const zd k = rd.KR[o], m = rd.MR[o];
@@ -222,7 +225,11 @@ __device__ bool solve_item(const RomDesc& rd, double w, const zd* tc, cx<T>* __r
         double worst = 0;
         for (int l = 0; l < L; ++l) {
             const double be = cm[0][l] / (an * cm[1][l] + s_bn[l]);
-            const bool ok = be <= tol || cm[2][l] <= tol * cm[1][l];
+            // a complex-FP32 factor contracts the error by about kappa u_32 per correction, so a
+            // small backward error alone leaves up to kappa tol in x: its columns must also have
+            // taken a correction below kDxF32 ||x|| (the remaining error is a fraction of it)
+            const bool ok = sizeof(T) == 8 ? (be <= tol || cm[2][l] <= tol * cm[1][l])
+                                           : (be <= tol && cm[2][l] <= kDxF32 * cm[1][l]) || cm[2][l] <= tol * cm[1][l];
             all = all && ok;
             if (!ok) worst = fmax(worst, be);
         }
