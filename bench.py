@@ -146,7 +146,8 @@ def _roofline(name, launches, ms, an, n_fact, n_solves, elt):
                                "launches": launches,
                                "avg_launch_us": 1e3 * ms / launches,
                                "work_per_launch": f"{an['gemm_flops'] * n_fact / launches:.4g} flop (8 (m - K1)^2 "
-                                                  f"(K1 - K0) per 128-column block of every large front)"})
+                                                  f"(K1 - K0) per 128-column block of every large front, in two "
+                                                  f"launches: the next block's columns, then the rest)"})
     if name in ("front_factor", "front_panel", "front_colstrip", "front_rowstrip"):
         flops = an["factor_flops"] * n_fact
         peak = PEAK_FP32_TFLOPS if elt == 8 else PEAK_FP64_TFLOPS

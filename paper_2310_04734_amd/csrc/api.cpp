@@ -575,6 +575,12 @@ cr_status cr_ctx_create(int device, void* hip_stream, const cr_allocator* alloca
 
 void cr_ctx_destroy(cr_ctx ctx) {
     if (!ctx) return;
+    if (ctx->aux) {
+        (void)hipStreamSynchronize(ctx->aux);
+        (void)hipEventDestroy(ctx->ev_fork);
+        (void)hipEventDestroy(ctx->ev_join);
+        (void)hipStreamDestroy(ctx->aux);
+    }
     delete ctx->sweep;
     delete ctx;
 }
@@ -851,7 +857,10 @@ std::unique_ptr<cr_basis_s> run_greedy(cr_sys sys, const cr_greedy_opts* o, cr_p
         std::vector<RomDesc> rd{desc_of(rom.get(), d_cw.p, Xc.p, 1)};
         int mi, ncv, np;
         E.run(rd, items, CR_FP64, false, s, &mi, &ncv, &np);
-        candidate_residuals(n, q, L, nc, B->KV.p, B->MV.p, n, sys->d_F.p, Xc.p, d_scal.p, d_w2.p, d_res2.p, partial, s);
+        {
+            ProfScope ps(sys->ctx, "resid", s);
+            candidate_residuals(n, q, L, nc, B->KV.p, B->MV.p, n, sys->d_F.p, Xc.p, d_scal.p, d_w2.p, d_res2.p, partial, s);
+        }
         CR_HIP(hipMemcpyAsync(res.data(), d_res2.p, nc * sizeof(double), hipMemcpyDeviceToHost, s));
         CR_HIP(hipStreamSynchronize(s));
         double mx = 0;

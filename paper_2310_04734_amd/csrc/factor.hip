@@ -112,32 +112,45 @@ __global__ void __launch_bounds__(kWG) k_front_factor(const int32_t* __restrict_
 //                     the block's earlier panels (rows tiled over workgroups);
 //   k_front_panel     one workgroup per front: pivots, scaling and the in-panel updates of the
 //                     fully-summed rows [k0, p), row swaps inside the block's columns [K0, k1);
-//   k_front_rowstrip  columns tiled over workgroups: the panel's row swaps on columns [k1, m)
-//                     and [0, K0), then rows [k0, k1) of columns [k1, m) receive the block's
-//                     earlier panels and are solved with the panel's unit-lower diagonal block;
-//                     and rows [p, m) of the panel (one row per thread) solved with its U;
-//   k_front_gemm      after the block's last panel: trailing GEMM with K = 128 on MFMA.
+//   k_front_rowstrip  the panel's row swaps on the block's later columns [k1, Kend), whose rows
+//                     [k0, k1) then receive the block's earlier panels and are solved with the
+//                     panel's unit-lower diagonal block; and rows [p, m) of the panel (one row per
+//                     thread) solved with its U.
+// After the block's panels:
+//   k_front_rowblock  the same row strips for the columns outside the block (the block's swaps
+//                     on [0, K0) and on [Kend, m), and U12 rows of the block on [Kend, m));
+//   k_front_gemm      trailing GEMM with K = 128 on MFMA: first the next block's columns, then
+//                     the rest on the context's second stream, where it overlaps the next
+//                     block's panels (which touch only that block's columns).
 // Swaps are applied before any update of the current block touches the swapped rows outside
 // the block's columns, so both rows of a swap are always in the same state.
 constexpr int kPanelLdsBytes = 96 * 1024;   // LDS for a panel's fully-summed rows (16 columns)
 
+// Two variants, each taking the fronts of its class and skipping the others: LDS = true stages
+// the fully-summed rows in LDS (p - k0 <= panel_lds_rows<T>()); LDS = false works on the front in
+// memory and needs only the small shared state, so it fits on a compute unit beside the trailing
+// GEMM's workgroups of the previous block.
 template <typename T>
+constexpr int panel_lds_rows() { return kPanelLdsBytes / (int)sizeof(cx<T>) / (kNB + 1); }
+
+template <typename T, bool LDS>
 __global__ void __launch_bounds__(kWG) k_front_panel(const int32_t* __restrict__ big_list, int step,
                                                     const int32_t* __restrict__ fsize, const int32_t* __restrict__ npiv,
                                                     const int32_t* __restrict__ first, const int64_t* __restrict__ front_off,
                                                     cx<T>* __restrict__ arena, int32_t* __restrict__ ipiv, T tiny,
                                                     int32_t* nperturb) {
-    constexpr int R = kPanelLdsBytes / (int)sizeof(cx<T>) / (kNB + 1);
+    constexpr int R = panel_lds_rows<T>();
     __shared__ LuShared<T> sh;
-    __shared__ cx<T> pl[R][kNB + 1];
     const int f = big_list[blockIdx.x];
     const int m = fsize[f], p = npiv[f], k0 = step * kNB;
-    if (k0 >= p) return;
+    if (k0 >= p || (p - k0 <= R) != LDS) return;
     const int K0 = (k0 / kOB) * kOB, k1 = min(k0 + kNB, p);
-    if (p - k0 <= R)
+    if constexpr (LDS) {
+        __shared__ cx<T> pl[R][kNB + 1];
         wg_panel_lds<T, R>(arena + front_off[f], m, p, k0, k1, ipiv + first[f], tiny, nperturb, sh, pl, K0);
-    else
+    } else {
         wg_panel<T>(arena + front_off[f], m, m, p, k0, k1, ipiv + first[f], tiny, nperturb, sh, K0, k1, false, p);
+    }
 }
 
 template <typename T>
@@ -154,6 +167,25 @@ __global__ void __launch_bounds__(kWG) k_front_colstrip(const int32_t* __restric
     wg_strip_update<T>(arena + front_off[f], m, r0, min(kST, m - r0), k0, k1 - k0, K0, k0 - K0, sh);
 }
 
+// col[k0:k0+16] <- D^{-1} col[k0:k0+16] with D unit lower (d, zero-padded past the panel's nb
+// rows and columns). The rows past nb solve to their own values (their rows of d are zero) and
+// are written back unchanged, so that loads and stores need no row conditions: the caller owns
+// the whole column, and rows at or past m (only possible past nb) are clamped to row m - 1,
+// which is past the panel as well. Branch-free stores keep the compiler from hoisting every
+// read of d into registers.
+template <typename T>
+__device__ __forceinline__ void unit_lower16(cx<T>* __restrict__ col, int k0, int m, const cx<T> (*d)[kNB + 1]) {
+    cx<T> xv[kNB];
+#pragma unroll
+    for (int r = 0; r < kNB; ++r) xv[r] = col[min(k0 + r, m - 1)];
+#pragma unroll
+    for (int r = 1; r < kNB; ++r)
+#pragma unroll
+        for (int q = 0; q < r; ++q) xv[r] = cfms(xv[r], d[r][q], xv[q]);
+#pragma unroll
+    for (int r = 0; r < kNB; ++r) col[min(k0 + r, m - 1)] = xv[r];
+}
+
 template <typename T>
 struct RowStripShared {
     StripShared<T> st;
@@ -162,7 +194,14 @@ struct RowStripShared {
     SwapShared sw;
 };
 
-template <typename T>
+// The row strip of a panel (see above). The factorisation defers the part outside the panel's
+// 128-column block (the swaps on columns [0, K0) and [Kend, m), and the rows [k0, k1) of U12
+// beyond the block) to k_front_rowblock, so that the next block's panels touch only their own
+// columns: the right columns here are [k1, Kend) with Kend the block's last pivot column + 1.
+// FULL: every front's panel at this step has 16 columns (p - k0 >= 16 or the front is done), so
+// the rows [p, m) part can load and store without column conditions (a conditional store after
+// the unrolled solve makes the compiler hoist every read of the diagonal block into registers).
+template <typename T, bool FULL>
 __global__ void __launch_bounds__(kWG) k_front_rowstrip(const int32_t* __restrict__ big_list, int step,
                                                        const int32_t* __restrict__ fsize, const int32_t* __restrict__ npiv,
                                                        const int32_t* __restrict__ first, const int64_t* __restrict__ front_off,
@@ -172,7 +211,8 @@ __global__ void __launch_bounds__(kWG) k_front_rowstrip(const int32_t* __restric
     const int m = fsize[f], p = npiv[f], k0 = step * kNB;
     if (k0 >= p) return;
     const int K0 = (k0 / kOB) * kOB, k1 = min(k0 + kNB, p), nb = k1 - k0;
-    const int nright = (m - k1 + kST - 1) / kST, nleft = (K0 + kST - 1) / kST;
+    const int Kend = min(K0 + kOB, p);
+    const int nright = (Kend - k1 + kST - 1) / kST, nleft = 0;
     const int nl21 = (m - p + kWG - 1) / kWG;
     const int x = blockIdx.x;
     if (x >= nright + nleft + nl21) return;
@@ -192,7 +232,7 @@ __global__ void __launch_bounds__(kWG) k_front_rowstrip(const int32_t* __restric
         if (i >= m) return;
         cx<T> a[kNB];
 #pragma unroll
-        for (int k = 0; k < kNB; ++k) a[k] = k < nb ? A[i + (size_t)(k0 + k) * m] : cx<T>{T(0), T(0)};
+        for (int k = 0; k < kNB; ++k) a[k] = (FULL || k < nb) ? A[i + (size_t)(k0 + k) * m] : cx<T>{T(0), T(0)};
 #pragma unroll
         for (int k = 0; k < kNB; ++k) {
             a[k] = cmul(a[k], sh.rd[k]);
@@ -201,12 +241,12 @@ __global__ void __launch_bounds__(kWG) k_front_rowstrip(const int32_t* __restric
         }
 #pragma unroll
         for (int k = 0; k < kNB; ++k)
-            if (k < nb) A[i + (size_t)(k0 + k) * m] = a[k];
+            if (FULL || k < nb) A[i + (size_t)(k0 + k) * m] = a[k];
         return;
     }
     const bool right = x < nright;
     const int c0 = right ? k1 + kST * x : kST * (x - nright);
-    const int nc = right ? min(kST, m - c0) : min(kST, K0 - c0);
+    const int nc = right ? min(kST, Kend - c0) : min(kST, K0 - c0);
     const int32_t* pv = ipiv + first[f];
     // the panel's swaps on this tile's columns, composed into one gather
     wg_apply_swaps<T>(A, m, pv, k0, k1, c0, c0 + nc, sh.sw);
@@ -217,25 +257,55 @@ __global__ void __launch_bounds__(kWG) k_front_rowstrip(const int32_t* __restric
         sh.d[i][k] = (i < nb && k < nb) ? A[k0 + i + (size_t)(k0 + k) * m] : cx<T>{T(0), T(0)};
     }
     __syncthreads();
-    if (t < nc) {
-        cx<T>* col = A + (size_t)(c0 + t) * m;
-        cx<T> xv[kNB];
-#pragma unroll
-        for (int r = 0; r < kNB; ++r) xv[r] = r < nb ? col[k0 + r] : cx<T>{T(0), T(0)};
-#pragma unroll
-        for (int r = 1; r < kNB; ++r)
-#pragma unroll
-            for (int q = 0; q < r; ++q) xv[r] = cfms(xv[r], sh.d[r][q], xv[q]);
-#pragma unroll
-        for (int r = 0; r < kNB; ++r)
-            if (r < nb) col[k0 + r] = xv[r];
+    if (t < nc) unit_lower16(A + (size_t)(c0 + t) * m, k0, m, sh.d);
+}
+
+// After the panels of 128-column block [K0, K1): the block's deferred row strips, one
+// workgroup per 64-column tile (blockIdx.y = front). Right tiles (columns [K1, m)): for each
+// panel in order, its row swaps, then rows [k0, k1) receive the block's earlier panels and are
+// solved with the panel's unit-lower diagonal block (U12 = L_bb^{-1} P A[K0:K1, K1:m]). Left tiles
+// (columns [0, K0), the factor's earlier L columns): the block's row swaps. Every tile's work
+// stays in its own columns.
+template <typename T>
+__global__ void __launch_bounds__(kWG) k_front_rowblock(const int32_t* __restrict__ big_list, int blk,
+                                                       const int32_t* __restrict__ fsize, const int32_t* __restrict__ npiv,
+                                                       const int32_t* __restrict__ first, const int64_t* __restrict__ front_off,
+                                                       const int32_t* __restrict__ ipiv, cx<T>* __restrict__ arena) {
+    __shared__ RowStripShared<T> sh;
+    const int f = big_list[blockIdx.y];
+    const int m = fsize[f], p = npiv[f], K0 = blk * kOB;
+    if (K0 >= p) return;
+    const int K1 = min(K0 + kOB, p);
+    const int nright = (m - K1 + kST - 1) / kST, nleft = (K0 + kST - 1) / kST;
+    const int x = blockIdx.x;
+    if (x >= nright + nleft) return;
+    const int t = threadIdx.x;
+    cx<T>* A = arena + front_off[f];
+    const int32_t* pv = ipiv + first[f];
+    const bool right = x < nright;
+    const int c0 = right ? K1 + kST * x : kST * (x - nright);
+    const int nc = right ? min(kST, m - c0) : min(kST, K0 - c0);
+    for (int k0 = K0; k0 < K1; k0 += kNB) {
+        const int k1 = min(k0 + kNB, K1), nb = k1 - k0;
+        wg_apply_swaps<T>(A, m, pv, k0, k1, c0, c0 + nc, sh.sw);
+        if (!right) continue;
+        if (K0 < k0) wg_strip_update<T>(A, m, k0, nb, c0, nc, K0, k0 - K0, sh.st);
+        __syncthreads();
+        for (int e = t; e < kNB * kNB; e += kWG) {
+            const int i = e % kNB, k = e / kNB;
+            sh.d[i][k] = (i < nb && k < nb) ? A[k0 + i + (size_t)(k0 + k) * m] : cx<T>{T(0), T(0)};
+        }
+        __syncthreads();
+        if (t < nc) unit_lower16(A + (size_t)(c0 + t) * m, k0, m, sh.d);
+        __syncthreads();
     }
 }
 
-// large fronts, after 128-column block b: trailing GEMM S -= L21 U12 on MFMA, one TW x TW tile
-// per workgroup (blockIdx.y = front)
+// large fronts, after 128-column block [K0, K1): trailing GEMM S -= L21 U12 on MFMA over rows
+// [K1, m) and a column range, one TW x TW tile per workgroup (blockIdx.y = front). cols 0: all
+// of [K1, m); 1: the next block's pivot columns [K1, K2), K2 = min(K1 + 128, p); 2: [K2, m).
 template <typename T, int TW>
-__global__ void __launch_bounds__(kWG) k_front_gemm(const int32_t* __restrict__ big_list, int blk,
+__global__ void __launch_bounds__(kWG) k_front_gemm(const int32_t* __restrict__ big_list, int blk, int cols,
                                                    const int32_t* __restrict__ fsize, const int32_t* __restrict__ npiv,
                                                    const int64_t* __restrict__ front_off, cx<T>* __restrict__ arena) {
     __shared__ GemmShared<T, TW> sh;
@@ -244,10 +314,13 @@ __global__ void __launch_bounds__(kWG) k_front_gemm(const int32_t* __restrict__ 
     if (K0 >= p) return;
     const int K1 = min(K0 + kOB, p);
     if (K1 >= m) return;
-    const int nt = (m - K1 + TW - 1) / TW;
+    const int K2 = max(K1, min(K1 + kOB, p));
+    const int jlo = cols == 2 ? K2 : K1, jhi = cols == 1 ? K2 : m;
+    if (jhi <= jlo) return;
+    const int nr = (m - K1 + TW - 1) / TW, ncl = (jhi - jlo + TW - 1) / TW;
     const int x = blockIdx.x;
-    if (x >= nt * nt) return;
-    wg_gemm_tile<T, TW>(arena + front_off[f], m, m, K0, K1 - K0, K1 + TW * (x % nt), K1 + TW * (x / nt), sh);
+    if (x >= nr * ncl) return;
+    wg_gemm_tile<T, TW>(arena + front_off[f], m, m, K0, K1 - K0, K1 + TW * (x % nr), jlo + TW * (x / nr), sh, jhi);
 }
 
 // ------------------------------------------------------------------ solves
@@ -1087,6 +1160,7 @@ template <typename T>
 void run_factor(Factor& f, cr_sys sys, double sigma, cx<T>* arena, T tiny, hipStream_t s) {
     const Symbolic& S = *sys->sym;
     const DevSymbolic& D = *sys->dsym;
+    hipStream_t aux = S.big_list.empty() ? nullptr : aux_stream(sys->ctx);
     for (int l = 0; l < S.nlevel; ++l) {
         const int nf = S.level_off[l + 1] - S.level_off[l];
         const int32_t* lf = D.level_fronts.p + S.level_off[l];
@@ -1106,50 +1180,99 @@ void run_factor(Factor& f, cr_sys sys, double sigma, cx<T>* arena, T tiny, hipSt
                                D.front_off.p, arena, f.ipiv.p, tiny, f.nperturb.p, D.big.p);
         }
         const int nbig = S.big_off[l + 1] - S.big_off[l];
+        if (nbig == 0) continue;
         const int32_t* bl = D.big_list.p + S.big_off[l];
-        for (int j = 0; j < S.nsteps[l]; ++j) {
-            unsigned gcol = 0, grow = 0;
+        // Blocks of 128 columns with one block of look-ahead: block b's panels (library stream)
+        // touch only the block's own columns, so they run while the trailing update of block
+        // b - 1 beyond b's columns runs on the second stream; then the deferred row strips of
+        // block b and the update of block b + 1's columns (library stream), and the rest of
+        // block b's update goes to the second stream.
+        const int per = kOB / kNB, nblk = (S.nsteps[l] + per - 1) / per;
+        const bool overlap = aux != nullptr;
+        bool pending = false;   // a trailing update is in flight on the second stream
+        for (int blk = 0; blk < nblk; ++blk) {
+            for (int j = blk * per; j < std::min(S.nsteps[l], (blk + 1) * per); ++j) {
+                unsigned gcol = 0, grow = 0;
+                bool any_lds = false, any_mem = false, full = true;
+                for (int q = S.big_off[l]; q < S.big_off[l + 1]; ++q) {
+                    const int f = S.big_list[q], m = S.fsize[f], p = S.npiv[f], k0 = j * kNB;
+                    if (k0 >= p) continue;
+                    (p - k0 <= panel_lds_rows<T>() ? any_lds : any_mem) = true;
+                    full = full && p - k0 >= kNB;
+                    const int K0 = (k0 / kOB) * kOB, k1 = std::min(k0 + kNB, p), Kend = std::min(K0 + kOB, p);
+                    gcol = std::max(gcol, (unsigned)((m - k0 + kST - 1) / kST));
+                    grow = std::max(grow, (unsigned)((Kend - k1 + kST - 1) / kST + (m - p + kWG - 1) / kWG));
+                }
+                if (j % per != 0 && gcol) {
+                    ProfScope ps(sys->ctx, "front_colstrip", s);
+                    hipLaunchKernelGGL(k_front_colstrip<T>, dim3(gcol, nbig), dim3(kWG), 0, s, bl, j, D.fsize.p,
+                                       D.npiv.p, D.front_off.p, arena);
+                }
+                if (any_mem) {
+                    ProfScope ps(sys->ctx, "front_panel", s);
+                    hipLaunchKernelGGL((k_front_panel<T, false>), dim3(nbig), dim3(kWG), 0, s, bl, j, D.fsize.p,
+                                       D.npiv.p, D.first.p, D.front_off.p, arena, f.ipiv.p, tiny, f.nperturb.p);
+                }
+                if (any_lds) {
+                    ProfScope ps(sys->ctx, "front_panel", s);
+                    hipLaunchKernelGGL((k_front_panel<T, true>), dim3(nbig), dim3(kWG), 0, s, bl, j, D.fsize.p,
+                                       D.npiv.p, D.first.p, D.front_off.p, arena, f.ipiv.p, tiny, f.nperturb.p);
+                }
+                if (grow) {
+                    ProfScope ps(sys->ctx, "front_rowstrip", s);
+                    if (full)
+                        hipLaunchKernelGGL((k_front_rowstrip<T, true>), dim3(grow, nbig), dim3(kWG), 0, s, bl, j,
+                                           D.fsize.p, D.npiv.p, D.first.p, D.front_off.p, f.ipiv.p, arena);
+                    else
+                        hipLaunchKernelGGL((k_front_rowstrip<T, false>), dim3(grow, nbig), dim3(kWG), 0, s, bl, j,
+                                           D.fsize.p, D.npiv.p, D.first.p, D.front_off.p, f.ipiv.p, arena);
+                }
+            }
+            if (pending) {
+                CR_HIP(hipStreamWaitEvent(s, sys->ctx->ev_join, 0));
+                pending = false;
+            }
+            unsigned gblk = 0, t_next = 0, t_rest = 0;
             for (int q = S.big_off[l]; q < S.big_off[l + 1]; ++q) {
-                const int f = S.big_list[q], m = S.fsize[f], p = S.npiv[f], k0 = j * kNB;
-                if (k0 >= p) continue;
-                const int K0 = (k0 / kOB) * kOB, k1 = std::min(k0 + kNB, p);
-                gcol = std::max(gcol, (unsigned)((m - k0 + kST - 1) / kST));
-                grow = std::max(grow, (unsigned)((m - k1 + kST - 1) / kST + (K0 + kST - 1) / kST +
-                                                 (m - p + kWG - 1) / kWG));
+                const int f = S.big_list[q], m = S.fsize[f], p = S.npiv[f], K0 = blk * kOB;
+                if (K0 >= p) continue;
+                const int K1 = std::min(K0 + kOB, p), K2 = std::max(K1, std::min(K1 + kOB, p));
+                gblk = std::max(gblk, (unsigned)((m - K1 + kST - 1) / kST + (K0 + kST - 1) / kST));
+                const unsigned nr = (unsigned)((m - K1 + kGT - 1) / kGT);
+                t_next = std::max(t_next, nr * (unsigned)((K2 - K1 + kGT - 1) / kGT));
+                t_rest = std::max(t_rest, nr * (unsigned)((m - K2 + kGT - 1) / kGT));
             }
-            if (j % (kOB / kNB) != 0 && gcol) {
-                ProfScope ps(sys->ctx, "front_colstrip", s);
-                hipLaunchKernelGGL(k_front_colstrip<T>, dim3(gcol, nbig), dim3(kWG), 0, s, bl, j, D.fsize.p, D.npiv.p,
-                                   D.front_off.p, arena);
-            }
-            {
-                ProfScope ps(sys->ctx, "front_panel", s);
-                hipLaunchKernelGGL(k_front_panel<T>, dim3(nbig), dim3(kWG), 0, s, bl, j, D.fsize.p, D.npiv.p, D.first.p,
-                                   D.front_off.p, arena, f.ipiv.p, tiny, f.nperturb.p);
-            }
-            if (grow) {
-                ProfScope ps(sys->ctx, "front_rowstrip", s);
-                hipLaunchKernelGGL(k_front_rowstrip<T>, dim3(grow, nbig), dim3(kWG), 0, s, bl, j, D.fsize.p, D.npiv.p,
+            if (gblk) {
+                ProfScope ps(sys->ctx, "front_rowblock", s);
+                hipLaunchKernelGGL(k_front_rowblock<T>, dim3(gblk, nbig), dim3(kWG), 0, s, bl, blk, D.fsize.p, D.npiv.p,
                                    D.first.p, D.front_off.p, f.ipiv.p, arena);
             }
-            if (j % (kOB / kNB) == kOB / kNB - 1 || j == S.nsteps[l] - 1) {
-                const int blk = j / (kOB / kNB);
-                int rmax = 0;   // largest trailing order of the level's fronts after this block
-                for (int q = S.big_off[l]; q < S.big_off[l + 1]; ++q) {
-                    const int f = S.big_list[q], m = S.fsize[f], p = S.npiv[f], K0 = blk * kOB;
-                    if (K0 >= p) continue;
-                    rmax = std::max(rmax, m - std::min(K0 + kOB, p));
+            // 64 x 64 tiles: 128 x 128 tiles (one wave per SIMD for their accumulators) were
+            // measured slower on the fuselage fronts
+            if (t_next) {
+                ProfScope ps(sys->ctx, "front_gemm", s);
+                hipLaunchKernelGGL((k_front_gemm<T, kGT>), dim3(t_next, nbig), dim3(kWG), 0, s, bl, blk, 1, D.fsize.p,
+                                   D.npiv.p, D.front_off.p, arena);
+            }
+            if (t_rest) {
+                hipStream_t gs = s;
+                if (overlap) {
+                    CR_HIP(hipEventRecord(sys->ctx->ev_fork, s));
+                    CR_HIP(hipStreamWaitEvent(aux, sys->ctx->ev_fork, 0));
+                    gs = aux;
                 }
-                if (rmax > 0) {
-                    // 64 x 64 tiles: 128 x 128 tiles (one wave per SIMD for their accumulators) were
-                    // measured slower on the fuselage fronts
-                    const unsigned nt = (unsigned)((rmax + kGT - 1) / kGT);
-                    ProfScope ps(sys->ctx, "front_gemm", s);
-                    hipLaunchKernelGGL((k_front_gemm<T, kGT>), dim3(nt * nt, nbig), dim3(kWG), 0, s, bl, blk, D.fsize.p,
-                                       D.npiv.p, D.front_off.p, arena);
+                {
+                    ProfScope ps(sys->ctx, "front_gemm", gs);
+                    hipLaunchKernelGGL((k_front_gemm<T, kGT>), dim3(t_rest, nbig), dim3(kWG), 0, gs, bl, blk, 2,
+                                       D.fsize.p, D.npiv.p, D.front_off.p, arena);
+                }
+                if (overlap) {
+                    CR_HIP(hipEventRecord(sys->ctx->ev_join, aux));
+                    pending = true;
                 }
             }
         }
+        if (pending) CR_HIP(hipStreamWaitEvent(s, sys->ctx->ev_join, 0));
     }
     hipLaunchKernelGGL(k_compose_pivots, dim3(S.nfront), dim3(kWG), 0, s, D.npiv.p, D.first.p, f.ipiv.p, f.psrc.p);
     CR_HIP(hipGetLastError());

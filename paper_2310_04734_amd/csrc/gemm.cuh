@@ -54,11 +54,11 @@ struct GemmShared {
 };
 
 // C[i0:i0+TW, j0:j0+TW] -= A[i0:, k0:k0+K] A[k0:k0+K, j0:] inside the m x m column-major front
-// (rows and columns >= m are skipped). 256 threads; wave w owns the (TW/2) x (TW/2) quadrant
+// (rows >= m and columns >= jend <= m are skipped). 256 threads; wave w owns the (TW/2) x (TW/2) quadrant
 // ((TW/2) (w & 1), (TW/2) (w >> 1)) as BI x BI blocks of 16 x 16 (BI = TW / 32).
 template <typename T, int TW = kGT>
 __device__ void wg_gemm_tile(cx<T>* __restrict__ A, int lda, int m, int k0, int K, int i0, int j0,
-                             GemmShared<T, TW>& sh) {
+                             GemmShared<T, TW>& sh, int jend) {
     typedef typename MfmaAcc<T>::type acc_t;
     constexpr int BI = TW / 32;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -84,7 +84,7 @@ __device__ void wg_gemm_tile(cx<T>* __restrict__ A, int lda, int m, int k0, int 
             const int i = e % TW, k = e / TW;
             ra[q] = (k < nk && i0 + i < m) ? A[i0 + i + (size_t)(k0 + kc + k) * lda] : cx<T>{T(0), T(0)};
             const int k2 = e % KC, j = e / KC;
-            rb[q] = (k2 < nk && j0 + j < m) ? A[k0 + kc + k2 + (size_t)(j0 + j) * lda] : cx<T>{T(0), T(0)};
+            rb[q] = (k2 < nk && j0 + j < jend) ? A[k0 + kc + k2 + (size_t)(j0 + j) * lda] : cx<T>{T(0), T(0)};
         }
     };
     fetch(0);
@@ -127,7 +127,7 @@ __device__ void wg_gemm_tile(cx<T>* __restrict__ A, int lda, int m, int k0, int 
     for (int a = 0; a < BI; ++a)
 #pragma unroll
         for (int b = 0; b < BI; ++b) {
-            const int j = min(j0 + wj + 16 * b + lj, m - 1);
+            const int j = min(j0 + wj + 16 * b + lj, jend - 1);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int i = min(i0 + wi + 16 * a + MfmaAcc<T>::row(lane, r), m - 1);
@@ -142,7 +142,7 @@ __device__ void wg_gemm_tile(cx<T>* __restrict__ A, int lda, int m, int k0, int 
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int i = i0 + wi + 16 * a + MfmaAcc<T>::row(lane, r);
-                if (i < m && j < m) {
+                if (i < m && j < jend) {
                     cx<T> x = cv[a][b][r];
                     x.re -= are[a][b][r];
                     x.im -= aim[a][b][r];

@@ -243,9 +243,23 @@ struct cr_ctx_s {
     int num_cu = 256;
     cr::SweepEngine* sweep = nullptr;   // persistent sweep workspaces (owned)
     cr::Profiler prof;
+    // second stream (default priority) for work that overlaps the library stream, with the
+    // events that order the two; created on first use, owned
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 namespace cr {
+// the context's second stream and its fork / join events, created on first use
+inline hipStream_t aux_stream(cr_ctx_s* ctx) {
+    if (!ctx->aux) {
+        CR_HIP(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
+        CR_HIP(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
+        CR_HIP(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
+    }
+    return ctx->aux;
+}
+
 // RAII bracket of one kernel launch (no-op while profiling is off)
 struct ProfScope {
     cr_ctx_s* ctx;
