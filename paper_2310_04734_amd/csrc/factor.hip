@@ -1021,6 +1021,68 @@ __global__ void __launch_bounds__(kWG) k_huge_rows(const int32_t* __restrict__ h
                         nc, sh, chunk * kSR, (chunk + 1) * kSR);
 }
 
+// The same row updates for kMfmaRhs or more right-hand sides, on the matrix cores: a workgroup
+// takes 16 rows and kSR right-hand sides, wave v sums the 64-column chunks v, v + 4, ... of the
+// source columns with all of a chunk's loads (F rows and solved values) in flight together, and
+// the four partial 16 x 16 tiles are added in LDS in wave order. Four times as many workgroups
+// as 64-row tiles, and one memory round trip per chunk instead of one per 32 columns.
+template <typename T>
+__global__ void __launch_bounds__(kWG) k_huge_rows_mfma(const int32_t* __restrict__ huge_list, int mode, int K0,
+                                                        SolveArgs<T> a) {
+    typedef typename MfmaAcc<T>::type acc_t;
+    __shared__ acc_t red_re[kWG / 64][64], red_im[kWG / 64][64];
+    const int f = huge_list[blockIdx.y];
+    int rowtile, chunk;
+    huge_tile_of((int)blockIdx.x, (a.nrhs + kSR - 1) / kSR, &rowtile, &chunk);
+    const int m = a.fsize[f], p = a.npiv[f];
+    int rb, re, c0, nc;
+    if (mode == 2) {
+        rb = 0, re = p, c0 = p, nc = m - p;
+    } else {
+        if (K0 >= p) return;
+        const int K1 = min(K0 + kHugeSB, p);
+        c0 = K0, nc = K1 - K0;
+        rb = mode == 0 ? K1 : 0;
+        re = mode == 0 ? m : K0;
+    }
+    const int r0 = rb + 16 * rowtile;
+    if (r0 >= re || nc <= 0) return;
+    const int rows = min(16, re - r0), l0 = chunk * kSR, nr = min(kSR, a.nrhs - l0);
+    const cx<T>* F = a.arena + a.front_off[f];
+    cx<T>* w = a.work + a.idx_off[f] * a.nrhs;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6, i = lane & 15, kk = lane >> 4;
+    acc_t dre = {0, 0, 0, 0}, dim = {0, 0, 0, 0};
+    for (int s0 = 64 * wave; s0 < nc; s0 += 64 * (kWG / 64)) {
+        const int ns = min(64, nc - s0);
+        cx<T> av[16], bv[16];
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            const int k = 4 * s + kk;
+            av[s] = (i < rows && k < ns) ? F[r0 + i + (size_t)(c0 + s0 + k) * m] : cx<T>{T(0), T(0)};
+            bv[s] = (k < ns && i < nr) ? w[c0 + s0 + k + (size_t)(l0 + i) * m] : cx<T>{T(0), T(0)};
+        }
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            dre = MfmaAcc<T>::mfma(av[s].re, bv[s].re, dre);
+            dre = MfmaAcc<T>::mfma(-av[s].im, bv[s].im, dre);
+            dim = MfmaAcc<T>::mfma(av[s].re, bv[s].im, dim);
+            dim = MfmaAcc<T>::mfma(av[s].im, bv[s].re, dim);
+        }
+    }
+    red_re[wave][lane] = dre;
+    red_im[wave][lane] = dim;
+    __syncthreads();
+    if (wave == 0) {
+        acc_t sr = red_re[0][lane], si = red_im[0][lane];
+#pragma unroll
+        for (int v = 1; v < kWG / 64; ++v) {
+            sr += red_re[v][lane];
+            si += red_im[v][lane];
+        }
+        mfma_tile_sub<T>(w + (size_t)l0 * m, m, r0, rows, nr, sr, si);
+    }
+}
+
 // the super-block [K0, K1) of one front (grid: one workgroup per huge front and chunk of kSR
 // right-hand sides; the chunks are independent)
 template <typename T, bool UPPER>
@@ -1290,6 +1352,17 @@ void launch_level(bool fwd, bool mr, int nf, hipStream_t s, const int32_t* lf, c
     }
 }
 
+// one launch of the huge-front row updates: the matrix-core kernel (16-row tiles) from kMfmaRhs
+// right-hand sides on, else the 64-row kernel
+template <typename T>
+void huge_rows(const int32_t* hl, int nh, int mode, int K0, unsigned tiles16, unsigned tiles64, const SolveArgs<T>& a,
+               hipStream_t s) {
+    if (a.nrhs >= kMfmaRhs)
+        hipLaunchKernelGGL(k_huge_rows_mfma<T>, dim3(huge_grid_x(tiles16, a.nrhs), nh), dim3(kWG), 0, s, hl, mode, K0, a);
+    else
+        hipLaunchKernelGGL(k_huge_rows<T>, dim3(huge_grid_x(tiles64, a.nrhs), nh), dim3(kWG), 0, s, hl, mode, K0, a);
+}
+
 template <typename T>
 void run_solve(const Factor& f, int nrhs, cx<T>* xp, cx<T>* work, hipStream_t s, const cx<T>* arena) {
     cr_sys sys = f.sys;
@@ -1329,14 +1402,16 @@ void run_solve(const Factor& f, int nrhs, cx<T>* xp, cx<T>* work, hipStream_t s,
             const int nh = S.huge_off[l + 1] - S.huge_off[l];
             const int32_t* hl = D.huge_list.p + S.huge_off[l];
             for (int K0 = 0; K0 < S.huge_piv[l]; K0 += kHugeSB) {
-                unsigned gx = 1;
+                unsigned gx = 1, gx16 = 1;
                 for (int q = S.huge_off[l]; q < S.huge_off[l + 1]; ++q) {
                     const int hf = S.huge_list[q], m = S.fsize[hf], p = S.npiv[hf];
-                    if (K0 < p) gx = std::max(gx, (unsigned)((m - std::min(K0 + kHugeSB, p) + kSB - 1) / kSB));
+                    if (K0 >= p) continue;
+                    gx = std::max(gx, (unsigned)((m - std::min(K0 + kHugeSB, p) + kSB - 1) / kSB));
+                    gx16 = std::max(gx16, (unsigned)((m - std::min(K0 + kHugeSB, p) + 15) / 16));
                 }
                 ProfScope ps(sys->ctx, "front_fwd_huge", s);
                 hipLaunchKernelGGL((k_huge_diag<T, false>), dim3(nh, nch), dim3(kHugeDiagWG), 0, s, hl, K0, a);
-                hipLaunchKernelGGL(k_huge_rows<T>, dim3(huge_grid_x(gx, nrhs), nh), dim3(kWG), 0, s, hl, 0, K0, a);
+                huge_rows(hl, nh, 0, K0, gx16, gx, a, s);
             }
         }
         for (int l = S.nlevel - 1; l >= 0; --l) {
@@ -1353,15 +1428,13 @@ void run_solve(const Factor& f, int nrhs, cx<T>* xp, cx<T>* work, hipStream_t s,
             const int32_t* hl = D.huge_list.p + S.huge_off[l];
             {
                 ProfScope ps(sys->ctx, "front_bwd_huge", s);
-                hipLaunchKernelGGL(k_huge_rows<T>, dim3(huge_grid_x((S.huge_piv[l] + kSB - 1) / kSB, nrhs), nh),
-                                   dim3(kWG), 0, s, hl, 2, 0, a);
+                huge_rows(hl, nh, 2, 0, (unsigned)((S.huge_piv[l] + 15) / 16), (unsigned)((S.huge_piv[l] + kSB - 1) / kSB),
+                          a, s);
             }
             for (int K0 = ((S.huge_piv[l] - 1) / kHugeSB) * kHugeSB; K0 >= 0; K0 -= kHugeSB) {
                 ProfScope ps(sys->ctx, "front_bwd_huge", s);
                 hipLaunchKernelGGL((k_huge_diag<T, true>), dim3(nh, nch), dim3(kHugeDiagWG), 0, s, hl, K0, a);
-                if (K0 > 0)
-                    hipLaunchKernelGGL(k_huge_rows<T>, dim3(huge_grid_x((K0 + kSB - 1) / kSB, nrhs), nh), dim3(kWG), 0,
-                                       s, hl, 1, K0, a);
+                if (K0 > 0) huge_rows(hl, nh, 1, K0, (unsigned)((K0 + 15) / 16), (unsigned)((K0 + kSB - 1) / kSB), a, s);
             }
         }
     }
