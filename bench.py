@@ -83,6 +83,9 @@ def _args():
     ap.add_argument("--batched-roms", type=int, default=256)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 256 MiB device to device 5 times (calibrates HBM byte counters)")
+    ap.add_argument("--factor-probe", action="store_true",
+                    help="only one complex-FP64 factorisation of the fuselage at 140 Hz and one solve with "
+                         "its 16 loads (a short program for profiler counter passes)")
     return ap.parse_args()
 
 
@@ -533,10 +536,34 @@ def copy_probe():
     print(json.dumps({"copy_probe_bytes_per_dispatch": 8 * n, "dispatches": 5}))
 
 
+def factor_probe():
+    """One FP64 factorisation of the fuselage system and one 16-load solve, nothing else timed or
+    checked: the kernels of one expansion point, for profiler counter passes."""
+    import torch
+
+    import paper_2310_04734_amd as P
+    import workloads as W
+    ctx = P.Context(0)
+    w = W.fuselage_workload()
+    g = P.assemble(ctx, w.mesh, w.loads, w.receivers)
+    an = g.analyse()
+    om = 2 * np.pi * 140.0
+    fac = g.factor(om, P.CR_FP64)
+    b = torch.zeros((g.n, g.L), dtype=torch.complex128, device=ctx.device)
+    b[: min(g.n, 1000)] = 1.0
+    fac.solve(b)
+    torch.cuda.synchronize()
+    print(json.dumps({"factor_probe": {"n": g.n, "gemm_flops": an["gemm_flops"], "factor_entries": an["factor_entries"],
+                                       "backward_error": fac.last_info["backward_error"]}}))
+
+
 def main():
     a = _args()
     if a.copy_probe:
         copy_probe()
+        return
+    if a.factor_probe:
+        factor_probe()
         return
     if a.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; how the path would shard over "

@@ -105,6 +105,13 @@ struct LuShared {
     int red_i[kWG / 64 + 1];
     SwapShared sw;
 };
+// the part of LuShared a panel step uses (pivot search and row swaps)
+template <typename T>
+struct PanelShared {
+    T red_v[kWG / 64 + 1];
+    int red_i[kWG / 64 + 1];
+    SwapShared sw;
+};
 
 // The row swaps ipiv[k0..k1) (row k exchanged with row ipiv[k], in order; absolute row indices)
 // applied to columns [ca, cb) of A as one gather: thread 0 composes them into "row r now holds
@@ -186,9 +193,9 @@ __device__ void wg_apply_swaps(cx<T>* __restrict__ A, int lda, const int* ipiv, 
 // in *nperturb.
 // LEAN = true keeps the long-column loop register-light (one row in flight per thread) for
 // callers whose occupancy matters more than memory-level parallelism (the reduced-model sweep).
-template <typename T, bool LEAN = false>
+template <typename T, bool LEAN = false, typename SH = LuShared<T>>
 __device__ __forceinline__ void wg_panel(cx<T>* __restrict__ A, int lda, int m, int p, int k0, int k1, int* __restrict__ ipiv, T tiny,
-                         int* nperturb, LuShared<T>& sh, int sw0, int sw1, bool trsm, int rend) {
+                         int* nperturb, SH& sh, int sw0, int sw1, bool trsm, int rend) {
     const int t = threadIdx.x;
     T best = T(-1);
     int bi = k0;
@@ -313,9 +320,9 @@ __device__ __forceinline__ void wg_panel(cx<T>* __restrict__ A, int lda, int m, 
 // LDS (p - k0 <= R): the 16 columns are staged in LDS, factored there, and written back; the row
 // swaps reach the block's earlier columns [sw0, k0) in global memory after the panel, composed
 // into one gather. Same arithmetic, same order.
-template <typename T, int R>
+template <typename T, int R, typename SH>
 __device__ void wg_panel_lds(cx<T>* __restrict__ A, int lda, int p, int k0, int k1, int* __restrict__ ipiv, T tiny,
-                             int* nperturb, LuShared<T>& sh, cx<T> (*P)[kNB + 1], int sw0) {
+                             int* nperturb, SH& sh, cx<T> (*P)[kNB + 1], int sw0) {
     const int t = threadIdx.x;
     const int rows = p - k0, nb = k1 - k0;
     // eight loads in flight per thread (a plain strided loop waits for each load in turn)

@@ -124,7 +124,9 @@ __global__ void __launch_bounds__(kWG) k_front_factor(const int32_t* __restrict_
 //                     block's panels (which touch only that block's columns).
 // Swaps are applied before any update of the current block touches the swapped rows outside
 // the block's columns, so both rows of a swap are always in the same state.
-constexpr int kPanelLdsBytes = 96 * 1024;   // LDS for a panel's fully-summed rows (16 columns)
+// LDS for a panel's fully-summed rows (16 columns): small enough that the panel fits on a
+// compute unit beside one workgroup of the overlapping trailing GEMM
+constexpr int kPanelLdsBytes = 48 * 1024;
 
 // Two variants, each taking the fronts of its class and skipping the others: LDS = true stages
 // the fully-summed rows in LDS (p - k0 <= panel_lds_rows<T>()); LDS = false works on the front in
@@ -140,7 +142,7 @@ __global__ void __launch_bounds__(kWG) k_front_panel(const int32_t* __restrict__
                                                     cx<T>* __restrict__ arena, int32_t* __restrict__ ipiv, T tiny,
                                                     int32_t* nperturb) {
     constexpr int R = panel_lds_rows<T>();
-    __shared__ LuShared<T> sh;
+    __shared__ PanelShared<T> sh;
     const int f = big_list[blockIdx.x];
     const int m = fsize[f], p = npiv[f], k0 = step * kNB;
     if (k0 >= p || (p - k0 <= R) != LDS) return;
