@@ -140,11 +140,17 @@ def _roofline(name, launches, ms, an, n_fact, n_solves, elt):
                                "work": "half the factor entries x element size per solve"})
     if name == "front_gemm":
         # trailing GEMMs of the large fronts on the matrix cores: exact flops from the analysis
+        # (8 real flops per complex multiply-add); the kernel forms each complex product from
+        # three real ones, so the matrix cores execute 3/4 of them
         flops = an["gemm_flops"] * n_fact
         peak = PEAK_FP32_TFLOPS if elt == 8 else PEAK_FP64_TFLOPS
         ach = flops / (ms * 1e-3) / 1e12
+        key = "fp64_mfma_tflops" if elt == 16 else "fp32_mfma_tflops"
         return _with_measured({"kernel": "front_gemm", "bound": "mfma", "achieved": ach, "peak": peak,
                                "unit": "TFLOP/s", "frac": ach / peak,
+                               "mfma_executed_tflops": 0.75 * ach,
+                               "mfma_executed_frac_of_measured": (0.75 * ach / MEASURED[key]) if MEASURED.get(key)
+                               else None,
                                "traffic": _measured_traffic(f"k_front_gemm<{'double' if elt == 16 else 'float'}, 64>"),
                                "launches": launches,
                                "avg_launch_us": 1e3 * ms / launches,

@@ -4,8 +4,9 @@
 // front can spread its Schur-complement update over the whole chip while small fronts run the
 // whole factorisation inside one workgroup.
 //
-// Complex arithmetic uses four real multiplies per product (no three-multiply variant), so the
-// rounding of every product is the textbook one.
+// Complex arithmetic here uses four real multiplies per product, so the rounding of every
+// product is the textbook one (the large fronts' trailing GEMM on the matrix cores, gemm.cuh,
+// uses three).
 #pragma once
 
 #include <hip/hip_runtime.h>

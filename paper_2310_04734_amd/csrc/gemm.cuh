@@ -6,8 +6,11 @@
 // right -- receives the contributions of panels 0..s-1 of the block (wg_strip_update); after
 // the block the trailing matrix receives all 128 columns at once, S -= L21 U12 with K = 128
 // (wg_gemm_tile), a complex GEMM on MFMA: v_mfma_f32_16x16x4f32 for complex-FP32 fronts and
-// v_mfma_f64_16x16x4f64 for FP64 fronts, each complex product as four real products into
-// separate real and imaginary accumulators.
+// v_mfma_f64_16x16x4f64 for FP64 fronts, each complex product as three real products
+// (Ar Br, Ai Bi, (Ar + Ai)(Br + Bi)): a quarter fewer matrix-core operations than four, with a
+// normwise error bound of the same order (the imaginary part's bound grows from
+// |Ar||Bi| + |Ai||Br| to (|Ar| + |Ai|)(|Br| + |Bi|) times u); the factor is only ever used
+// under FP64 refinement with a certified backward error.
 //
 // MFMA 16x16x4 operand layout (lane l of a 64-wide wavefront, checked on gfx950): A[i][k] with
 // i = l % 16, k = l / 16; B[k][j] with j = l % 16, k = l / 16; the accumulator's item r is
@@ -63,13 +66,16 @@ __device__ void wg_gemm_tile(cx<T>* __restrict__ A, int lda, int m, int k0, int 
     constexpr int BI = TW / 32;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wi = (TW / 2) * (w & 1), wj = (TW / 2) * (w >> 1);
-    acc_t are[BI][BI], aim[BI][BI];
+    // three real products per complex one: p1 = sum Ar Br, p2 = sum Ai Bi,
+    // p3 = sum (Ar + Ai)(Br + Bi); Re = p1 - p2, Im = p3 - p1 - p2
+    acc_t p1[BI][BI], p2[BI][BI], p3[BI][BI];
 #pragma unroll
     for (int a = 0; a < BI; ++a)
 #pragma unroll
         for (int b = 0; b < BI; ++b) {
-            are[a][b] = acc_t{0, 0, 0, 0};
-            aim[a][b] = acc_t{0, 0, 0, 0};
+            p1[a][b] = acc_t{0, 0, 0, 0};
+            p2[a][b] = acc_t{0, 0, 0, 0};
+            p3[a][b] = acc_t{0, 0, 0, 0};
         }
     constexpr int KC = GemmShared<T, TW>::KC;
     constexpr int PER = TW * KC / kWG;   // entries of each operand chunk per thread
@@ -102,40 +108,43 @@ __device__ void wg_gemm_tile(cx<T>* __restrict__ A, int lda, int m, int k0, int 
         const int li = lane & 15, lk = lane >> 4;
         for (int kk = 0; kk < nk; kk += 4) {
             cx<T> av[BI], bv[BI];
+            T as[BI], bs[BI];
 #pragma unroll
-            for (int a = 0; a < BI; ++a) av[a] = sh.a[kk + lk][wi + 16 * a + li];
+            for (int a = 0; a < BI; ++a) {
+                av[a] = sh.a[kk + lk][wi + 16 * a + li];
+                as[a] = av[a].re + av[a].im;
+            }
 #pragma unroll
-            for (int b = 0; b < BI; ++b) bv[b] = sh.b[kk + lk][wj + 16 * b + li];
+            for (int b = 0; b < BI; ++b) {
+                bv[b] = sh.b[kk + lk][wj + 16 * b + li];
+                bs[b] = bv[b].re + bv[b].im;
+            }
 #pragma unroll
             for (int a = 0; a < BI; ++a)
 #pragma unroll
                 for (int b = 0; b < BI; ++b) {
-                    are[a][b] = MfmaAcc<T>::mfma(av[a].re, bv[b].re, are[a][b]);
-                    are[a][b] = MfmaAcc<T>::mfma(-av[a].im, bv[b].im, are[a][b]);
-                    aim[a][b] = MfmaAcc<T>::mfma(av[a].re, bv[b].im, aim[a][b]);
-                    aim[a][b] = MfmaAcc<T>::mfma(av[a].im, bv[b].re, aim[a][b]);
+                    p1[a][b] = MfmaAcc<T>::mfma(av[a].re, bv[b].re, p1[a][b]);
+                    p2[a][b] = MfmaAcc<T>::mfma(av[a].im, bv[b].im, p2[a][b]);
+                    p3[a][b] = MfmaAcc<T>::mfma(as[a], bs[b], p3[a][b]);
                 }
         }
     }
-    // epilogue: each lane owns 4 rows of one column per 16 x 16 block; all of the lane's C
-    // entries are loaded before the first store, so the read-modify-write pays one memory
-    // latency instead of one per entry (entries outside the front read a clamped address and
-    // are not stored)
+    // epilogue: each lane owns 4 rows of one column per 16 x 16 block; a row of blocks at a time,
+    // all of its C entries are loaded before the first store (entries outside the front read a
+    // clamped address and are not stored)
     const int lj = lane & 15;
-    cx<T> cv[BI][BI][4];
 #pragma unroll
-    for (int a = 0; a < BI; ++a)
+    for (int a = 0; a < BI; ++a) {
+        cx<T> cv[BI][4];
 #pragma unroll
         for (int b = 0; b < BI; ++b) {
             const int j = min(j0 + wj + 16 * b + lj, jend - 1);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int i = min(i0 + wi + 16 * a + MfmaAcc<T>::row(lane, r), m - 1);
-                cv[a][b][r] = A[i + (size_t)j * lda];
+                cv[b][r] = A[i + (size_t)j * lda];
             }
         }
-#pragma unroll
-    for (int a = 0; a < BI; ++a)
 #pragma unroll
         for (int b = 0; b < BI; ++b) {
             const int j = j0 + wj + 16 * b + lj;
@@ -143,13 +152,15 @@ __device__ void wg_gemm_tile(cx<T>* __restrict__ A, int lda, int m, int k0, int 
             for (int r = 0; r < 4; ++r) {
                 const int i = i0 + wi + 16 * a + MfmaAcc<T>::row(lane, r);
                 if (i < m && j < jend) {
-                    cx<T> x = cv[a][b][r];
-                    x.re -= are[a][b][r];
-                    x.im -= aim[a][b][r];
+                    cx<T> x = cv[b][r];
+                    const T s1 = p1[a][b][r], s2 = p2[a][b][r];
+                    x.re -= s1 - s2;
+                    x.im -= p3[a][b][r] - s1 - s2;
                     A[i + (size_t)j * lda] = x;
                 }
             }
         }
+    }
 }
 
 template <typename T>
