@@ -941,8 +941,8 @@ __global__ void __launch_bounds__(256) k_resid_partial(int64_t n, int q, int L, 
 // Large q x L on the matrix cores: a workgroup takes 64 rows (16 per wave) and kRG candidates;
 // for each candidate c the wave forms its A operand (K~V - w_c^2 M~V)[rows, k..k+4) from one load
 // of K~V and M~V (shared by the kRG candidates) and multiplies it with X_c[k..k+4, 16 loads] from
-// LDS, v_mfma_f64_16x16x4f64, each complex product as four real ones into real and imaginary
-// accumulators; the epilogue subtracts the product from s_c F and sums |.|^2.
+// LDS, v_mfma_f64_16x16x4f64, each complex product as three real ones (Ar Br, Ai Bi,
+// (Ar + Ai)(Br + Bi)); the epilogue subtracts the product from s_c F and sums |.|^2.
 constexpr int kRG = 8;    // candidates per workgroup
 constexpr int kRK = 16;   // rows of X staged in LDS per chunk
 typedef double rf64x4 __attribute__((ext_vector_type(4)));
@@ -952,6 +952,7 @@ __global__ void __launch_bounds__(256) k_resid_mfma(int64_t n, int q, int L, int
                                                     const zd* __restrict__ X, const zd* __restrict__ scal,
                                                     const double* __restrict__ w2, double* __restrict__ partial) {
     __shared__ zd sx[kRG][kRK][16];
+    __shared__ double sxs[kRG][kRK][16];   // re + im of sx (three real products per complex one)
     __shared__ double red[4][kRG];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int li = lane & 15, lk = lane >> 4;
@@ -970,11 +971,13 @@ __global__ void __launch_bounds__(256) k_resid_mfma(int64_t n, int q, int L, int
     }
     for (int l0 = 0; l0 < L; l0 += 16) {
         const int nl = min(16, L - l0);
-        rf64x4 are[kRG], aim[kRG];
+        // p1 = sum ar br, p2 = sum ai bi, p3 = sum (ar + ai)(br + bi): Re = p1 - p2, Im = p3 - p1 - p2
+        rf64x4 p1[kRG], p2[kRG], p3[kRG];
 #pragma unroll
         for (int c = 0; c < kRG; ++c) {
-            are[c] = rf64x4{0, 0, 0, 0};
-            aim[c] = rf64x4{0, 0, 0, 0};
+            p1[c] = rf64x4{0, 0, 0, 0};
+            p2[c] = rf64x4{0, 0, 0, 0};
+            p3[c] = rf64x4{0, 0, 0, 0};
         }
         // software pipeline: the next chunk's X entries and A-operand rows are loaded into
         // registers while the current chunk is multiplied
@@ -1003,6 +1006,7 @@ __global__ void __launch_bounds__(256) k_resid_mfma(int64_t n, int q, int L, int
             for (int u = 0; u < XPER; ++u) {
                 const int e = t + 256 * u;
                 sx[e / (16 * kRK)][(e / 16) % kRK][e % 16] = xr[u];
+                sxs[e / (16 * kRK)][(e / 16) % kRK][e % 16] = xr[u].re + xr[u].im;
             }
 #pragma unroll
             for (int s = 0; s < kRK / 4; ++s) {
@@ -1012,16 +1016,19 @@ __global__ void __launch_bounds__(256) k_resid_mfma(int64_t n, int q, int L, int
             __syncthreads();
             if (k0 + kRK < q) fetch(k0 + kRK);
 #pragma unroll 1
-            for (int s = 0; s < kRK / 4; ++s)
+            for (int s = 0; s < kRK / 4; ++s) {
+                const double kvs = kv[s].re + kv[s].im, mvs = mv[s].re + mv[s].im;
 #pragma unroll
                 for (int c = 0; c < kRG; ++c) {
                     const zd b = sx[c][4 * s + lk][li];
+                    const double bsum = sxs[c][4 * s + lk][li];
                     const double ar = kv[s].re - w2c[c] * mv[s].re, ai = kv[s].im - w2c[c] * mv[s].im;
-                    are[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, b.re, are[c], 0, 0, 0);
-                    are[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, b.im, are[c], 0, 0, 0);
-                    aim[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, b.im, aim[c], 0, 0, 0);
-                    aim[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, b.re, aim[c], 0, 0, 0);
+                    const double asum = kvs - w2c[c] * mvs;
+                    p1[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, b.re, p1[c], 0, 0, 0);
+                    p2[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, b.im, p2[c], 0, 0, 0);
+                    p3[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(asum, bsum, p3[c], 0, 0, 0);
                 }
+            }
         }
         // accumulator item r of lane l: row lk + 4 r of the wave's 16, load column li
         zd fv[4];
@@ -1038,8 +1045,9 @@ __global__ void __launch_bounds__(256) k_resid_mfma(int64_t n, int q, int L, int
             const zd sc = li < nl ? scal[(c0 + c) * L + l0 + li] : zd{0.0, 0.0};
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const double rr = fv[r].re * sc.re - fv[r].im * sc.im - are[c][r];
-                const double ri = fv[r].re * sc.im + fv[r].im * sc.re - aim[c][r];
+                const double s1 = p1[c][r], s2 = p2[c][r];
+                const double rr = fv[r].re * sc.re - fv[r].im * sc.im - (s1 - s2);
+                const double ri = fv[r].re * sc.im + fv[r].im * sc.re - (p3[c][r] - s1 - s2);
                 if (rok[r]) acc2[c] += rr * rr + ri * ri;
             }
         }
