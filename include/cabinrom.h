@@ -429,6 +429,13 @@ typedef struct {
    leave up to kappa(A_R) 1e-14 in X. A frequency whose refinement stalls or runs out of
    corrections is redone with a complex-FP64 LU (counted in fp64_fallbacks). CR_FP64
    solves once, and refines only a frequency whose LU had to perturb a pivot.
+   CR_FP64 models without D_R and frequency-dependent terms, with q <= 512, L <= 16 and
+   n_o <= 256 are solved through the Hessenberg-triangular form of the pencil instead (the same
+   result up to rounding): on first use the library reduces (K_R, M_R) with unitary Q, Z to
+   Q^H K_R Z = H upper Hessenberg, Q^H M_R Z = T upper triangular (kept with the model, 2 q^2 +
+   q (L + n_o) complex entries of device memory), and each frequency solves
+   (H - w^2 T) x~ = Q^H F_R (i w)^flags with partial pivoting in O(q^2), Y = (C_R Z) x~. A
+   numerically singular pivot sends that frequency to the dense LU with FP64 refinement.
    Y_dev: nfreq x L x n_o complex128, receiver index fastest ([w][l][o]).
    Errors: CR_E_NOT_CONVERGED when a refined frequency misses the tolerance (Y and info are
    still written); CR_E_UNSUPPORTED for q > 4096 or L > 64. */
@@ -447,7 +454,9 @@ cr_status cr_sweep_windows(int32_t nwin, const cr_rom* roms, const double* win_h
                            const double* omegas, cr_precision prec, cr_z* Y_dev, cr_sweep_info* info);
 
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
-   loops, harnesses that forbid hipMalloc): cr_sweep with the same arguments, results and errors,
+   loops, harnesses that forbid hipMalloc): cr_sweep with the same arguments, results (always
+   through the dense LU: for CR_FP64 models that cr_sweep solves through the Hessenberg form, the
+   two agree to rounding) and errors,
    but every buffer it needs beyond the reduced model, omegas and Y_dev (model descriptor, work
    queue, statistics, a device copy of the frequencies, per-workgroup LU and refinement
    workspaces) lives in a static device array of 128 MiB that each device holds from its first

@@ -51,6 +51,10 @@ struct cr_rom_s {
     std::vector<TermMeta> tmeta;
     std::vector<DevBuf<zd>> TR;
     DevBuf<zd> tcoef;   // per-call coefficient table (nfreq x nterm)
+    // Hessenberg-triangular form of (K_R, M_R) for FP64 sweeps (built on first use)
+    bool ht_ready = false;
+    DevBuf<zd> htH, htT, htF, htC;
+    DevBuf<double> htN;
 };
 
 struct cr_basis_s {
@@ -435,6 +439,33 @@ void fill_sweep_info(cr_sweep_info* info, int mi, int nc, int fb, int np, double
     info->seconds = secs;
 }
 
+// whether a sweep of r in this precision (and with refinement requested or not) takes the
+// Hessenberg-triangular path
+bool use_ht(const cr_rom_s* r, cr_precision prec, bool refine, int out_x) {
+    return prec == CR_FP64 && !refine && !out_x && ht_eligible(r->q, r->L, r->n_o, r->has_d, (int)r->tmeta.size());
+}
+
+// Reduce the models that take the Hessenberg-triangular path and have no reduced form yet, one
+// workgroup per model in one launch.
+void ensure_ht(const std::vector<cr_rom_s*>& roms, hipStream_t s) {
+    std::vector<HtJob> jobs;
+    std::vector<cr_rom_s*> todo;
+    for (cr_rom_s* r : roms) {
+        if (r->ht_ready || std::find(todo.begin(), todo.end(), r) != todo.end()) continue;
+        const size_t q = (size_t)r->q;
+        r->htH.alloc(q * q);
+        r->htT.alloc(q * q);
+        r->htF.alloc(q * (size_t)r->L);
+        r->htC.alloc((size_t)r->n_o * q);
+        r->htN.alloc(2);
+        jobs.push_back(HtJob{r->KR.p, r->MR.p, r->FR.p, r->CR.p, r->htH.p, r->htT.p, r->htF.p, r->htC.p, r->htN.p,
+                             r->q, r->L, r->n_o});
+        todo.push_back(r);
+    }
+    ht_reduce(jobs, s);
+    for (cr_rom_s* r : todo) r->ht_ready = true;
+}
+
 RomDesc desc_of(const cr_rom_s* r, const double* omegas_dev, zd* out, int out_x) {
     RomDesc d;
     d.KR = r->KR.p;
@@ -452,7 +483,18 @@ RomDesc desc_of(const cr_rom_s* r, const double* omegas_dev, zd* out, int out_x)
     d.nterm = 0;
     for (int t = 0; t < kMaxTerms; ++t) d.T[t] = nullptr;
     d.tcoef = nullptr;
+    d.H = d.Th = d.Ft = d.Ct = nullptr;
+    d.htnorm = nullptr;
     return d;
+}
+
+// point the descriptor at the model's Hessenberg-triangular form (built by ensure_ht)
+void attach_ht(const cr_rom_s* r, RomDesc& d) {
+    d.H = r->htH.p;
+    d.Th = r->htT.p;
+    d.Ft = r->htF.p;
+    d.Ct = r->htC.p;
+    d.htnorm = r->htN.p;
 }
 
 // Frequency-dependent terms of a reduced model: upload the coefficient table of the given host
@@ -1197,6 +1239,10 @@ cr_status cr_sweep(cr_rom r, int32_t nfreq, const double* omegas, cr_precision p
         if (nfreq) CR_HIP(hipMemcpyAsync(E.d_omega.p, omegas, nfreq * sizeof(double), hipMemcpyHostToDevice, s));
         std::vector<RomDesc> roms{desc_of(r, E.d_omega.p, reinterpret_cast<zd*>(Y_dev), 0)};
         attach_terms(r, roms[0], omegas, nfreq, s);
+        if (nfreq && use_ht(r, prec, prec == CR_MIXED, 0)) {
+            ensure_ht({r}, s);
+            attach_ht(r, roms[0]);
+        }
         std::vector<int2> items(nfreq);
         for (int i = 0; i < nfreq; ++i) items[i] = make_int2(0, i);
         int mi = 0, nc = 0, np = 0, fb = 0;
@@ -1279,6 +1325,15 @@ cr_status cr_sweep_batched(cr_ctx ctx, int32_t nrom, const cr_rom* roms, int32_t
                            "cr_sweep_batched: a model with frequency-dependent terms appears twice");
             attach_terms(roms[m], ds[m], omegas + (size_t)m * nfreq, nfreq, s);
         }
+        const bool refine = prec == CR_MIXED || (tune && tune->refine);
+        {
+            std::vector<cr_rom_s*> hts;
+            for (int m = 0; m < nrom; ++m)
+                if (nfreq && use_ht(roms[m], prec, refine, 0)) hts.push_back(roms[m]);
+            ensure_ht(hts, s);
+            for (int m = 0; m < nrom; ++m)
+                if (nfreq && use_ht(roms[m], prec, refine, 0)) attach_ht(roms[m], ds[m]);
+        }
         // longest first: q^3 descending, then model index, then frequency
         std::vector<int> order(nrom);
         std::iota(order.begin(), order.end(), 0);
@@ -1288,7 +1343,6 @@ cr_status cr_sweep_batched(cr_ctx ctx, int32_t nrom, const cr_rom* roms, int32_t
         for (int m : order)
             for (int i = 0; i < nfreq; ++i) items.push_back(make_int2(m, i));
         int mi = 0, nc = 0, np = 0, fb = 0;
-        const bool refine = prec == CR_MIXED || (tune && tune->refine);
         const int gpc = tune && tune->grid_per_cu > 0 ? tune->grid_per_cu : 2;
         const int lds = tune && tune->variant == 1 ? tune->nb * 1024 : 0;
         E.prepare(ds, items, s);
@@ -1401,6 +1455,15 @@ extern "C" cr_status cr_sweep_plan_create(cr_ctx ctx, int32_t nrom, const cr_rom
                        "cr_sweep_plan_create: reduced models with frequency-dependent terms need cr_sweep");
             ds[m] = desc_of(roms[m], P->omegas.p + (size_t)m * nfreq, reinterpret_cast<zd*>(Y_dev[m]), 0);
         }
+        const bool refine = prec == CR_MIXED || (tune && tune->refine);
+        {
+            std::vector<cr_rom_s*> hts;
+            for (int m = 0; m < nrom; ++m)
+                if (use_ht(roms[m], prec, refine, 0)) hts.push_back(roms[m]);
+            ensure_ht(hts, s);
+            for (int m = 0; m < nrom; ++m)
+                if (use_ht(roms[m], prec, refine, 0)) attach_ht(roms[m], ds[m]);
+        }
         std::vector<int> order(nrom);
         std::iota(order.begin(), order.end(), 0);
         std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return ds[a].q > ds[b].q; });
@@ -1408,7 +1471,6 @@ extern "C" cr_status cr_sweep_plan_create(cr_ctx ctx, int32_t nrom, const cr_rom
         items.reserve(nw);
         for (int m : order)
             for (int i = 0; i < nfreq; ++i) items.push_back(make_int2(m, i));
-        const bool refine = prec == CR_MIXED || (tune && tune->refine);
         if (!tune || tune->variant == 0) {
             P->eng->autotune(ds, items, prec, refine, s, &P->gpc, &P->lds, &P->tune_ms);
         } else {

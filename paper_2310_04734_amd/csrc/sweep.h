@@ -22,13 +22,35 @@ struct RomDesc {
     int nterm;
     const zd* T[kMaxTerms];
     const zd* tcoef;       // nfreq x nterm (this model's frequencies)
+    // Hessenberg-triangular form of the pencil, for models without D_R and terms: Q^H K_R Z = H
+    // (upper Hessenberg), Q^H M_R Z = Th (upper triangular), Ft = Q^H F_R, Ct = C_R Z (n_o x q),
+    // htnorm = {max |H|, max |Th|}; null when absent
+    const zd *H, *Th, *Ft, *Ct;
+    const double* htnorm;
 };
+
+// One reduction to Hessenberg-triangular form (k_ht_reduce): inputs K_R, M_R, F_R, C_R of one
+// model, outputs H, Th, Ft, Ct and htnorm (device, caller-allocated).
+struct HtJob {
+    const zd *KR, *MR, *FR, *CR;
+    zd *H, *Th, *Ft, *Ct;
+    double* htnorm;
+    int q, L, n_o;
+};
+constexpr int kHtMaxQ = 512, kHtMaxL = 16, kHtMaxOut = 256;   // limits of the Hessenberg sweep
+// whether a model can take the Hessenberg sweep (FP64 sweeps without refinement, outputs Y)
+inline bool ht_eligible(int q, int L, int n_o, bool has_d, int nterm) {
+    return !has_d && nterm == 0 && q >= 1 && q <= kHtMaxQ && L >= 1 && L <= kHtMaxL && n_o >= 1 && n_o <= kHtMaxOut;
+}
+void ht_reduce(const std::vector<HtJob>& jobs, hipStream_t s);
 
 struct SweepEngine {
     int num_cu = 256;
     cr_ctx_s* ctx = nullptr;
     DevBuf<RomDesc> d_roms;
-    DevBuf<int2> d_items;
+    DevBuf<int2> d_items;     // dense-LU items first (nitems), then nht Hessenberg items
+    DevBuf<int2> d_redo;      // Hessenberg items handed to the dense path (count in d_stats[6])
+    int nht = 0, nht_big = 0, qht = 0;   // Hessenberg items, of which nht_big have q > 256
     DevBuf<int> d_stats;
     DevBuf<zd> wsA, wsX, wsR, wsB, wsD;
     DevBuf<int> wsP;

@@ -244,13 +244,17 @@ __device__ bool solve_item(const RomDesc& rd, double w, const zd* tc, cx<T>* __r
 }
 
 // stats: [0] max refinement iterations, [1] not converged, [2] perturbed pivots,
-//        [3] FP64 fallbacks, [4] work-queue counter
+//        [3] FP64 fallbacks, [4] dense work-queue counter, [5] Hessenberg work-queue counter
+//        (orders <= 256), [6] Hessenberg items handed to the dense path, [7] their work-queue
+//        counter, [8] Hessenberg work-queue counter (orders above 256)
+// nitems_dev (when not null) holds the item count on the device (the redo list of the Hessenberg
+// sweep); qctr is the stats index of this launch's work-queue counter.
 template <typename T>
 __global__ void __launch_bounds__(kWG) k_sweep(const RomDesc* __restrict__ roms, const int2* __restrict__ items, int nitems,
                                                int64_t slot_a, int64_t slot_v, zd* __restrict__ wsA, int* __restrict__ wsP,
                                                zd* __restrict__ wsX, zd* __restrict__ wsR, zd* __restrict__ wsB,
                                                zd* __restrict__ wsD, int refine, int max_iter, double tol,
-                                               int* __restrict__ stats, int q_lds) {
+                                               int* __restrict__ stats, int q_lds, const int* nitems_dev, int qctr) {
     __shared__ LuShared<double> sh;   // large enough for the FP32 variant as well
     extern __shared__ double dyn_lds[];   // reduced matrix of orders q <= q_lds (LDS-resident variant)
     __shared__ double red[8];
@@ -265,7 +269,8 @@ __global__ void __launch_bounds__(kWG) k_sweep(const RomDesc* __restrict__ roms,
     zd* R = wsR + (size_t)blockIdx.x * slot_v;
     zd* Bv = wsB + (size_t)blockIdx.x * slot_v;
     zd* Dslot = wsD + (size_t)blockIdx.x * slot_v;
-    int* counter = stats + 4;
+    int* counter = stats + qctr;
+    if (nitems_dev) nitems = *nitems_dev;
     for (;;) {
         if (t == 0) s_item = atomicAdd(counter, 1);
         __syncthreads();
@@ -339,6 +344,369 @@ __global__ void __launch_bounds__(kWG) k_sweep(const RomDesc* __restrict__ roms,
     }
 }
 
+// ------------------------------------------------------------ Hessenberg-triangular sweep
+// For a model without D_R and frequency-dependent terms the pencil is reduced once to
+// Hessenberg-triangular form (unitary Q, Z): Q^H K_R Z = H upper Hessenberg, Q^H M_R Z = Th upper
+// triangular; then A_R(w) = Q (H - w^2 Th) Z^H and y = C_R A_R^{-1} b = (C_R Z) (H - w^2 Th)^{-1}
+// (Q^H b). Each frequency is an O(q^2) solve with an upper Hessenberg matrix instead of an
+// O(q^3) dense LU; the reduction costs O(q^3) once per model.
+
+__device__ __forceinline__ zd zmul(zd a, zd b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ __forceinline__ zd zconjmul(zd a, zd b) { return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re}; }   // conj(a) b
+__device__ __forceinline__ double zabs1(zd a) { return fabs(a.re) + fabs(a.im); }
+
+// Rotation G = [[c, s], [-conj(s), c]] (c real) with G [a; b] = [r; 0]
+__device__ __forceinline__ void givens(zd a, zd b, double& c, zd& s, zd& r) {
+    const double aa = hypot(a.re, a.im), bb = hypot(b.re, b.im);
+    if (bb == 0.0) {
+        c = 1.0;
+        s = {0.0, 0.0};
+        r = a;
+        return;
+    }
+    if (aa == 0.0) {
+        c = 0.0;
+        s = {b.re / bb, -b.im / bb};   // conj(b) / |b|
+        r = {bb, 0.0};
+        return;
+    }
+    const double nr = hypot(aa, bb);
+    c = aa / nr;
+    const zd ph = {a.re / aa, a.im / aa};
+    s = zmul(ph, zd{b.re / nr, -b.im / nr});   // (a / |a|) conj(b) / r
+    r = {ph.re * nr, ph.im * nr};
+}
+
+// Moler-Stewart reduction of one model per workgroup (all data in global memory):
+//   phase 1: Th upper triangular by row rotations (rows i-1, i), column by column bottom-up, applied
+//            to Th, H and Ft (the rotations of a column are chained through that column only, so
+//            one thread computes them and every thread then streams its own columns);
+//   phase 2: for each column j of H and i = q-1 .. j+2: a row rotation zeroes H[i][j] (applied to
+//            H, Th, Ft) and creates Th[i][i-1], which a column rotation on (i-1, i) zeroes
+//            (applied to Th, H and Ct). The row rotations of column j are chained through column j
+//            of H only (the column rotations touch columns > j), so they are computed up front.
+__global__ void __launch_bounds__(kWG) k_ht_reduce(const HtJob* __restrict__ jobs) {
+    __shared__ double rc[kHtMaxQ];
+    __shared__ zd rs[kHtMaxQ];
+    __shared__ zd tpair[2];   // Th[i][i] and Th[i][i-1] after the row rotation of a phase-2 step
+    __shared__ double red[8];
+    const HtJob jb = jobs[blockIdx.x];
+    const int q = jb.q, L = jb.L, no = jb.n_o, t = threadIdx.x;
+    zd* __restrict__ H = jb.H;
+    zd* __restrict__ T = jb.Th;
+    zd* __restrict__ Ft = jb.Ft;
+    zd* __restrict__ Ct = jb.Ct;
+    for (int e = t; e < q * q; e += kWG) {
+        H[e] = jb.KR[e];
+        T[e] = jb.MR[e];
+    }
+    for (int e = t; e < q * L; e += kWG) Ft[e] = jb.FR[e];
+    for (int e = t; e < no * q; e += kWG) Ct[e] = jb.CR[e];
+    __syncthreads();
+    // ---- phase 1
+    for (int j = 0; j < q - 1; ++j) {
+        if (t == 0) {
+            zd b = T[(q - 1) + (size_t)j * q];
+            for (int i = q - 1; i > j; --i) {
+                const zd a = T[(i - 1) + (size_t)j * q];
+                zd r;
+                givens(a, b, rc[i], rs[i], r);
+                T[i + (size_t)j * q] = {0.0, 0.0};
+                b = r;
+            }
+            T[j + (size_t)j * q] = b;
+        }
+        __syncthreads();
+        const int nT = q - 1 - j, ncol = nT + q + L;
+        for (int ci = t; ci < ncol; ci += kWG) {
+            zd* x = ci < nT ? T + (size_t)(j + 1 + ci) * q : ci < nT + q ? H + (size_t)(ci - nT) * q : Ft + (size_t)(ci - nT - q) * q;
+            zd carry = x[q - 1];
+            for (int i = q - 1; i > j; --i) {
+                const zd xa = x[i - 1];
+                const double c = rc[i];
+                const zd s = rs[i];
+                const zd sx = zconjmul(s, xa);   // conj(s) xa
+                x[i] = {c * carry.re - sx.re, c * carry.im - sx.im};
+                const zd sc = zmul(s, carry);
+                carry = {c * xa.re + sc.re, c * xa.im + sc.im};
+            }
+            x[j] = carry;
+        }
+        __syncthreads();
+    }
+    // ---- phase 2
+    for (int j = 0; j + 2 < q; ++j) {
+        if (t == 0) {
+            zd b = H[(q - 1) + (size_t)j * q];
+            for (int i = q - 1; i > j + 1; --i) {
+                const zd a = H[(i - 1) + (size_t)j * q];
+                zd r;
+                givens(a, b, rc[i], rs[i], r);
+                H[i + (size_t)j * q] = {0.0, 0.0};
+                b = r;
+            }
+            H[(j + 1) + (size_t)j * q] = b;
+        }
+        __syncthreads();
+        for (int i = q - 1; i > j + 1; --i) {
+            const double c = rc[i];
+            const zd s = rs[i];
+            // row rotation on rows (i-1, i): H columns j+1..q-1, Th columns i-1..q-1, Ft columns
+            const int nH = q - 1 - j, nT = q - i + 1, ncol = nH + nT + L;
+            for (int ci = t; ci < ncol; ci += kWG) {
+                int col;
+                zd* x;
+                if (ci < nH) { col = j + 1 + ci; x = H + (size_t)col * q; }
+                else if (ci < nH + nT) { col = i - 1 + (ci - nH); x = T + (size_t)col * q; }
+                else { col = -1; x = Ft + (size_t)(ci - nH - nT) * q; }
+                const zd xa = x[i - 1], xb = x[i];
+                const zd sb = zmul(s, xb), sa = zconjmul(s, xa);
+                const zd na = {c * xa.re + sb.re, c * xa.im + sb.im};
+                const zd nb = {c * xb.re - sa.re, c * xb.im - sa.im};
+                x[i - 1] = na;
+                x[i] = nb;
+                if (ci >= nH && ci < nH + nT) {
+                    if (col == i) tpair[0] = nb;        // Th[i][i]
+                    if (col == i - 1) tpair[1] = nb;    // Th[i][i-1] (the fill)
+                }
+            }
+            __syncthreads();
+            // column rotation on (i-1, i) zeroing Th[i][i-1]: [x_{i-1}, x_i] G with G [Th_ii; Th_i,i-1] = [r; 0]
+            double c2;
+            zd s2, r2;
+            givens(tpair[0], tpair[1], c2, s2, r2);
+            const int nrow = (i + 1) + q + no;
+            for (int ri = t; ri < nrow; ri += kWG) {
+                zd *x0, *x1;
+                if (ri <= i) { x0 = T + ri + (size_t)(i - 1) * q; x1 = T + ri + (size_t)i * q; }
+                else if (ri < i + 1 + q) { const int rr = ri - (i + 1); x0 = H + rr + (size_t)(i - 1) * q; x1 = H + rr + (size_t)i * q; }
+                else { const int rr = ri - (i + 1) - q; x0 = Ct + rr + (size_t)(i - 1) * no; x1 = Ct + rr + (size_t)i * no; }
+                const zd a0 = *x0, a1 = *x1;
+                const zd sc = zconjmul(s2, a1);   // conj(s) x_i
+                const zd sa = zmul(s2, a0);
+                *x0 = {c2 * a0.re - sc.re, c2 * a0.im - sc.im};
+                *x1 = {sa.re + c2 * a1.re, sa.im + c2 * a1.im};
+                if (ri == i) *x0 = {0.0, 0.0};   // Th[i][i-1], zero up to rounding
+            }
+            __syncthreads();
+        }
+    }
+    // largest entries of the Hessenberg and triangular parts (the pivot threshold of the sweep)
+    double hm = 0, tm = 0;
+    for (int e = t; e < q * q; e += kWG) {
+        const int i = e % q, jj = e / q;
+        if (i <= jj + 1) hm = fmax(hm, zabs1(H[e]));
+        if (i <= jj) tm = fmax(tm, zabs1(T[e]));
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        hm = fmax(hm, __shfl_xor(hm, off));
+        tm = fmax(tm, __shfl_xor(tm, off));
+    }
+    if ((t & 63) == 0) { red[t >> 6] = hm; red[4 + (t >> 6)] = tm; }
+    __syncthreads();
+    if (t == 0) {
+        jb.htnorm[0] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+        jb.htnorm[1] = fmax(fmax(red[4], red[5]), fmax(red[6], red[7]));
+    }
+}
+
+// A pointer read from a descriptor in memory is a generic one, and loads through it are flat
+// memory instructions, which also count against the LDS wait counter; the kernels' descriptors
+// hold global-memory arrays only, so they say so.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define CR_GLOBAL_AS __attribute__((address_space(1)))
+#else
+#define CR_GLOBAL_AS   // the host pass only parses kernel bodies
+#endif
+template <typename T>
+__device__ __forceinline__ const CR_GLOBAL_AS T* gp(const T* p) {
+    return (const CR_GLOBAL_AS T*)p;
+}
+template <typename T>
+__device__ __forceinline__ CR_GLOBAL_AS T* gpw(T* p) {
+    return (CR_GLOBAL_AS T*)p;
+}
+
+// Workgroup barrier that orders LDS only: outstanding global loads (the prefetched columns of the
+// next steps) stay in flight across it, which a full __syncthreads (a workgroup fence on all
+// memory) would wait for at every step. For loops whose threads share data through LDS alone.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// One (model, frequency) item of a Hessenberg model per workgroup pass: A = H - w^2 Th (upper
+// Hessenberg). Column elimination from the bottom: at step k = q-1 .. 1 the columns (k-1, k) are
+// swapped when |A[k][k-1]| > |A[k][k]| (partial pivoting on row k) and column k-1 loses mu times
+// column k so that A[k][k-1] = 0; column k and row k are then final (A E = A' upper triangular,
+// E the product of the column operations), so y_k = b_k / A'[k][k] and b_i -= A'[i][k] y_k
+// (i < k) at once: back substitution fused with the elimination, nothing stored. The outputs
+// Y = (C_R Z) x = (C_R Z E) y: the same column operations on Ct's columns, whose final column k
+// multiplies y_k. NT threads (q <= NT): thread t owns row t of A and b, and the top n_o threads
+// own the output rows (threads NT - n_o + o), so that they hold no row of A when q + n_o <= NT.
+// A pivot below eps^2 max|A| (numerically singular) is replaced in its direction and the item
+// is listed in `redo` for the dense path with FP64 refinement. qctr: stats index of the queue.
+template <int NT>
+__global__ void __launch_bounds__(NT) k_sweep_hess(const RomDesc* __restrict__ roms, const int2* __restrict__ items,
+                                                   int nitems, int* __restrict__ stats, int2* __restrict__ redo, int qctr) {
+    constexpr int R = 1;
+    __shared__ int s_item;
+    __shared__ zd s_y[2][kHtMaxL];
+    __shared__ zd s_mu[2];
+    __shared__ int s_sw[2];
+    __shared__ int s_pert;
+    const int t = threadIdx.x;
+    int* counter = stats + qctr;
+    for (;;) {
+        if (t == 0) {
+            s_item = atomicAdd(counter, 1);
+            s_pert = 0;
+        }
+        __syncthreads();
+        const int next = s_item;
+        __syncthreads();
+        if (next >= nitems) break;
+        const int2 it = items[next];
+        const RomDesc rd = roms[it.x];
+        const int q = rd.q, L = rd.L, no = rd.n_o;
+        const double w = rd.omegas[it.y], w2 = w * w;
+        const auto H = gp(rd.H);
+        const auto Th = gp(rd.Th);
+        const auto Ct = gp(rd.Ct);
+        const auto Ft = gp(rd.Ft);
+        const auto flags = gp(rd.flags);
+        const double tiny = (gp(rd.htnorm)[0] + w2 * gp(rd.htnorm)[1]) * 1.23e-32;   // eps^2 max|A|
+        auto aval = [&](int i, int jj) -> zd {
+            const zd h = H[i + (size_t)jj * q];
+            if (i > jj) return h;
+            const zd tt = Th[i + (size_t)jj * q];
+            return {h.re - w2 * tt.re, h.im - w2 * tt.im};
+        };
+        // u[r]: row i of the original column k-1 at step k; u1, u2: columns k-2, k-3 (loaded
+        // three steps ahead of their use)
+        zd c[R], u[R], u1[R], u2[R], b[R][kHtMaxL];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = t + NT * r;
+            c[r] = u[r] = u1[r] = u2[r] = zd{0.0, 0.0};
+#pragma unroll
+            for (int l = 0; l < kHtMaxL; ++l) b[r][l] = zd{0.0, 0.0};
+            if (i < q) {
+                c[r] = aval(i, q - 1);
+                if (q >= 2) u[r] = aval(i, q - 2);
+                if (q >= 3 && i <= q - 2) u1[r] = aval(i, q - 3);
+                if (q >= 4 && i <= q - 3) u2[r] = aval(i, q - 4);
+#pragma unroll
+                for (int l = 0; l < kHtMaxL; ++l) {
+                    if (l < L) {
+                        const zd f = Ft[i + (size_t)l * q];
+                        b[r][l] = flags[l] ? zd{-w * f.im, w * f.re} : f;
+                    }
+                }
+            }
+        }
+        const int o = t - (NT - no);   // output row of this thread, if o >= 0
+        const bool orow = o >= 0;
+        zd cw = {0.0, 0.0}, uw = {0.0, 0.0}, uw1 = {0.0, 0.0}, uw2 = {0.0, 0.0}, yo[kHtMaxL];
+#pragma unroll
+        for (int l = 0; l < kHtMaxL; ++l) yo[l] = zd{0.0, 0.0};
+        if (orow) {
+            cw = Ct[o + (size_t)(q - 1) * no];
+            if (q >= 2) uw = Ct[o + (size_t)(q - 2) * no];
+            if (q >= 3) uw1 = Ct[o + (size_t)(q - 3) * no];
+            if (q >= 4) uw2 = Ct[o + (size_t)(q - 4) * no];
+        }
+        for (int k = q - 1; k >= 0; --k) {
+            const int sl = k & 1;
+            // the owner of row k: pivot, multiplier and y_k
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (t + NT * r != k) continue;
+                zd piv = c[r], oth = u[r];
+                int sw = 0;
+                if (k > 0 && zabs1(oth) > zabs1(piv)) {
+                    const zd x = piv;
+                    piv = oth;
+                    oth = x;
+                    sw = 1;
+                }
+                if (!(zabs1(piv) > tiny)) {
+                    const double mg = zabs1(piv);
+                    piv = mg > 0 ? zd{piv.re / mg * tiny, piv.im / mg * tiny} : zd{tiny, 0.0};
+                    s_pert = 1;
+                }
+                const double den = piv.re * piv.re + piv.im * piv.im;
+                const zd inv = {piv.re / den, -piv.im / den};
+                s_mu[sl] = zmul(oth, inv);
+                s_sw[sl] = sw;
+#pragma unroll
+                for (int l = 0; l < kHtMaxL; ++l)
+                    if (l < L) s_y[sl][l] = zmul(b[r][l], inv);
+            }
+            lds_barrier();   // the step's pivot data; column prefetches stay in flight
+            const zd mu = s_mu[sl];
+            const int sw = s_sw[sl];
+            // column operation on the thread's rows and output row: cc[r] / ccw = final column k
+            zd cc[R], ccw = {0.0, 0.0};
+            bool act[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int i = t + NT * r;
+                act[r] = i < k;
+                cc[r] = zd{0.0, 0.0};
+                if (!act[r]) continue;
+                zd uu = u[r], c0 = c[r];
+                if (sw) { const zd x = uu; uu = c0; c0 = x; }
+                const zd m = zmul(mu, c0);
+                c[r] = {uu.re - m.re, uu.im - m.im};   // column k-1 after the operation
+                cc[r] = c0;
+                u[r] = u1[r];
+                u1[r] = u2[r];
+                if (k >= 4 && i <= k - 3) u2[r] = aval(i, k - 4);   // used at step k - 3
+            }
+            if (orow) {
+                zd uu = uw, c0 = cw;
+                if (sw) { const zd x = uu; uu = c0; c0 = x; }
+                if (k > 0) {
+                    const zd m = zmul(mu, c0);
+                    cw = {uu.re - m.re, uu.im - m.im};
+                }
+                ccw = c0;
+                uw = uw1;
+                uw1 = uw2;
+                if (k >= 4) uw2 = Ct[o + (size_t)(k - 4) * no];
+            }
+            // b_i -= A'[i][k] y_k and Y_o += W'[o][k] y_k, y_k read from LDS load by load
+#pragma unroll
+            for (int l = 0; l < kHtMaxL; ++l) {
+                const zd yl = l < L ? s_y[sl][l] : zd{0.0, 0.0};
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const zd p = zmul(cc[r], yl);
+                    b[r][l] = {b[r][l].re - p.re, b[r][l].im - p.im};
+                }
+                const zd p = zmul(ccw, yl);
+                yo[l] = {yo[l].re + p.re, yo[l].im + p.im};
+            }
+        }
+        __syncthreads();
+        if (s_pert) {
+            if (t == 0) {
+                const int slot = atomicAdd(stats + 6, 1);
+                redo[slot] = it;
+                atomicAdd(stats + 2, 1);
+            }
+        } else if (orow) {
+            auto yout = gpw(rd.out + (size_t)it.y * L * no);
+#pragma unroll
+            for (int l = 0; l < kHtMaxL; ++l)
+                if (l < L) yout[o + (size_t)l * no] = yo[l];
+        }
+        __syncthreads();
+    }
+}
+
 }  // namespace
 
 // LDS-resident variant: the reduced matrix stays in LDS when q^2 entries fit the budget
@@ -352,20 +720,35 @@ static int q_lds_for(cr_precision prec, int lds_bytes) {
 void SweepEngine::prepare(const std::vector<RomDesc>& roms, const std::vector<int2>& items, hipStream_t s) {
     qmax = 0;
     Lmax = 0;
+    qht = 0;
     for (const RomDesc& r : roms) {
         qmax = std::max(qmax, r.q);
         Lmax = std::max(Lmax, r.L);
+        if (r.H) qht = std::max(qht, r.q);
     }
     CR_REQUIRE(qmax <= 4096, CR_E_UNSUPPORTED, "reduced order above 4096");
     CR_REQUIRE(Lmax <= 64, CR_E_UNSUPPORTED, "more than 64 load columns in a reduced model");
-    nitems = (int)items.size();
+    // dense-LU items first (in the given order), then the Hessenberg models' items of order above
+    // 256, then the other Hessenberg items
+    std::vector<int2> ordered;
+    ordered.reserve(items.size());
+    for (const int2& it : items)
+        if (!roms[it.x].H) ordered.push_back(it);
+    nitems = (int)ordered.size();
+    for (const int2& it : items)
+        if (roms[it.x].H && roms[it.x].q > kWG) ordered.push_back(it);
+    nht_big = (int)ordered.size() - nitems;
+    for (const int2& it : items)
+        if (roms[it.x].H && roms[it.x].q <= kWG) ordered.push_back(it);
+    nht = (int)ordered.size() - nitems;
     d_roms.reserve(roms.size());
-    d_items.reserve(items.size());
-    d_stats.reserve(8);
+    d_items.reserve(ordered.size());
+    d_redo.reserve(std::max(nht, 1));
+    d_stats.reserve(16);
     if (!roms.empty())
         CR_HIP(hipMemcpyAsync(d_roms.p, roms.data(), roms.size() * sizeof(RomDesc), hipMemcpyHostToDevice, s));
-    if (!items.empty())
-        CR_HIP(hipMemcpyAsync(d_items.p, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+    if (!ordered.empty())
+        CR_HIP(hipMemcpyAsync(d_items.p, ordered.data(), ordered.size() * sizeof(int2), hipMemcpyHostToDevice, s));
     CR_HIP(hipStreamSynchronize(s));
 }
 
@@ -373,34 +756,67 @@ void SweepEngine::prepare(const std::vector<RomDesc>& roms, const std::vector<in
 // LDS budget for the LDS-resident variant. Only kernels are enqueued (no memset / memcpy), so
 // the launch can be captured in a graph.
 void SweepEngine::launch(cr_precision prec, bool refine, int grid_per_cu, int lds_bytes, hipStream_t s) {
-    if (nitems == 0) return;
+    if (nitems + nht == 0) return;
     const int64_t slot_a = (int64_t)qmax * qmax, slot_v = (int64_t)qmax * std::max(Lmax, 1);
-    const int grid = std::min<int>(nitems, std::max(1, grid_per_cu) * num_cu);
+    const int grid = std::min<int>(std::max(nitems, nht), std::max(1, grid_per_cu) * num_cu);
     wsA.reserve((size_t)grid * slot_a);
     wsP.reserve((size_t)grid * 4096);
     wsX.reserve((size_t)grid * slot_v);
     wsR.reserve((size_t)grid * slot_v);
     wsB.reserve((size_t)grid * slot_v);
     wsD.reserve((size_t)grid * slot_v);
-    fill_zero(d_stats.p, 8, s);
+    fill_zero(d_stats.p, 16, s);
     const int q_lds = q_lds_for(prec, lds_bytes);
     const size_t dyn = q_lds > 0 ? (size_t)lds_bytes : 0;
     ProfScope ps(ctx, "sweep", s);
-    if (prec == CR_MIXED) {
-        if (dyn > 65536) CR_HIP(hipFuncSetAttribute((const void*)k_sweep<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
-        hipLaunchKernelGGL(k_sweep<float>, dim3(grid), dim3(kWG), dyn, s, d_roms.p, d_items.p, nitems, slot_a, slot_v,
-                           wsA.p, wsP.p, wsX.p, wsR.p, wsB.p, wsD.p, 1, 10, 1e-14, d_stats.p, q_lds);
-    } else {
-        if (dyn > 65536) CR_HIP(hipFuncSetAttribute((const void*)k_sweep<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
-        hipLaunchKernelGGL(k_sweep<double>, dim3(grid), dim3(kWG), dyn, s, d_roms.p, d_items.p, nitems, slot_a, slot_v,
-                           wsA.p, wsP.p, wsX.p, wsR.p, wsB.p, wsD.p, refine ? 1 : 0, 10, 1e-14, d_stats.p, q_lds);
+    if (nitems > 0) {
+        const int g = std::min(grid, nitems);
+        if (prec == CR_MIXED) {
+            if (dyn > 65536) CR_HIP(hipFuncSetAttribute((const void*)k_sweep<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
+            hipLaunchKernelGGL(k_sweep<float>, dim3(g), dim3(kWG), dyn, s, d_roms.p, d_items.p, nitems, slot_a, slot_v,
+                               wsA.p, wsP.p, wsX.p, wsR.p, wsB.p, wsD.p, 1, 10, 1e-14, d_stats.p, q_lds, nullptr, 4);
+        } else {
+            if (dyn > 65536) CR_HIP(hipFuncSetAttribute((const void*)k_sweep<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
+            hipLaunchKernelGGL(k_sweep<double>, dim3(g), dim3(kWG), dyn, s, d_roms.p, d_items.p, nitems, slot_a, slot_v,
+                               wsA.p, wsP.p, wsX.p, wsR.p, wsB.p, wsD.p, refine ? 1 : 0, 10, 1e-14, d_stats.p, q_lds,
+                               nullptr, 4);
+        }
+    }
+    if (nht > 0) {
+        // Hessenberg models (FP64, no refinement requested): one item per workgroup pass, then
+        // the items with a numerically singular pivot through the dense path with refinement
+        // orders above 256 first (512-thread workgroups, one per compute unit), then the others
+        const int g = std::min(nht, std::max(1, grid_per_cu) * num_cu);
+        if (nht_big > 0)
+            hipLaunchKernelGGL(k_sweep_hess<2 * kWG>, dim3(std::min(nht_big, num_cu)), dim3(2 * kWG), 0, s, d_roms.p,
+                               d_items.p + nitems, nht_big, d_stats.p, d_redo.p, 8);
+        if (nht > nht_big)
+            hipLaunchKernelGGL(k_sweep_hess<kWG>, dim3(std::min(g, nht - nht_big)), dim3(kWG), 0, s, d_roms.p,
+                               d_items.p + nitems + nht_big, nht - nht_big, d_stats.p, d_redo.p, 5);
+        hipLaunchKernelGGL(k_sweep<double>, dim3(std::min(g, num_cu)), dim3(kWG), 0, s, d_roms.p, d_redo.p, 0, slot_a,
+                           slot_v, wsA.p, wsP.p, wsX.p, wsR.p, wsB.p, wsD.p, 1, 10, 1e-14, d_stats.p, 0,
+                           d_stats.p + 6, 7);
     }
     CR_HIP(hipGetLastError());
 }
 
+// ---------------------------------------------------------------- reduction to HT form
+void ht_reduce(const std::vector<HtJob>& jobs, hipStream_t s) {
+    if (jobs.empty()) return;
+    for (const HtJob& j : jobs)
+        CR_REQUIRE(j.q >= 1 && j.q <= kHtMaxQ && j.L >= 1 && j.L <= kHtMaxL && j.n_o >= 1 && j.n_o <= kHtMaxOut,
+                   CR_E_UNSUPPORTED, "Hessenberg-triangular reduction: model out of range");
+    DevBuf<HtJob> d;
+    d.alloc(jobs.size());
+    CR_HIP(hipMemcpyAsync(d.p, jobs.data(), jobs.size() * sizeof(HtJob), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_ht_reduce, dim3((unsigned)jobs.size()), dim3(kWG), 0, s, d.p);
+    CR_HIP(hipGetLastError());
+    CR_HIP(hipStreamSynchronize(s));
+}
+
 void SweepEngine::read_stats(hipStream_t s, int* max_its, int* not_conv, int* perturbed, int* fallbacks) {
     int st[8] = {0};
-    if (nitems > 0) CR_HIP(hipMemcpyAsync(st, d_stats.p, sizeof(st), hipMemcpyDeviceToHost, s));
+    if (nitems + nht > 0) CR_HIP(hipMemcpyAsync(st, d_stats.p, sizeof(st), hipMemcpyDeviceToHost, s));
     CR_HIP(hipStreamSynchronize(s));
     *max_its = st[0];
     *not_conv = st[1];
@@ -539,10 +955,10 @@ void sweep_noalloc(int device, int num_cu, const RomDesc& rd_in, const double* o
     fill_zero(d_stats, 8, s);
     if (prec == CR_MIXED)
         hipLaunchKernelGGL(k_sweep<float>, dim3(grid), dim3(kWG), 0, s, d_desc, d_items, nfreq, slot_a, slot_v, wsA, wsP,
-                           wsX, wsR, wsB, wsD, 1, 10, 1e-14, d_stats, 0);
+                           wsX, wsR, wsB, wsD, 1, 10, 1e-14, d_stats, 0, nullptr, 4);
     else
         hipLaunchKernelGGL(k_sweep<double>, dim3(grid), dim3(kWG), 0, s, d_desc, d_items, nfreq, slot_a, slot_v, wsA, wsP,
-                           wsX, wsR, wsB, wsD, 0, 10, 1e-14, d_stats, 0);
+                           wsX, wsR, wsB, wsD, 0, 10, 1e-14, d_stats, 0, nullptr, 4);
     CR_HIP(hipGetLastError());
     int st[8];
     CR_HIP(hipMemcpyAsync(st, d_stats, sizeof(st), hipMemcpyDeviceToHost, s));

@@ -58,7 +58,13 @@ def test_noalloc_matches_sweep_two_calls(P, ctx, prec):
         R = P.Rom.from_arrays(ctx, r["KR"], r["MR"], r["FR"], r["CR"], r["flags"])
         ref = R.sweep(om, prec=prec).cpu().numpy()
         got = R.sweep_noalloc(om, prec=prec).cpu().numpy()
-        assert np.array_equal(got, ref)
+        if prec == 1:
+            assert np.array_equal(got, ref)   # same kernels: complex-FP32 LU + FP64 refinement
+        else:
+            # cr_sweep solves an FP64 model without damping through its Hessenberg-triangular
+            # form, which needs device memory of its own; the allocation-free call keeps the dense
+            # LU: the two agree to rounding
+            assert rom.relative_error(got, ref).max() <= 1e-10
         assert R.last_info["not_converged"] == 0
         assert rom.relative_error(got, rom.sweep(r, om)).max() <= 1e-6
     # an empty sweep is a no-op
