@@ -200,10 +200,11 @@ struct RowStripShared {
 // 128-column block (the swaps on columns [0, K0) and [Kend, m), and the rows [k0, k1) of U12
 // beyond the block) to k_front_rowblock, so that the next block's panels touch only their own
 // columns: the right columns here are [k1, Kend) with Kend the block's last pivot column + 1.
-// FULL: every front's panel at this step has 16 columns (p - k0 >= 16 or the front is done), so
-// the rows [p, m) part can load and store without column conditions (a conditional store after
-// the unrolled solve makes the compiler hoist every read of the diagonal block into registers).
-template <typename T, bool FULL>
+// The rows [p, m) part loads and stores without column conditions (a conditional store after the
+// unrolled solve makes the compiler hoist every read of the diagonal block into registers and
+// spill): a panel of nb < 16 columns reads column k0 + nb - 1 in place of the missing ones and
+// stores the columns in reverse order, so that column's last store is its own solved value.
+template <typename T>
 __global__ void __launch_bounds__(kWG) k_front_rowstrip(const int32_t* __restrict__ big_list, int step,
                                                        const int32_t* __restrict__ fsize, const int32_t* __restrict__ npiv,
                                                        const int32_t* __restrict__ first, const int64_t* __restrict__ front_off,
@@ -234,7 +235,7 @@ __global__ void __launch_bounds__(kWG) k_front_rowstrip(const int32_t* __restric
         if (i >= m) return;
         cx<T> a[kNB];
 #pragma unroll
-        for (int k = 0; k < kNB; ++k) a[k] = (FULL || k < nb) ? A[i + (size_t)(k0 + k) * m] : cx<T>{T(0), T(0)};
+        for (int k = 0; k < kNB; ++k) a[k] = A[i + (size_t)(k0 + min(k, nb - 1)) * m];
 #pragma unroll
         for (int k = 0; k < kNB; ++k) {
             a[k] = cmul(a[k], sh.rd[k]);
@@ -242,8 +243,7 @@ __global__ void __launch_bounds__(kWG) k_front_rowstrip(const int32_t* __restric
             for (int j = k + 1; j < kNB; ++j) a[j] = cfms(a[j], a[k], sh.d[k][j]);
         }
 #pragma unroll
-        for (int k = 0; k < kNB; ++k)
-            if (FULL || k < nb) A[i + (size_t)(k0 + k) * m] = a[k];
+        for (int k = kNB - 1; k >= 0; --k) A[i + (size_t)(k0 + min(k, nb - 1)) * m] = a[k];
         return;
     }
     const bool right = x < nright;
@@ -1260,12 +1260,11 @@ void run_factor(Factor& f, cr_sys sys, double sigma, cx<T>* arena, T tiny, hipSt
         for (int blk = 0; blk < nblk; ++blk) {
             for (int j = blk * per; j < std::min(S.nsteps[l], (blk + 1) * per); ++j) {
                 unsigned gcol = 0, grow = 0;
-                bool any_lds = false, any_mem = false, full = true;
+                bool any_lds = false, any_mem = false;
                 for (int q = S.big_off[l]; q < S.big_off[l + 1]; ++q) {
                     const int f = S.big_list[q], m = S.fsize[f], p = S.npiv[f], k0 = j * kNB;
                     if (k0 >= p) continue;
                     (p - k0 <= panel_lds_rows<T>() ? any_lds : any_mem) = true;
-                    full = full && p - k0 >= kNB;
                     const int K0 = (k0 / kOB) * kOB, k1 = std::min(k0 + kNB, p), Kend = std::min(K0 + kOB, p);
                     gcol = std::max(gcol, (unsigned)((m - k0 + kST - 1) / kST));
                     grow = std::max(grow, (unsigned)((Kend - k1 + kST - 1) / kST + (m - p + kWG - 1) / kWG));
@@ -1287,12 +1286,8 @@ void run_factor(Factor& f, cr_sys sys, double sigma, cx<T>* arena, T tiny, hipSt
                 }
                 if (grow) {
                     ProfScope ps(sys->ctx, "front_rowstrip", s);
-                    if (full)
-                        hipLaunchKernelGGL((k_front_rowstrip<T, true>), dim3(grow, nbig), dim3(kWG), 0, s, bl, j,
-                                           D.fsize.p, D.npiv.p, D.first.p, D.front_off.p, f.ipiv.p, arena);
-                    else
-                        hipLaunchKernelGGL((k_front_rowstrip<T, false>), dim3(grow, nbig), dim3(kWG), 0, s, bl, j,
-                                           D.fsize.p, D.npiv.p, D.first.p, D.front_off.p, f.ipiv.p, arena);
+                    hipLaunchKernelGGL(k_front_rowstrip<T>, dim3(grow, nbig), dim3(kWG), 0, s, bl, j, D.fsize.p,
+                                       D.npiv.p, D.first.p, D.front_off.p, f.ipiv.p, arena);
                 }
             }
             if (pending) {

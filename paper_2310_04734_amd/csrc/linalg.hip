@@ -939,12 +939,14 @@ __global__ void __launch_bounds__(256) k_resid_partial(int64_t n, int q, int L, 
 }
 
 // Large q x L on the matrix cores: a workgroup takes 64 rows (16 per wave) and kRG candidates;
-// for each candidate c the wave forms its A operand (K~V - w_c^2 M~V)[rows, k..k+4) from one load
-// of K~V and M~V (shared by the kRG candidates) and multiplies it with X_c[k..k+4, 16 loads] from
-// LDS, v_mfma_f64_16x16x4f64, each complex product as three real ones (Ar Br, Ai Bi,
-// (Ar + Ai)(Br + Bi)); the epilogue subtracts the product from s_c F and sums |.|^2.
-constexpr int kRG = 8;    // candidates per workgroup
-constexpr int kRK = 16;   // rows of X staged in LDS per chunk
+// for each candidate c the wave forms its A operand (K~V - w_c^2 M~V)[rows, k..k+4) from one read
+// of K~V and M~V (shared by the kRG candidates) and multiplies it with X_c[k..k+4, 16 loads],
+// v_mfma_f64_16x16x4f64, each complex product as three real ones (Ar Br, Ai Bi,
+// (Ar + Ai)(Br + Bi)); the epilogue subtracts the product from s_c F and sums |.|^2. X, its
+// re + im sums and the wave's K~V, M~V rows pass through LDS kRK columns at a time (held in
+// registers they would be indexed by the loop counter and spill to scratch).
+constexpr int kRG = 8;   // candidates per workgroup
+constexpr int kRK = 8;   // columns of the basis per chunk
 typedef double rf64x4 __attribute__((ext_vector_type(4)));
 
 __global__ void __launch_bounds__(256) k_resid_mfma(int64_t n, int q, int L, int ncand, const zd* __restrict__ KV,
@@ -953,6 +955,7 @@ __global__ void __launch_bounds__(256) k_resid_mfma(int64_t n, int q, int L, int
                                                     const double* __restrict__ w2, double* __restrict__ partial) {
     __shared__ zd sx[kRG][kRK][16];
     __shared__ double sxs[kRG][kRK][16];   // re + im of sx (three real products per complex one)
+    __shared__ zd sa[4][2][kRK][16];       // per wave: K~V and M~V [column][row]
     __shared__ double red[4][kRG];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int li = lane & 15, lk = lane >> 4;
@@ -982,7 +985,7 @@ __global__ void __launch_bounds__(256) k_resid_mfma(int64_t n, int q, int L, int
         // software pipeline: the next chunk's X entries and A-operand rows are loaded into
         // registers while the current chunk is multiplied
         constexpr int XPER = kRG * kRK * 16 / 256;
-        zd xr[XPER], kv[kRK / 4], mv[kRK / 4], kvn[kRK / 4], mvn[kRK / 4];
+        zd xr[XPER], kvn[kRK / 4], mvn[kRK / 4];
         auto fetch = [&](int k0) {
 #pragma unroll
             for (int u = 0; u < XPER; ++u) {
@@ -1010,19 +1013,20 @@ __global__ void __launch_bounds__(256) k_resid_mfma(int64_t n, int q, int L, int
             }
 #pragma unroll
             for (int s = 0; s < kRK / 4; ++s) {
-                kv[s] = kvn[s];
-                mv[s] = mvn[s];
+                sa[wave][0][4 * s + lk][li] = kvn[s];
+                sa[wave][1][4 * s + lk][li] = mvn[s];
             }
             __syncthreads();
             if (k0 + kRK < q) fetch(k0 + kRK);
 #pragma unroll 1
             for (int s = 0; s < kRK / 4; ++s) {
-                const double kvs = kv[s].re + kv[s].im, mvs = mv[s].re + mv[s].im;
+                const zd kv = sa[wave][0][4 * s + lk][li], mv = sa[wave][1][4 * s + lk][li];
+                const double kvs = kv.re + kv.im, mvs = mv.re + mv.im;
 #pragma unroll
                 for (int c = 0; c < kRG; ++c) {
                     const zd b = sx[c][4 * s + lk][li];
                     const double bsum = sxs[c][4 * s + lk][li];
-                    const double ar = kv[s].re - w2c[c] * mv[s].re, ai = kv[s].im - w2c[c] * mv[s].im;
+                    const double ar = kv.re - w2c[c] * mv.re, ai = kv.im - w2c[c] * mv.im;
                     const double asum = kvs - w2c[c] * mvs;
                     p1[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, b.re, p1[c], 0, 0, 0);
                     p2[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, b.im, p2[c], 0, 0, 0);
@@ -1041,14 +1045,13 @@ __global__ void __launch_bounds__(256) k_resid_mfma(int64_t n, int q, int L, int
         }
 #pragma unroll
         for (int c = 0; c < kRG; ++c) {
-            if (c >= nc) break;
-            const zd sc = li < nl ? scal[(c0 + c) * L + l0 + li] : zd{0.0, 0.0};
+            const zd sc = (c < nc && li < nl) ? scal[(c0 + c) * L + l0 + li] : zd{0.0, 0.0};
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const double s1 = p1[c][r], s2 = p2[c][r];
                 const double rr = fv[r].re * sc.re - fv[r].im * sc.im - (s1 - s2);
                 const double ri = fv[r].re * sc.im + fv[r].im * sc.re - (p3[c][r] - s1 - s2);
-                if (rok[r]) acc2[c] += rr * rr + ri * ri;
+                if (rok[r] && c < nc) acc2[c] += rr * rr + ri * ri;
             }
         }
     }
