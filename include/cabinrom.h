@@ -222,6 +222,16 @@ cr_status cr_analyse(cr_sys sys, cr_analysis_info* info);
    change the schedule, not the arithmetic's definition (same pivots up to rounding). */
 cr_status cr_set_front_classes(cr_sys sys, int32_t big_m, int32_t huge_m);
 
+/* Panel split of the large fronts, any time before cr_factor: a 16-column panel with at least
+   min_rows fully-summed rows at or below it (default 1024; 0 = never, else >= 512) is factored
+   by ceil(rows / 256) workgroups, at most 64 per front and 256 per launch, that keep its rows in
+   registers and meet at a device-wide barrier per column; otherwise one workgroup per front
+   streams the panel. Same pivots and the same operations in the same order: the factor is
+   bit-identical either way. If the split's workgroups are not resident together within about a
+   second, cr_factor fails with CR_E_HIP and the factor is not used. CR_E_INVALID for
+   0 < min_rows < 512. */
+cr_status cr_set_panel_split(cr_sys sys, int32_t min_rows);
+
 /* ---------------------------------------------------------------- factor / solve --------- */
 
 typedef struct { int32_t n_perturbed; double seconds; } cr_factor_info;

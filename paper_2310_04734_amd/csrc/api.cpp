@@ -737,6 +737,14 @@ cr_status cr_set_front_classes(cr_sys sys, int32_t big_m, int32_t huge_m) {
     });
 }
 
+cr_status cr_set_panel_split(cr_sys sys, int32_t min_rows) {
+    if (!sys) return CR_E_INVALID;
+    return cr_guard(sys->ctx, [&] {
+        CR_REQUIRE(min_rows == 0 || min_rows >= 512, CR_E_INVALID, "cr_set_panel_split: min_rows must be 0 or >= 512");
+        sys->fclass.split_rows = min_rows;
+    });
+}
+
 cr_status cr_analyse(cr_sys sys, cr_analysis_info* info) {
     if (!sys) return CR_E_INVALID;
     return cr_guard(sys->ctx, [&] {

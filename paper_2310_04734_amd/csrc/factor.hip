@@ -12,6 +12,7 @@
 // The fronts stay resident in one device arena (HBM is large enough that the contribution
 // blocks need no stack), so the L and U parts are the factor used by the solves.
 #include <algorithm>
+#include <utility>
 #include <chrono>
 #include <cmath>
 
@@ -135,8 +136,21 @@ constexpr int kPanelLdsBytes = 48 * 1024;
 template <typename T>
 constexpr int panel_lds_rows() { return kPanelLdsBytes / (int)sizeof(cx<T>) / (kNB + 1); }
 
+// Split panels (k_front_panel_coop below): rows per workgroup, limits, and the class rule shared
+// by the host and the kernels.
+constexpr int kCoopRPT = 1;          // panel rows per thread (in registers)
+constexpr int kCoopRows = kCoopRPT * kWG;   // panel rows per workgroup
+constexpr int kCoopMaxG = 64;        // workgroups per front
+constexpr int kCoopMaxWG = 256;      // workgroups of one launch (all must be resident at once)
+constexpr int kCoopSpins = 1 << 20;  // barrier polls before a wait is declared failed
+
+__host__ __device__ constexpr int coop_groups(int rows, int min_rows) {
+    return (min_rows > 0 && rows >= min_rows && (rows + kCoopRows - 1) / kCoopRows <= kCoopMaxG)
+               ? (rows + kCoopRows - 1) / kCoopRows : 0;
+}
+
 template <typename T, bool LDS>
-__global__ void __launch_bounds__(kWG) k_front_panel(const int32_t* __restrict__ big_list, int step,
+__global__ void __launch_bounds__(kWG) k_front_panel(const int32_t* __restrict__ big_list, int step, int split_rows,
                                                     const int32_t* __restrict__ fsize, const int32_t* __restrict__ npiv,
                                                     const int32_t* __restrict__ first, const int64_t* __restrict__ front_off,
                                                     cx<T>* __restrict__ arena, int32_t* __restrict__ ipiv, T tiny,
@@ -145,7 +159,7 @@ __global__ void __launch_bounds__(kWG) k_front_panel(const int32_t* __restrict__
     __shared__ PanelShared<T> sh;
     const int f = big_list[blockIdx.x];
     const int m = fsize[f], p = npiv[f], k0 = step * kNB;
-    if (k0 >= p || (p - k0 <= R) != LDS) return;
+    if (k0 >= p || (p - k0 <= R) != LDS || coop_groups(p - k0, split_rows) > 0) return;
     const int K0 = (k0 / kOB) * kOB, k1 = min(k0 + kNB, p);
     if constexpr (LDS) {
         __shared__ cx<T> pl[R][kNB + 1];
@@ -153,6 +167,213 @@ __global__ void __launch_bounds__(kWG) k_front_panel(const int32_t* __restrict__
     } else {
         wg_panel<T>(arena + front_off[f], m, m, p, k0, k1, ipiv + first[f], tiny, nperturb, sh, K0, k1, false, p);
     }
+}
+
+// Panels with many fully-summed rows (p - k0 >= the system's split threshold) are spread over
+// G = ceil((p - k0) / kCoopRows) workgroups that hold the panel's rows in registers (kCoopRPT
+// rows of 16 entries per thread) for the whole panel: the single-workgroup panel streams the
+// panel through one compute unit once per column, at that unit's share of the L2 bandwidth.
+// Per column k, every workgroup publishes its best pivot candidate (largest cabs1 among its rows
+// >= k, lowest row on ties), that candidate's row and, for the owner of row k, row k itself;
+// after a barrier of the front's G workgroups every workgroup takes the same winner (same rule),
+// swaps, scales and updates its rows with the same complex operations in the same order as
+// wg_panel, so the factor is bit-identical to the single-workgroup panel. Publications
+// alternate between two buffers by column parity: a workgroup reads column k's buffer before it
+// arrives at column k + 1's barrier, which no workgroup passes before every one has arrived.
+template <typename T>
+struct CoopPub {
+    T cand_v[2][kCoopMaxG];
+    int cand_i[2][kCoopMaxG];
+    cx<T> row[2][kCoopMaxG][kNB];
+    cx<T> rowk[2][kNB];
+};
+constexpr int kCoopBarInts = 64;   // per front slot: one 64-bit barrier word (256-byte stride)
+
+// Barrier of one front's G workgroups on one 64-bit word: generation << 32 | arrivals. The
+// arrival is one acquire-release add that returns the generation; the last arrival advances the
+// generation and takes the arrivals back to zero with a second (release) add; the others poll
+// the generation (acquire). Stores before the barrier are visible to every workgroup of the
+// front after it. Waits are bounded: a wait past kCoopSpins polls sets *fail and returns false,
+// so the kernel always ends (the host then reports the factor invalid).
+__device__ bool coop_barrier(unsigned long long* word, int G, int* fail) {
+    __shared__ int ok_sh;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        const unsigned long long old = __hip_atomic_fetch_add(word, 1ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned g0 = (unsigned)(old >> 32);
+        if ((unsigned)old == (unsigned)(G - 1)) {
+            __hip_atomic_fetch_add(word, (1ull << 32) - (unsigned long long)G, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            for (int spins = 0;
+                 (unsigned)(__hip_atomic_load(word, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >> 32) == g0;) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > kCoopSpins) {
+                    atomicExch(fail, 1);
+                    ok = 0;
+                    break;
+                }
+            }
+        }
+        ok_sh = ok;
+    }
+    __syncthreads();
+    return ok_sh != 0;
+}
+
+// f(integral_constant<int, 0>), ..., f(integral_constant<int, N - 1>) in order
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_seq(F&& f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+    static_for_seq(f, std::make_integer_sequence<int, N>{});
+}
+
+// grid (max G, fronts of the level): blockIdx.y = the front's slot in pub and bar
+template <typename T>
+__global__ void __launch_bounds__(kWG) k_front_panel_coop(const int32_t* __restrict__ big_list, int step, int min_rows,
+                                                         const int32_t* __restrict__ fsize, const int32_t* __restrict__ npiv,
+                                                         const int32_t* __restrict__ first, const int64_t* __restrict__ front_off,
+                                                         cx<T>* __restrict__ arena, int32_t* __restrict__ ipiv, T tiny,
+                                                         int32_t* nperturb, CoopPub<T>* __restrict__ pub, int* bar, int* fail) {
+    __shared__ PanelShared<T> sh;
+    // the column's publications, loaded in one batch after its barrier
+    __shared__ T s_cv[kCoopMaxG];
+    __shared__ int s_ci[kCoopMaxG];
+    __shared__ cx<T> s_rows[kCoopMaxG + 1][kNB];   // candidate rows, then row k
+    __shared__ T s_pv;
+    __shared__ int s_pi, s_w;
+    const int f = big_list[blockIdx.y];
+    const int m = fsize[f], p = npiv[f], k0 = step * kNB;
+    if (k0 >= p) return;
+    const int G = coop_groups(p - k0, min_rows);
+    const int g = blockIdx.x, t = threadIdx.x;
+    if (g >= G || __hip_atomic_load(fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    const int K0 = (k0 / kOB) * kOB, k1 = min(k0 + kNB, p), nb = k1 - k0;
+    cx<T>* A = arena + front_off[f];
+    int32_t* piv = ipiv + first[f];
+    CoopPub<T>& P = pub[blockIdx.y];
+    unsigned long long* word = reinterpret_cast<unsigned long long*>(bar + kCoopBarInts * blockIdx.y);
+    int ir[kCoopRPT];
+    bool own[kCoopRPT];
+    cx<T> a[kCoopRPT][kNB];
+    T best = T(-1);
+    int bi = k0;
+#pragma unroll
+    for (int r = 0; r < kCoopRPT; ++r) {
+        ir[r] = k0 + g * kCoopRows + r * kWG + t;
+        own[r] = ir[r] < p;
+#pragma unroll
+        for (int jj = 0; jj < kNB; ++jj)
+            a[r][jj] = (own[r] && jj < nb) ? A[ir[r] + (size_t)(k0 + jj) * m] : cx<T>{T(0), T(0)};
+        if (own[r]) {
+            const T v = cabs1(a[r][0]);
+            if (v > best) { best = v; bi = ir[r]; }
+        }
+    }
+    bool alive = true;   // false once a barrier wait has failed: the remaining steps are skipped
+    // the column steps are instantiated one by one (a loop, even under an unroll pragma, is too
+    // large for the unroller and would index a[][] at run time, i.e. in scratch)
+    static_for<kNB>([&](auto kc) {
+        constexpr int kk = decltype(kc)::value;
+        const int k = k0 + kk, par = kk & 1;
+        if (kk < nb && alive) {
+            T lv;
+            int li;
+            wg_argmax(best, bi, sh.red_v, sh.red_i, lv, li);
+            if (t == 0) {
+                P.cand_v[par][g] = lv;
+                P.cand_i[par][g] = li;
+            }
+#pragma unroll
+            for (int r = 0; r < kCoopRPT; ++r) {
+                if (own[r] && ir[r] == li)
+#pragma unroll
+                    for (int jj = 0; jj < kNB; ++jj) P.row[par][g][jj] = a[r][jj];
+                if (own[r] && ir[r] == k)
+#pragma unroll
+                    for (int jj = 0; jj < kNB; ++jj) P.rowk[par][jj] = a[r][jj];
+            }
+            alive = coop_barrier(word, G, fail);   // uniform over the workgroup
+        }
+        if (kk < nb && alive) {
+            // every candidate with its row, and row k, in one round of loads
+            if (t < G) {
+                s_cv[t] = P.cand_v[par][t];
+                s_ci[t] = P.cand_i[par][t];
+            }
+            for (int e = t; e < (G + 1) * kNB; e += kWG)
+                s_rows[e / kNB][e % kNB] = e < G * kNB ? P.row[par][e / kNB][e % kNB] : P.rowk[par][e % kNB];
+            __syncthreads();
+            if (t < 64) {
+                // the winner among the G candidates: largest value, lowest row
+                T v = T(-1);
+                int i = k, w = 0;
+                if (t < G) {
+                    v = s_cv[t];
+                    i = s_ci[t];
+                    w = t;
+                }
+                for (int off = 32; off > 0; off >>= 1) {
+                    const T ov = __shfl_xor(v, off);
+                    const int oi = __shfl_xor(i, off), ow = __shfl_xor(w, off);
+                    if (ov > v || (ov == v && oi < i)) { v = ov; i = oi; w = ow; }
+                }
+                if (t == 0) { s_pv = v; s_pi = i; s_w = w; }
+            }
+            __syncthreads();
+            const T pv = s_pv;
+            const int pi = min(max(s_pi, k), p - 1);   // always so; the clamp keeps ipiv a row of the front
+            const cx<T>* su = s_rows[pi == k ? G : s_w];   // the pivot row
+            // the swap of rows k and pi over the panel's columns
+#pragma unroll
+            for (int r = 0; r < kCoopRPT; ++r) {
+                if (own[r] && ir[r] == k) {
+#pragma unroll
+                    for (int jj = 0; jj < kNB; ++jj) a[r][jj] = su[jj];
+                } else if (own[r] && ir[r] == pi) {
+#pragma unroll
+                    for (int jj = 0; jj < kNB; ++jj) a[r][jj] = s_rows[G][jj];
+                }
+            }
+            cx<T> d = su[kk];
+            if (!(pv > tiny)) {   // tiny or NaN pivot: static perturbation (as wg_panel)
+                const T mag = cabs1(d);
+                if (mag > T(0)) { d.re = d.re / mag * tiny; d.im = d.im / mag * tiny; }
+                else { d.re = tiny; d.im = T(0); }
+                if (g == 0 && t == 0) atomicAdd(nperturb, 1);
+            }
+            if (g == 0 && t == 0) piv[k] = pi;
+            const cx<T> rc = crecip(d);
+            best = T(-1);
+            bi = k + 1;
+#pragma unroll
+            for (int r = 0; r < kCoopRPT; ++r) {
+                if (own[r] && ir[r] == k) a[r][kk] = d;
+                if (own[r] && ir[r] > k) {
+                    const cx<T> l = cmul(a[r][kk], rc);
+                    a[r][kk] = l;
+#pragma unroll
+                    for (int jj = kk + 1; jj < kNB; ++jj) a[r][jj] = cfms(a[r][jj], l, su[jj]);
+                    if (kk + 1 < kNB) {
+                        const T v = cabs1(a[r][kk + 1]);
+                        if (v > best) { best = v; bi = ir[r]; }
+                    }
+                }
+            }
+            __syncthreads();   // s_rows is rewritten at the next column
+        }
+    });
+    if (!alive) return;
+#pragma unroll
+    for (int r = 0; r < kCoopRPT; ++r)
+#pragma unroll
+        for (int jj = 0; jj < kNB; ++jj)
+            if (own[r] && jj < nb) A[ir[r] + (size_t)(k0 + jj) * m] = a[r][jj];
+    // the panel's swaps on the block's earlier columns [K0, k0), as one gather
+    if (g == 0 && K0 < k0) wg_apply_swaps<T>(A, m, piv, k0, k1, K0, k0, sh.sw);
 }
 
 template <typename T>
@@ -1225,6 +1446,15 @@ void run_factor(Factor& f, cr_sys sys, double sigma, cx<T>* arena, T tiny, hipSt
     const Symbolic& S = *sys->sym;
     const DevSymbolic& D = *sys->dsym;
     hipStream_t aux = S.big_list.empty() ? nullptr : aux_stream(sys->ctx);
+    const int split_rows = sys->fclass.split_rows;
+    if (split_rows > 0 && !S.big_list.empty()) {
+        // split-panel publications and barrier counters, one slot per large front of a level
+        size_t slots = 0;
+        for (int l = 0; l < S.nlevel; ++l) slots = std::max(slots, (size_t)(S.big_off[l + 1] - S.big_off[l]));
+        f.coop_pub.reserve((slots * sizeof(CoopPub<T>) + sizeof(double) - 1) / sizeof(double));
+        f.coop_bar.reserve(slots * kCoopBarInts);
+        fill_zero(f.coop_bar.p, (int64_t)(slots * kCoopBarInts), s);
+    }
     for (int l = 0; l < S.nlevel; ++l) {
         const int nf = S.level_off[l + 1] - S.level_off[l];
         const int32_t* lf = D.level_fronts.p + S.level_off[l];
@@ -1259,12 +1489,20 @@ void run_factor(Factor& f, cr_sys sys, double sigma, cx<T>* arena, T tiny, hipSt
         bool pending = false;   // a trailing update is in flight on the second stream
         for (int blk = 0; blk < nblk; ++blk) {
             for (int j = blk * per; j < std::min(S.nsteps[l], (blk + 1) * per); ++j) {
-                unsigned gcol = 0, grow = 0;
-                bool any_lds = false, any_mem = false;
+                unsigned gcol = 0, grow = 0, gsplit = 0;
+                bool any_lds = false, any_mem = false, any_split = false;
+                int nsplit = 0;   // workgroups of the split panels
                 for (int q = S.big_off[l]; q < S.big_off[l + 1]; ++q) {
                     const int f = S.big_list[q], m = S.fsize[f], p = S.npiv[f], k0 = j * kNB;
                     if (k0 >= p) continue;
-                    (p - k0 <= panel_lds_rows<T>() ? any_lds : any_mem) = true;
+                    const int G = p - k0 <= panel_lds_rows<T>() ? 0 : coop_groups(p - k0, split_rows);
+                    if (p - k0 <= panel_lds_rows<T>()) any_lds = true;
+                    else if (G == 0) any_mem = true;
+                    else {
+                        any_split = true;
+                        nsplit += G;
+                        gsplit = std::max(gsplit, (unsigned)G);
+                    }
                     const int K0 = (k0 / kOB) * kOB, k1 = std::min(k0 + kNB, p), Kend = std::min(K0 + kOB, p);
                     gcol = std::max(gcol, (unsigned)((m - k0 + kST - 1) / kST));
                     grow = std::max(grow, (unsigned)((Kend - k1 + kST - 1) / kST + (m - p + kWG - 1) / kWG));
@@ -1274,14 +1512,24 @@ void run_factor(Factor& f, cr_sys sys, double sigma, cx<T>* arena, T tiny, hipSt
                     hipLaunchKernelGGL(k_front_colstrip<T>, dim3(gcol, nbig), dim3(kWG), 0, s, bl, j, D.fsize.p,
                                        D.npiv.p, D.front_off.p, arena);
                 }
+                // every workgroup of a split launch must be resident at once: beyond kCoopMaxWG the
+                // step's panels all take the single-workgroup kernel
+                const int split = nsplit <= kCoopMaxWG ? split_rows : 0;
+                if (any_split && !split) any_mem = true;
+                if (any_split && split) {
+                    ProfScope ps(sys->ctx, "front_panel", s);
+                    hipLaunchKernelGGL(k_front_panel_coop<T>, dim3(gsplit, nbig), dim3(kWG), 0, s, bl, j, split, D.fsize.p,
+                                       D.npiv.p, D.first.p, D.front_off.p, arena, f.ipiv.p, tiny, f.nperturb.p,
+                                       reinterpret_cast<CoopPub<T>*>(f.coop_pub.p), f.coop_bar.p, f.nperturb.p + 1);
+                }
                 if (any_mem) {
                     ProfScope ps(sys->ctx, "front_panel", s);
-                    hipLaunchKernelGGL((k_front_panel<T, false>), dim3(nbig), dim3(kWG), 0, s, bl, j, D.fsize.p,
+                    hipLaunchKernelGGL((k_front_panel<T, false>), dim3(nbig), dim3(kWG), 0, s, bl, j, split, D.fsize.p,
                                        D.npiv.p, D.first.p, D.front_off.p, arena, f.ipiv.p, tiny, f.nperturb.p);
                 }
                 if (any_lds) {
                     ProfScope ps(sys->ctx, "front_panel", s);
-                    hipLaunchKernelGGL((k_front_panel<T, true>), dim3(nbig), dim3(kWG), 0, s, bl, j, D.fsize.p,
+                    hipLaunchKernelGGL((k_front_panel<T, true>), dim3(nbig), dim3(kWG), 0, s, bl, j, split, D.fsize.p,
                                        D.npiv.p, D.first.p, D.front_off.p, arena, f.ipiv.p, tiny, f.nperturb.p);
                 }
                 if (grow) {
@@ -1531,7 +1779,7 @@ void numeric_factor(Factor& f, cr_sys sys, double omega, cr_precision prec, hipS
     // largest |entry| of the shifted matrix sets the perturbation threshold
     f.amax.reserve(1);
     fill_zero(f.amax.p, 1, s);
-    fill_zero(f.nperturb.p, 1, s);
+    fill_zero(f.nperturb.p, 2, s);
     hipLaunchKernelGGL(k_maxabs_entries, dim3(256), dim3(256), 0, s, f.opK, f.opM, nnz, sigma, f.amax.p);
     unsigned long long hm = 0;
     CR_HIP(hipMemcpyAsync(&hm, f.amax.p, sizeof(hm), hipMemcpyDeviceToHost, s));
@@ -1549,10 +1797,12 @@ void numeric_factor(Factor& f, cr_sys sys, double omega, cr_precision prec, hipS
         f.arena64.reserve(S.arena);
         run_factor<double>(f, sys, sigma, reinterpret_cast<cx<double>*>(f.arena64.p), 1e-8 * amax, s);
     }
-    int32_t np = 0;
-    CR_HIP(hipMemcpyAsync(&np, f.nperturb.p, sizeof(np), hipMemcpyDeviceToHost, s));
+    int32_t np[2] = {0, 0};
+    CR_HIP(hipMemcpyAsync(np, f.nperturb.p, sizeof(np), hipMemcpyDeviceToHost, s));
     CR_HIP(hipStreamSynchronize(s));
-    f.n_perturbed = np;
+    CR_REQUIRE(np[1] == 0, CR_E_HIP,
+               "a split panel's workgroups were not resident together (barrier wait timed out): the factor is invalid");
+    f.n_perturbed = np[0];
 }
 
 // one application of the stored factor: Xout = A~^{-1} B (both FP64, old numbering)

@@ -184,6 +184,7 @@ void finalize_sys(cr_sys sys);
 // solved with many workgroups
 struct FrontClasses {
     int32_t big_m = 192, huge_m = 1024;
+    int32_t split_rows = 1024;   // panels with this many fully-summed rows use several workgroups (0: never)
 };
 
 std::unique_ptr<Symbolic> analyse_pattern(int64_t n, const std::vector<int64_t>& rowptr,
@@ -324,8 +325,10 @@ struct Factor {
     DevBuf<zf> arena32;   // complex64 fronts (MIXED)
     DevBuf<int32_t> ipiv; // local pivot row per pivot (n)
     DevBuf<int32_t> psrc; // per pivot: source row of the front's composed swaps (n)
-    DevBuf<int32_t> nperturb;
+    DevBuf<int32_t> nperturb;   // [0] perturbed pivots, [1] a split panel's barrier wait failed
     DevBuf<unsigned long long> amax;
+    DevBuf<double> coop_pub;    // split panels: pivot candidates and rows published per front slot
+    DevBuf<int32_t> coop_bar;   // split panels: barrier counters per front slot
     int32_t n_perturbed = 0;
     double anorm = 0, anorm_omega = -1;   // ||A~||_inf at the factored shift
     // the shifted operator A~ = opK - opS opM on the system's pattern: (K~, M~, w^2), or for a

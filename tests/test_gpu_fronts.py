@@ -161,3 +161,38 @@ def test_profile_select_times_only_named_kernels(P, ctx, plate):
     prof = ctx.profile_read()
     ctx.profile(False)
     assert "front_fwd" in prof and "front_bwd" in prof
+
+
+@pytest.fixture(scope="module")
+def fuselage_mid():
+    """A mid-size fuselage (~8e4 DoF): its top fronts have panels of a few thousand rows."""
+    return W.fuselage_workload(n_core=18, n_ring=9, h_z=0.08, n_freq=8)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_split_panels_bit_identical(P, ctx, fuselage_mid, prec):
+    """Panels spread over several workgroups (rows in registers, a barrier per column) take the
+    same pivots and the same operations in the same order as the one-workgroup panel: solves with
+    the two factors agree bit for bit (and two factors without the split agree with each other,
+    so the comparison rests on a deterministic factorisation)."""
+    _flush(f"split panels prec={prec}")
+    w = fuselage_mid
+    g = P.assemble(ctx, w.mesh, w.loads, w.receivers)
+    info = g.analyse()
+    assert info["max_front"] >= 2048, info
+    om = 2 * np.pi * 150.0
+    nn = g.n
+    u = W.SplitMix64(23).uniforms(2 * 4 * nn)
+    B = torch.from_numpy((u[:4 * nn] + 1j * u[4 * nn:]).reshape(nn, 4)).to(ctx.device)
+    xs, nps = [], []
+    for split in (0, 0, 512, 1024):
+        g.set_panel_split(split)
+        fac = g.factor(om, prec)
+        nps.append(fac.n_perturbed)
+        xs.append(fac.solve(B, max_iter=0, tol=1.0).cpu())   # the factor alone, no refinement
+        del fac
+    assert len(set(nps)) == 1, nps
+    for x in xs[1:]:
+        assert torch.equal(x, xs[0])
+    with pytest.raises(P.CabinRomError):
+        g.set_panel_split(100)
