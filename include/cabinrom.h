@@ -298,7 +298,9 @@ typedef struct {
     int32_t deflated;          /* columns dropped by the 1e-10 norm-ratio rule             */
     int32_t n_shifts;
     int32_t ir_iterations;     /* total refinement corrections over all solves             */
-    double max_backward_error; /* over all shifted solves                                  */
+    double max_backward_error; /* over all shifted solves; each is refined in FP64 until its
+                                  normwise backward error is <= max(1e-14, sqrt(n) eps), the
+                                  stopping rule of LAPACK's mixed-precision solver          */
     int32_t n_perturbed;
     int32_t fp64_refactorizations; /* CR_MIXED expansion points refactored in complex FP64
                                       because FP64 refinement of the FP32 factor stalled   */

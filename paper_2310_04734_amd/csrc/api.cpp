@@ -2,6 +2,7 @@
 // Krylov basis (fixed and greedy expansion points), the Galerkin projection, and reduced
 // models. Kernels live in factor.hip, linalg.hip and sweep.hip.
 #include <algorithm>
+#include <cfloat>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -235,19 +236,23 @@ void mass_apply(const Factor& fac, cr_sys sys, int b, const zd* X, int64_t ldx, 
     else spmm_shifted(sys, fac.opMass, fac.opMass, 0.0, b, X, ldx, Y, ldy, s);
 }
 
-// X = A_j^{-1} B for b columns with FP64 refinement; a complex-FP32 factor whose classic
-// refinement stalls (kappa(A_j) u_32 >~ 1) is refactored in complex FP64 once, which is cheaper
-// than a Krylov refinement of every one of its solves
+// X = A_j^{-1} B for b columns with FP64 refinement until the normwise backward error is at most
+// max(1e-14, sqrt(n) eps), the stopping rule of LAPACK's mixed-precision solver (dsgesv:
+// ||r|| <= sqrt(n) eps ||A|| ||x||): below it a correction is under the rounding level of a
+// backward-stable solve at this size. A complex-FP32 factor whose classic refinement stalls
+// (kappa(A_j) u_32 >~ 1) is refactored in complex FP64 once, which is cheaper than a Krylov
+// refinement of every one of its solves.
 void shifted_solve(cr_basis B, Factor& fac, SolveWork& sw, double omega, int b, const zd* rhs, zd* X) {
     cr_sys sys = B->sys;
     hipStream_t s = sys->ctx->stream;
+    const double tol = std::max(1e-14, std::sqrt((double)sys->n) * DBL_EPSILON);
     double berr = 0;
-    int its = solve_scaled(fac, b, rhs, X, 10, 1e-14, &berr, sw, s, false, fac.prec == CR_FP64);
-    if (!(berr <= 1e-14) && fac.prec == CR_MIXED) {
+    int its = solve_scaled(fac, b, rhs, X, 10, tol, &berr, sw, s, false, fac.prec == CR_FP64);
+    if (!(berr <= tol) && fac.prec == CR_MIXED) {
         numeric_factor(fac, sys, omega, CR_FP64, s);
         B->n_perturbed += fac.n_perturbed;
         B->fp64_refactorizations++;
-        its += solve_scaled(fac, b, rhs, X, 10, 1e-14, &berr, sw, s, false);
+        its += solve_scaled(fac, b, rhs, X, 10, tol, &berr, sw, s, false);
     }
     B->ir_iterations += its;
     B->max_berr = std::max(B->max_berr, berr);
