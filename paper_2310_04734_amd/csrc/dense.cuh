@@ -67,6 +67,17 @@ __device__ __forceinline__ void batched_for(int n, Load ld, Store st) {
     }
 }
 
+// Workgroup barrier that orders LDS only: outstanding global loads (prefetches of later steps)
+// stay in flight across it, which a full __syncthreads (a workgroup fence on all memory) would
+// wait for. For points where the threads share data through LDS alone; the global loads must
+// then be global-address-space ones (flat loads are counted with LDS accesses and would be
+// waited for as well).
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Workgroup max-reduction of (value, index); lowest index wins ties. Uses red_v/red_i in LDS
 // (kWG / 64 + 1 entries each). All threads receive the result.
 template <typename T>

@@ -739,12 +739,11 @@ __device__ __forceinline__ cx<T> group_panel_partial(const cx<T>* __restrict__ F
 // MfmaAcc<T>::row(l, r), column l % 16 of the tile.
 constexpr int kMfmaRhs = 4;   // right-hand sides from which the panel products use the matrix cores
 
-template <typename T>
+template <typename T, int H = 8>   // H: K steps whose loads are issued together
 __device__ __forceinline__ void mfma_panel_accum(typename MfmaAcc<T>::type& dre, typename MfmaAcc<T>::type& dim,
                                                  const cx<T>* __restrict__ Frow, int64_t ldf, bool rok, int ncols,
                                                  const cx<T> (*y)[kSR], int nr) {
     const int lane = threadIdx.x & 63, i = lane & 15, kk = lane >> 4;
-    constexpr int H = 8;   // K steps whose loads are issued together
 #pragma unroll
     for (int s0 = 0; s0 < kSB / 4; s0 += H) {
         if (4 * s0 >= ncols) break;
@@ -766,18 +765,22 @@ __device__ __forceinline__ void mfma_panel_accum(typename MfmaAcc<T>::type& dre,
     }
 }
 
-// w[tr0 + row + j ldw] -= D[row][j] for row < trows, j < nr (one wave)
+// w[tr0 + row + j ldw] -= D[row][j] for row < trows, j < nr (one wave), in two halves so that the
+// tile's entries can be loaded before its products are formed
 template <typename T>
-__device__ __forceinline__ void mfma_tile_sub(cx<T>* w, int64_t ldw, int tr0, int trows, int nr,
-                                              const typename MfmaAcc<T>::type& dre,
-                                              const typename MfmaAcc<T>::type& dim) {
+__device__ __forceinline__ void mfma_tile_load(cx<T> (&cv)[4], const cx<T>* w, int64_t ldw, int tr0, int trows, int nr) {
     const int lane = threadIdx.x & 63, j = lane & 15;
-    cx<T> cv[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int ro = MfmaAcc<T>::row(lane, r);
         cv[r] = (ro < trows && j < nr) ? w[tr0 + ro + (size_t)j * ldw] : cx<T>{T(0), T(0)};
     }
+}
+template <typename T>
+__device__ __forceinline__ void mfma_tile_store(cx<T> (&cv)[4], cx<T>* w, int64_t ldw, int tr0, int trows, int nr,
+                                                const typename MfmaAcc<T>::type& dre,
+                                                const typename MfmaAcc<T>::type& dim) {
+    const int lane = threadIdx.x & 63, j = lane & 15;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int ro = MfmaAcc<T>::row(lane, r);
@@ -788,6 +791,14 @@ __device__ __forceinline__ void mfma_tile_sub(cx<T>* w, int64_t ldw, int tr0, in
         }
     }
 }
+template <typename T>
+__device__ __forceinline__ void mfma_tile_sub(cx<T>* w, int64_t ldw, int tr0, int trows, int nr,
+                                              const typename MfmaAcc<T>::type& dre,
+                                              const typename MfmaAcc<T>::type& dim) {
+    cx<T> cv[4];
+    mfma_tile_load<T>(cv, w, ldw, tr0, trows, nr);
+    mfma_tile_store<T>(cv, w, ldw, tr0, trows, nr, dre, dim);
+}
 
 // w[r + j ldw] -= sum_{k < ncols} Fc[r + k ldf] y[k][j] for r in [r0, r0 + rows), j < nr
 template <typename T, int NT>
@@ -795,11 +806,15 @@ __device__ __forceinline__ void mfma_rows_update(cx<T>* w, int64_t ldw, int r0, 
                                  int ncols, const cx<T> (*y)[kSR]) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, i = lane & 15;
     const int ntile = rows > 0 ? (rows + 15) / 16 : 0;
+    // the 512-thread super-block kernel has the registers to issue all 16 K steps' loads at once
+    constexpr int H = NT == 512 ? 16 : 8;
     for (int tile = wave; tile < ntile; tile += NT / 64) {
         typename MfmaAcc<T>::type dre = {0, 0, 0, 0}, dim = {0, 0, 0, 0};
         const int tr0 = r0 + 16 * tile, trows = min(16, rows - 16 * tile);
-        mfma_panel_accum<T>(dre, dim, Fc + tr0 + i, ldf, i < trows, ncols, y, nr);
-        mfma_tile_sub<T>(w, ldw, tr0, trows, nr, dre, dim);
+        cx<T> cv[4];
+        mfma_tile_load<T>(cv, w, ldw, tr0, trows, nr);
+        mfma_panel_accum<T, H>(dre, dim, Fc + tr0 + i, ldf, i < trows, ncols, y, nr);
+        mfma_tile_store<T>(cv, w, ldw, tr0, trows, nr, dre, dim);
     }
 }
 
@@ -1320,23 +1335,36 @@ __global__ void __launch_bounds__(kHugeDiagWG) k_huge_diag(const int32_t* __rest
     cx<T>* w = a.work + a.idx_off[f] * a.nrhs;
     const int nrhs = a.nrhs;
     const int lc = (int)blockIdx.y * kSR;
+    // the diagonal blocks do not depend on the solve: the next one is loaded into registers while
+    // the current one is solved and its panel applied
+    constexpr int DPER = kSB * kSB / NT;
+    cx<T> dn[DPER];
+    auto fetch_d = [&](int kb) {
+        const int nb = min(kSB, K1 - kb);
+#pragma unroll
+        for (int u = 0; u < DPER; ++u) {
+            const int e = t + u * NT, i = e % kSB, k = e / kSB;
+            dn[u] = (i < nb && k < nb) ? F[kb + i + (size_t)(kb + k) * m] : (UPPER ? cx<T>{T(1), T(0)} : cx<T>{T(0), T(0)});
+        }
+    };
     for (int l0 = lc; l0 < min(nrhs, lc + kSR); l0 += kSR) {
         const int nr = min(kSR, nrhs - l0);
         const int kfirst = UPPER ? K0 + ((K1 - 1 - K0) / kSB) * kSB : K0;
+        fetch_d(kfirst);
         for (int kb = kfirst; UPPER ? kb >= K0 : kb < K1; kb += UPPER ? -kSB : kSB) {
             const int nb = min(kSB, K1 - kb);
             __syncthreads();
-            batched_for<NT, kSB * kSB / NT>(kSB * kSB,
-                [&](int e) {
-                    const int i = e % kSB, k = e / kSB;
-                    return (i < nb && k < nb) ? F[kb + i + (size_t)(kb + k) * m]
-                                              : (UPPER ? cx<T>{T(1), T(0)} : cx<T>{T(0), T(0)});
-                },
-                [&](int e, cx<T> v) { sh.d[e % kSB][e / kSB] = v; });
+#pragma unroll
+            for (int u = 0; u < DPER; ++u) {
+                const int e = t + u * NT;
+                sh.d[e % kSB][e / kSB] = dn[u];
+            }
             if (UPPER && t < kSB) sh.rd[t] = t < nb ? crecip(F[kb + t + (size_t)(kb + t) * m]) : cx<T>{T(1), T(0)};
-            __syncthreads();
+            const int knext = kb + (UPPER ? -kSB : kSB);
+            if (UPPER ? knext >= K0 : knext < K1) fetch_d(knext);
+            lds_barrier();   // the block in LDS (the prefetch stays in flight)
             wave_diag_solve<T, NT, UPPER>(w, m, kb, nb, l0, nr, sh);
-            __syncthreads();
+            lds_barrier();   // the solved values in sh.y; the panel below reads no row the solve wrote
             // the rest of the super-block with the block's panel
             if (UPPER)
                 panel_fms<T, NT, 0, true>(w + (size_t)l0 * m, m, K0, kb - K0, nr, F + (size_t)kb * m, nb, sh);

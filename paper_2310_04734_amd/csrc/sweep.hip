@@ -527,14 +527,6 @@ __device__ __forceinline__ CR_GLOBAL_AS T* gpw(T* p) {
     return (CR_GLOBAL_AS T*)p;
 }
 
-// Workgroup barrier that orders LDS only: outstanding global loads (the prefetched columns of the
-// next steps) stay in flight across it, which a full __syncthreads (a workgroup fence on all
-// memory) would wait for at every step. For loops whose threads share data through LDS alone.
-__device__ __forceinline__ void lds_barrier() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
 
 // One (model, frequency) item of a Hessenberg model per workgroup pass: A = H - w^2 Th (upper
 // Hessenberg). Column elimination from the bottom: at step k = q-1 .. 1 the columns (k-1, k) are
