@@ -227,10 +227,12 @@ cr_status cr_set_front_classes(cr_sys sys, int32_t big_m, int32_t huge_m);
    by ceil(rows / 256) workgroups, at most 64 per front and 256 per launch, that keep its rows in
    registers and meet at a device-wide barrier per column; otherwise one workgroup per front
    streams the panel. Same pivots and the same operations in the same order: the factor is
-   bit-identical either way. If the split's workgroups are not resident together within about a
-   second, cr_factor fails with CR_E_HIP and the factor is not used. CR_E_INVALID for
-   0 < min_rows < 512. */
-cr_status cr_set_panel_split(cr_sys sys, int32_t min_rows);
+   bit-identical either way. Every barrier wait is bounded by max_polls polls of the barrier word
+   (0 = the default, 2^20 polls, about a second): a wait that runs out ends its workgroup, the
+   split panels of that factorisation are skipped, and cr_factor fails with CR_E_HIP (the factor
+   is not used; the next cr_factor starts afresh). A small max_polls forces that path for tests.
+   CR_E_INVALID for 0 < min_rows < 512 or max_polls < 0. */
+cr_status cr_set_panel_split(cr_sys sys, int32_t min_rows, int32_t max_polls);
 
 /* ---------------------------------------------------------------- factor / solve --------- */
 

@@ -173,7 +173,7 @@ _sig("cr_sweep_windows", I32, I32, P, P, I32, P, I32, P, C.POINTER(cr_sweep_info
 _sig("cr_sweep_states", I32, P, I32, P, I32, P, C.POINTER(cr_sweep_info))
 _sig("cr_analyse", I32, P, C.POINTER(cr_analysis_info))
 _sig("cr_set_front_classes", I32, P, I32, I32)
-_sig("cr_set_panel_split", I32, P, I32)
+_sig("cr_set_panel_split", I32, P, I32, I32)
 _sig("cr_factor", I32, P, D, I32, C.POINTER(P), C.POINTER(cr_factor_info))
 _sig("cr_fact_destroy", None, P)
 _sig("cr_solve", I32, P, I32, P, P, C.POINTER(cr_ir_opts), C.POINTER(cr_solve_info))
@@ -324,8 +324,8 @@ class System:
     def set_front_classes(self, big_m=192, huge_m=1024):
         self.ctx.check(lib.cr_set_front_classes(self.h, int(big_m), int(huge_m)))
 
-    def set_panel_split(self, min_rows=1024):
-        self.ctx.check(lib.cr_set_panel_split(self.h, int(min_rows)))
+    def set_panel_split(self, min_rows=1024, max_polls=0):
+        self.ctx.check(lib.cr_set_panel_split(self.h, int(min_rows), int(max_polls)))
 
     def analyse(self):
         info = cr_analysis_info()

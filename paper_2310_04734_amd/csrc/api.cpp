@@ -742,11 +742,13 @@ cr_status cr_set_front_classes(cr_sys sys, int32_t big_m, int32_t huge_m) {
     });
 }
 
-cr_status cr_set_panel_split(cr_sys sys, int32_t min_rows) {
+cr_status cr_set_panel_split(cr_sys sys, int32_t min_rows, int32_t max_polls) {
     if (!sys) return CR_E_INVALID;
     return cr_guard(sys->ctx, [&] {
         CR_REQUIRE(min_rows == 0 || min_rows >= 512, CR_E_INVALID, "cr_set_panel_split: min_rows must be 0 or >= 512");
+        CR_REQUIRE(max_polls >= 0, CR_E_INVALID, "cr_set_panel_split: max_polls must be >= 0");
         sys->fclass.split_rows = min_rows;
+        sys->fclass.split_polls = max_polls;
     });
 }
 

@@ -142,7 +142,7 @@ constexpr int kCoopRPT = 1;          // panel rows per thread (in registers)
 constexpr int kCoopRows = kCoopRPT * kWG;   // panel rows per workgroup
 constexpr int kCoopMaxG = 64;        // workgroups per front
 constexpr int kCoopMaxWG = 256;      // workgroups of one launch (all must be resident at once)
-constexpr int kCoopSpins = 1 << 20;  // barrier polls before a wait is declared failed
+constexpr int kCoopSpins = 1 << 20;  // default bound on a barrier wait's polls (about a second)
 
 __host__ __device__ constexpr int coop_groups(int rows, int min_rows) {
     return (min_rows > 0 && rows >= min_rows && (rows + kCoopRows - 1) / kCoopRows <= kCoopMaxG)
@@ -193,9 +193,9 @@ constexpr int kCoopBarInts = 64;   // per front slot: one 64-bit barrier word (2
 // arrival is one acquire-release add that returns the generation; the last arrival advances the
 // generation and takes the arrivals back to zero with a second (release) add; the others poll
 // the generation (acquire). Stores before the barrier are visible to every workgroup of the
-// front after it. Waits are bounded: a wait past kCoopSpins polls sets *fail and returns false,
+// front after it. Waits are bounded: a wait past max_polls polls sets *fail and returns false,
 // so the kernel always ends (the host then reports the factor invalid).
-__device__ bool coop_barrier(unsigned long long* word, int G, int* fail) {
+__device__ bool coop_barrier(unsigned long long* word, int G, int max_polls, int* fail) {
     __shared__ int ok_sh;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -208,7 +208,7 @@ __device__ bool coop_barrier(unsigned long long* word, int G, int* fail) {
             for (int spins = 0;
                  (unsigned)(__hip_atomic_load(word, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >> 32) == g0;) {
                 __builtin_amdgcn_s_sleep(1);
-                if (++spins > kCoopSpins) {
+                if (++spins > max_polls) {
                     atomicExch(fail, 1);
                     ok = 0;
                     break;
@@ -237,7 +237,8 @@ __global__ void __launch_bounds__(kWG) k_front_panel_coop(const int32_t* __restr
                                                          const int32_t* __restrict__ fsize, const int32_t* __restrict__ npiv,
                                                          const int32_t* __restrict__ first, const int64_t* __restrict__ front_off,
                                                          cx<T>* __restrict__ arena, int32_t* __restrict__ ipiv, T tiny,
-                                                         int32_t* nperturb, CoopPub<T>* __restrict__ pub, int* bar, int* fail) {
+                                                         int32_t* nperturb, CoopPub<T>* __restrict__ pub, int* bar, int max_polls,
+                                                         int* fail) {
     __shared__ PanelShared<T> sh;
     // the column's publications, loaded in one batch after its barrier
     __shared__ T s_cv[kCoopMaxG];
@@ -250,10 +251,15 @@ __global__ void __launch_bounds__(kWG) k_front_panel_coop(const int32_t* __restr
     if (k0 >= p) return;
     const int G = coop_groups(p - k0, min_rows);
     const int g = blockIdx.x, t = threadIdx.x;
-    if (g >= G || __hip_atomic_load(fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    if (g >= G) return;
     const int K0 = (k0 / kOB) * kOB, k1 = min(k0 + kNB, p), nb = k1 - k0;
     cx<T>* A = arena + front_off[f];
     int32_t* piv = ipiv + first[f];
+    // identity pivots first: a factorisation whose barrier wait failed (then every later split
+    // panel is skipped) still leaves valid rows for the swap kernels that follow; the workgroup
+    // overwrites them with the real pivots as it goes
+    if (g == 0 && t < nb) piv[k0 + t] = k0 + t;
+    if (__hip_atomic_load(fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     CoopPub<T>& P = pub[blockIdx.y];
     unsigned long long* word = reinterpret_cast<unsigned long long*>(bar + kCoopBarInts * blockIdx.y);
     int ir[kCoopRPT];
@@ -296,7 +302,7 @@ __global__ void __launch_bounds__(kWG) k_front_panel_coop(const int32_t* __restr
 #pragma unroll
                     for (int jj = 0; jj < kNB; ++jj) P.rowk[par][jj] = a[r][jj];
             }
-            alive = coop_barrier(word, G, fail);   // uniform over the workgroup
+            alive = coop_barrier(word, G, max_polls, fail);   // uniform over the workgroup
         }
         if (kk < nb && alive) {
             // every candidate with its row, and row k, in one round of loads
@@ -1548,7 +1554,8 @@ void run_factor(Factor& f, cr_sys sys, double sigma, cx<T>* arena, T tiny, hipSt
                     ProfScope ps(sys->ctx, "front_panel", s);
                     hipLaunchKernelGGL(k_front_panel_coop<T>, dim3(gsplit, nbig), dim3(kWG), 0, s, bl, j, split, D.fsize.p,
                                        D.npiv.p, D.first.p, D.front_off.p, arena, f.ipiv.p, tiny, f.nperturb.p,
-                                       reinterpret_cast<CoopPub<T>*>(f.coop_pub.p), f.coop_bar.p, f.nperturb.p + 1);
+                                       reinterpret_cast<CoopPub<T>*>(f.coop_pub.p), f.coop_bar.p,
+                                       sys->fclass.split_polls > 0 ? sys->fclass.split_polls : kCoopSpins, f.nperturb.p + 1);
                 }
                 if (any_mem) {
                     ProfScope ps(sys->ctx, "front_panel", s);

@@ -185,6 +185,7 @@ void finalize_sys(cr_sys sys);
 struct FrontClasses {
     int32_t big_m = 192, huge_m = 1024;
     int32_t split_rows = 1024;   // panels with this many fully-summed rows use several workgroups (0: never)
+    int32_t split_polls = 0;     // bound on a split panel's barrier polls (0: the default, about a second)
 };
 
 std::unique_ptr<Symbolic> analyse_pattern(int64_t n, const std::vector<int64_t>& rowptr,

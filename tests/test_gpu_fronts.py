@@ -196,3 +196,28 @@ def test_split_panels_bit_identical(P, ctx, fuselage_mid, prec):
         assert torch.equal(x, xs[0])
     with pytest.raises(P.CabinRomError):
         g.set_panel_split(100)
+
+
+def test_split_panel_barrier_timeout_reports_error(P, ctx, fuselage_mid):
+    """The split panel's bounded barrier wait, forced to run out from the host (one poll): the
+    factorisation ends with CR_E_HIP instead of hanging or returning a wrong factor, and the next
+    factorisation of the same system (default bound) is exact again."""
+    _flush("split panel barrier timeout")
+    w = fuselage_mid
+    g = P.assemble(ctx, w.mesh, w.loads, w.receivers)
+    g.analyse()
+    om = 2 * np.pi * 150.0
+    nn = g.n
+    u = W.SplitMix64(29).uniforms(2 * nn)
+    B = torch.from_numpy((u[:nn] + 1j * u[nn:]).reshape(nn, 1)).to(ctx.device)
+    g.set_panel_split(0)
+    ref = g.factor(om, 0).solve(B, max_iter=0, tol=1.0).cpu()
+    g.set_panel_split(1024, max_polls=1)
+    with pytest.raises(P.CabinRomError) as ei:
+        g.factor(om, 0)
+    assert ei.value.name == "CR_E_HIP", str(ei.value)
+    g.set_panel_split(1024)
+    x = g.factor(om, 0).solve(B, max_iter=0, tol=1.0).cpu()
+    assert torch.equal(x, ref)
+    with pytest.raises(P.CabinRomError):
+        g.set_panel_split(1024, max_polls=-1)
