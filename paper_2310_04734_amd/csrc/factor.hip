@@ -386,14 +386,13 @@ template <typename T>
 __global__ void __launch_bounds__(kWG) k_front_colstrip(const int32_t* __restrict__ big_list, int step,
                                                        const int32_t* __restrict__ fsize, const int32_t* __restrict__ npiv,
                                                        const int64_t* __restrict__ front_off, cx<T>* __restrict__ arena) {
-    __shared__ StripShared<T> sh;
     const int f = big_list[blockIdx.y];
     const int m = fsize[f], p = npiv[f], k0 = step * kNB;
     if (k0 >= p) return;
     const int K0 = (k0 / kOB) * kOB, k1 = min(k0 + kNB, p);
     const int r0 = k0 + kST * (int)blockIdx.x;
     if (r0 >= m || K0 == k0) return;
-    wg_strip_update<T>(arena + front_off[f], m, r0, min(kST, m - r0), k0, k1 - k0, K0, k0 - K0, sh);
+    wg_strip_update<T>(arena + front_off[f], m, r0, min(kST, m - r0), k0, k1 - k0, K0, k0 - K0);
 }
 
 // col[k0:k0+16] <- D^{-1} col[k0:k0+16] with D unit lower (d, zero-padded past the panel's nb
@@ -417,7 +416,6 @@ __device__ __forceinline__ void unit_lower16(cx<T>* __restrict__ col, int k0, in
 
 template <typename T>
 struct RowStripShared {
-    StripShared<T> st;
     cx<T> d[kNB][kNB + 1];   // diagonal block of the panel (unit-lower L and U)
     cx<T> rd[kNB];           // reciprocals of U's diagonal
     SwapShared sw;
@@ -480,7 +478,7 @@ __global__ void __launch_bounds__(kWG) k_front_rowstrip(const int32_t* __restric
     // the panel's swaps on this tile's columns, composed into one gather
     wg_apply_swaps<T>(A, m, pv, k0, k1, c0, c0 + nc, sh.sw);
     if (!right) return;
-    if (K0 < k0) wg_strip_update<T>(A, m, k0, nb, c0, nc, K0, k0 - K0, sh.st);
+    if (K0 < k0) wg_strip_update<T>(A, m, k0, nb, c0, nc, K0, k0 - K0);
     for (int e = t; e < kNB * kNB; e += kWG) {
         const int i = e % kNB, k = e / kNB;
         sh.d[i][k] = (i < nb && k < nb) ? A[k0 + i + (size_t)(k0 + k) * m] : cx<T>{T(0), T(0)};
@@ -518,7 +516,7 @@ __global__ void __launch_bounds__(kWG) k_front_rowblock(const int32_t* __restric
         const int k1 = min(k0 + kNB, K1), nb = k1 - k0;
         wg_apply_swaps<T>(A, m, pv, k0, k1, c0, c0 + nc, sh.sw);
         if (!right) continue;
-        if (K0 < k0) wg_strip_update<T>(A, m, k0, nb, c0, nc, K0, k0 - K0, sh.st);
+        if (K0 < k0) wg_strip_update<T>(A, m, k0, nb, c0, nc, K0, k0 - K0);
         __syncthreads();
         for (int e = t; e < kNB * kNB; e += kWG) {
             const int i = e % kNB, k = e / kNB;

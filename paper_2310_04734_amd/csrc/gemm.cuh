@@ -163,67 +163,55 @@ __device__ void wg_gemm_tile(cx<T>* __restrict__ A, int lda, int m, int k0, int 
     }
 }
 
+// C[r0:r0+nr, c0:c0+nc] -= A[r0:r0+nr, k0:k0+K] A[k0:k0+K, c0:c0+nc] with nr, nc <= 64 and K a
+// multiple of 4 (the in-block updates of the panel chain): 16 x 16 output tiles, one per wave at a
+// time, on the matrix cores with three real products per complex one (as the trailing GEMM);
+// each wave loads its operands straight from memory, eight K steps at a time, so the update
+// needs no LDS and no workgroup barrier. The caller synchronises before another wave reads C.
 template <typename T>
-struct StripShared {
-    cx<T> l[kST][kNB + 1];    // rows x 16 (one panel of K)
-    cx<T> u[kNB][kST + 1];    // 16 x columns
-};
-
-// C[r0:r0+nr, c0:c0+nc] -= A[r0:r0+nr, k0:k0+K] A[k0:k0+K, c0:c0+nc] with nr, nc <= 64,
-// nr * nc <= 1024 and K a multiple of 16 (the in-block updates before a panel).
-template <typename T>
-__device__ void wg_strip_update(cx<T>* __restrict__ A, int lda, int r0, int nr, int c0, int nc, int k0, int K,
-                                StripShared<T>& sh) {
-    const int t = threadIdx.x;
-    cx<T> acc[4];
+__device__ void wg_strip_update(cx<T>* __restrict__ A, int lda, int r0, int nr, int c0, int nc, int k0, int K) {
+    typedef typename MfmaAcc<T>::type acc_t;
+    constexpr int H = 8;   // K steps (of 4) whose loads are issued together
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int tr = (nr + 15) / 16, ntile = tr * ((nc + 15) / 16);
+    for (int tile = wave; tile < ntile; tile += kWG / 64) {
+        const int R0 = r0 + 16 * (tile % tr), C0 = c0 + 16 * (tile / tr);
+        const int trows = min(16, r0 + nr - R0), tcols = min(16, c0 + nc - C0);
+        acc_t p1 = {0, 0, 0, 0}, p2 = {0, 0, 0, 0}, p3 = {0, 0, 0, 0};
+        const bool aok = li < trows, bok = li < tcols;
+        for (int s0 = 0; 4 * s0 < K; s0 += H) {
+            cx<T> av[H], bv[H];
 #pragma unroll
-    for (int g = 0; g < 4; ++g) acc[g] = {T(0), T(0)};
-    constexpr int PER = kST * kNB / kWG;   // staged entries of each operand per thread
-    for (int kc = 0; kc < K; kc += kNB) {
-        // all loads of the chunk in flight before the first LDS store
-        cx<T> rl[PER], ru[PER];
+            for (int s = 0; s < H; ++s) {
+                const int k = 4 * (s0 + s) + lk;
+                const bool kin = k < K;
+                av[s] = (aok && kin) ? A[R0 + li + (size_t)(k0 + k) * lda] : cx<T>{T(0), T(0)};
+                bv[s] = (bok && kin) ? A[k0 + k + (size_t)(C0 + li) * lda] : cx<T>{T(0), T(0)};
+            }
 #pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int e = t + q * kWG;
-            rl[q] = e < nr * kNB ? A[r0 + e % nr + (size_t)(k0 + kc + e / nr) * lda] : cx<T>{T(0), T(0)};
-            ru[q] = e < kNB * nc ? A[k0 + kc + e % kNB + (size_t)(c0 + e / kNB) * lda] : cx<T>{T(0), T(0)};
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int e = t + q * kWG;
-            if (e < nr * kNB) sh.l[e % nr][e / nr] = rl[q];
-            if (e < kNB * nc) sh.u[e % kNB][e / kNB] = ru[q];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            const int e = t + g * kWG;
-            if (e < nr * nc) {
-                const int i = e % nr, j = e / nr;
-                cx<T> a = acc[g];
-#pragma unroll 4
-                for (int k = 0; k < kNB; ++k) {
-                    a.re += sh.l[i][k].re * sh.u[k][j].re - sh.l[i][k].im * sh.u[k][j].im;
-                    a.im += sh.l[i][k].re * sh.u[k][j].im + sh.l[i][k].im * sh.u[k][j].re;
-                }
-                acc[g] = a;
+            for (int s = 0; s < H; ++s) {
+                p1 = MfmaAcc<T>::mfma(av[s].re, bv[s].re, p1);
+                p2 = MfmaAcc<T>::mfma(av[s].im, bv[s].im, p2);
+                p3 = MfmaAcc<T>::mfma(av[s].re + av[s].im, bv[s].re + bv[s].im, p3);
             }
         }
-    }
-    cx<T> cv[4];
+        // item r of the accumulators: row MfmaAcc<T>::row(lane, r) of the tile, column li
+        cx<T> cv[4];
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
-        const int e = t + g * kWG;
-        cv[g] = e < nr * nc ? A[r0 + e % nr + (size_t)(c0 + e / nr) * lda] : cx<T>{T(0), T(0)};
-    }
+        for (int r = 0; r < 4; ++r) {
+            const int ro = MfmaAcc<T>::row(lane, r);
+            cv[r] = (ro < trows && li < tcols) ? A[R0 + ro + (size_t)(C0 + li) * lda] : cx<T>{T(0), T(0)};
+        }
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
-        const int e = t + g * kWG;
-        if (e < nr * nc) {
-            cv[g].re -= acc[g].re;
-            cv[g].im -= acc[g].im;
-            A[r0 + e % nr + (size_t)(c0 + e / nr) * lda] = cv[g];
+        for (int r = 0; r < 4; ++r) {
+            const int ro = MfmaAcc<T>::row(lane, r);
+            if (ro < trows && li < tcols) {
+                const T s1 = p1[r], s2 = p2[r];
+                cv[r].re -= s1 - s2;
+                cv[r].im -= p3[r] - s1 - s2;
+                A[R0 + ro + (size_t)(C0 + li) * lda] = cv[r];
+            }
         }
     }
 }
