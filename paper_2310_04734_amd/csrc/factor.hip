@@ -1491,13 +1491,14 @@ void run_factor(Factor& f, cr_sys sys, double sigma, cx<T>* arena, T tiny, hipSt
         const int nf = S.level_off[l + 1] - S.level_off[l];
         const int32_t* lf = D.level_fronts.p + S.level_off[l];
         {
-            // workgroups per front: one per 16 columns of the level's largest front, at most 512
+            // workgroups per front: one per 32 columns of the level's largest front, at most 256
             // (the top fronts are the largest memory traffic of the assembly: m^2 entries zeroed
-            // and the children's contribution blocks added, which 64 workgroups cannot stream
-            // at the memory's rate)
+            // and the children's contribution blocks added, which 64 workgroups cannot stream at
+            // the memory's rate; on the fuselage fronts 32 columns per workgroup measured faster
+            // than 8, 16 or 64, and a cap of 256 faster than 128, 512 or 1024)
             int mmax = 0;
             for (int q = S.level_off[l]; q < S.level_off[l + 1]; ++q) mmax = std::max(mmax, S.fsize[S.level_fronts[q]]);
-            const unsigned split = (unsigned)std::min(512, std::max(1, mmax / 16));
+            const unsigned split = (unsigned)std::min(256, std::max(1, mmax / 32));
             ProfScope ps(sys->ctx, "front_assemble", s);
             hipLaunchKernelGGL(k_front_assemble<T>, dim3(nf, split), dim3(kWG), 0, s, lf, D.fsize.p, D.front_off.p, D.child_off.p,
                                D.child_list.p, D.npiv.p, D.cmap_off.p, D.cmap.p, D.ent_off.p, D.ent_src.p, D.ent_dst.p,
