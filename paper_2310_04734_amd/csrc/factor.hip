@@ -382,6 +382,10 @@ __global__ void __launch_bounds__(kWG) k_front_panel_coop(const int32_t* __restr
     if (g == 0 && K0 < k0) wg_apply_swaps<T>(A, m, piv, k0, k1, K0, k0, sh.sw);
 }
 
+// rows of a column strip per workgroup (8 MFMA tiles, two per wave; 128 rows measured faster than
+// 32 or 64 on the fuselage fronts, while the row tiles keep kST = 64 columns)
+constexpr int kCST = 128;
+
 template <typename T>
 __global__ void __launch_bounds__(kWG) k_front_colstrip(const int32_t* __restrict__ big_list, int step,
                                                        const int32_t* __restrict__ fsize, const int32_t* __restrict__ npiv,
@@ -390,9 +394,9 @@ __global__ void __launch_bounds__(kWG) k_front_colstrip(const int32_t* __restric
     const int m = fsize[f], p = npiv[f], k0 = step * kNB;
     if (k0 >= p) return;
     const int K0 = (k0 / kOB) * kOB, k1 = min(k0 + kNB, p);
-    const int r0 = k0 + kST * (int)blockIdx.x;
+    const int r0 = k0 + kCST * (int)blockIdx.x;
     if (r0 >= m || K0 == k0) return;
-    wg_strip_update<T>(arena + front_off[f], m, r0, min(kST, m - r0), k0, k1 - k0, K0, k0 - K0);
+    wg_strip_update<T>(arena + front_off[f], m, r0, min(kCST, m - r0), k0, k1 - k0, K0, k0 - K0);
 }
 
 // col[k0:k0+16] <- D^{-1} col[k0:k0+16] with D unit lower (d, zero-padded past the panel's nb
@@ -1537,7 +1541,7 @@ void run_factor(Factor& f, cr_sys sys, double sigma, cx<T>* arena, T tiny, hipSt
                         gsplit = std::max(gsplit, (unsigned)G);
                     }
                     const int K0 = (k0 / kOB) * kOB, k1 = std::min(k0 + kNB, p), Kend = std::min(K0 + kOB, p);
-                    gcol = std::max(gcol, (unsigned)((m - k0 + kST - 1) / kST));
+                    gcol = std::max(gcol, (unsigned)((m - k0 + kCST - 1) / kCST));
                     grow = std::max(grow, (unsigned)((Kend - k1 + kST - 1) / kST + (m - p + kWG - 1) / kWG));
                 }
                 if (j % per != 0 && gcol) {
